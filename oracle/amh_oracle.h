@@ -1,0 +1,89 @@
+/*
+ * CPU oracle for the checkerboard PatchMatch pass of AMHMVS
+ * (Xu & Tao, "Multi-View Stereo with Asymmetric Checkerboard Propagation and
+ * Multi-Hypothesis Joint View Selection", arXiv 1805.07920).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, double-precision
+ * restatement of the method, used to judge the GPU library.  Only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg may call it; the
+ * library never does.  It shares no code, header, table or constant with the
+ * GPU path.
+ *
+ * Parity status per function (pins live in tests/):
+ *   orc_philox4x64_10      pinned (bit-exact vs numpy.random.Philox)
+ *   orc_project            pinned (closed-form homography, renderer geometry)
+ *   orc_matching_cost      pinned (numpy.cov / corrcoef reductions, invariances,
+ *                          exact integer-disparity case)
+ *   orc_view_selection     pinned (hand-computed matrices, closed forms of Eq. 2-4)
+ *   orc_acp_offsets        pinned (invariants of the region table)
+ *   orc_pass / orc_run     pinned by recovery of rendered ground truth, brute-force
+ *                          plane sweep and order independence; the refinement step,
+ *                          the initial cost and the empty-selection fallback are
+ *                          readings the paper does not fix: parity unpinned.
+ */
+#ifndef AMH_ORACLE_H
+#define AMH_ORACLE_H
+#include <stdint.h>
+
+#define ORC_MAX_SRC 32
+#define ORC_N_OFFSETS 72
+
+typedef struct {
+    int W, H, n_src;
+    const float *ref;                 /* H*W row-major intensities in [0,255] */
+    const float *src[ORC_MAX_SRC];    /* source j: srcH[j]*srcW[j] row-major */
+    int srcW[ORC_MAX_SRC], srcH[ORC_MAX_SRC];
+    double Kref[9], Rref[9], tref[3]; /* X_cam = R X_world + t, row-major 3x3 */
+    double Ksrc[ORC_MAX_SRC][9], Rsrc[ORC_MAX_SRC][9], tsrc[ORC_MAX_SRC][3];
+} orc_views;
+
+typedef struct {
+    int refine, include_self;
+    double d_min, d_max, sigma_color, sigma_spatial;
+    double tau_mc_init, alpha, beta, tau_up;
+    int n1, n2, k;
+    uint64_t seed;
+    int view_mode;   /* 0: joint view selection (the method); 1: plain mean over all views
+                        (a static objective, used only by the brute-force sweep pin) */
+} orc_params;
+
+typedef struct {
+    double *plane;   /* P*4: n_x, n_y, n_z, d_p with n.X + d_p = 0 in the reference camera frame */
+    double *cost;    /* P */
+    uint32_t *S;     /* P: view-selection set of the pixel's last update (bit j = source j) */
+    int32_t *v;      /* P: most important view of the last update, -1 if none */
+} orc_state;
+
+typedef struct {
+    double mfinal[9];   /* aggregated cost of rows 0..7 (regions) and 8 (self); +inf if absent */
+    double M[9][ORC_MAX_SRC];
+    int row_valid[9];
+    int cand_index[8];  /* index into the offset table of the picked neighbour, -1 if none */
+    double w[ORC_MAX_SRC];
+    uint32_t S;
+    int v;
+    int chosen;         /* 0..7 region row, 8 self, 9+c refinement candidate c */
+    double cand_cost[6];
+    double cand_plane[6][4];
+    int n_cand;
+    int robust;         /* 1 if every decision of this pixel clears the margin delta */
+} orc_diag;
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double orc_u24(uint64_t w);
+int orc_acp_offsets(int *dx, int *dy, int *region);
+void orc_project(const orc_views *V, double sx, double sy, const double plane[4], int j, double out[3]);
+double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, const double plane[4], int j);
+double orc_tau(const orc_params *p, int t);
+void orc_view_selection(const orc_params *p, int t, const double *M, const int *row_valid, int N,
+                        uint32_t S_prev, int v_prev, uint32_t *S_out, int *v_out, double *w_out);
+void orc_random_plane(const orc_views *V, const orc_params *p, int x, int y, uint64_t t, uint64_t purpose,
+                      double plane[4]);
+void orc_init(const orc_views *V, const orc_params *p, orc_state *s);
+void orc_pass(const orc_views *V, const orc_params *p, orc_state *s, int t, int colour,
+              const int *order, int n_order, double delta, orc_diag *diag);
+void orc_run(const orc_views *V, const orc_params *p, orc_state *s, int iters);
+void orc_depth_normal(const orc_views *V, const orc_state *s, double *depth, double *normal);
+int orc_num_threads(void);
+
+#endif
