@@ -15,9 +15,11 @@
  *   R2  region geometry of the asymmetric propagation (the figure that fixes it
  *       is missing): near regions are V-shaped wedges of 7 pixels, far regions
  *       are axial strips of 11 pixels at odd distances 3..23.
- *   R3  a hypothesis whose window centre does not project into the source
- *       with positive depth, or whose depth at the pixel is outside
- *       [d_min, d_max], costs 2.
+ *   R3  a hypothesis costs 2 if its depth at the pixel is outside
+ *       [d_min, d_max] (by more than a relative 1e-5), if the window centre
+ *       does not project inside the source image, or if any window sample's
+ *       ray meets the plane behind the reference camera or lands behind the
+ *       source camera.
  *   R4  the window is 11x11 sampled at every other row and column: offsets
  *       {-5,-3,-1,1,3,5}^2, 36 samples.
  *   R5  bilateral weight exp(-|dI|/(2 sI^2) - |dx|/(2 sx^2)) with the colour
@@ -202,7 +204,9 @@ static double bilinear(const float *img, int W, int H, double px, double py)
 double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, const double plane[4], int j)
 {
     double depth = depth_at(V, x, y, plane);
-    if (!(depth > 0.0) || depth < p->d_min || depth > p->d_max) return 2.0;
+    /* the range test tolerates a relative 1e-5, so that planes built at a clamped end of the
+       range (refinement) are not rejected by the last bit of their reconstruction (R3) */
+    if (!(depth > 0.0) || depth < p->d_min * (1.0 - 1e-5) || depth > p->d_max * (1.0 + 1e-5)) return 2.0;
     double c[3];
     orc_project(V, x, y, plane, j, c);
     if (!(c[2] > 0.0)) return 2.0;
@@ -218,8 +222,14 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             double dcol = fabs(a[n] - ac);
             double dsp = sqrt((double)(dx * dx + dy * dy));
             w[n] = exp(-dcol / (2.0 * p->sigma_color * p->sigma_color) - dsp / (2.0 * p->sigma_spatial * p->sigma_spatial));
+            /* every sample's ray must meet the plane in front of the reference camera and the
+               point must lie in front of the source camera (R3) */
+            double rs[3];
+            ray_of(V, x + dx, y + dy, rs);
+            if (!(-plane[3] / dot3(plane, rs) > 0.0)) return 2.0;
             double h[3];
             orc_project(V, x + dx, y + dy, plane, j, h);
+            if (!(h[2] > 0.0)) return 2.0;
             b[n] = bilinear(V->src[j], V->srcW[j], V->srcH[j], h[0] / h[2], h[1] / h[2]);
             ++n;
         }
@@ -305,7 +315,10 @@ void orc_view_selection(const orc_params *p, int t, const double *M, const int *
     *v_out = v;
 }
 
-/* robustness of the view-selection decisions to perturbations of size delta in M */
+/* Robustness of the view-selection decisions to perturbations of size delta
+ * in M, as bits: ORC_ROBUST_S (the good-view tests), ORC_ROBUST_V (the argmax
+ * v_t), ORC_ROBUST_TOPK (the top-k cut).  A good-view test that can flip
+ * changes the weights, so it clears every bit. */
 static int view_selection_robust(const orc_params *p, int t, const double *M, const int *row_valid, int N,
                                  uint32_t S, int v_prev, double delta)
 {
@@ -331,7 +344,7 @@ static int view_selection_robust(const orc_params *p, int t, const double *M, co
         if (nv > 0 && can_true && can_false) return 0;
         psi[j] = nv > 0 ? sc / nv : 0.0;
     }
-    /* the argmax (v_t) and the top-k cut need clear gaps */
+    int bits = ORC_ROBUST_S | ORC_ROBUST_V | ORC_ROBUST_TOPK;
     double mods[ORC_MAX_SRC];
     double top1 = -1.0, top2 = -1.0;
     int n = 0;
@@ -341,7 +354,7 @@ static int view_selection_robust(const orc_params *p, int t, const double *M, co
         if (psi[j] > top1) { top2 = top1; top1 = psi[j]; }
         else if (psi[j] > top2) top2 = psi[j];
     }
-    if (n >= 2 && top1 - top2 < 2 * dpsi) return 0;
+    if (n >= 2 && top1 - top2 < 2 * dpsi) bits &= ~ORC_ROBUST_V;
     if (n > p->k) {
         /* gap between the k-th and (k+1)-th modified importance */
         double s[ORC_MAX_SRC];
@@ -349,9 +362,9 @@ static int view_selection_robust(const orc_params *p, int t, const double *M, co
         for (int a = 0; a < n; ++a)
             for (int b = a + 1; b < n; ++b)
                 if (s[b] > s[a]) { double tmp = s[a]; s[a] = s[b]; s[b] = tmp; }
-        if (s[p->k - 1] - s[p->k] < 4 * dpsi) return 0;
+        if (s[p->k - 1] - s[p->k] < 4 * dpsi) bits &= ~ORC_ROBUST_TOPK;
     }
-    return 1;
+    return bits;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -487,9 +500,13 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
     memcpy(cur, planes[best], sizeof(cur));
     double cur_cost = mf[best];
     int chosen = best;
-    int robust = view_selection_robust(p, t, Mflat, valid, N, S, s->v[idx], delta);
+    int robust = view_selection_robust(p, t, Mflat, valid, N, S, s->v[idx], delta) | ORC_ROBUST_ARGMIN |
+                 ORC_ROBUST_REFINE;
+    if (!(robust & ORC_ROBUST_S)) robust = 0;
     for (int r = 0; r < 9; ++r)
-        if (valid[r] && r != best && fabs(mf[r] - mf[best]) < 4 * delta) robust = 0;
+        if (valid[r] && r != best && fabs(mf[r] - mf[best]) < 4 * delta &&
+            memcmp(planes[r], planes[best], sizeof(planes[r])) != 0)
+            robust &= ~ORC_ROBUST_ARGMIN; /* identical planes tie exactly on any implementation */
 
     /* refinement (R13) */
     int n_cand = 0;
@@ -526,7 +543,7 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
             for (int j = 0; j < N; ++j)
                 if (w[j] > 0.0) acc += w[j] * orc_matching_cost(V, p, x, y, cand[c], j);
             cand_cost[c] = acc / sw;
-            if (fabs(cand_cost[c] - cur_cost) < 4 * delta) robust = 0;
+            if (fabs(cand_cost[c] - cur_cost) < 4 * delta) robust &= ~ORC_ROBUST_REFINE;
             if (cand_cost[c] < cur_cost) {
                 cur_cost = cand_cost[c];
                 memcpy(cur, cand[c], sizeof(cur));

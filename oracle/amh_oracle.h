@@ -28,6 +28,13 @@
 #define ORC_MAX_SRC 32
 #define ORC_N_OFFSETS 72
 
+/* decisions of a pixel update that clear a given margin (orc_diag.robust) */
+#define ORC_ROBUST_S 1       /* good-view tests (S_t) */
+#define ORC_ROBUST_V 2       /* most important view v_t */
+#define ORC_ROBUST_TOPK 4    /* top-k cut of the weights */
+#define ORC_ROBUST_ARGMIN 8  /* best hypothesis */
+#define ORC_ROBUST_REFINE 16 /* refinement acceptances */
+
 typedef struct {
     int W, H, n_src;
     const float *ref;                 /* H*W row-major intensities in [0,255] */
@@ -66,7 +73,7 @@ typedef struct {
     double cand_cost[6];
     double cand_plane[6][4];
     int n_cand;
-    int robust;         /* 1 if every decision of this pixel clears the margin delta */
+    int robust;         /* ORC_ROBUST_* bits of the decisions that clear the margin delta */
 } orc_diag;
 
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
