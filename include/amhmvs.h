@@ -1,0 +1,186 @@
+/*
+ * amhmvs.h -- C-ABI of the MI355X (gfx950) checkerboard PatchMatch library.
+ *
+ * The library computes the depth and normal map of one reference image from N
+ * calibrated source images with the method of Xu & Tao, "Multi-View Stereo with
+ * Asymmetric Checkerboard Propagation and Multi-Hypothesis Joint View
+ * Selection" (arXiv 1805.07920):
+ *   - random scene-plane hypotheses per pixel (Sec. 2 / 3, PatchMatch init),
+ *   - red/black checkerboard half-passes (Sec. 3.1, Fig. 2(a)) in which every
+ *     pixel takes the lowest-cost neighbour of each of 8 asymmetric regions
+ *     (Sec. 3.1, Fig. 2(d)), scores the 8 planes (plus its own) on every source
+ *     with the bilaterally weighted NCC over an 11x11 window sampled every
+ *     other row and column (Sec. 3.3, Eq. 8), infers per-pixel view weights
+ *     from the 8 x N cost matrix (Sec. 3.2, Eq. 1-6), keeps the plane with the
+ *     lowest aggregated cost (Eq. 7) and refines it (Sec. 3.3).
+ *
+ * Conventions
+ *   - Every call returns amh_status; AMH_OK is 0, errors are negative.  No C++
+ *     exception crosses the ABI.  amh_last_error() returns a message for the
+ *     last failing call on a context.
+ *   - Arguments are validated on the host before any HIP call, so invalid
+ *     arguments are reported even on a machine without a GPU.
+ *   - Cameras map world points to camera coordinates by X_cam = R X + t (R, K
+ *     row-major).  K must be upper triangular with K[8] != 0.  Pixel (x, y) has
+ *     its centre at integer coordinates, y points down; depth is camera z.
+ *   - Images are row-major grayscale intensities on the [0, 255] scale.
+ *   - Ownership: the caller owns every buffer it passes in; the context owns
+ *     every buffer it allocates and frees them in amh_destroy.
+ *   - Streams: all device work of a context runs in order on the HIP stream
+ *     given to amh_create (NULL = the null stream).  Calls that return data to
+ *     host memory synchronise that stream; calls with device destinations are
+ *     stream-ordered and return without waiting.
+ *   - A context is used by one host thread at a time.
+ *   - Limits: 1..32 sources per reference (the view-selection set is a 32-bit
+ *     mask); images up to 16384 x 16384.
+ */
+#ifndef AMHMVS_H
+#define AMHMVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amh_ctx amh_ctx;
+
+typedef enum {
+    AMH_OK = 0,
+    AMH_E_INVALID_ARG = -1, /* a pointer, size or parameter is out of its documented range */
+    AMH_E_OOM = -2,         /* a device allocation failed */
+    AMH_E_HIP = -3,         /* the HIP runtime reported an error (no device, launch failure, ...) */
+    AMH_E_STATE = -4,       /* the call needs an earlier call that has not happened (e.g. views, a run) */
+    AMH_E_UNSUPPORTED = -5  /* a valid request outside what this build supports */
+} amh_status;
+
+typedef enum { AMH_F32 = 0, AMH_F16 = 1 } amh_dtype;
+
+/* Calibrated pinhole camera: x ~ K (R X + t). */
+typedef struct {
+    double K[9], R[9], t[3];
+    int width, height;
+} amh_camera;
+
+/* An image handed to amh_init_views.  data points to height rows of
+ * pitch_elems elements (pitch_elems >= width) of type dtype, in host memory
+ * (on_device = 0) or device memory of the context's GPU (on_device = 1). */
+typedef struct {
+    const void *data;
+    int width, height;
+    int64_t pitch_elems;
+    amh_dtype dtype;
+    int on_device;
+} amh_image;
+
+/* Method parameters.  amh_params_default() fills the paper's values
+ * (Sec. 4: tau_mc_init 0.8, alpha 90, beta 0.3, n1 2, n2 3, tau_up 1.2, k 4,
+ * sigma_color 3, sigma_spatial 30). */
+typedef struct {
+    int refine;          /* 1: perturbation refinement after each pixel update (Sec. 3.3) */
+    int include_self;    /* 1: the pixel's current plane competes in the final argmin */
+    float depth_min, depth_max;
+    float sigma_color, sigma_spatial;   /* bilateral NCC weights (Eq. 8) */
+    float tau_mc_init, alpha;           /* threshold schedule (Eq. 2) */
+    float beta;                         /* confidence width (Eq. 3) */
+    float tau_up;                       /* good-view upper threshold (Sec. 3.2) */
+    int n1, n2, k;                      /* good-view counts and top-k (Sec. 3.2) */
+    uint64_t seed;                      /* key of the counter-based random generator */
+    int timing;                         /* 1: record per-pass device times (amh_get_stats) */
+} amh_params;
+
+/* Counters of the work performed since the last amh_begin / amh_run_checkerboard. */
+typedef struct {
+    uint64_t evals_total;       /* hypothesis x view NCC evaluations (36 samples each) */
+    uint64_t evals_init;        /* ... in the random initialisation */
+    uint64_t evals_propagation; /* ... of the 8 propagated planes and the pixel's own */
+    uint64_t evals_refine;      /* ... of refinement candidates */
+    int n_passes;
+    float ms_per_pass[64];      /* device time of each half-pass (timing = 1), else 0 */
+    float ms_init;
+} amh_stats;
+
+/* Batched job (see amh_run_batch). */
+typedef struct {
+    int ref;             /* view index (amh_init_views order) of the reference image */
+    const int *srcs;     /* n_src view indices of its sources (host memory) */
+    int n_src;
+    int iters;
+} amh_job;
+
+/* Fills *out with the paper's parameters, depth range [2, 6], refine 1,
+ * include_self 1, seed 0, timing 0.  INVALID_ARG if out is NULL. */
+amh_status amh_params_default(amh_params *out);
+
+/* Creates a context on the current HIP device.  p: parameters (copied).
+ * hip_stream: a hipStream_t or NULL.  INVALID_ARG on bad parameters (checked
+ * first), HIP if no device is usable. */
+amh_status amh_create(amh_ctx **out, const amh_params *p, void *hip_stream);
+
+/* Replaces the parameters of a context (INVALID_ARG if out of range). */
+amh_status amh_set_params(amh_ctx *ctx, const amh_params *p);
+
+/* Registers n_views images with their cameras (index = view id).  The library
+ * copies them into its own device buffers: a float32 copy for use as a
+ * reference, and a gather layout of the same values for use as a source, in
+ * float32 or float16 (store_sources_as; float32 input is rounded to nearest
+ * even).  The caller's buffers may be freed on return.  Replaces any views
+ * registered before. */
+amh_status amh_init_views(amh_ctx *ctx, int n_views, const amh_image *views, const amh_camera *cams,
+                          amh_dtype store_sources_as);
+
+/* Selects the reference view and its n_src sources for the following calls,
+ * builds the per-view plane-induced warp constants (Sec. 3.3) and allocates
+ * the per-pixel state.  Resets the statistics. */
+amh_status amh_begin(amh_ctx *ctx, int ref, const int *srcs, int n_src);
+
+/* Random initialisation of every pixel's plane (Philox keyed by the seed,
+ * counter = pixel, iteration 0); initial cost = mean of the k lowest per-view
+ * costs; empty view-selection memory. */
+amh_status amh_init_hypotheses(amh_ctx *ctx);
+
+/* One checkerboard half-pass of iteration t (0-based) on the pixels of one
+ * colour (0 = red, (x + y) even; 1 = black): asymmetric propagation, cost
+ * matrix, joint view selection, best plane, refinement (Sec. 3.1-3.3). */
+amh_status amh_pass(amh_ctx *ctx, int t, int colour);
+
+/* amh_begin + amh_init_hypotheses + iters x (red pass, black pass). */
+amh_status amh_run_checkerboard(amh_ctx *ctx, int ref, const int *srcs, int n_src, int iters);
+
+/* Copies the result of the current reference: depth (H*W, camera z), normal
+ * (H*W*3, unit, facing the camera) and cost (H*W, aggregated NCC cost).  Any
+ * of the three may be NULL.  dst_on_device: destinations are device pointers. */
+amh_status amh_get_depth_normal_cost(amh_ctx *ctx, float *depth, float *normal, float *cost, int dst_on_device);
+
+/* Per-pixel state of the current reference: planes (H*W*4: n_x, n_y, n_z, d
+ * with n.X + d = 0 in the reference camera frame), cost (H*W), S (H*W view
+ * masks, bit j = j-th source of amh_begin), v (H*W, most important view or -1).
+ * get: any pointer may be NULL; set: all four are required.  on_device as above. */
+amh_status amh_get_state(amh_ctx *ctx, float *planes, float *cost, uint32_t *S, int32_t *v, int dst_on_device);
+amh_status amh_set_state(amh_ctx *ctx, const float *planes, const float *cost, const uint32_t *S,
+                         const int32_t *v, int src_on_device);
+
+/* Matching cost (Eq. 8) of Q fixed hypotheses on every source of amh_begin:
+ * planes (Q*4), pix (Q*2 ints: x, y) -> costs (Q*n_src, row-major by query).
+ * All three in host memory (on_device = 0) or device memory (1). */
+amh_status amh_score_fixed(amh_ctx *ctx, const float *planes, const int *pix, int Q, float *costs, int on_device);
+
+/* Runs n_jobs reference images (views registered by amh_init_views) in one
+ * batch: all passes of all jobs inside one captured HIP graph of persistent
+ * launches.  Results are read with amh_get_job_result. */
+amh_status amh_run_batch(amh_ctx *ctx, int n_jobs, const amh_job *jobs);
+amh_status amh_get_job_result(amh_ctx *ctx, int job, float *depth, float *normal, float *cost, int dst_on_device);
+
+/* Work counters and timings of the current reference (or of the last batch). */
+amh_status amh_get_stats(const amh_ctx *ctx, amh_stats *out);
+
+const char *amh_status_str(amh_status s);
+const char *amh_last_error(const amh_ctx *ctx);
+
+/* Frees the context and everything it owns.  NULL is ignored. */
+void amh_destroy(amh_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,298 @@
+"""Python binding of libamhmvs (include/amhmvs.h): argument marshalling only.
+
+Every step of the method runs in the library's gfx950 kernels; this module
+converts numpy arrays / torch tensors to pointers and checks return codes.
+torch is used only for device memory and the stream.  If the compiled library
+is missing the import of :func:`lib` fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libamhmvs.so")
+
+AMH_OK, AMH_E_INVALID_ARG, AMH_E_OOM, AMH_E_HIP, AMH_E_STATE, AMH_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+AMH_F32, AMH_F16 = 0, 1
+
+# every function the header declares (checked against include/amhmvs.h by the tests)
+EXPORTS = [
+    "amh_params_default", "amh_create", "amh_set_params", "amh_init_views", "amh_begin", "amh_init_hypotheses",
+    "amh_pass", "amh_run_checkerboard", "amh_get_depth_normal_cost", "amh_get_state", "amh_set_state",
+    "amh_score_fixed", "amh_run_batch", "amh_get_job_result", "amh_get_stats", "amh_status_str",
+    "amh_last_error", "amh_destroy",
+]
+
+
+class AmhError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"amhmvs status {status}: {msg}")
+        self.status = status
+
+
+class amh_camera(C.Structure):
+    _fields_ = [("K", C.c_double * 9), ("R", C.c_double * 9), ("t", C.c_double * 3),
+                ("width", C.c_int), ("height", C.c_int)]
+
+
+class amh_image(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("width", C.c_int), ("height", C.c_int), ("pitch_elems", C.c_int64),
+                ("dtype", C.c_int), ("on_device", C.c_int)]
+
+
+class amh_params(C.Structure):
+    _fields_ = [("refine", C.c_int), ("include_self", C.c_int), ("depth_min", C.c_float), ("depth_max", C.c_float),
+                ("sigma_color", C.c_float), ("sigma_spatial", C.c_float), ("tau_mc_init", C.c_float),
+                ("alpha", C.c_float), ("beta", C.c_float), ("tau_up", C.c_float), ("n1", C.c_int), ("n2", C.c_int),
+                ("k", C.c_int), ("seed", C.c_uint64), ("timing", C.c_int)]
+
+
+class amh_stats(C.Structure):
+    _fields_ = [("evals_total", C.c_uint64), ("evals_init", C.c_uint64), ("evals_propagation", C.c_uint64),
+                ("evals_refine", C.c_uint64), ("n_passes", C.c_int), ("ms_per_pass", C.c_float * 64),
+                ("ms_init", C.c_float)]
+
+
+class amh_job(C.Structure):
+    _fields_ = [("ref", C.c_int), ("srcs", C.POINTER(C.c_int)), ("n_src", C.c_int), ("iters", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C-ABI library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() (no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, fp = C.c_void_p, C.c_int, C.c_float
+        L.amh_params_default.argtypes = [C.POINTER(amh_params)]
+        L.amh_create.argtypes = [C.POINTER(vp), C.POINTER(amh_params), vp]
+        L.amh_set_params.argtypes = [vp, C.POINTER(amh_params)]
+        L.amh_init_views.argtypes = [vp, ip, C.POINTER(amh_image), C.POINTER(amh_camera), ip]
+        L.amh_begin.argtypes = [vp, ip, C.POINTER(C.c_int), ip]
+        L.amh_init_hypotheses.argtypes = [vp]
+        L.amh_pass.argtypes = [vp, ip, ip]
+        L.amh_run_checkerboard.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
+        L.amh_get_depth_normal_cost.argtypes = [vp, vp, vp, vp, ip]
+        L.amh_get_state.argtypes = [vp, vp, vp, vp, vp, ip]
+        L.amh_set_state.argtypes = [vp, vp, vp, vp, vp, ip]
+        L.amh_score_fixed.argtypes = [vp, vp, vp, ip, vp, ip]
+        L.amh_run_batch.argtypes = [vp, ip, C.POINTER(amh_job)]
+        L.amh_get_job_result.argtypes = [vp, ip, vp, vp, vp, ip]
+        L.amh_get_stats.argtypes = [vp, C.POINTER(amh_stats)]
+        L.amh_status_str.argtypes = [ip]
+        L.amh_status_str.restype = C.c_char_p
+        L.amh_last_error.argtypes = [vp]
+        L.amh_last_error.restype = C.c_char_p
+        L.amh_destroy.argtypes = [vp]
+        L.amh_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def params_default(**kw) -> amh_params:
+    p = amh_params()
+    rc = lib().amh_params_default(C.byref(p))
+    if rc != AMH_OK:
+        raise AmhError(rc, "amh_params_default")
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _camera(cam) -> amh_camera:
+    c = amh_camera()
+    c.K[:] = np.asarray(cam.K, np.float64).ravel().tolist()
+    c.R[:] = np.asarray(cam.R, np.float64).ravel().tolist()
+    c.t[:] = np.asarray(cam.t, np.float64).ravel().tolist()
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _ptr(x):
+    """(pointer, on_device) of a numpy array or torch tensor; None -> (None, 0)."""
+    if x is None:
+        return None, 0
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return x.ctypes.data, 0
+    import torch
+
+    if isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return x.data_ptr(), 1 if x.is_cuda else 0
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _current_stream():
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Context:
+    """One amh_ctx: registered views, the current reference and its per-pixel state."""
+
+    def __init__(self, params: amh_params | None = None, stream=None, **kw):
+        self.L = lib()
+        self.p = params if params is not None else params_default(**kw)
+        h = C.c_void_p()
+        s = stream if stream is not None else _current_stream()
+        rc = self.L.amh_create(C.byref(h), C.byref(self.p), s)
+        if rc != AMH_OK:
+            raise AmhError(rc, "amh_create: " + self.L.amh_status_str(rc).decode())
+        self.h = h
+        self._keep = []
+        self.W = self.H = 0
+        self.n_src = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.amh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != AMH_OK:
+            raise AmhError(rc, f"{what}: {self.L.amh_last_error(self.h).decode()}")
+
+    # --- calls of the C-ABI -----------------------------------------------------------
+    def set_params(self, params: amh_params):
+        self._check(self.L.amh_set_params(self.h, C.byref(params)), "amh_set_params")
+        self.p = params
+
+    def init_views(self, images, cams, store_as: int = AMH_F32):
+        n = len(images)
+        arr = (amh_image * n)()
+        camarr = (amh_camera * n)()
+        keep = []
+        for i, (im, cam) in enumerate(zip(images, cams)):
+            ptr, dev = _ptr(im)
+            if dev:
+                import torch
+
+                dt = AMH_F16 if im.dtype == torch.float16 else AMH_F32
+                if im.dtype not in (torch.float16, torch.float32):
+                    raise TypeError("images must be float32 or float16")
+            else:
+                if im.dtype not in (np.float16, np.float32):
+                    raise TypeError("images must be float32 or float16")
+                dt = AMH_F16 if im.dtype == np.float16 else AMH_F32
+            keep.append(im)
+            H, W = im.shape
+            arr[i] = amh_image(ptr, W, H, W, dt, dev)
+            camarr[i] = _camera(cam)
+        self._check(self.L.amh_init_views(self.h, n, arr, camarr, store_as), "amh_init_views")
+        self._views_shape = [tuple(im.shape) for im in images]
+
+    def begin(self, ref: int, srcs):
+        s = (C.c_int * len(srcs))(*[int(v) for v in srcs])
+        self._check(self.L.amh_begin(self.h, ref, s, len(srcs)), "amh_begin")
+        self.H, self.W = self._views_shape[ref]
+        self.n_src = len(srcs)
+
+    def init_hypotheses(self):
+        self._check(self.L.amh_init_hypotheses(self.h), "amh_init_hypotheses")
+
+    def pass_(self, t: int, colour: int):
+        self._check(self.L.amh_pass(self.h, t, colour), "amh_pass")
+
+    def run_checkerboard(self, ref: int, srcs, iters: int):
+        s = (C.c_int * len(srcs))(*[int(v) for v in srcs])
+        self._check(self.L.amh_run_checkerboard(self.h, ref, s, len(srcs), iters), "amh_run_checkerboard")
+        self.H, self.W = self._views_shape[ref]
+        self.n_src = len(srcs)
+
+    def get_depth_normal_cost(self, depth=None, normal=None, cost=None):
+        """Host numpy outputs by default; pass device tensors to fill them in place."""
+        if depth is None and normal is None and cost is None:
+            depth = np.zeros((self.H, self.W), np.float32)
+            normal = np.zeros((self.H, self.W, 3), np.float32)
+            cost = np.zeros((self.H, self.W), np.float32)
+        ptrs = [_ptr(x) for x in (depth, normal, cost)]
+        devs = {d for p, d in ptrs if p is not None}
+        if len(devs) > 1:
+            raise ValueError("outputs must all be host or all device")
+        dev = devs.pop() if devs else 0
+        self._check(self.L.amh_get_depth_normal_cost(self.h, ptrs[0][0], ptrs[1][0], ptrs[2][0], dev),
+                    "amh_get_depth_normal_cost")
+        return depth, normal, cost
+
+    def get_state(self):
+        P = (self.H, self.W)
+        planes = np.zeros(P + (4,), np.float32)
+        cost = np.zeros(P, np.float32)
+        S = np.zeros(P, np.uint32)
+        v = np.zeros(P, np.int32)
+        self._check(self.L.amh_get_state(self.h, planes.ctypes.data, cost.ctypes.data, S.ctypes.data,
+                                         v.ctypes.data, 0), "amh_get_state")
+        return planes, cost, S, v
+
+    def set_state(self, planes, cost, S, v):
+        arrs = [np.ascontiguousarray(planes, np.float32), np.ascontiguousarray(cost, np.float32),
+                np.ascontiguousarray(S, np.uint32), np.ascontiguousarray(v, np.int32)]
+        self._check(self.L.amh_set_state(self.h, *[a.ctypes.data for a in arrs], 0), "amh_set_state")
+
+    def score_fixed(self, planes, pix):
+        planes = np.ascontiguousarray(planes, np.float32).reshape(-1, 4)
+        pix = np.ascontiguousarray(pix, np.int32).reshape(-1, 2)
+        Q = planes.shape[0]
+        out = np.zeros((Q, self.n_src), np.float32)
+        self._check(self.L.amh_score_fixed(self.h, planes.ctypes.data, pix.ctypes.data, Q, out.ctypes.data, 0),
+                    "amh_score_fixed")
+        return out
+
+    def run_batch(self, jobs):
+        arr = (amh_job * len(jobs))()
+        keep = []
+        for i, jb in enumerate(jobs):
+            s = (C.c_int * len(jb["srcs"]))(*[int(v) for v in jb["srcs"]])
+            keep.append(s)
+            arr[i] = amh_job(int(jb["ref"]), s, len(jb["srcs"]), int(jb["iters"]))
+        self._check(self.L.amh_run_batch(self.h, len(jobs), arr), "amh_run_batch")
+        self._jobs_shape = [self._views_shape[int(jb["ref"])] for jb in jobs]
+
+    def get_job_result(self, job: int, depth=None, normal=None, cost=None):
+        H, W = self._jobs_shape[job]
+        if depth is None and normal is None and cost is None:
+            depth = np.zeros((H, W), np.float32)
+            normal = np.zeros((H, W, 3), np.float32)
+            cost = np.zeros((H, W), np.float32)
+        ptrs = [_ptr(x) for x in (depth, normal, cost)]
+        dev = max(d for _, d in ptrs)
+        self._check(self.L.amh_get_job_result(self.h, job, ptrs[0][0], ptrs[1][0], ptrs[2][0], dev),
+                    "amh_get_job_result")
+        return depth, normal, cost
+
+    def get_stats(self) -> dict:
+        s = amh_stats()
+        self._check(self.L.amh_get_stats(self.h, C.byref(s)), "amh_get_stats")
+        return dict(evals_total=s.evals_total, evals_init=s.evals_init, evals_propagation=s.evals_propagation,
+                    evals_refine=s.evals_refine, n_passes=s.n_passes,
+                    ms_per_pass=list(s.ms_per_pass[:s.n_passes]), ms_init=s.ms_init)

@@ -1,0 +1,693 @@
+// Host runtime and C-ABI of the checkerboard PatchMatch library (include/amhmvs.h).
+// Validates every argument before touching HIP, owns all device buffers of a
+// context, and orders all work on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "amh_internal.h"
+#include "amhmvs.h"
+
+using namespace amh;
+
+namespace {
+
+struct View {
+    int W = 0, H = 0;
+    float *img = nullptr;   // float32 copy (reference use)
+    void *quads = nullptr;  // gather layout (source use)
+    int half = 0;
+    double K[9], R[9], t[3];
+};
+
+struct JobResult {
+    int W = 0, H = 0;
+    float4 *planes = nullptr;
+    float *cost = nullptr;
+    uint32_t *S = nullptr;
+    int32_t *v = nullptr;
+};
+
+}  // namespace
+
+struct amh_ctx {
+    amh_params p;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    int half = 0;
+    std::vector<View> views;
+    // current reference
+    int ref = -1;
+    std::vector<int> srcs;
+    std::vector<ViewDev> h_viewc;
+    ViewDev *d_viewc = nullptr;
+    size_t viewc_cap = 0;
+    RefDev refdev{};
+    float4 *planes = nullptr;
+    float *cost = nullptr;
+    uint32_t *S = nullptr;
+    int32_t *v = nullptr;
+    size_t state_cap = 0;
+    bool have_state = false;
+    unsigned long long *counters = nullptr;
+    // timing
+    std::vector<hipEvent_t> ev;  // pairs: [2i] start, [2i+1] stop
+    int n_timed = 0;
+    hipEvent_t ev_init[2] = {nullptr, nullptr};
+    bool init_timed = false;
+    // batch results
+    std::vector<JobResult> jobs;
+    unsigned long long batch_counts[3] = {0, 0, 0};
+    bool batch_stats = false;
+};
+
+namespace {
+
+int g_alloc_count = 0;
+
+amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIPCHK(c, expr)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return fail((c), AMH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// device allocation with an optional injected failure (AMH_FAIL_ALLOC_AT=n fails the n-th call, 1-based)
+amh_status dalloc(amh_ctx *c, void **ptr, size_t bytes) {
+    ++g_alloc_count;
+    const char *inj = getenv("AMH_FAIL_ALLOC_AT");
+    if (inj && atoi(inj) == g_alloc_count) return fail(c, AMH_E_OOM, "injected allocation failure (%zu bytes)", bytes);
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(c, AMH_E_OOM, "hipMalloc(%zu) failed: out of memory", bytes);
+    if (e != hipSuccess) return fail(c, AMH_E_HIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    return AMH_OK;
+}
+
+bool finite_all(const double *a, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+amh_status check_params(amh_ctx *c, const amh_params *p) {
+    if (!p) return fail(c, AMH_E_INVALID_ARG, "params is NULL");
+    if (!(p->depth_min > 0.f) || !(p->depth_max > p->depth_min) || !std::isfinite(p->depth_max))
+        return fail(c, AMH_E_INVALID_ARG, "need 0 < depth_min < depth_max < inf");
+    if (!(p->sigma_color > 0.f) || !(p->sigma_spatial > 0.f) || !std::isfinite(p->sigma_color) ||
+        !std::isfinite(p->sigma_spatial))
+        return fail(c, AMH_E_INVALID_ARG, "sigma_color and sigma_spatial must be positive and finite");
+    if (!(p->alpha > 0.f) || !(p->beta > 0.f) || !std::isfinite(p->tau_mc_init) || !std::isfinite(p->tau_up))
+        return fail(c, AMH_E_INVALID_ARG, "alpha and beta must be positive; thresholds finite");
+    if (p->n1 < 0 || p->n1 > 8 || p->n2 < 0 || p->n2 > 9 || p->k < 1 || p->k > kMaxSrc)
+        return fail(c, AMH_E_INVALID_ARG, "need 0 <= n1 <= 8, 0 <= n2 <= 9, 1 <= k <= 32");
+    if ((p->refine != 0 && p->refine != 1) || (p->include_self != 0 && p->include_self != 1) ||
+        (p->timing != 0 && p->timing != 1))
+        return fail(c, AMH_E_INVALID_ARG, "refine, include_self and timing are 0 or 1");
+    return AMH_OK;
+}
+
+amh_status check_camera(amh_ctx *c, const amh_camera &cam, int i) {
+    if (!finite_all(cam.K, 9) || !finite_all(cam.R, 9) || !finite_all(cam.t, 3))
+        return fail(c, AMH_E_INVALID_ARG, "camera %d has non-finite entries", i);
+    if (cam.K[3] != 0.0 || cam.K[6] != 0.0 || cam.K[7] != 0.0 || cam.K[8] == 0.0)
+        return fail(c, AMH_E_UNSUPPORTED, "camera %d: K must be upper triangular with K[8] != 0", i);
+    const double fx = cam.K[0] / cam.K[8], fy = cam.K[4] / cam.K[8];
+    if (fx == 0.0 || fy == 0.0) return fail(c, AMH_E_INVALID_ARG, "camera %d: singular K", i);
+    return AMH_OK;
+}
+
+MethodDev method_dev(const amh_params &p, int t) {
+    MethodDev m;
+    m.d_min = p.depth_min;
+    m.d_max = p.depth_max;
+    m.inv_2sc2 = (float)(1.0 / (2.0 * (double)p.sigma_color * p.sigma_color));
+    m.inv_2sx2 = (float)(1.0 / (2.0 * (double)p.sigma_spatial * p.sigma_spatial));
+    m.tau = (float)((double)p.tau_mc_init * std::exp(-(double)t * t / (double)p.alpha));
+    m.tau_up = p.tau_up;
+    m.inv_2b2 = (float)(1.0 / (2.0 * (double)p.beta * p.beta));
+    m.n1 = p.n1;
+    m.n2 = p.n2;
+    m.k = p.k;
+    m.include_self = p.include_self;
+    m.refine = p.refine;
+    m.seed = p.seed;
+    return m;
+}
+
+void kinv_upper(const double Kin[9], double &a, double &b, double &cc, double &e, double &f) {
+    const double s = Kin[8];
+    const double fx = Kin[0] / s, sk = Kin[1] / s, cx = Kin[2] / s, fy = Kin[4] / s, cy = Kin[5] / s;
+    a = 1.0 / fx;
+    b = -sk / (fx * fy);
+    cc = (sk * cy - cx * fy) / (fx * fy);
+    e = 1.0 / fy;
+    f = -cy / fy;
+}
+
+void mat3_mul(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// warp constants of source view j relative to reference view r
+ViewDev view_dev(const View &r, const View &s) {
+    double Rrel[9], RrT[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) RrT[3 * i + j] = r.R[3 * j + i];
+    mat3_mul(s.R, RrT, Rrel);
+    double trel[3];
+    for (int i = 0; i < 3; ++i)
+        trel[i] = s.t[i] - (Rrel[3 * i] * r.t[0] + Rrel[3 * i + 1] * r.t[1] + Rrel[3 * i + 2] * r.t[2]);
+    double a, b, cc, e, f;
+    kinv_upper(r.K, a, b, cc, e, f);
+    const double Kinv[9] = {a, b, cc, 0, e, f, 0, 0, 1};
+    double Ks[9];
+    for (int i = 0; i < 9; ++i) Ks[i] = s.K[i] / s.K[8];
+    double KR[9];
+    mat3_mul(Ks, Rrel, KR);
+    ViewDev v;
+    mat3_mul(KR, Kinv, v.A);
+    for (int i = 0; i < 3; ++i) v.b[i] = Ks[3 * i] * trel[0] + Ks[3 * i + 1] * trel[1] + Ks[3 * i + 2] * trel[2];
+    v.quads = s.quads;
+    v.W = s.W;
+    v.H = s.H;
+    return v;
+}
+
+void free_view(View &v) {
+    if (v.img) (void)hipFree(v.img);
+    if (v.quads) (void)hipFree(v.quads);
+    v.img = nullptr;
+    v.quads = nullptr;
+}
+
+void free_job(JobResult &j) {
+    if (j.planes) (void)hipFree(j.planes);
+    if (j.cost) (void)hipFree(j.cost);
+    if (j.S) (void)hipFree(j.S);
+    if (j.v) (void)hipFree(j.v);
+    j = JobResult{};
+}
+
+PassArgs pass_args(amh_ctx *c, int t, int colour) {
+    PassArgs a;
+    a.ref = c->refdev;
+    a.views = c->d_viewc;
+    a.n_src = (int)c->srcs.size();
+    a.m = method_dev(c->p, t);
+    a.st = StateDev{c->planes, c->cost, c->S, c->v};
+    a.t = t;
+    a.colour = colour;
+    const int W = c->refdev.W, H = c->refdev.H;
+    const int per_row = (W + 1) / 2;  // same-colour pixels per row (upper bound)
+    a.tiles_x = (per_row + kTilePix - 1) / kTilePix;
+    const int tiles_y = (H + kTileRows - 1) / kTileRows;
+    a.n_tiles = a.tiles_x * tiles_y;
+    a.counters = c->counters;
+    return a;
+}
+
+amh_status ensure_events(amh_ctx *c, int n) {
+    while ((int)c->ev.size() < 2 * n) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    return AMH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *amh_status_str(amh_status s) {
+    switch (s) {
+        case AMH_OK: return "ok";
+        case AMH_E_INVALID_ARG: return "invalid argument";
+        case AMH_E_OOM: return "out of device memory";
+        case AMH_E_HIP: return "HIP runtime error";
+        case AMH_E_STATE: return "call out of order";
+        case AMH_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *amh_last_error(const amh_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+amh_status amh_params_default(amh_params *out) {
+    if (!out) return AMH_E_INVALID_ARG;
+    memset(out, 0, sizeof *out);
+    out->refine = 1;
+    out->include_self = 1;
+    out->depth_min = 2.f;
+    out->depth_max = 6.f;
+    out->sigma_color = 3.f;
+    out->sigma_spatial = 30.f;
+    out->tau_mc_init = 0.8f;
+    out->alpha = 90.f;
+    out->beta = 0.3f;
+    out->tau_up = 1.2f;
+    out->n1 = 2;
+    out->n2 = 3;
+    out->k = 4;
+    out->seed = 0;
+    out->timing = 0;
+    return AMH_OK;
+}
+
+amh_status amh_create(amh_ctx **out, const amh_params *p, void *hip_stream) {
+    if (!out) return AMH_E_INVALID_ARG;
+    *out = nullptr;
+    amh_status st = check_params(nullptr, p);
+    if (st != AMH_OK) return st;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return AMH_E_HIP;
+    amh_ctx *c = new (std::nothrow) amh_ctx();
+    if (!c) return AMH_E_OOM;
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return AMH_E_HIP;
+    }
+    st = dalloc(c, (void **)&c->counters, sizeof(unsigned long long) * 3 * kCounterSlots);
+    if (st != AMH_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return AMH_OK;
+}
+
+amh_status amh_set_params(amh_ctx *c, const amh_params *p) {
+    if (!c) return AMH_E_INVALID_ARG;
+    amh_status st = check_params(c, p);
+    if (st != AMH_OK) return st;
+    c->p = *p;
+    return AMH_OK;
+}
+
+amh_status amh_init_views(amh_ctx *c, int n_views, const amh_image *views, const amh_camera *cams,
+                          amh_dtype store_as) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (n_views < 1 || n_views > 4096 || !views || !cams)
+        return fail(c, AMH_E_INVALID_ARG, "need 1 <= n_views <= 4096 and non-NULL views and cams");
+    if (store_as != AMH_F32 && store_as != AMH_F16) return fail(c, AMH_E_INVALID_ARG, "store_as must be F32 or F16");
+    for (int i = 0; i < n_views; ++i) {
+        const amh_image &im = views[i];
+        if (!im.data) return fail(c, AMH_E_INVALID_ARG, "view %d: data is NULL", i);
+        if (im.width < 1 || im.height < 1 || im.width > 16384 || im.height > 16384)
+            return fail(c, AMH_E_INVALID_ARG, "view %d: size %dx%d outside 1..16384", i, im.width, im.height);
+        if (im.pitch_elems < im.width) return fail(c, AMH_E_INVALID_ARG, "view %d: pitch < width", i);
+        if (im.dtype != AMH_F32 && im.dtype != AMH_F16) return fail(c, AMH_E_INVALID_ARG, "view %d: bad dtype", i);
+        if (im.on_device != 0 && im.on_device != 1) return fail(c, AMH_E_INVALID_ARG, "view %d: on_device is 0/1", i);
+        if (cams[i].width != im.width || cams[i].height != im.height)
+            return fail(c, AMH_E_INVALID_ARG, "view %d: camera size differs from image size", i);
+        amh_status st = check_camera(c, cams[i], i);
+        if (st != AMH_OK) return st;
+    }
+    // replace the registered views; buffers of a view with the same size and storage type are reused
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<View> old = std::move(c->views);
+    c->views.clear();
+    c->have_state = false;
+    c->ref = -1;
+    c->half = store_as == AMH_F16;
+    void *staging = nullptr;
+    size_t staging_cap = 0;
+    amh_status result = AMH_OK;
+    for (int i = 0; i < n_views && result == AMH_OK; ++i) {
+        const amh_image &im = views[i];
+        View v;
+        v.W = im.width;
+        v.H = im.height;
+        v.half = c->half;
+        memcpy(v.K, cams[i].K, sizeof v.K);
+        memcpy(v.R, cams[i].R, sizeof v.R);
+        memcpy(v.t, cams[i].t, sizeof v.t);
+        const size_t px = (size_t)v.W * v.H;
+        const size_t qbytes = (size_t)(v.W + 1) * (v.H + 1) * (c->half ? 8 : 16);
+        if (i < (int)old.size() && old[i].W == v.W && old[i].H == v.H && old[i].half == v.half && old[i].img) {
+            v.img = old[i].img;
+            v.quads = old[i].quads;
+            old[i].img = nullptr;
+            old[i].quads = nullptr;
+        } else {
+            if ((result = dalloc(c, (void **)&v.img, px * sizeof(float))) != AMH_OK) break;
+            if ((result = dalloc(c, &v.quads, qbytes)) != AMH_OK) {
+                free_view(v);
+                break;
+            }
+        }
+        const size_t esz = im.dtype == AMH_F16 ? 2 : 4;
+        const void *src = im.data;
+        int64_t pitch = im.pitch_elems;
+        if (!im.on_device) {
+            const size_t need = px * esz;
+            if (need > staging_cap) {
+                if (staging) (void)hipFree(staging);
+                staging = nullptr;
+                staging_cap = 0;
+                if ((result = dalloc(c, &staging, need)) != AMH_OK) {
+                    free_view(v);
+                    break;
+                }
+                staging_cap = need;
+            }
+            hipError_t e = hipMemcpy2DAsync(staging, v.W * esz, im.data, (size_t)im.pitch_elems * esz, v.W * esz, v.H,
+                                            hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) {
+                free_view(v);
+                result = fail(c, AMH_E_HIP, "upload of view %d: %s", i, hipGetErrorString(e));
+                break;
+            }
+            src = staging;
+            pitch = v.W;
+        }
+        hipError_t e = launch_convert_to_f32(src, im.dtype == AMH_F16 ? 1 : 0, pitch, v.W, v.H, v.img, c->stream);
+        if (e == hipSuccess) e = launch_pack_quads(v.img, v.W, v.H, v.quads, c->half, c->stream);
+        if (e != hipSuccess) {
+            free_view(v);
+            result = fail(c, AMH_E_HIP, "layout kernels of view %d: %s", i, hipGetErrorString(e));
+            break;
+        }
+        if (!im.on_device) {
+            // the staging buffer is reused by the next host view: wait for this one
+            e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) {
+                free_view(v);
+                result = fail(c, AMH_E_HIP, "view %d: %s", i, hipGetErrorString(e));
+                break;
+            }
+        }
+        c->views.push_back(v);
+    }
+    if (staging) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(staging);
+    }
+    for (auto &v : old) free_view(v);
+    if (result != AMH_OK) {
+        for (auto &v : c->views) free_view(v);
+        c->views.clear();
+    }
+    return result;
+}
+
+amh_status amh_begin(amh_ctx *c, int ref, const int *srcs, int n_src) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (c->views.empty()) return fail(c, AMH_E_STATE, "no views registered (amh_init_views)");
+    const int nv = (int)c->views.size();
+    if (ref < 0 || ref >= nv) return fail(c, AMH_E_INVALID_ARG, "ref %d outside 0..%d", ref, nv - 1);
+    if (!srcs || n_src < 1 || n_src > kMaxSrc) return fail(c, AMH_E_INVALID_ARG, "need 1 <= n_src <= 32 sources");
+    for (int i = 0; i < n_src; ++i) {
+        if (srcs[i] < 0 || srcs[i] >= nv) return fail(c, AMH_E_INVALID_ARG, "source %d: view %d out of range", i, srcs[i]);
+        if (srcs[i] == ref) return fail(c, AMH_E_INVALID_ARG, "source %d is the reference", i);
+        for (int k = 0; k < i; ++k)
+            if (srcs[k] == srcs[i]) return fail(c, AMH_E_INVALID_ARG, "source view %d listed twice", srcs[i]);
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the previous constants may still be in flight
+    const View &r = c->views[ref];
+    c->ref = ref;
+    c->srcs.assign(srcs, srcs + n_src);
+    c->h_viewc.resize(n_src);
+    for (int i = 0; i < n_src; ++i) c->h_viewc[i] = view_dev(r, c->views[srcs[i]]);
+    if ((size_t)n_src > c->viewc_cap) {
+        if (c->d_viewc) (void)hipFree(c->d_viewc);
+        c->d_viewc = nullptr;
+        c->viewc_cap = 0;
+        amh_status st = dalloc(c, (void **)&c->d_viewc, sizeof(ViewDev) * kMaxSrc);
+        if (st != AMH_OK) return st;
+        c->viewc_cap = kMaxSrc;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_viewc, c->h_viewc.data(), sizeof(ViewDev) * n_src, hipMemcpyHostToDevice, c->stream));
+    c->refdev.img = r.img;
+    c->refdev.W = r.W;
+    c->refdev.H = r.H;
+    kinv_upper(r.K, c->refdev.kinv_a, c->refdev.kinv_b, c->refdev.kinv_c, c->refdev.kinv_e, c->refdev.kinv_f);
+    const size_t P = (size_t)r.W * r.H;
+    if (P > c->state_cap) {
+        if (c->planes) (void)hipFree(c->planes);
+        if (c->cost) (void)hipFree(c->cost);
+        if (c->S) (void)hipFree(c->S);
+        if (c->v) (void)hipFree(c->v);
+        c->planes = nullptr;
+        c->cost = nullptr;
+        c->S = nullptr;
+        c->v = nullptr;
+        c->state_cap = 0;
+        amh_status st;
+        if ((st = dalloc(c, (void **)&c->planes, P * sizeof(float4))) != AMH_OK) return st;
+        if ((st = dalloc(c, (void **)&c->cost, P * sizeof(float))) != AMH_OK) return st;
+        if ((st = dalloc(c, (void **)&c->S, P * sizeof(uint32_t))) != AMH_OK) return st;
+        if ((st = dalloc(c, (void **)&c->v, P * sizeof(int32_t))) != AMH_OK) return st;
+        c->state_cap = P;
+    }
+    c->have_state = false;
+    c->n_timed = 0;
+    c->init_timed = false;
+    c->batch_stats = false;
+    HIPCHK(c, launch_zero_u64(c->counters, 3 * kCounterSlots, c->stream));
+    return AMH_OK;
+}
+
+amh_status amh_init_hypotheses(amh_ctx *c) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
+    const int half = c->half;
+    if (c->p.timing) {
+        for (int i = 0; i < 2; ++i)
+            if (!c->ev_init[i]) HIPCHK(c, hipEventCreate(&c->ev_init[i]));
+        HIPCHK(c, hipEventRecord(c->ev_init[0], c->stream));
+    }
+    for (int colour = 0; colour < 2; ++colour) {
+        PassArgs a = pass_args(c, 0, colour);
+        HIPCHK(c, launch_init(a, half, c->stream));
+    }
+    if (c->p.timing) {
+        HIPCHK(c, hipEventRecord(c->ev_init[1], c->stream));
+        c->init_timed = true;
+    }
+    c->have_state = true;
+    return AMH_OK;
+}
+
+amh_status amh_pass(amh_ctx *c, int t, int colour) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (t < 0 || t > 1000000 || (colour != 0 && colour != 1))
+        return fail(c, AMH_E_INVALID_ARG, "need t >= 0 and colour 0 or 1");
+    if (c->ref < 0 || !c->have_state) return fail(c, AMH_E_STATE, "no initialised state (amh_init_hypotheses)");
+    PassArgs a = pass_args(c, t, colour);
+    const bool timed = c->p.timing && c->n_timed < 64;
+    if (timed) {
+        amh_status st = ensure_events(c, c->n_timed + 1);
+        if (st != AMH_OK) return st;
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->n_timed], c->stream));
+    }
+    HIPCHK(c, launch_pass(a, c->half, c->stream));
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->n_timed + 1], c->stream));
+        ++c->n_timed;
+    }
+    return AMH_OK;
+}
+
+amh_status amh_run_checkerboard(amh_ctx *c, int ref, const int *srcs, int n_src, int iters) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (iters < 0 || iters > 1000) return fail(c, AMH_E_INVALID_ARG, "iters must be in 0..1000");
+    amh_status st = amh_begin(c, ref, srcs, n_src);
+    if (st != AMH_OK) return st;
+    if ((st = amh_init_hypotheses(c)) != AMH_OK) return st;
+    for (int t = 0; t < iters; ++t)
+        for (int colour = 0; colour < 2; ++colour)
+            if ((st = amh_pass(c, t, colour)) != AMH_OK) return st;
+    return AMH_OK;
+}
+
+amh_status amh_get_depth_normal_cost(amh_ctx *c, float *depth, float *normal, float *cost, int dst_on_device) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (dst_on_device != 0 && dst_on_device != 1) return fail(c, AMH_E_INVALID_ARG, "dst_on_device is 0 or 1");
+    if (c->ref < 0 || !c->have_state) return fail(c, AMH_E_STATE, "no result yet");
+    const size_t P = (size_t)c->refdev.W * c->refdev.H;
+    StateDev st{c->planes, c->cost, c->S, c->v};
+    if (dst_on_device) {
+        HIPCHK(c, launch_outputs(c->refdev, st, depth, normal, cost, c->stream));
+        return AMH_OK;
+    }
+    float *tmp = nullptr;
+    amh_status s = dalloc(c, (void **)&tmp, P * 5 * sizeof(float));
+    if (s != AMH_OK) return s;
+    hipError_t e = launch_outputs(c->refdev, st, depth ? tmp : nullptr, normal ? tmp + P : nullptr,
+                                  cost ? tmp + 4 * P : nullptr, c->stream);
+    if (e == hipSuccess && depth) e = hipMemcpyAsync(depth, tmp, P * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && normal) e = hipMemcpyAsync(normal, tmp + P, P * 12, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && cost) e = hipMemcpyAsync(cost, tmp + 4 * P, P * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, AMH_E_HIP, "get_depth_normal_cost: %s", hipGetErrorString(e));
+    return AMH_OK;
+}
+
+amh_status amh_get_state(amh_ctx *c, float *planes, float *cost, uint32_t *S, int32_t *v, int dst_on_device) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (dst_on_device != 0 && dst_on_device != 1) return fail(c, AMH_E_INVALID_ARG, "dst_on_device is 0 or 1");
+    if (c->ref < 0 || !c->have_state) return fail(c, AMH_E_STATE, "no state yet");
+    const size_t P = (size_t)c->refdev.W * c->refdev.H;
+    const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (planes) HIPCHK(c, hipMemcpyAsync(planes, c->planes, P * 16, k, c->stream));
+    if (cost) HIPCHK(c, hipMemcpyAsync(cost, c->cost, P * 4, k, c->stream));
+    if (S) HIPCHK(c, hipMemcpyAsync(S, c->S, P * 4, k, c->stream));
+    if (v) HIPCHK(c, hipMemcpyAsync(v, c->v, P * 4, k, c->stream));
+    if (!dst_on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return AMH_OK;
+}
+
+amh_status amh_set_state(amh_ctx *c, const float *planes, const float *cost, const uint32_t *S, const int32_t *v,
+                         int src_on_device) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (!planes || !cost || !S || !v) return fail(c, AMH_E_INVALID_ARG, "all four state arrays are required");
+    if (src_on_device != 0 && src_on_device != 1) return fail(c, AMH_E_INVALID_ARG, "src_on_device is 0 or 1");
+    if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
+    const size_t P = (size_t)c->refdev.W * c->refdev.H;
+    const hipMemcpyKind k = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(c, hipMemcpyAsync(c->planes, planes, P * 16, k, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->cost, cost, P * 4, k, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->S, S, P * 4, k, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->v, v, P * 4, k, c->stream));
+    if (!src_on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_state = true;
+    return AMH_OK;
+}
+
+amh_status amh_score_fixed(amh_ctx *c, const float *planes, const int *pix, int Q, float *costs, int on_device) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (Q < 0 || Q > (1 << 24)) return fail(c, AMH_E_INVALID_ARG, "need 0 <= Q <= 2^24");
+    if (on_device != 0 && on_device != 1) return fail(c, AMH_E_INVALID_ARG, "on_device is 0 or 1");
+    if (Q > 0 && (!planes || !pix || !costs)) return fail(c, AMH_E_INVALID_ARG, "NULL buffer");
+    if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
+    const int N = (int)c->srcs.size();
+    if (!on_device)
+        for (int i = 0; i < Q; ++i)
+            if (pix[2 * i] < 0 || pix[2 * i] >= c->refdev.W || pix[2 * i + 1] < 0 || pix[2 * i + 1] >= c->refdev.H)
+                return fail(c, AMH_E_INVALID_ARG, "query %d: pixel outside the reference image", i);
+    if (Q == 0) return AMH_OK;
+    ScoreArgs a;
+    a.ref = c->refdev;
+    a.views = c->d_viewc;
+    a.n_src = N;
+    a.m = method_dev(c->p, 0);
+    a.Q = Q;
+    if (on_device) {
+        a.planes = reinterpret_cast<const float4 *>(planes);
+        a.pix = reinterpret_cast<const int2 *>(pix);
+        a.costs = costs;
+        HIPCHK(c, launch_score(a, c->half, c->stream));
+        return AMH_OK;
+    }
+    unsigned char *buf = nullptr;
+    const size_t bp = (size_t)Q * 16, bq = (size_t)Q * 8, bc = (size_t)Q * N * 4;
+    amh_status s = dalloc(c, (void **)&buf, bp + bq + bc);
+    if (s != AMH_OK) return s;
+    hipError_t e = hipMemcpyAsync(buf, planes, bp, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf + bp, pix, bq, hipMemcpyHostToDevice, c->stream);
+    a.planes = reinterpret_cast<const float4 *>(buf);
+    a.pix = reinterpret_cast<const int2 *>(buf + bp);
+    a.costs = reinterpret_cast<float *>(buf + bp + bq);
+    if (e == hipSuccess) e = launch_score(a, c->half, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(costs, a.costs, bc, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(c, AMH_E_HIP, "score_fixed: %s", hipGetErrorString(e));
+    return AMH_OK;
+}
+
+amh_status amh_run_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
+    if (!c) return AMH_E_INVALID_ARG;
+    (void)n_jobs;
+    (void)jobs;
+    return fail(c, AMH_E_UNSUPPORTED, "batched execution is not built yet");
+}
+
+amh_status amh_get_job_result(amh_ctx *c, int job, float *depth, float *normal, float *cost, int dst_on_device) {
+    if (!c) return AMH_E_INVALID_ARG;
+    (void)job;
+    (void)depth;
+    (void)normal;
+    (void)cost;
+    (void)dst_on_device;
+    return fail(c, AMH_E_STATE, "no batch has run");
+}
+
+amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
+    amh_ctx *c = const_cast<amh_ctx *>(cc);
+    if (!c || !out) return AMH_E_INVALID_ARG;
+    memset(out, 0, sizeof *out);
+    if (c->batch_stats) {
+        out->evals_init = c->batch_counts[0];
+        out->evals_propagation = c->batch_counts[1];
+        out->evals_refine = c->batch_counts[2];
+    } else {
+        std::vector<unsigned long long> h(3 * kCounterSlots);
+        HIPCHK(c, hipMemcpyAsync(h.data(), c->counters, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        unsigned long long s[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < kCounterSlots; ++i) s[k] += h[k * kCounterSlots + i];
+        out->evals_init = s[0];
+        out->evals_propagation = s[1];
+        out->evals_refine = s[2];
+    }
+    out->evals_total = out->evals_init + out->evals_propagation + out->evals_refine;
+    out->n_passes = c->n_timed;
+    for (int i = 0; i < c->n_timed && i < 64; ++i) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventSynchronize(c->ev[2 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        out->ms_per_pass[i] = ms;
+    }
+    if (c->init_timed) {
+        HIPCHK(c, hipEventSynchronize(c->ev_init[1]));
+        HIPCHK(c, hipEventElapsedTime(&out->ms_init, c->ev_init[0], c->ev_init[1]));
+    }
+    return AMH_OK;
+}
+
+void amh_destroy(amh_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &v : c->views) free_view(v);
+    for (auto &j : c->jobs) free_job(j);
+    if (c->d_viewc) (void)hipFree(c->d_viewc);
+    if (c->planes) (void)hipFree(c->planes);
+    if (c->cost) (void)hipFree(c->cost);
+    if (c->S) (void)hipFree(c->S);
+    if (c->v) (void)hipFree(c->v);
+    if (c->counters) (void)hipFree(c->counters);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    for (auto e : c->ev_init)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

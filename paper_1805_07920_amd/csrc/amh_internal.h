@@ -1,0 +1,84 @@
+// Internal interface between the host runtime (amh_api.hip) and the gfx950
+// kernels (amh_kernels.hip).  Plain-old-data structs passed by value to kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amh {
+
+constexpr int kMaxSrc = 32;
+constexpr int kCounterSlots = 256;    // eval counters are spread over slots to avoid one hot atomic
+constexpr int kWaves = 4;             // waves per workgroup of the pass kernels
+constexpr int kGroups = 7;            // pixels per wave (7 groups x 9 lanes = 63 lanes)
+constexpr int kRows = 9;              // 8 propagated hypotheses + the pixel's own
+constexpr int kTileRows = kWaves;     // image rows per workgroup tile
+constexpr int kTilePix = kGroups;     // same-colour pixels per tile row
+
+// One source view relative to the current reference (Sec. 3.3: plane-induced warp).
+// Homogeneous source pixel of reference pixel (x, y) on the plane with inverse
+// depth q(x, y):  A (x, y, 1)^T + b q.
+struct ViewDev {
+    double A[9];            // K_j R_rel K_ref^-1 (row-major)
+    double b[3];            // K_j t_rel
+    const void *quads;      // (H+1) x (W+1) texel quads, float4 or 4 x half
+    int W, H;
+};
+
+struct RefDev {
+    const float *img;       // H x W float32 reference intensities
+    int W, H;
+    double kinv_a, kinv_b, kinv_c, kinv_e, kinv_f;  // K_ref^-1 = [[a, b, c], [0, e, f], [0, 0, 1]]
+};
+
+struct MethodDev {
+    float d_min, d_max;
+    float inv_2sc2, inv_2sx2;    // 1 / (2 sigma_color^2), 1 / (2 sigma_spatial^2)
+    float tau, tau_up;           // tau_mc(t) of the pass, upper threshold
+    float inv_2b2;               // 1 / (2 beta^2)
+    int n1, n2, k;
+    int include_self, refine;
+    uint64_t seed;
+};
+
+struct StateDev {
+    float4 *planes;              // H x W (n_x, n_y, n_z, d)
+    float *cost;
+    uint32_t *S;
+    int32_t *v;
+};
+
+struct PassArgs {
+    RefDev ref;
+    const ViewDev *views;        // device array [n_src]
+    int n_src;
+    MethodDev m;
+    StateDev st;
+    int t, colour;
+    int tiles_x, n_tiles;        // tile grid of this colour
+    unsigned long long *counters;  // [3][kCounterSlots]: init, propagation, refinement evals
+};
+
+struct ScoreArgs {
+    RefDev ref;
+    const ViewDev *views;
+    int n_src;
+    MethodDev m;
+    const float4 *planes;        // Q
+    const int2 *pix;             // Q
+    int Q;
+    float *costs;                // Q x n_src
+};
+
+// launchers (amh_kernels.hip); all return the launch status
+hipError_t launch_convert_to_f32(const void *src, int src_dtype, int64_t pitch, int W, int H, float *dst,
+                                 hipStream_t s);
+hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int half, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_init(const PassArgs &a, int half, hipStream_t s);
+hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s);
+hipError_t launch_score(const ScoreArgs &a, int half, hipStream_t s);
+hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, float *normal, float *cost,
+                          hipStream_t s);
+size_t pass_lds_bytes(int n_src);
+
+}  // namespace amh

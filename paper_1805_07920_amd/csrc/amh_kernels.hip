@@ -1,0 +1,842 @@
+// gfx950 kernels of the checkerboard PatchMatch pass (Xu & Tao, arXiv 1805.07920).
+//
+// Work mapping of the pass (Sec. 3.1-3.3): a wave64 holds 7 pixels of one
+// colour on one image row, 9 lanes each.  Lane r < 8 owns the hypothesis
+// propagated from asymmetric region r, lane 8 the pixel's own plane; the
+// 64th lane idles.  All lanes of a wave warp into the same source view at the
+// same time, so their bilinear gathers hit neighbouring texels.  A workgroup
+// (4 waves) covers a tile of 4 rows x 7 same-colour pixels; its reference
+// window (tile + 5 px halo) is staged once in LDS.  The 9 x N cost matrix of a
+// pixel lives in LDS, one column per view; view selection is split over the
+// 9 lanes of the pixel and the final argmin is a 9-lane reduction.  MFMA is
+// not used: the work is per-sample gathers and scalar arithmetic, bounded by
+// the vector ALU.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "amh_internal.h"
+
+namespace amh {
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw,
+// "Parallel random numbers: as easy as 1, 2, 3", SC'11).  Key (seed, 0),
+// counter (pixel, iteration, purpose, 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox(uint64_t pix, uint64_t it, uint64_t purpose, uint64_t seed, float u[4]) {
+    uint64_t c0 = pix, c1 = it, c2 = purpose, c3 = 0;
+    uint64_t k0 = seed, k1 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+        uint64_t h0 = __umul64hi(m0, c0), l0 = m0 * c0;
+        uint64_t h1 = __umul64hi(m1, c2), l1 = m1 * c2;
+        uint64_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+        c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    // top 24 bits -> [0, 1), exact in float
+    u[0] = (float)(uint32_t)(c0 >> 40) * 0x1p-24f;
+    u[1] = (float)(uint32_t)(c1 >> 40) * 0x1p-24f;
+    u[2] = (float)(uint32_t)(c2 >> 40) * 0x1p-24f;
+    u[3] = (float)(uint32_t)(c3 >> 40) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
+// Asymmetric checkerboard propagation regions (Sec. 3.1, Fig. 2(d)).
+// Regions 0-3: near V-shaped wedges (7 candidates) up/down/left/right,
+// regions 4-7: far axial strips (11 candidates, odd distances 3..23).
+// Candidate e of the "up" wedge sits at level l = (e + 1) / 2 (0..3) beside
+// the axis, alternating left/right; far candidates step by 2 px.
+// Every offset has odd |dx| + |dy|, i.e. the other colour.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int region_size(int r) { return r < 4 ? 7 : 11; }
+
+__device__ __forceinline__ void region_offset(int r, int e, int &dx, int &dy) {
+    int ux, uy;
+    if (r < 4) {
+        int lvl = (e + 1) >> 1;
+        int side = (e & 1) ? -1 : 1;
+        ux = side * lvl;
+        uy = -(lvl + 1);
+    } else {
+        ux = 0;
+        uy = -(3 + 2 * e);
+    }
+    switch (r & 3) {
+        case 0: dx = ux; dy = uy; break;     // up
+        case 1: dx = ux; dy = -uy; break;    // down
+        case 2: dx = uy; dy = ux; break;     // left
+        default: dx = -uy; dy = ux; break;   // right
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Texel quads: entry (y0 + 1, x0 + 1) of a (H+1) x (W+1) array holds the 4
+// texels of the bilinear footprint with top-left (x0, y0), indices clamped to
+// the image, so one 16-byte (or 8-byte) load serves a sample.
+// ---------------------------------------------------------------------------
+template <int HALF>
+__device__ __forceinline__ float4 load_quad(const void *base, int idx);
+
+template <>
+__device__ __forceinline__ float4 load_quad<0>(const void *base, int idx) {
+    return reinterpret_cast<const float4 *>(base)[idx];
+}
+
+template <>
+__device__ __forceinline__ float4 load_quad<1>(const void *base, int idx) {
+    uint2 r = reinterpret_cast<const uint2 *>(base)[idx];
+    __half2 a = __builtin_bit_cast(__half2, r.x), b = __builtin_bit_cast(__half2, r.y);
+    float2 fa = __half22float2(a), fb = __half22float2(b);
+    return make_float4(fa.x, fa.y, fb.x, fb.y);
+}
+
+// ---------------------------------------------------------------------------
+// Reference window of a pixel (Sec. 3.3): 36 samples at offsets
+// {-5,-3,-1,1,3,5}^2, bilateral weights w = exp(-|a - a_c| / (2 sc^2)
+// - dist / (2 sx^2)) from the reference patch.  Stored per sample as
+// (w, w * (a - mean_w a)) so that the source loop only accumulates moments of
+// the source samples.  Returns 1/sum(w) and the reference's weighted variance.
+// ---------------------------------------------------------------------------
+struct WinStats {
+    float invW, var_a;
+};
+
+template <typename Reader>
+__device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodDev &m, float2 *rw, int write_phase,
+                                                 int write_stride) {
+    float a[36];
+    const float ac = rd(0, 0);
+    float sw = 0.f, swa = 0.f;
+    float w[36];
+#pragma unroll
+    for (int s = 0; s < 36; ++s) {
+        const int du = -5 + 2 * (s % 6), dv = -5 + 2 * (s / 6);
+        a[s] = rd(du, dv);
+        const float dist = __builtin_sqrtf((float)(du * du + dv * dv));
+        w[s] = __expf(-fabsf(a[s] - ac) * m.inv_2sc2 - dist * m.inv_2sx2);
+        sw += w[s];
+        swa = fmaf(w[s], a[s], swa);
+    }
+    const float invW = 1.f / sw;
+    const float mean = swa * invW;
+    float saa = 0.f;
+#pragma unroll
+    for (int s = 0; s < 36; ++s) {
+        const float ap = a[s] - mean;
+        const float wap = w[s] * ap;
+        saa = fmaf(wap, ap, saa);
+        if ((s % write_stride) == write_phase) rw[s] = make_float2(w[s], wap);
+    }
+    WinStats ws;
+    ws.invW = invW;
+    ws.var_a = saa * invW;
+    return ws;
+}
+
+// ---------------------------------------------------------------------------
+// Bilaterally weighted NCC of one hypothesis on one source (Sec. 3.3, Eq. 8).
+// The window centre is projected in double precision and the warp is
+// re-expressed relative to the integer texel under it, so the 36 sample
+// positions keep ~1e-6 px precision in float at any image size.  Source
+// moments are exact two-pass (mean first, then centred sums).
+//   q0, qu, qv: inverse depth of the plane along the pixel ray and its
+//   change per reference pixel in x and y.
+// ---------------------------------------------------------------------------
+template <int HALF>
+__device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__restrict__ rw, const WinStats &ws, int x,
+                                          int y, double q0, float qu, float qv) {
+    const double P0x = fma(vw.A[1], (double)y, fma(vw.A[0], (double)x, vw.A[2])) + vw.b[0] * q0;
+    const double P0y = fma(vw.A[4], (double)y, fma(vw.A[3], (double)x, vw.A[5])) + vw.b[1] * q0;
+    const double P0z = fma(vw.A[7], (double)y, fma(vw.A[6], (double)x, vw.A[8])) + vw.b[2] * q0;
+    if (!(P0z > 0.0)) return 2.f;
+    const double rz = 1.0 / P0z;
+    const double cu = P0x * rz, cv = P0y * rz;
+    const int W = vw.W, H = vw.H;
+    if (!(cu >= 0.0 && cu <= (double)(W - 1) && cv >= 0.0 && cv <= (double)(H - 1))) return 2.f;
+    const int ix = (int)floor(cu), iy = (int)floor(cv);
+    const float N0x = (float)(P0x - (double)ix * P0z);
+    const float N0y = (float)(P0y - (double)iy * P0z);
+    const float Z0 = (float)P0z;
+    const float puz = (float)vw.A[6] + (float)vw.b[2] * qu;
+    const float pvz = (float)vw.A[7] + (float)vw.b[2] * qv;
+    const float pux = (float)vw.A[0] + (float)vw.b[0] * qu - (float)ix * puz;
+    const float puy = (float)vw.A[3] + (float)vw.b[1] * qu - (float)iy * puz;
+    const float pvx = (float)vw.A[1] + (float)vw.b[0] * qv - (float)ix * pvz;
+    const float pvy = (float)vw.A[4] + (float)vw.b[1] * qv - (float)iy * pvz;
+    // every sample must see the plane in front of the source camera: the depth is affine in the
+    // window offsets, so the four corners decide
+    const float zc0 = Z0 - 5.f * puz - 5.f * pvz, zc1 = Z0 + 5.f * puz - 5.f * pvz;
+    const float zc2 = Z0 - 5.f * puz + 5.f * pvz, zc3 = Z0 + 5.f * puz + 5.f * pvz;
+    if (!(fminf(fminf(zc0, zc1), fminf(zc2, zc3)) > 1e-20f)) return 2.f;
+
+    const void *__restrict__ quads = vw.quads;
+    const int Wp = W + 1;
+    // pass 1: the 36 bilinear samples (kept in registers) and their weighted mean
+    float val[36];
+    float sb = 0.f;
+#pragma unroll
+    for (int sv = 0; sv < 6; ++sv) {
+        const float vf = -5.f + 2.f * sv;
+        const float rx = fmaf(vf, pvx, N0x), ry = fmaf(vf, pvy, N0y), rzz = fmaf(vf, pvz, Z0);
+#pragma unroll
+        for (int su = 0; su < 6; ++su) {
+            const float uf = -5.f + 2.f * su;
+            const float nx = fmaf(uf, pux, rx), ny = fmaf(uf, puy, ry), nz = fmaf(uf, puz, rzz);
+            const float r = __builtin_amdgcn_rcpf(nz);
+            const float dx = nx * r, dy = ny * r;
+            const float fx0 = floorf(dx), fy0 = floorf(dy);
+            const float fx = dx - fx0, fy = dy - fy0;
+            int xi = (int)fx0 + ix, yi = (int)fy0 + iy;
+            xi = min(max(xi, -1), W - 1);
+            yi = min(max(yi, -1), H - 1);
+            const float4 q = load_quad<HALF>(quads, (yi + 1) * Wp + (xi + 1));
+            const float top = fmaf(fx, q.y - q.x, q.x);
+            const float bot = fmaf(fx, q.w - q.z, q.z);
+            const float v = fmaf(fy, bot - top, top);
+            val[sv * 6 + su] = v;
+            sb = fmaf(rw[sv * 6 + su].x, v, sb);
+        }
+    }
+    // pass 2: centred moments (exact two-pass: no cancellation when a sample is far from the mean)
+    const float mb = sb * ws.invW;
+    float sbb = 0.f, sab = 0.f;
+#pragma unroll
+    for (int s = 0; s < 36; ++s) {
+        const float2 wa = rw[s];
+        const float d = val[s] - mb;
+        sbb = fmaf(wa.x * d, d, sbb);
+        sab = fmaf(wa.y, d, sab);
+    }
+    const float var_b = sbb * ws.invW;
+    const float cov = sab * ws.invW;
+    if (ws.var_a < 1e-5f || var_b < 1e-5f) return 2.f;
+    const float mm = 1.f - cov * rsqrtf(ws.var_a * var_b);
+    return fminf(fmaxf(mm, 0.f), 2.f);
+}
+
+// inverse-depth terms of a plane at reference pixel (x, y): q = -(n . K^-1 (x, y, 1)) / d
+struct PlaneQ {
+    double q0;
+    float qu, qv;
+    bool ok;  // depth at the pixel inside [d_min, d_max]
+};
+
+__device__ __forceinline__ PlaneQ plane_q(const RefDev &ref, const MethodDev &m, float4 pl, int x, int y) {
+    const double rx = fma(ref.kinv_a, (double)x, fma(ref.kinv_b, (double)y, ref.kinv_c));
+    const double ry = fma(ref.kinv_e, (double)y, ref.kinv_f);
+    const double nr = (double)pl.x * rx + (double)pl.y * ry + (double)pl.z;
+    const double d = (double)pl.w;
+    PlaneQ q;
+    const double depth = -d / nr;
+    // range test with a relative tolerance of 1e-5: refinement clamps depths to the ends of the
+    // range, and the plane rebuilt from a clamped depth must not fail on its last bit
+    q.ok = depth > 0.0 && depth >= (double)m.d_min * (1.0 - 1e-5) && depth <= (double)m.d_max * (1.0 + 1e-5);
+    q.q0 = -nr / d;
+    const float invd = (float)(-1.0 / d);
+    q.qu = (float)(pl.x * ref.kinv_a) * invd;
+    q.qv = (float)(pl.x * ref.kinv_b + pl.y * ref.kinv_e) * invd;
+    // every window sample's ray must meet the plane in front of the camera: the inverse depth is
+    // affine in the window offsets, so the four corners decide
+    const float qc = (float)q.q0, hu = 5.f * q.qu, hv = 5.f * q.qv;
+    q.ok = q.ok && fminf(fminf(qc - hu - hv, qc + hu - hv), fminf(qc - hu + hv, qc + hu + hv)) > 0.f;
+    return q;
+}
+
+// viewing ray K_ref^-1 (x, y, 1) of a reference pixel (its z component is 1)
+__device__ __forceinline__ float2 ref_ray(const RefDev &ref, int x, int y) {
+    return make_float2((float)fma(ref.kinv_a, (double)x, fma(ref.kinv_b, (double)y, ref.kinv_c)),
+                       (float)fma(ref.kinv_e, (double)y, ref.kinv_f));
+}
+
+// plane through the point at `depth` on the ray r with normal n turned to face the camera
+__device__ __forceinline__ float4 plane_from(float2 r, float depth, float nx, float ny, float nz) {
+    float nr = nx * r.x + ny * r.y + nz;
+    if (nr > 0.f) {
+        nx = -nx; ny = -ny; nz = -nz; nr = -nr;
+    }
+    return make_float4(nx, ny, nz, -depth * nr);
+}
+
+// uniform direction on the sphere: z = 1 - 2 u1, azimuth 2 pi u2
+__device__ __forceinline__ void normal_from_uniforms(float u1, float u2, float &nx, float &ny, float &nz) {
+    const float z = 1.f - 2.f * u1;
+    const float s = sqrtf(fmaxf(0.f, 1.f - z * z));
+    float sn, cs;
+    sincospif(2.f * u2, &sn, &cs);
+    nx = s * cs; ny = s * sn; nz = z;
+}
+
+__device__ __forceinline__ float plane_depth(float2 r, float4 pl) {
+    return -pl.w / (pl.x * r.x + pl.y * r.y + pl.z);
+}
+
+// ---------------------------------------------------------------------------
+// Tile mapping.  Workgroups are spread round-robin over the 8 XCDs; logical
+// tiles are renumbered so that each XCD walks a contiguous band of rows and
+// keeps its sources' footprint in its own L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int n_tiles) {
+    const int per = (n_tiles + 7) >> 3;
+    const int b = blockIdx.x;
+    const int L = (b & 7) * per + (b >> 3);
+    return L < n_tiles ? L : -1;
+}
+
+// LDS carve-up of the pass / init kernels
+struct PassLds {
+    float *tile;     // kTileRows + 10 rows x (2 * kTilePix + 10) cols of reference intensities
+    float2 *rw;      // [wave][group][36]
+    float4 *pl;      // [256] hypothesis of each lane
+    float *ms;       // [wave][n_src][64] costs, reused for refinement results
+    float *mf;       // [256] aggregated cost / scratch
+    float *psi;      // [wave][group][32] importance, < 0 outside S_t
+    int *valid;      // [256]
+    unsigned char *act;  // [wave][group][32] active views for refinement
+};
+
+constexpr int kTileH = kTileRows + 10;
+constexpr int kTileW = 2 * kTilePix + 10;
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t lds_layout(int n_src, size_t off[8]) {
+    size_t o = 0;
+    off[0] = o; o = align16(o + sizeof(float) * kTileH * kTileW);
+    off[1] = o; o = align16(o + sizeof(float2) * kWaves * kGroups * 36);
+    off[2] = o; o = align16(o + sizeof(float4) * 256);
+    off[3] = o; o = align16(o + sizeof(float) * kWaves * (n_src > 7 ? n_src : 7) * 64);
+    off[4] = o; o = align16(o + sizeof(float) * 256);
+    off[5] = o; o = align16(o + sizeof(float) * kWaves * kGroups * kMaxSrc);
+    off[6] = o; o = align16(o + sizeof(int) * 256);
+    off[7] = o; o = align16(o + kWaves * kGroups * kMaxSrc);
+    return o;
+}
+
+size_t pass_lds_bytes(int n_src) {
+    size_t off[8];
+    return lds_layout(n_src, off);
+}
+
+__device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src) {
+    size_t off[8];
+    lds_layout(n_src, off);
+    PassLds L;
+    L.tile = reinterpret_cast<float *>(smem + off[0]);
+    L.rw = reinterpret_cast<float2 *>(smem + off[1]);
+    L.pl = reinterpret_cast<float4 *>(smem + off[2]);
+    L.ms = reinterpret_cast<float *>(smem + off[3]);
+    L.mf = reinterpret_cast<float *>(smem + off[4]);
+    L.psi = reinterpret_cast<float *>(smem + off[5]);
+    L.valid = reinterpret_cast<int *>(smem + off[6]);
+    L.act = smem + off[7];
+    return L;
+}
+
+// reference tile of a workgroup: rows y0-5 .. y0+kTileRows+4, cols x0-5 .. x0+2*kTilePix+4, clamped
+__device__ __forceinline__ void stage_tile(const RefDev &ref, float *tile, int y0, int x0) {
+    for (int i = threadIdx.x; i < kTileH * kTileW; i += blockDim.x) {
+        const int ty = i / kTileW, tx = i - ty * kTileW;
+        const int gy = min(max(y0 - 5 + ty, 0), ref.H - 1);
+        const int gx = min(max(x0 - 5 + tx, 0), ref.W - 1);
+        tile[i] = ref.img[(size_t)gy * ref.W + gx];
+    }
+}
+
+struct TileReader {
+    const float *tile;
+    int cy, cx;  // pixel position inside the tile
+    const RefDev *ref;
+    int x, y;
+    __device__ __forceinline__ float operator()(int du, int dv) const {
+        // clamp to the image exactly like the global reader: positions are clamped in image space
+        const int gx = min(max(x + du, 0), ref->W - 1), gy = min(max(y + dv, 0), ref->H - 1);
+        return tile[(cy + (gy - y)) * kTileW + (cx + (gx - x))];
+    }
+};
+
+struct GlobalReader {
+    const RefDev *ref;
+    int x, y;
+    __device__ __forceinline__ float operator()(int du, int dv) const {
+        const int gx = min(max(x + du, 0), ref->W - 1), gy = min(max(y + dv, 0), ref->H - 1);
+        return ref->img[(size_t)gy * ref->W + gx];
+    }
+};
+
+__device__ __forceinline__ void count_evals(unsigned long long *counters, int kind, unsigned long long n) {
+    // one atomic per wave, spread over slots
+    const int lane = threadIdx.x & 63;
+    unsigned long long tot = n;
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
+    if (lane == 0 && tot)
+        atomicAdd(&counters[kind * kCounterSlots + ((blockIdx.x * kWaves + (threadIdx.x >> 6)) % kCounterSlots)], tot);
+}
+
+// ---------------------------------------------------------------------------
+// Random initialisation (PatchMatch random planes; initial cost = mean of the
+// k lowest per-view costs).  Same tile mapping as the pass, one launch per
+// colour.  Lane r of a pixel scores views r, r+9, r+18, r+27.
+// ---------------------------------------------------------------------------
+template <int HALF>
+__global__ __launch_bounds__(256) void init_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = xcd_tile(a.n_tiles);
+    if (L < 0) return;
+    PassLds S = carve(smem, a.n_src);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int grp = lane / kRows, row = lane - grp * kRows;
+    const int ty = L / a.tiles_x, tx = L - ty * a.tiles_x;
+    const int y0 = ty * kTileRows, x0 = tx * 2 * kTilePix;
+    const int y = y0 + wave;
+    const int x = 2 * (tx * kTilePix + grp) + ((y + a.colour) & 1);
+    const bool pix_ok = grp < kGroups && y < a.ref.H && x < a.ref.W;
+
+    stage_tile(a.ref, S.tile, y0, x0);
+    __syncthreads();
+    float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * 36;
+    WinStats ws = {1.f, 0.f};
+    if (pix_ok) {
+        TileReader rd{S.tile, 5 + wave, 5 + (x - x0), &a.ref, x, y};
+        ws = build_window(rd, a.m, rw, row, kRows);
+    }
+    __syncthreads();
+
+    const int N = a.n_src;
+    float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
+    float *mcol = S.ms + wave * N * 64;  // m of view j for group g at mcol[j * 64 + g * 9]
+    int n_eval = 0;
+    if (pix_ok) {
+        float u[4], nx, ny, nz;
+        philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
+        const float2 r = ref_ray(a.ref, x, y);
+        const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
+        normal_from_uniforms(u[1], u[2], nx, ny, nz);
+        pl = plane_from(r, depth, nx, ny, nz);
+        const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
+        for (int j = row; j < N; j += kRows) {
+            const float c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+            mcol[j * 64 + grp * kRows] = c;
+            ++n_eval;
+        }
+    }
+    __syncthreads();
+    if (pix_ok && row == 0) {
+        // mean of the k lowest costs, in ascending order
+        const int kk = a.m.k < N ? a.m.k : N;
+        uint32_t taken = 0;
+        float sum = 0.f;
+        for (int r = 0; r < kk; ++r) {
+            int best = -1;
+            float bc = 0.f;
+            for (int j = 0; j < N; ++j) {
+                if ((taken >> j) & 1u) continue;
+                const float c = mcol[j * 64 + grp * kRows];
+                if (best < 0 || c < bc) { best = j; bc = c; }
+            }
+            taken |= 1u << best;
+            sum += bc;
+        }
+        const size_t p = (size_t)y * a.ref.W + x;
+        a.st.planes[p] = pl;
+        a.st.cost[p] = sum / (float)kk;
+        a.st.S[p] = 0u;
+        a.st.v[p] = -1;
+    }
+    count_evals(a.counters, 0, (unsigned long long)n_eval);
+}
+
+// ---------------------------------------------------------------------------
+// One checkerboard half-pass (Sec. 3.1 - 3.3).
+// ---------------------------------------------------------------------------
+template <int HALF>
+__global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = xcd_tile(a.n_tiles);
+    if (L < 0) return;
+    PassLds S = carve(smem, a.n_src);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int grp = lane / kRows, row = lane - grp * kRows;
+    const int g = grp < kGroups ? grp : 0;
+    const int ty = L / a.tiles_x, tx = L - ty * a.tiles_x;
+    const int y0 = ty * kTileRows, x0 = tx * 2 * kTilePix;
+    const int y = y0 + wave;
+    const int x = 2 * (tx * kTilePix + grp) + ((y + a.colour) & 1);
+    const int W = a.ref.W, H = a.ref.H;
+    const bool pix_ok = grp < kGroups && y < H && x < W;
+    const size_t p = pix_ok ? (size_t)y * W + x : 0;
+    const int N = a.n_src;
+    const MethodDev &m = a.m;
+
+    stage_tile(a.ref, S.tile, y0, x0);
+
+    // (1) asymmetric propagation: lane r < 8 takes the lowest-cost candidate of region r
+    float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
+    bool valid = false;
+    if (pix_ok) {
+        if (row < 8) {
+            int bx = -1, by = -1;
+            float bc = 0.f;
+            const int ne = region_size(row);
+            for (int e = 0; e < ne; ++e) {
+                int dx, dy;
+                region_offset(row, e, dx, dy);
+                const int nx = x + dx, ny = y + dy;
+                if (nx < 0 || nx >= W || ny < 0 || ny >= H) continue;
+                const float c = a.st.cost[(size_t)ny * W + nx];
+                if (bx < 0 || c < bc) { bx = nx; by = ny; bc = c; }
+            }
+            if (bx >= 0) {
+                valid = true;
+                pl = a.st.planes[(size_t)by * W + bx];
+            }
+        } else {
+            valid = m.include_self != 0;
+            pl = a.st.planes[p];
+        }
+    }
+    S.pl[tid] = pl;
+    S.valid[tid] = valid ? 1 : 0;
+    __syncthreads();
+
+    // (2) reference window, split over the 9 lanes of the pixel
+    float2 *rw = S.rw + (wave * kGroups + g) * 36;
+    WinStats ws = {1.f, 0.f};
+    if (pix_ok) {
+        TileReader rd{S.tile, 5 + wave, 5 + (x - x0), &a.ref, x, y};
+        ws = build_window(rd, m, rw, row, kRows);
+    }
+    __syncthreads();
+
+    // (3) cost matrix (Eq. 1) plus the own row: one column per view
+    float *mcol = S.ms + wave * N * 64;
+    const PlaneQ q = plane_q(a.ref, m, pl, x, y);
+    int n_prop = 0;
+    for (int j = 0; j < N; ++j) {
+        float c = 2.f;
+        if (valid) {
+            c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+            ++n_prop;
+        }
+        mcol[j * 64 + lane] = c;
+    }
+    __syncthreads();
+
+    // (4) view inference, part 1 (Sec. 3.2): lane r judges views r, r+9, ...
+    //     good view: more than n1 costs below tau and fewer than n2 above tau_up;
+    //     importance: mean confidence exp(-m^2 / (2 beta^2)) over the valid rows
+    float *psi = S.psi + (wave * kGroups + g) * kMaxSrc;
+    int nv = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) nv += S.valid[wave * 64 + g * kRows + i];
+    if (pix_ok) {
+        for (int j = row; j < N; j += kRows) {
+            int lt = 0, gt = 0;
+            float sc = 0.f;
+            for (int i = 0; i < 8; ++i) {
+                if (!S.valid[wave * 64 + g * kRows + i]) continue;
+                const float c = mcol[j * 64 + g * kRows + i];
+                lt += c < m.tau;
+                gt += c > m.tau_up;
+                sc += __expf(-c * c * m.inv_2b2);
+            }
+            psi[j] = (nv > 0 && lt > m.n1 && gt < m.n2) ? sc / (float)nv : -1.f;
+        }
+    }
+    __syncthreads();
+
+    // (5) view inference, part 2 (every lane of the pixel, identical result):
+    //     S_t, v_t = argmax psi, modified importance (x2 for v_{t-1}), top-k,
+    //     0.2 for views that left the selection, uniform fallback (Eq. 4-6)
+    uint32_t Sm = 0, keep = 0;
+    int vt = -1;
+    int vprev = -1;
+    uint32_t Sprev = 0;
+    float wsum = 0.f;
+    bool uniform = false;
+    if (pix_ok) {
+        vprev = a.st.v[p];
+        Sprev = a.st.S[p];
+        float best = 0.f;
+        for (int j = 0; j < N; ++j) {
+            const float ps = psi[j];
+            if (ps >= 0.f) {
+                Sm |= 1u << j;
+                if (vt < 0 || ps > best) { vt = j; best = ps; }
+            }
+        }
+        for (int r = 0; r < m.k; ++r) {
+            int bj = -1;
+            float bm = 0.f;
+            for (int j = 0; j < N; ++j) {
+                if (!((Sm >> j) & 1u) || ((keep >> j) & 1u)) continue;
+                const float md = (j == vprev ? 2.f : 1.f) * psi[j];
+                if (bj < 0 || md > bm) { bj = j; bm = md; }
+            }
+            if (bj < 0) break;
+            keep |= 1u << bj;
+        }
+        for (int j = 0; j < N; ++j) {
+            if ((keep >> j) & 1u) wsum += (j == vprev ? 2.f : 1.f) * psi[j];
+            else if (!((Sm >> j) & 1u) && ((Sprev >> j) & 1u)) wsum += 0.2f;
+        }
+        uniform = !(wsum > 0.f);
+        if (uniform) wsum = (float)N;
+    }
+    auto weight = [=](int j) -> float {
+        if (uniform) return 1.f;
+        if ((keep >> j) & 1u) return (j == vprev ? 2.f : 1.f) * psi[j];
+        if (!((Sm >> j) & 1u) && ((Sprev >> j) & 1u)) return 0.2f;
+        return 0.f;
+    };
+
+    // (6) unified cost of the lane's hypothesis (Eq. 7)
+    float mfin = __builtin_inff();
+    if (valid) {
+        float acc = 0.f;
+        for (int j = 0; j < N; ++j) acc = fmaf(weight(j), mcol[j * 64 + lane], acc);
+        mfin = acc / wsum;
+    }
+    S.mf[tid] = mfin;
+    __syncthreads();
+
+    // (7) best hypothesis: own plane first, then region order; strictly lower wins
+    int brow = -1;
+    float bcost = 0.f;
+    if (pix_ok) {
+        const int base = wave * 64 + g * kRows;
+        if (S.valid[base + 8]) { brow = 8; bcost = S.mf[base + 8]; }
+        for (int r = 0; r < 8; ++r) {
+            if (!S.valid[base + r]) continue;
+            const float c = S.mf[base + r];
+            if (brow < 0 || c < bcost) { brow = r; bcost = c; }
+        }
+        if (brow < 0) { brow = 8; bcost = S.mf[base + 8]; }  // no valid row at all (1-pixel image, no self)
+    }
+    float4 best = pix_ok ? S.pl[wave * 64 + g * kRows + brow] : make_float4(0.f, 0.f, -1.f, 1.f);
+    unsigned char *act = S.act + (wave * kGroups + g) * kMaxSrc;
+    int nw = 0;
+    if (pix_ok) {
+        for (int j = 0; j < N; ++j)
+            if (weight(j) > 0.f) ++nw;
+        if (row == 0) {
+            int c = 0;
+            for (int j = 0; j < N; ++j)
+                if (weight(j) > 0.f) act[c++] = (unsigned char)j;
+        }
+    }
+    __syncthreads();
+
+    // (8) refinement (Sec. 3.3): perturbed (and, from t = 3, random) depth/normal candidates,
+    //     scored with the same weights on the views that carry weight; strictly lower wins
+    int n_ref = 0;
+    if (m.refine) {
+        const int ncand = a.t >= 3 ? 6 : 3;
+        // candidate c combines depth {dprt, dcur, dprt, drnd, dcur, drnd}[c] with normal
+        // {best, nprt, nprt, best, nrnd, nrnd}[c]; planes are rebuilt on demand (no private arrays)
+        float2 rr = make_float2(0.f, 0.f);
+        float dcur = 0.f, dprt = 0.f, drnd = 0.f;
+        float npx = 0.f, npy = 0.f, npz = -1.f, nqx = 0.f, nqy = 0.f, nqz = -1.f;
+        if (pix_ok) {
+            rr = ref_ray(a.ref, x, y);
+            dcur = plane_depth(rr, best);
+            const float rho = ldexpf(1.f, -(a.t + 2));
+            float ua[4];
+            philox(p, (uint64_t)a.t, 1, m.seed, ua);
+            dprt = dcur + (2.f * ua[0] - 1.f) * rho * (m.d_max - m.d_min);
+            dprt = fminf(fmaxf(dprt, m.d_min), m.d_max);
+            npx = best.x + 2.f * rho * (2.f * ua[1] - 1.f);
+            npy = best.y + 2.f * rho * (2.f * ua[2] - 1.f);
+            npz = best.z + 2.f * rho * (2.f * ua[3] - 1.f);
+            const float inv = 1.f / sqrtf(npx * npx + npy * npy + npz * npz);
+            npx *= inv; npy *= inv; npz *= inv;
+            if (ncand == 6) {
+                float ub[4];
+                philox(p, (uint64_t)a.t, 2, m.seed, ub);
+                drnd = m.d_min + ub[0] * (m.d_max - m.d_min);
+                normal_from_uniforms(ub[1], ub[2], nqx, nqy, nqz);
+            }
+        }
+        const float nbx = best.x, nby = best.y, nbz = best.z;
+        auto cand_plane = [=](int c) -> float4 {
+            // lane-wise selects on scalars (a select between aggregate members would go through memory)
+            const bool dc = c == 1 || c == 4, dr = c == 3 || c == 5;
+            const bool use_b = c == 0 || c == 3, use_p = c == 1 || c == 2;
+            float d = dprt, nx = nqx, ny = nqy, nz = nqz;
+            d = dc ? dcur : d;
+            d = dr ? drnd : d;
+            nx = use_p ? npx : nx;
+            ny = use_p ? npy : ny;
+            nz = use_p ? npz : nz;
+            nx = use_b ? nbx : nx;
+            ny = use_b ? nby : ny;
+            nz = use_b ? nbz : nz;
+            return plane_from(rr, d, nx, ny, nz);
+        };
+        float *res = S.ms + wave * N * 64 + g * (6 * N);  // reuse the cost-matrix area (7 * 6N <= 64N)
+        const int pairs = pix_ok ? ncand * nw : 0;
+        for (int it = 0;; ++it) {
+            const int qi = row + kRows * it;
+            const bool act_lane = qi < pairs;
+            if (!__any(act_lane)) break;
+            if (act_lane) {
+                const int c = qi / nw;
+                const int j = act[qi - c * nw];
+                const float4 cp = cand_plane(c);
+                const PlaneQ cq = plane_q(a.ref, m, cp, x, y);
+                const float cost = cq.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, cq.q0, cq.qu, cq.qv) : 2.f;
+                res[qi] = weight(j) * cost;
+                ++n_ref;
+            }
+        }
+        __syncthreads();
+        if (pix_ok) {
+            for (int c = 0; c < ncand; ++c) {
+                float acc = 0.f;
+                for (int i = 0; i < nw; ++i) acc += res[c * nw + i];
+                const float cc = acc / wsum;
+                if (cc < bcost) {
+                    bcost = cc;
+                    best = cand_plane(c);
+                }
+            }
+        }
+    }
+
+    // (9) write the pixel
+    if (pix_ok && row == 0) {
+        a.st.planes[p] = best;
+        a.st.cost[p] = bcost;
+        a.st.S[p] = Sm;
+        a.st.v[p] = vt;
+    }
+    count_evals(a.counters, 1, (unsigned long long)n_prop);
+    if (m.refine) count_evals(a.counters, 2, (unsigned long long)n_ref);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed hypotheses: one thread per (query, view).
+// ---------------------------------------------------------------------------
+template <int HALF>
+__global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
+    __shared__ float2 rwbuf[64 * 36];
+    const int gid = blockIdx.x * 64 + threadIdx.x;
+    const int total = a.Q * a.n_src;
+    if (gid >= total) return;  // no barrier in this kernel
+    const int qi = gid / a.n_src, j = gid - qi * a.n_src;
+    const int2 px = a.pix[qi];
+    const float4 pl = a.planes[qi];
+    float2 *rw = rwbuf + threadIdx.x * 36;
+    GlobalReader rd{&a.ref, px.x, px.y};
+    const WinStats ws = build_window(rd, a.m, rw, 0, 1);
+    const PlaneQ q = plane_q(a.ref, a.m, pl, px.x, px.y);
+    a.costs[gid] = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, px.x, px.y, q.q0, q.qu, q.qv) : 2.f;
+}
+
+// ---------------------------------------------------------------------------
+// Layout kernels
+// ---------------------------------------------------------------------------
+__global__ void convert_kernel(const void *src, int dtype, int64_t pitch, int W, int H, float *dst) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= W || y >= H) return;
+    float v;
+    if (dtype == 0) v = reinterpret_cast<const float *>(src)[(size_t)y * pitch + x];
+    else v = __half2float(reinterpret_cast<const __half *>(src)[(size_t)y * pitch + x]);
+    dst[(size_t)y * W + x] = v;
+}
+
+__global__ void pack_quads_kernel(const float *img, int W, int H, void *quads, int half) {
+    const int xx = blockIdx.x * blockDim.x + threadIdx.x, yy = blockIdx.y;  // 0..W, 0..H
+    if (xx > W || yy > H) return;
+    const int x0 = min(max(xx - 1, 0), W - 1), x1 = min(max(xx, 0), W - 1);
+    const int y0 = min(max(yy - 1, 0), H - 1), y1 = min(max(yy, 0), H - 1);
+    const float a = img[(size_t)y0 * W + x0], b = img[(size_t)y0 * W + x1];
+    const float c = img[(size_t)y1 * W + x0], d = img[(size_t)y1 * W + x1];
+    const size_t i = (size_t)yy * (W + 1) + xx;
+    if (!half) {
+        reinterpret_cast<float4 *>(quads)[i] = make_float4(a, b, c, d);
+    } else {
+        __half2 lo = __floats2half2_rn(a, b), hi = __floats2half2_rn(c, d);
+        reinterpret_cast<uint2 *>(quads)[i] = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void outputs_kernel(RefDev ref, StateDev st, float *depth, float *normal, float *cost) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= ref.W || y >= ref.H) return;
+    const size_t p = (size_t)y * ref.W + x;
+    const float4 pl = st.planes[p];
+    if (depth) {
+        const double rx = fma(ref.kinv_a, (double)x, fma(ref.kinv_b, (double)y, ref.kinv_c));
+        const double ry = fma(ref.kinv_e, (double)y, ref.kinv_f);
+        depth[p] = (float)(-(double)pl.w / ((double)pl.x * rx + (double)pl.y * ry + (double)pl.z));
+    }
+    if (normal) {
+        normal[3 * p] = pl.x;
+        normal[3 * p + 1] = pl.y;
+        normal[3 * p + 2] = pl.z;
+    }
+    if (cost) cost[p] = st.cost[p];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_convert_to_f32(const void *src, int src_dtype, int64_t pitch, int W, int H, float *dst,
+                                 hipStream_t s) {
+    dim3 grid((W + 255) / 256, H);
+    hipLaunchKernelGGL(convert_kernel, grid, dim3(256), 0, s, src, src_dtype, pitch, W, H, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int half, hipStream_t s) {
+    dim3 grid((W + 1 + 255) / 256, H + 1);
+    hipLaunchKernelGGL(pack_quads_kernel, grid, dim3(256), 0, s, img, W, H, quads, half);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
+
+hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
+    const size_t lds = pass_lds_bytes(a.n_src);
+    if (half) hipLaunchKernelGGL(init_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL(init_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
+    const size_t lds = pass_lds_bytes(a.n_src);
+    if (half) hipLaunchKernelGGL(pass_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL(pass_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const ScoreArgs &a, int half, hipStream_t s) {
+    const int total = a.Q * a.n_src;
+    if (total == 0) return hipSuccess;
+    dim3 grid((total + 63) / 64);
+    if (half) hipLaunchKernelGGL(score_kernel<1>, grid, dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(score_kernel<0>, grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, float *normal, float *cost,
+                          hipStream_t s) {
+    dim3 grid((ref.W + 255) / 256, ref.H);
+    hipLaunchKernelGGL(outputs_kernel, grid, dim3(256), 0, s, ref, st, depth, normal, cost);
+    return hipGetLastError();
+}
+
+}  // namespace amh

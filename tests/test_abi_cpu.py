@@ -1,0 +1,91 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/amhmvs.h declares, and validates arguments before any HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def amh():
+    import paper_1805_07920_amd as amh
+
+    if not os.path.exists(amh.LIB_PATH):
+        from paper_1805_07920_amd import build
+
+        build.build()
+    return amh
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "amhmvs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(amh_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_function(amh):
+    L = amh.lib()
+    declared = header_functions()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(L, name), f"{name} declared in the header but not exported"
+    assert sorted(amh.EXPORTS) == declared
+
+
+def test_params_default_are_the_papers(amh):
+    p = amh.params_default()
+    assert (p.tau_mc_init, p.alpha, p.beta, p.tau_up) == pytest.approx((0.8, 90.0, 0.3, 1.2))
+    assert (p.n1, p.n2, p.k) == (2, 3, 4)
+    assert (p.sigma_color, p.sigma_spatial) == (3.0, 30.0)
+    assert (p.depth_min, p.depth_max, p.refine, p.include_self) == (2.0, 6.0, 1, 1)
+    assert amh.lib().amh_params_default(None) == amh.AMH_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("field,value", [("depth_min", -1.0), ("depth_max", 1.0), ("sigma_color", 0.0),
+                                         ("beta", 0.0), ("k", 0), ("k", 33), ("n1", -1), ("refine", 2),
+                                         ("alpha", -3.0), ("depth_max", float("inf"))])
+def test_create_rejects_bad_params_before_touching_hip(amh, field, value):
+    p = amh.params_default()
+    setattr(p, field, value)
+    h = C.c_void_p()
+    assert amh.lib().amh_create(C.byref(h), C.byref(p), None) == amh.AMH_E_INVALID_ARG
+    assert not h.value
+
+
+def test_null_arguments(amh):
+    L = amh.lib()
+    p = amh.params_default()
+    assert L.amh_create(None, C.byref(p), None) == amh.AMH_E_INVALID_ARG
+    assert L.amh_create(C.byref(C.c_void_p()), None, None) == amh.AMH_E_INVALID_ARG
+    for call in (lambda: L.amh_set_params(None, C.byref(p)), lambda: L.amh_init_views(None, 1, None, None, 0),
+                 lambda: L.amh_begin(None, 0, None, 1), lambda: L.amh_init_hypotheses(None),
+                 lambda: L.amh_pass(None, 0, 0), lambda: L.amh_run_checkerboard(None, 0, None, 1, 3),
+                 lambda: L.amh_get_depth_normal_cost(None, None, None, None, 0),
+                 lambda: L.amh_get_state(None, None, None, None, None, 0),
+                 lambda: L.amh_set_state(None, None, None, None, None, 0),
+                 lambda: L.amh_score_fixed(None, None, None, 0, None, 0), lambda: L.amh_run_batch(None, 0, None),
+                 lambda: L.amh_get_job_result(None, 0, None, None, None, 0),
+                 lambda: L.amh_get_stats(None, None)):
+        assert call() == amh.AMH_E_INVALID_ARG
+    L.amh_destroy(None)
+    assert L.amh_last_error(None) == b"NULL context"
+
+
+def test_status_strings(amh):
+    L = amh.lib()
+    assert L.amh_status_str(0) == b"ok"
+    assert L.amh_status_str(amh.AMH_E_OOM) == b"out of device memory"
+    assert L.amh_status_str(123) == b"unknown status"
+
+
+def test_no_gpu_means_hip_error(amh):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(amh.AmhError) as e:
+        amh.Context()
+    assert e.value.status == amh.AMH_E_HIP
