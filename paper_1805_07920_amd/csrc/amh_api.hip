@@ -317,8 +317,8 @@ amh_status amh_init_views(amh_ctx *c, int n_views, const amh_image *views, const
     for (int i = 0; i < n_views; ++i) {
         const amh_image &im = views[i];
         if (!im.data) return fail(c, AMH_E_INVALID_ARG, "view %d: data is NULL", i);
-        if (im.width < 1 || im.height < 1 || im.width > 16384 || im.height > 16384)
-            return fail(c, AMH_E_INVALID_ARG, "view %d: size %dx%d outside 1..16384", i, im.width, im.height);
+        if (im.width < 1 || im.height < 1 || im.width > 16383 || im.height > 16383)
+            return fail(c, AMH_E_INVALID_ARG, "view %d: size %dx%d outside 1..16383", i, im.width, im.height);
         if (im.pitch_elems < im.width) return fail(c, AMH_E_INVALID_ARG, "view %d: pitch < width", i);
         if (im.dtype != AMH_F32 && im.dtype != AMH_F16) return fail(c, AMH_E_INVALID_ARG, "view %d: bad dtype", i);
         if (im.on_device != 0 && im.on_device != 1) return fail(c, AMH_E_INVALID_ARG, "view %d: on_device is 0/1", i);

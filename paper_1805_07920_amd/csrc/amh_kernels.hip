@@ -16,6 +16,14 @@
 
 #include "amh_internal.h"
 
+// Minimum waves per SIMD the pass kernels are compiled for (a register budget
+// of 512 / waves VGPRs).  At 2 the compiler settles at ~165 VGPRs (3 waves per
+// SIMD) with the row pipeline of ncc_cost; forcing 4 waves spills and measured
+// slower on the 1920x1280 / 10-source workload (5.43 vs 5.02 ms per half-pass).
+#ifndef AMH_PASS_WAVES_PER_EU
+#define AMH_PASS_WAVES_PER_EU 2
+#endif
+
 namespace amh {
 
 // ---------------------------------------------------------------------------
@@ -73,24 +81,94 @@ __device__ __forceinline__ void region_offset(int r, int e, int &dx, int &dy) {
 }
 
 // ---------------------------------------------------------------------------
-// Texel quads: entry (y0 + 1, x0 + 1) of a (H+1) x (W+1) array holds the 4
-// texels of the bilinear footprint with top-left (x0, y0), indices clamped to
-// the image, so one 16-byte (or 8-byte) load serves a sample.
+// Texel quads: entry (y0 + 1, x0 + 1) of a (H+1) x (W+1) array describes the
+// bilinear footprint with top-left texel (x0, y0), indices clamped to the
+// image, so one 16-byte (or 8-byte) load serves a sample.
+//   float32: the bilinear coefficients (a, b - a, c - a, a - b - c + d) of the
+//            texels a = (x0,y0), b = (x0+1,y0), c = (x0,y0+1), d = (x0+1,y0+1),
+//            so a sample is a + fx (b - a) + fy ((c - a) + fx (a - b - c + d)):
+//            3 FMAs;
+//   float16: the texels themselves (a, b, c, d) (differences would not be exact
+//            in half precision).
+// Offsets are 32-bit byte offsets from a wave-uniform base (global loads with
+// a scalar base address).
 // ---------------------------------------------------------------------------
-template <int HALF>
-__device__ __forceinline__ float4 load_quad(const void *base, int idx);
+typedef const __attribute__((address_space(1))) unsigned char gbyte;
+typedef float gf4 __attribute__((ext_vector_type(4)));
+typedef _Float16 gh4 __attribute__((ext_vector_type(4)));
 
+template <int HALF>
+struct QuadT {
+    typedef gf4 type;
+};
 template <>
-__device__ __forceinline__ float4 load_quad<0>(const void *base, int idx) {
-    return reinterpret_cast<const float4 *>(base)[idx];
+struct QuadT<1> {
+    typedef gh4 type;
+};
+
+template <int HALF>
+__device__ __forceinline__ typename QuadT<HALF>::type load_quad(const void *base, uint32_t off) {
+    return *reinterpret_cast<const __attribute__((address_space(1))) typename QuadT<HALF>::type *>((gbyte *)base +
+                                                                                                   off);
 }
 
+__device__ __forceinline__ float eval_quad_f32(gf4 q, float fx, float fy) {
+    return fmaf(fy, fmaf(fx, q.w, q.z), fmaf(fx, q.y, q.x));
+}
+
+__device__ __forceinline__ float eval_quad_f16(gh4 q, float fx, float fy) {
+    const float a = (float)q.x, b = (float)q.y, c = (float)q.z, d = (float)q.w;
+    const float top = fmaf(fx, b - a, a);
+    const float bot = fmaf(fx, d - c, c);
+    return fmaf(fy, bot - top, top);
+}
+
+template <int HALF>
+__device__ __forceinline__ float eval_quad(typename QuadT<HALF>::type q, float fx, float fy);
 template <>
-__device__ __forceinline__ float4 load_quad<1>(const void *base, int idx) {
-    uint2 r = reinterpret_cast<const uint2 *>(base)[idx];
-    __half2 a = __builtin_bit_cast(__half2, r.x), b = __builtin_bit_cast(__half2, r.y);
-    float2 fa = __half22float2(a), fb = __half22float2(b);
-    return make_float4(fa.x, fa.y, fb.x, fb.y);
+__device__ __forceinline__ float eval_quad<0>(gf4 q, float fx, float fy) { return eval_quad_f32(q, fx, fy); }
+template <>
+__device__ __forceinline__ float eval_quad<1>(gh4 q, float fx, float fy) { return eval_quad_f16(q, fx, fy); }
+
+// floor(x) converted to int in one instruction, and a 3-operand clamp
+__device__ __forceinline__ int cvt_floor(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+__device__ __forceinline__ int med3i(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// Warps the 6 samples of window row vf (pixel offset -5..5) into the source and
+// issues their texel loads.  The homogeneous source position of window offset
+// (u, v) is (N0 + u Pu + v Pv) relative to the texel (ix, iy); texel indices
+// are clamped to the image (-1..W-1 in absolute terms, the quad layout holds
+// the clamped footprint).
+template <int HALF>
+__device__ __forceinline__ void issue_row(const void *quads, float vf, float N0x, float N0y, float Z0, float pux,
+                                          float puy, float puz, float pvx, float pvy, float pvz, int xlo, int xhi,
+                                          int ylo, int yhi, int row_bytes, int base,
+                                          typename QuadT<HALF>::type (&qd)[6], float (&fxs)[6], float (&fys)[6]) {
+    constexpr int kEntry = HALF ? 8 : 16;
+    const float rx = fmaf(vf, pvx, N0x), ry = fmaf(vf, pvy, N0y), rzz = fmaf(vf, pvz, Z0);
+#pragma unroll
+    for (int su = 0; su < 6; ++su) {
+        const float uf = -5.f + 2.f * su;
+        const float nx = fmaf(uf, pux, rx), ny = fmaf(uf, puy, ry), nz = fmaf(uf, puz, rzz);
+        const float r = __builtin_amdgcn_rcpf(nz);
+        const float dx = nx * r, dy = ny * r;
+        const int xr = med3i(cvt_floor(dx), xlo, xhi);
+        const int yr = med3i(cvt_floor(dy), ylo, yhi);
+        fxs[su] = __builtin_amdgcn_fractf(dx);
+        fys[su] = __builtin_amdgcn_fractf(dy);
+        // modulo-2^32 arithmetic; the true offset is in [0, (W+1)(H+1) * entry) < 2^32
+        const uint32_t off = (uint32_t)__mul24(yr, row_bytes) + (uint32_t)base + (uint32_t)xr * kEntry;
+        qd[su] = load_quad<HALF>(quads, off);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -103,6 +181,12 @@ __device__ __forceinline__ float4 load_quad<1>(const void *base, int idx) {
 struct WinStats {
     float invW, var_a;
 };
+
+// A pixel's window block in LDS: 36 x (w, w (a - mean)) followed by 6 per-row
+// constants (1 / W_r, W_r / W_<=r, W_<r W_r / W_<=r, A_r) with W_r the row's
+// weight sum and A_r its sum of w (a - mean); they let the source moments be
+// formed row by row and merged exactly (see ncc_cost).
+constexpr int kWinStride = 48;  // float2 units: 36 + 6 float4
 
 template <typename Reader>
 __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodDev &m, float2 *rw, int write_phase,
@@ -123,12 +207,24 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
     const float invW = 1.f / sw;
     const float mean = swa * invW;
     float saa = 0.f;
+    float4 *rowc = reinterpret_cast<float4 *>(rw + 36);
+    float wcum = 0.f;
 #pragma unroll
-    for (int s = 0; s < 36; ++s) {
-        const float ap = a[s] - mean;
-        const float wap = w[s] * ap;
-        saa = fmaf(wap, ap, saa);
-        if ((s % write_stride) == write_phase) rw[s] = make_float2(w[s], wap);
+    for (int r = 0; r < 6; ++r) {
+        float wr = 0.f, ar = 0.f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int s = r * 6 + k;
+            const float ap = a[s] - mean;
+            const float wap = w[s] * ap;
+            saa = fmaf(wap, ap, saa);
+            wr += w[s];
+            ar += wap;
+            if ((s % write_stride) == write_phase) rw[s] = make_float2(w[s], wap);
+        }
+        const float wprev = wcum;
+        wcum += wr;
+        if ((r % write_stride) == write_phase) rowc[r] = make_float4(1.f / wr, wr / wcum, wprev * wr / wcum, ar);
     }
     WinStats ws;
     ws.invW = invW;
@@ -146,8 +242,9 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
 //   change per reference pixel in x and y.
 // ---------------------------------------------------------------------------
 template <int HALF>
-__device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__restrict__ rw, const WinStats &ws, int x,
-                                          int y, double q0, float qu, float qv) {
+__device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__restrict__ rw_in, const WinStats &ws,
+                                          int x, int y, double q0, float qu, float qv) {
+    const float2 *__restrict__ rw = rw_in;
     const double P0x = fma(vw.A[1], (double)y, fma(vw.A[0], (double)x, vw.A[2])) + vw.b[0] * q0;
     const double P0y = fma(vw.A[4], (double)y, fma(vw.A[3], (double)x, vw.A[5])) + vw.b[1] * q0;
     const double P0z = fma(vw.A[7], (double)y, fma(vw.A[6], (double)x, vw.A[8])) + vw.b[2] * q0;
@@ -173,45 +270,57 @@ __device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__res
     if (!(fminf(fminf(zc0, zc1), fminf(zc2, zc3)) > 1e-20f)) return 2.f;
 
     const void *__restrict__ quads = vw.quads;
-    const int Wp = W + 1;
-    // pass 1: the 36 bilinear samples (kept in registers) and their weighted mean
-    float val[36];
-    float sb = 0.f;
+    // texel indices relative to (ix, iy), clamped to [-1, W-1] x [-1, H-1] in absolute terms;
+    // byte offset = base + yrel * row_bytes + xrel * entry_bytes (non-negative after clamping)
+    constexpr int kEntry = HALF ? 8 : 16;
+    const int row_bytes = (W + 1) * kEntry;
+    const int xlo = -1 - ix, xhi = W - 1 - ix, ylo = -1 - iy, yhi = H - 1 - iy;
+    const int base = ((iy + 1) * (W + 1) + (ix + 1)) * kEntry;
+    // Source moments row by row: the 6 samples of a window row are held, their weighted mean,
+    // centred square sum and cross sum with the reference formed exactly (two passes over the
+    // row), and the rows merged with the parallel-variance update (Chan, Golub, LeVeque):
+    //   mean' = mean + (mu_r - mean) W_r / W_<=r,
+    //   M2'   = M2 + M2_r + (mu_r - mean)^2 W_<r W_r / W_<=r,
+    //   C'    = C + C_r + (mu_r - mean') A_r + (mean - mean') A_<r.
+    // No cancellation at any size of the offsets, and only 6 samples live at a time.
+    const float4 *__restrict__ rowc = reinterpret_cast<const float4 *>(rw + 36);
+    float mu = 0.f, m2 = 0.f, cab = 0.f, acum = 0.f;
+    // software pipeline: the gathers of row sv + 1 are issued before row sv's moments
+    typename QuadT<HALF>::type qd[6];
+    float fxs[6], fys[6];
+    issue_row<HALF>(quads, -5.f, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi, row_bytes, base,
+                    qd, fxs, fys);
 #pragma unroll
     for (int sv = 0; sv < 6; ++sv) {
-        const float vf = -5.f + 2.f * sv;
-        const float rx = fmaf(vf, pvx, N0x), ry = fmaf(vf, pvy, N0y), rzz = fmaf(vf, pvz, Z0);
+        float v6[6];
+        float srow = 0.f;
 #pragma unroll
         for (int su = 0; su < 6; ++su) {
-            const float uf = -5.f + 2.f * su;
-            const float nx = fmaf(uf, pux, rx), ny = fmaf(uf, puy, ry), nz = fmaf(uf, puz, rzz);
-            const float r = __builtin_amdgcn_rcpf(nz);
-            const float dx = nx * r, dy = ny * r;
-            const float fx0 = floorf(dx), fy0 = floorf(dy);
-            const float fx = dx - fx0, fy = dy - fy0;
-            int xi = (int)fx0 + ix, yi = (int)fy0 + iy;
-            xi = min(max(xi, -1), W - 1);
-            yi = min(max(yi, -1), H - 1);
-            const float4 q = load_quad<HALF>(quads, (yi + 1) * Wp + (xi + 1));
-            const float top = fmaf(fx, q.y - q.x, q.x);
-            const float bot = fmaf(fx, q.w - q.z, q.z);
-            const float v = fmaf(fy, bot - top, top);
-            val[sv * 6 + su] = v;
-            sb = fmaf(rw[sv * 6 + su].x, v, sb);
+            v6[su] = eval_quad<HALF>(qd[su], fxs[su], fys[su]);
+            srow = fmaf(rw[sv * 6 + su].x, v6[su], srow);
         }
-    }
-    // pass 2: centred moments (exact two-pass: no cancellation when a sample is far from the mean)
-    const float mb = sb * ws.invW;
-    float sbb = 0.f, sab = 0.f;
+        if (sv < 5)
+            issue_row<HALF>(quads, -3.f + 2.f * sv, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
+                            row_bytes, base, qd, fxs, fys);
+        const float4 rc = rowc[sv];
+        const float mur = srow * rc.x;
+        float m2r = 0.f, cr = 0.f;
 #pragma unroll
-    for (int s = 0; s < 36; ++s) {
-        const float2 wa = rw[s];
-        const float d = val[s] - mb;
-        sbb = fmaf(wa.x * d, d, sbb);
-        sab = fmaf(wa.y, d, sab);
+        for (int su = 0; su < 6; ++su) {
+            const float2 wa = rw[sv * 6 + su];
+            const float d = v6[su] - mur;
+            m2r = fmaf(wa.x * d, d, m2r);
+            cr = fmaf(wa.y, d, cr);
+        }
+        const float delta = mur - mu;
+        const float mun = fmaf(delta, rc.y, mu);
+        m2 += fmaf(rc.z * delta, delta, m2r);
+        cab += fmaf(mur - mun, rc.w, fmaf(mu - mun, acum, cr));
+        acum += rc.w;
+        mu = mun;
     }
-    const float var_b = sbb * ws.invW;
-    const float cov = sab * ws.invW;
+    const float var_b = m2 * ws.invW;
+    const float cov = cab * ws.invW;
     if (ws.var_a < 1e-5f || var_b < 1e-5f) return 2.f;
     const float mm = 1.f - cov * rsqrtf(ws.var_a * var_b);
     return fminf(fmaxf(mm, 0.f), 2.f);
@@ -288,13 +397,15 @@ __device__ __forceinline__ int xcd_tile(int n_tiles) {
 // LDS carve-up of the pass / init kernels
 struct PassLds {
     float *tile;     // kTileRows + 10 rows x (2 * kTilePix + 10) cols of reference intensities
-    float2 *rw;      // [wave][group][36]
+    float2 *rw;      // [wave][group][kWinStride] window blocks
     float4 *pl;      // [256] hypothesis of each lane
     float *ms;       // [wave][n_src][64] costs, reused for refinement results
     float *mf;       // [256] aggregated cost / scratch
     float *psi;      // [wave][group][32] importance, < 0 outside S_t
     int *valid;      // [256]
     unsigned char *act;  // [wave][group][32] active views for refinement
+    float4 *cand;    // [wave][group][6] refinement candidates
+    float *wgt;      // [wave][group][32] view weights of each pixel
 };
 
 constexpr int kTileH = kTileRows + 10;
@@ -302,26 +413,28 @@ constexpr int kTileW = 2 * kTilePix + 10;
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t lds_layout(int n_src, size_t off[8]) {
+__host__ __device__ inline size_t lds_layout(int n_src, size_t off[10]) {
     size_t o = 0;
     off[0] = o; o = align16(o + sizeof(float) * kTileH * kTileW);
-    off[1] = o; o = align16(o + sizeof(float2) * kWaves * kGroups * 36);
+    off[1] = o; o = align16(o + sizeof(float2) * kWaves * kGroups * kWinStride);
     off[2] = o; o = align16(o + sizeof(float4) * 256);
     off[3] = o; o = align16(o + sizeof(float) * kWaves * (n_src > 7 ? n_src : 7) * 64);
     off[4] = o; o = align16(o + sizeof(float) * 256);
     off[5] = o; o = align16(o + sizeof(float) * kWaves * kGroups * kMaxSrc);
     off[6] = o; o = align16(o + sizeof(int) * 256);
     off[7] = o; o = align16(o + kWaves * kGroups * kMaxSrc);
+    off[8] = o; o = align16(o + sizeof(float4) * kWaves * kGroups * 6);
+    off[9] = o; o = align16(o + sizeof(float) * kWaves * kGroups * kMaxSrc);
     return o;
 }
 
 size_t pass_lds_bytes(int n_src) {
-    size_t off[8];
+    size_t off[10];
     return lds_layout(n_src, off);
 }
 
 __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src) {
-    size_t off[8];
+    size_t off[10];
     lds_layout(n_src, off);
     PassLds L;
     L.tile = reinterpret_cast<float *>(smem + off[0]);
@@ -332,6 +445,8 @@ __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src) {
     L.psi = reinterpret_cast<float *>(smem + off[5]);
     L.valid = reinterpret_cast<int *>(smem + off[6]);
     L.act = smem + off[7];
+    L.cand = reinterpret_cast<float4 *>(smem + off[8]);
+    L.wgt = reinterpret_cast<float *>(smem + off[9]);
     return L;
 }
 
@@ -381,7 +496,8 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 // colour.  Lane r of a pixel scores views r, r+9, r+18, r+27.
 // ---------------------------------------------------------------------------
 template <int HALF>
-__global__ __launch_bounds__(256) void init_kernel(PassArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void init_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = xcd_tile(a.n_tiles);
     if (L < 0) return;
@@ -396,7 +512,7 @@ __global__ __launch_bounds__(256) void init_kernel(PassArgs a) {
 
     stage_tile(a.ref, S.tile, y0, x0);
     __syncthreads();
-    float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * 36;
+    float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * kWinStride;
     WinStats ws = {1.f, 0.f};
     if (pix_ok) {
         TileReader rd{S.tile, 5 + wave, 5 + (x - x0), &a.ref, x, y};
@@ -452,7 +568,8 @@ __global__ __launch_bounds__(256) void init_kernel(PassArgs a) {
 // One checkerboard half-pass (Sec. 3.1 - 3.3).
 // ---------------------------------------------------------------------------
 template <int HALF>
-__global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = xcd_tile(a.n_tiles);
     if (L < 0) return;
@@ -502,7 +619,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
     __syncthreads();
 
     // (2) reference window, split over the 9 lanes of the pixel
-    float2 *rw = S.rw + (wave * kGroups + g) * 36;
+    float2 *rw = S.rw + (wave * kGroups + g) * kWinStride;
     WinStats ws = {1.f, 0.f};
     if (pix_ok) {
         TileReader rd{S.tile, 5 + wave, 5 + (x - x0), &a.ref, x, y};
@@ -585,18 +702,24 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
         uniform = !(wsum > 0.f);
         if (uniform) wsum = (float)N;
     }
-    auto weight = [=](int j) -> float {
-        if (uniform) return 1.f;
-        if ((keep >> j) & 1u) return (j == vprev ? 2.f : 1.f) * psi[j];
-        if (!((Sm >> j) & 1u) && ((Sprev >> j) & 1u)) return 0.2f;
-        return 0.f;
-    };
+    // the weights of the pixel, shared through LDS (lane r writes views r, r+9, ...)
+    float *wgt = S.wgt + (wave * kGroups + g) * kMaxSrc;
+    if (pix_ok) {
+        for (int j = row; j < N; j += kRows) {
+            float wj = 0.f;
+            if (uniform) wj = 1.f;
+            else if ((keep >> j) & 1u) wj = (j == vprev ? 2.f : 1.f) * psi[j];
+            else if (!((Sm >> j) & 1u) && ((Sprev >> j) & 1u)) wj = 0.2f;
+            wgt[j] = wj;
+        }
+    }
+    __syncthreads();
 
     // (6) unified cost of the lane's hypothesis (Eq. 7)
     float mfin = __builtin_inff();
     if (valid) {
         float acc = 0.f;
-        for (int j = 0; j < N; ++j) acc = fmaf(weight(j), mcol[j * 64 + lane], acc);
+        for (int j = 0; j < N; ++j) acc = fmaf(wgt[j], mcol[j * 64 + lane], acc);
         mfin = acc / wsum;
     }
     S.mf[tid] = mfin;
@@ -616,65 +739,50 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
         if (brow < 0) { brow = 8; bcost = S.mf[base + 8]; }  // no valid row at all (1-pixel image, no self)
     }
     float4 best = pix_ok ? S.pl[wave * 64 + g * kRows + brow] : make_float4(0.f, 0.f, -1.f, 1.f);
-    unsigned char *act = S.act + (wave * kGroups + g) * kMaxSrc;
-    int nw = 0;
-    if (pix_ok) {
-        for (int j = 0; j < N; ++j)
-            if (weight(j) > 0.f) ++nw;
-        if (row == 0) {
-            int c = 0;
-            for (int j = 0; j < N; ++j)
-                if (weight(j) > 0.f) act[c++] = (unsigned char)j;
-        }
-    }
-    __syncthreads();
 
     // (8) refinement (Sec. 3.3): perturbed (and, from t = 3, random) depth/normal candidates,
     //     scored with the same weights on the views that carry weight; strictly lower wins
     int n_ref = 0;
     if (m.refine) {
         const int ncand = a.t >= 3 ? 6 : 3;
-        // candidate c combines depth {dprt, dcur, dprt, drnd, dcur, drnd}[c] with normal
-        // {best, nprt, nprt, best, nrnd, nrnd}[c]; planes are rebuilt on demand (no private arrays)
-        float2 rr = make_float2(0.f, 0.f);
-        float dcur = 0.f, dprt = 0.f, drnd = 0.f;
-        float npx = 0.f, npy = 0.f, npz = -1.f, nqx = 0.f, nqy = 0.f, nqz = -1.f;
+        unsigned char *act = S.act + (wave * kGroups + g) * kMaxSrc;
+        float4 *cand = S.cand + (wave * kGroups + g) * 6;
+        int nw = 0;
         if (pix_ok) {
-            rr = ref_ray(a.ref, x, y);
-            dcur = plane_depth(rr, best);
-            const float rho = ldexpf(1.f, -(a.t + 2));
-            float ua[4];
-            philox(p, (uint64_t)a.t, 1, m.seed, ua);
-            dprt = dcur + (2.f * ua[0] - 1.f) * rho * (m.d_max - m.d_min);
-            dprt = fminf(fmaxf(dprt, m.d_min), m.d_max);
-            npx = best.x + 2.f * rho * (2.f * ua[1] - 1.f);
-            npy = best.y + 2.f * rho * (2.f * ua[2] - 1.f);
-            npz = best.z + 2.f * rho * (2.f * ua[3] - 1.f);
-            const float inv = 1.f / sqrtf(npx * npx + npy * npy + npz * npz);
-            npx *= inv; npy *= inv; npz *= inv;
-            if (ncand == 6) {
-                float ub[4];
-                philox(p, (uint64_t)a.t, 2, m.seed, ub);
-                drnd = m.d_min + ub[0] * (m.d_max - m.d_min);
-                normal_from_uniforms(ub[1], ub[2], nqx, nqy, nqz);
+            for (int j = 0; j < N; ++j) nw += wgt[j] > 0.f;
+            if (row == 0) {
+                int c = 0;
+                for (int j = 0; j < N; ++j)
+                    if (wgt[j] > 0.f) act[c++] = (unsigned char)j;
+                // candidates: (dprt, n), (d, nprt), (dprt, nprt) [, (drnd, n), (d, nrnd), (drnd, nrnd)]
+                const float2 rr = ref_ray(a.ref, x, y);
+                const float dcur = plane_depth(rr, best);
+                const float rho = ldexpf(1.f, -(a.t + 2));
+                float ua[4];
+                philox(p, (uint64_t)a.t, 1, m.seed, ua);
+                float dprt = dcur + (2.f * ua[0] - 1.f) * rho * (m.d_max - m.d_min);
+                dprt = fminf(fmaxf(dprt, m.d_min), m.d_max);
+                float npx = best.x + 2.f * rho * (2.f * ua[1] - 1.f);
+                float npy = best.y + 2.f * rho * (2.f * ua[2] - 1.f);
+                float npz = best.z + 2.f * rho * (2.f * ua[3] - 1.f);
+                const float inv = 1.f / sqrtf(npx * npx + npy * npy + npz * npz);
+                npx *= inv; npy *= inv; npz *= inv;
+                cand[0] = plane_from(rr, dprt, best.x, best.y, best.z);
+                cand[1] = plane_from(rr, dcur, npx, npy, npz);
+                cand[2] = plane_from(rr, dprt, npx, npy, npz);
+                if (ncand == 6) {
+                    float ub[4], qx, qy, qz;
+                    philox(p, (uint64_t)a.t, 2, m.seed, ub);
+                    const float drnd = m.d_min + ub[0] * (m.d_max - m.d_min);
+                    normal_from_uniforms(ub[1], ub[2], qx, qy, qz);
+                    cand[3] = plane_from(rr, drnd, best.x, best.y, best.z);
+                    cand[4] = plane_from(rr, dcur, qx, qy, qz);
+                    cand[5] = plane_from(rr, drnd, qx, qy, qz);
+                }
             }
         }
-        const float nbx = best.x, nby = best.y, nbz = best.z;
-        auto cand_plane = [=](int c) -> float4 {
-            // lane-wise selects on scalars (a select between aggregate members would go through memory)
-            const bool dc = c == 1 || c == 4, dr = c == 3 || c == 5;
-            const bool use_b = c == 0 || c == 3, use_p = c == 1 || c == 2;
-            float d = dprt, nx = nqx, ny = nqy, nz = nqz;
-            d = dc ? dcur : d;
-            d = dr ? drnd : d;
-            nx = use_p ? npx : nx;
-            ny = use_p ? npy : ny;
-            nz = use_p ? npz : nz;
-            nx = use_b ? nbx : nx;
-            ny = use_b ? nby : ny;
-            nz = use_b ? nbz : nz;
-            return plane_from(rr, d, nx, ny, nz);
-        };
+        __syncthreads();
+        // (candidate, active view) pairs spread over the 9 lanes of the pixel
         float *res = S.ms + wave * N * 64 + g * (6 * N);  // reuse the cost-matrix area (7 * 6N <= 64N)
         const int pairs = pix_ok ? ncand * nw : 0;
         for (int it = 0;; ++it) {
@@ -684,10 +792,10 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
             if (act_lane) {
                 const int c = qi / nw;
                 const int j = act[qi - c * nw];
-                const float4 cp = cand_plane(c);
+                const float4 cp = cand[c];
                 const PlaneQ cq = plane_q(a.ref, m, cp, x, y);
                 const float cost = cq.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, cq.q0, cq.qu, cq.qv) : 2.f;
-                res[qi] = weight(j) * cost;
+                res[qi] = wgt[j] * cost;
                 ++n_ref;
             }
         }
@@ -699,7 +807,7 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
                 const float cc = acc / wsum;
                 if (cc < bcost) {
                     bcost = cc;
-                    best = cand_plane(c);
+                    best = cand[c];
                 }
             }
         }
@@ -721,14 +829,14 @@ __global__ __launch_bounds__(256) void pass_kernel(PassArgs a) {
 // ---------------------------------------------------------------------------
 template <int HALF>
 __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
-    __shared__ float2 rwbuf[64 * 36];
+    __shared__ __align__(16) float2 rwbuf[64 * kWinStride];
     const int gid = blockIdx.x * 64 + threadIdx.x;
     const int total = a.Q * a.n_src;
     if (gid >= total) return;  // no barrier in this kernel
     const int qi = gid / a.n_src, j = gid - qi * a.n_src;
     const int2 px = a.pix[qi];
     const float4 pl = a.planes[qi];
-    float2 *rw = rwbuf + threadIdx.x * 36;
+    float2 *rw = rwbuf + threadIdx.x * kWinStride;
     GlobalReader rd{&a.ref, px.x, px.y};
     const WinStats ws = build_window(rd, a.m, rw, 0, 1);
     const PlaneQ q = plane_q(a.ref, a.m, pl, px.x, px.y);
@@ -756,7 +864,10 @@ __global__ void pack_quads_kernel(const float *img, int W, int H, void *quads, i
     const float c = img[(size_t)y1 * W + x0], d = img[(size_t)y1 * W + x1];
     const size_t i = (size_t)yy * (W + 1) + xx;
     if (!half) {
-        reinterpret_cast<float4 *>(quads)[i] = make_float4(a, b, c, d);
+        // bilinear coefficients, each rounded once from its exact double value
+        const double da = a, db = b, dc = c, dd = d;
+        reinterpret_cast<float4 *>(quads)[i] =
+            make_float4(a, (float)(db - da), (float)(dc - da), (float)((da - db) - (dc - dd)));
     } else {
         __half2 lo = __floats2half2_rn(a, b), hi = __floats2half2_rn(c, d);
         reinterpret_cast<uint2 *>(quads)[i] = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));

@@ -205,41 +205,40 @@ def _texture(seed: int, pid: int, u: torch.Tensor, v: torch.Tensor, spacing: flo
 def _cast(cam: Camera, planes: list, xs: torch.Tensor, ys: torch.Tensor, seed: int, spacing: float):
     """Intersect camera rays through pixel coords (xs, ys) with the world.
 
-    Returns (intensity, camera z-depth, plane id) tensors shaped like xs."""
+    Returns (intensity, camera z-depth, plane id) tensors shaped like xs.  Element-wise arithmetic on
+    the three coordinates (no small matrix products)."""
     dev = xs.device
-    Kinv = torch.tensor(np.linalg.inv(cam.K), dtype=torch.float64, device=dev)
-    Rt = torch.tensor(cam.R.T, dtype=torch.float64, device=dev)
-    C = torch.tensor(cam.center, dtype=torch.float64, device=dev)
-    # camera-frame ray with z = 1, then world direction
-    rc = torch.stack([Kinv[0, 0] * xs + Kinv[0, 1] * ys + Kinv[0, 2],
-                      Kinv[1, 1] * ys + Kinv[1, 2], torch.ones_like(xs)], dim=-1)
-    dw = rc @ Rt.T
+    Ki = np.linalg.inv(cam.K)
+    R = cam.R
+    C = cam.center
+    # camera-frame ray with z = 1, then its world direction R^T r (the hit distance is the camera z)
+    rx = Ki[0, 0] * xs + Ki[0, 1] * ys + Ki[0, 2]
+    ry = Ki[1, 1] * ys + Ki[1, 2]
+    dw = [R[0, i] * rx + R[1, i] * ry + R[2, i] for i in range(3)]
     best_t = torch.full_like(xs, math.inf)
     best_id = torch.full(xs.shape, -1, dtype=torch.int64, device=dev)
     for pid, pl in enumerate(planes):
-        n = torch.tensor(pl.n, dtype=torch.float64, device=dev)
-        den = dw @ n
-        num = -(float(pl.n @ cam.center) + pl.o)
+        den = pl.n[0] * dw[0] + pl.n[1] * dw[1] + pl.n[2] * dw[2]
+        num = -(float(pl.n @ C) + pl.o)
         tt = num / den
         ok = (tt > 1e-6) & (tt < best_t)
         if math.isfinite(pl.hu):
-            X = C + tt.unsqueeze(-1) * dw
-            d = X - torch.tensor(pl.p0, dtype=torch.float64, device=dev)
-            u = d @ torch.tensor(pl.e1, dtype=torch.float64, device=dev)
-            v = d @ torch.tensor(pl.e2, dtype=torch.float64, device=dev)
+            d = [C[i] - pl.p0[i] + tt * dw[i] for i in range(3)]
+            u = pl.e1[0] * d[0] + pl.e1[1] * d[1] + pl.e1[2] * d[2]
+            v = pl.e2[0] * d[0] + pl.e2[1] * d[1] + pl.e2[2] * d[2]
             ok = ok & (u.abs() <= pl.hu) & (v.abs() <= pl.hv)
         best_t = torch.where(ok, tt, best_t)
         best_id = torch.where(ok, torch.full_like(best_id, pid), best_id)
-    X = C + best_t.clamp(max=1e6).unsqueeze(-1) * dw
+    tcl = best_t.clamp(max=1e6)
     inten = torch.zeros_like(xs)
     for pid, pl in enumerate(planes):
         m = best_id == pid
         if not bool(m.any()):
             continue
-        Xm = X[m]
-        d = Xm - torch.tensor(pl.p0, dtype=torch.float64, device=dev)
-        u = d @ torch.tensor(pl.e1, dtype=torch.float64, device=dev)
-        v = d @ torch.tensor(pl.e2, dtype=torch.float64, device=dev)
+        tm = tcl[m]
+        d = [C[i] - pl.p0[i] + tm * dw[i][m] for i in range(3)]
+        u = pl.e1[0] * d[0] + pl.e1[1] * d[1] + pl.e1[2] * d[2]
+        v = pl.e2[0] * d[0] + pl.e2[1] * d[1] + pl.e2[2] * d[2]
         if pl.const >= 0:
             val = torch.full_like(u, pl.const)
         else:

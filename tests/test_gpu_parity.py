@@ -3,9 +3,10 @@
 Bars (written here, derived in the design notes):
   * fixed hypotheses: |cost_gpu - cost_oracle| <= 1e-4 per hypothesis and view;
   * one half-pass from the same state: on every pixel whose decisions clear a
-    margin of 2e-4 in the oracle (robust pixels), the GPU keeps exactly the
-    oracle's plane (bit-exact when it is a propagated one, 1e-5 when refined),
-    the same view set S_t and best view v_t, and a cost within 1e-4;
+    margin of 1e-5 in the oracle (robust pixels; measured GPU cost errors are
+    ~1e-6), the GPU keeps exactly the oracle's plane (bit-exact when it is a
+    propagated one, 1e-5 when refined), the same view set S_t, and a cost
+    within 1e-4; v_t agrees wherever its own argmax clears the margin;
   * full runs: >= 99.5 % of pixels within 0.1 % relative depth.
 """
 import sys
@@ -149,7 +150,7 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
     st = O.State.from_arrays(pl0, c0, S0, v0)
     Wd, Hd = sc.width, sc.height
     order = np.array([i for i in range(Wd * Hd) if ((i % Wd) + (i // Wd)) % 2 == colour], np.int32)
-    dg = O.run_pass(V, P, st, t, colour, order=order, delta=2e-4, diag=True)
+    dg = O.run_pass(V, P, st, t, colour, order=order, delta=1e-5, diag=True)
     bits = np.array([d.robust for d in dg])
     # the plane and the cost depend on the view tests, the top-k cut, the argmin and refinement;
     # v_t additionally on its own argmax (ORC_ROBUST_* bits of the oracle)
