@@ -165,11 +165,33 @@ amh_status amh_set_state(amh_ctx *ctx, const float *planes, const float *cost, c
  * All three in host memory (on_device = 0) or device memory (1). */
 amh_status amh_score_fixed(amh_ctx *ctx, const float *planes, const int *pix, int Q, float *costs, int on_device);
 
-/* Runs n_jobs reference images (views registered by amh_init_views) in one
- * batch: all passes of all jobs inside one captured HIP graph of persistent
- * launches.  Results are read with amh_get_job_result. */
+/* Runs n_jobs reference images (views registered by amh_init_views; sizes and
+ * view counts may differ) as one batch: one launch per phase (init of a
+ * colour, or a half-pass) covering the tiles of every job that is still
+ * iterating, all phases captured in one HIP graph.  The graph is kept and
+ * replayed while the job list, the views and the parameters stay the same.
+ * Stream-ordered; results are read with amh_get_job_result, work counters
+ * with amh_get_stats and per-job completion times with amh_get_job_times.
+ * INVALID_ARG on bad jobs (checked before any HIP call), STATE without views. */
 amh_status amh_run_batch(amh_ctx *ctx, int n_jobs, const amh_job *jobs);
+
+/* Depth / normal / cost of job `job` of the last batch (as amh_get_depth_normal_cost). */
 amh_status amh_get_job_result(amh_ctx *ctx, int job, float *depth, float *normal, float *cost, int dst_on_device);
+
+/* Completion time of every job of the last batch, in ms after the batch started
+ * (device clock, stamped by the workgroup that finished the job's last tile).
+ * n must equal the batch's job count.  Synchronises the stream. */
+amh_status amh_get_job_times(amh_ctx *ctx, int n, float *job_ms);
+
+/* Autotuner: times the batch under each launch configuration (tile order:
+ * XCD bands or hardware order, x job order: as given or largest first;
+ * configuration = tile_order + 2 * job_order), keeps the fastest for the
+ * following launches of this context (single images included) and returns
+ * it in *best_config (may be NULL) with the measured ms in ms_per_config[4]
+ * (may be NULL; -1 where not measured).  If the environment variable
+ * AMH_TUNE_CACHE names a file, the choice is looked up there by shape bucket
+ * (job count, largest view count, pixel count) and appended after tuning. */
+amh_status amh_tune(amh_ctx *ctx, int n_jobs, const amh_job *jobs, int *best_config, float *ms_per_config);
 
 /* Work counters and timings of the current reference (or of the last batch). */
 amh_status amh_get_stats(const amh_ctx *ctx, amh_stats *out);

@@ -22,9 +22,10 @@ AMH_F32, AMH_F16 = 0, 1
 EXPORTS = [
     "amh_params_default", "amh_create", "amh_set_params", "amh_init_views", "amh_begin", "amh_init_hypotheses",
     "amh_pass", "amh_run_checkerboard", "amh_get_depth_normal_cost", "amh_get_state", "amh_set_state",
-    "amh_score_fixed", "amh_run_batch", "amh_get_job_result", "amh_get_stats", "amh_status_str",
-    "amh_last_error", "amh_destroy",
+    "amh_score_fixed", "amh_run_batch", "amh_get_job_result", "amh_get_job_times", "amh_tune", "amh_get_stats",
+    "amh_status_str", "amh_last_error", "amh_destroy",
 ]
+N_TUNE_CONFIGS = 4  # tile order {XCD bands, hardware} x job order {given, largest first}
 
 
 class AmhError(RuntimeError):
@@ -85,6 +86,8 @@ def lib():
         L.amh_score_fixed.argtypes = [vp, vp, vp, ip, vp, ip]
         L.amh_run_batch.argtypes = [vp, ip, C.POINTER(amh_job)]
         L.amh_get_job_result.argtypes = [vp, ip, vp, vp, vp, ip]
+        L.amh_get_job_times.argtypes = [vp, ip, C.POINTER(C.c_float)]
+        L.amh_tune.argtypes = [vp, ip, C.POINTER(amh_job), C.POINTER(C.c_int), C.POINTER(C.c_float)]
         L.amh_get_stats.argtypes = [vp, C.POINTER(amh_stats)]
         L.amh_status_str.argtypes = [ip]
         L.amh_status_str.restype = C.c_char_p
@@ -268,15 +271,35 @@ class Context:
                     "amh_score_fixed")
         return out
 
-    def run_batch(self, jobs):
+    @staticmethod
+    def _jobs(jobs):
         arr = (amh_job * len(jobs))()
         keep = []
         for i, jb in enumerate(jobs):
             s = (C.c_int * len(jb["srcs"]))(*[int(v) for v in jb["srcs"]])
             keep.append(s)
             arr[i] = amh_job(int(jb["ref"]), s, len(jb["srcs"]), int(jb["iters"]))
+        return arr, keep
+
+    def run_batch(self, jobs):
+        arr, keep = self._jobs(jobs)
         self._check(self.L.amh_run_batch(self.h, len(jobs), arr), "amh_run_batch")
         self._jobs_shape = [self._views_shape[int(jb["ref"])] for jb in jobs]
+
+    def tune(self, jobs):
+        """Autotune the launch configuration on this batch; returns (best, ms per configuration)."""
+        arr, keep = self._jobs(jobs)
+        best = C.c_int(-1)
+        ms = (C.c_float * N_TUNE_CONFIGS)()
+        self._check(self.L.amh_tune(self.h, len(jobs), arr, C.byref(best), ms), "amh_tune")
+        self._jobs_shape = [self._views_shape[int(jb["ref"])] for jb in jobs]
+        return int(best.value), list(ms)
+
+    def get_job_times(self):
+        n = len(self._jobs_shape)
+        out = (C.c_float * n)()
+        self._check(self.L.amh_get_job_times(self.h, n, out), "amh_get_job_times")
+        return np.array(out[:], np.float64)
 
     def get_job_result(self, job: int, depth=None, normal=None, cost=None):
         H, W = self._jobs_shape[job]

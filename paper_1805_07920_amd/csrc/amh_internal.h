@@ -56,6 +56,31 @@ struct PassArgs {
     int t, colour;
     int tiles_x, n_tiles;        // tile grid of this colour
     unsigned long long *counters;  // [3][kCounterSlots]: init, propagation, refinement evals
+    int order;                   // tile order: 0 XCD bands, 1 hardware order
+};
+
+// one reference image of a batch
+struct BatchJobDev {
+    RefDev ref;
+    const ViewDev *views;        // n_src warp constants
+    int n_src;
+    StateDev st;
+    int tiles_x, n_tiles;        // tile grid of one colour
+};
+
+// one phase (init of a colour, or a half-pass) over the active jobs of a batch
+struct BatchPhaseArgs {
+    const BatchJobDev *jobs;
+    const int *tile_start;       // [n_active + 1] prefix sums of the active jobs' tile counts
+    const int *job_of;           // [n_active] job index of each active entry
+    const int *is_last;          // [n_active] 1 if this phase is the job's last one
+    int n_active, total_tiles;
+    MethodDev m;
+    int t, colour, kind;         // kind 0: init, 1: half-pass
+    int order;
+    unsigned long long *counters;
+    unsigned long long *tiles_done;  // [n_jobs] tiles finished in the job's last phase
+    unsigned long long *job_end; // [n_jobs] device clock at the job's completion
 };
 
 struct ScoreArgs {
@@ -79,6 +104,8 @@ hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s);
 hipError_t launch_score(const ScoreArgs &a, int half, hipStream_t s);
 hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, float *normal, float *cost,
                           hipStream_t s);
+hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s);
+hipError_t launch_stamp(unsigned long long *p, hipStream_t s);
 size_t pass_lds_bytes(int n_src);
 
 }  // namespace amh

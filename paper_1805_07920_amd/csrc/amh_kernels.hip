@@ -387,9 +387,12 @@ __device__ __forceinline__ float plane_depth(float2 r, float4 pl) {
 // tiles are renumbered so that each XCD walks a contiguous band of rows and
 // keeps its sources' footprint in its own L2.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int xcd_tile(int n_tiles) {
-    const int per = (n_tiles + 7) >> 3;
+// order 0: XCD bands (block b runs on XCD b mod 8 and takes the (b / 8)-th tile of
+// that XCD's band); order 1: hardware order (block b takes tile b).
+__device__ __forceinline__ int tile_of_block(int n_tiles, int order) {
     const int b = blockIdx.x;
+    if (order == 1) return b < n_tiles ? b : -1;
+    const int per = (n_tiles + 7) >> 3;
     const int L = (b & 7) * per + (b >> 3);
     return L < n_tiles ? L : -1;
 }
@@ -496,11 +499,7 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 // colour.  Lane r of a pixel scores views r, r+9, r+18, r+27.
 // ---------------------------------------------------------------------------
 template <int HALF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
-void init_kernel(PassArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int L = xcd_tile(a.n_tiles);
-    if (L < 0) return;
+__device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned char *smem) {
     PassLds S = carve(smem, a.n_src);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int grp = lane / kRows, row = lane - grp * kRows;
@@ -568,11 +567,7 @@ void init_kernel(PassArgs a) {
 // One checkerboard half-pass (Sec. 3.1 - 3.3).
 // ---------------------------------------------------------------------------
 template <int HALF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
-void pass_kernel(PassArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int L = xcd_tile(a.n_tiles);
-    if (L < 0) return;
+__device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned char *smem) {
     PassLds S = carve(smem, a.n_src);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int grp = lane / kRows, row = lane - grp * kRows;
@@ -825,6 +820,78 @@ void pass_kernel(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Single-image launches: one workgroup per tile of the colour.
+// ---------------------------------------------------------------------------
+template <int HALF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void init_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = tile_of_block(a.n_tiles, a.order);
+    if (L < 0) return;
+    init_body<HALF>(a, L, smem);
+}
+
+template <int HALF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void pass_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = tile_of_block(a.n_tiles, a.order);
+    if (L < 0) return;
+    pass_body<HALF>(a, L, smem);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launch: one phase (init of a colour, or a half-pass) of many
+// reference images of different sizes and view counts.  The tiles of the
+// active jobs are concatenated; a workgroup finds its job by binary search in
+// the prefix sums and runs the same body as the single-image kernels.  The
+// workgroup that finishes the last tile of a job's last phase stamps the
+// device clock (per-job completion time within the batch).
+// ---------------------------------------------------------------------------
+template <int HALF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void batch_kernel(BatchPhaseArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = tile_of_block(b.total_tiles, b.order);
+    if (g < 0) return;
+    int lo = 0, hi = b.n_active;  // tile_start[lo] <= g < tile_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (b.tile_start[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const int j = b.job_of[lo];
+    const BatchJobDev &J = b.jobs[j];
+    PassArgs a;
+    a.ref = J.ref;
+    a.views = J.views;
+    a.n_src = J.n_src;
+    a.m = b.m;
+    a.st = J.st;
+    a.t = b.t;
+    a.colour = b.colour;
+    a.tiles_x = J.tiles_x;
+    a.n_tiles = J.n_tiles;
+    a.counters = b.counters;
+    a.order = b.order;
+    const int L = g - b.tile_start[lo];
+    if (b.kind == 0) init_body<HALF>(a, L, smem);
+    else pass_body<HALF>(a, L, smem);
+    if (b.is_last[lo]) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (atomicAdd(&b.tiles_done[j], 1ull) == (unsigned long long)(J.n_tiles - 1))
+                b.job_end[j] = wall_clock64();
+        }
+    }
+}
+
+__global__ void stamp_kernel(unsigned long long *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = wall_clock64();
+}
+
+// ---------------------------------------------------------------------------
 // Fixed hypotheses: one thread per (query, view).
 // ---------------------------------------------------------------------------
 template <int HALF>
@@ -900,21 +967,29 @@ __global__ void outputs_kernel(RefDev ref, StateDev st, float *depth, float *nor
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Clears an error left by an earlier, unrelated runtime call, so that the
+// hipGetLastError() after the launch reports the launch itself.
+#define AMH_LAUNCH(...)                  \
+    do {                                 \
+        (void)hipGetLastError();         \
+        hipLaunchKernelGGL(__VA_ARGS__); \
+    } while (0)
+
 hipError_t launch_convert_to_f32(const void *src, int src_dtype, int64_t pitch, int W, int H, float *dst,
                                  hipStream_t s) {
     dim3 grid((W + 255) / 256, H);
-    hipLaunchKernelGGL(convert_kernel, grid, dim3(256), 0, s, src, src_dtype, pitch, W, H, dst);
+    AMH_LAUNCH(convert_kernel, grid, dim3(256), 0, s, src, src_dtype, pitch, W, H, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int half, hipStream_t s) {
     dim3 grid((W + 1 + 255) / 256, H + 1);
-    hipLaunchKernelGGL(pack_quads_kernel, grid, dim3(256), 0, s, img, W, H, quads, half);
+    AMH_LAUNCH(pack_quads_kernel, grid, dim3(256), 0, s, img, W, H, quads, half);
     return hipGetLastError();
 }
 
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
-    hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    AMH_LAUNCH(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -922,15 +997,28 @@ static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
     const size_t lds = pass_lds_bytes(a.n_src);
-    if (half) hipLaunchKernelGGL(init_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL(init_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    if (half) AMH_LAUNCH(init_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    else AMH_LAUNCH(init_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
     const size_t lds = pass_lds_bytes(a.n_src);
-    if (half) hipLaunchKernelGGL(pass_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL(pass_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    if (half) AMH_LAUNCH(pass_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    else AMH_LAUNCH(pass_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s) {
+    if (b.total_tiles == 0) return hipSuccess;
+    const size_t lds = pass_lds_bytes(max_src);
+    if (half) AMH_LAUNCH(batch_kernel<1>, dim3(grid_for(b.total_tiles)), dim3(256), lds, s, b);
+    else AMH_LAUNCH(batch_kernel<0>, dim3(grid_for(b.total_tiles)), dim3(256), lds, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(unsigned long long *p, hipStream_t s) {
+    AMH_LAUNCH(stamp_kernel, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
@@ -938,15 +1026,15 @@ hipError_t launch_score(const ScoreArgs &a, int half, hipStream_t s) {
     const int total = a.Q * a.n_src;
     if (total == 0) return hipSuccess;
     dim3 grid((total + 63) / 64);
-    if (half) hipLaunchKernelGGL(score_kernel<1>, grid, dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(score_kernel<0>, grid, dim3(64), 0, s, a);
+    if (half) AMH_LAUNCH(score_kernel<1>, grid, dim3(64), 0, s, a);
+    else AMH_LAUNCH(score_kernel<0>, grid, dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, float *normal, float *cost,
                           hipStream_t s) {
     dim3 grid((ref.W + 255) / 256, ref.H);
-    hipLaunchKernelGGL(outputs_kernel, grid, dim3(256), 0, s, ref, st, depth, normal, cost);
+    AMH_LAUNCH(outputs_kernel, grid, dim3(256), 0, s, ref, st, depth, normal, cost);
     return hipGetLastError();
 }
 

@@ -1,0 +1,145 @@
+"""Batched execution (many reference images of uneven sizes and view counts in
+one captured graph of per-phase launches) against per-image runs.
+
+The batch runs the same kernel bodies with the same random streams, so every
+job's result must equal a single-image run bit for bit; graph replays (with
+other work in between) must reproduce the first run; the autotuned launch
+configuration must not change results.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def amh():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_07920_amd as amh
+
+    amh.lib()
+    return amh
+
+
+SPECS = [  # (W, H, n_src, iters, seed)
+    (96, 64, 3, 2, 21),
+    (131, 77, 5, 3, 22),
+    (64, 48, 2, 1, 23),
+    (150, 90, 4, 0, 24),
+    (40, 30, 6, 3, 25),
+]
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    import scenegen
+
+    images, cams, jobs = [], [], []
+    for W, H, n, iters, seed in SPECS:
+        sc = scenegen.make_scene(W, H, n, 30.0, 3, seed, gain=0.05, supersample=2)
+        base = len(images)
+        images += [np.ascontiguousarray(im) for im in sc.images]
+        cams += sc.cams
+        jobs.append(dict(ref=base, srcs=list(range(base + 1, base + n + 1)), iters=iters))
+    return images, cams, jobs
+
+
+def _single(amh, images, cams, jb, **kw):
+    with amh.Context(**kw) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_checkerboard(jb["ref"], jb["srcs"], jb["iters"])
+        out = ctx.get_depth_normal_cost()
+        st = ctx.get_stats()
+    return out, st
+
+
+def test_batch_equals_single_runs(amh, batch_setup):
+    say("case batch == single")
+    images, cams, jobs = batch_setup
+    kw = dict(refine=1, seed=13)
+    with amh.Context(**kw) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_batch(jobs)
+        res = [ctx.get_job_result(i) for i in range(len(jobs))]
+        st = ctx.get_stats()
+        times = ctx.get_job_times()
+    tot = dict(evals_init=0, evals_propagation=0, evals_refine=0)
+    for i, jb in enumerate(jobs):
+        (d, n, c), s = _single(amh, images, cams, jb, **kw)
+        for a, b in zip(res[i], (d, n, c)):
+            assert np.array_equal(a, b), f"job {i} differs from its single-image run"
+        for k in tot:
+            tot[k] += s[k]
+    for k in tot:
+        assert st[k] == tot[k]
+    say("  job completion ms", np.round(times, 3))
+    assert np.all(np.isfinite(times)) and np.all(times >= 0)
+
+
+def test_graph_replay_reproduces(amh, batch_setup):
+    say("case graph replay")
+    images, cams, jobs = batch_setup
+    with amh.Context(refine=1, seed=5) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_batch(jobs)
+        first = [ctx.get_job_result(i) for i in range(len(jobs))]
+        for rep in range(3):
+            # unrelated work on the same context between replays
+            ctx.run_checkerboard(jobs[1]["ref"], jobs[1]["srcs"], 1)
+            ctx.get_depth_normal_cost()
+            ctx.run_batch(jobs)  # replays the captured graph
+            again = [ctx.get_job_result(i) for i in range(len(jobs))]
+            for a, b in zip(first, again):
+                for x, y in zip(a, b):
+                    assert np.array_equal(x, y), f"replay {rep} differs"
+
+
+def test_tuned_configuration_keeps_results(amh, batch_setup):
+    say("case autotune")
+    images, cams, jobs = batch_setup
+    with amh.Context(refine=1, seed=7) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_batch(jobs)
+        ref = [ctx.get_job_result(i) for i in range(len(jobs))]
+        best, ms = ctx.tune(jobs)
+        say("  best config", best, "ms", np.round(ms, 3))
+        assert 0 <= best < amh.N_TUNE_CONFIGS
+        assert all(m > 0 for m in ms)
+        ctx.run_batch(jobs)
+        out = [ctx.get_job_result(i) for i in range(len(jobs))]
+    for a, b in zip(ref, out):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_batch_errors(amh, batch_setup):
+    say("case batch errors")
+    images, cams, jobs = batch_setup
+    with amh.Context() as ctx:
+        with pytest.raises(amh.AmhError) as e:
+            ctx.run_batch(jobs)
+        assert e.value.status == amh.AMH_E_STATE
+        ctx.init_views(images, cams)
+        with pytest.raises(amh.AmhError) as e:
+            ctx._jobs_shape = [(1, 1)]
+            ctx.get_job_result(0)
+        assert e.value.status == amh.AMH_E_STATE
+        bad = [dict(jobs[0]), dict(jobs[1])]
+        bad[1]["srcs"] = [bad[1]["ref"]]
+        with pytest.raises(amh.AmhError) as e:
+            ctx.run_batch(bad)
+        assert e.value.status == amh.AMH_E_INVALID_ARG
+        bad[1]["srcs"] = [len(images)]
+        with pytest.raises(amh.AmhError) as e:
+            ctx.run_batch(bad)
+        assert e.value.status == amh.AMH_E_INVALID_ARG
