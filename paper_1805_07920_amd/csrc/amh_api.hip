@@ -352,12 +352,12 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hj[a].n_tiles > hj[b].n_tiles; });
     // phases and their tables
     struct Phase {
-        int kind, colour, t, n_active, total, off;
+        int kind, colour, t, n_active, total, off, grid;
     };
     std::vector<Phase> phases;
     std::vector<int> tab;
     auto add_phase = [&](int kind, int colour, int t) {
-        Phase ph{kind, colour, t, 0, 0, (int)tab.size()};
+        Phase ph{kind, colour, t, 0, 0, (int)tab.size(), 0};
         std::vector<int> act;
         for (int j : order)
             if (kind == 0 || jobs[j].iters > t) act.push_back(j);
@@ -375,6 +375,39 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
             const bool last = colour == 1 && ((kind == 0 && jobs[j].iters == 0) || (kind == 1 && t == jobs[j].iters - 1));
             tab.push_back(last ? 1 : 0);
         }
+        // per-XCD ranges of the concatenated tiles, cut at equal shares of work (a tile's work is
+        // proportional to its job's view count); the launch gives every XCD as many workgroups as
+        // the longest range
+        double work = 0;
+        for (int j : act) work += (double)hj[j].n_tiles * hj[j].n_src;
+        const size_t xs = tab.size();
+        int x = 1, g0 = 0;
+        double cum = 0;
+        tab.push_back(0);
+        for (int j : act) {
+            const double wt = hj[j].n_src;
+            for (int k = 0; k < hj[j].n_tiles && x < 8;) {
+                // tiles of this job up to the next cut
+                const double need = work * x / 8.0 - cum;
+                const int take = std::min(hj[j].n_tiles - k, (int)std::ceil(need / wt));
+                k += take;
+                g0 += take;
+                cum += take * wt;
+                if (cum >= work * x / 8.0 - 1e-9) {
+                    tab.push_back(g0);
+                    ++x;
+                }
+            }
+            if (x >= 8) break;
+        }
+        while (x < 8) {  // rounding left cuts over
+            tab.push_back(g0);
+            ++x;
+        }
+        tab.push_back(acc);
+        int longest = 1;
+        for (int i = 0; i < 8; ++i) longest = std::max(longest, tab[xs + i + 1] - tab[xs + i]);
+        ph.grid = c->cfg_order == 0 ? 8 * longest : acc;
         phases.push_back(ph);
     };
     add_phase(0, 0, 0);
@@ -402,8 +435,10 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         b.tile_start = c->d_tables + ph.off;
         b.job_of = c->d_tables + ph.off + ph.n_active + 1;
         b.is_last = c->d_tables + ph.off + 2 * ph.n_active + 1;
+        b.xcd_start = c->d_tables + ph.off + 3 * ph.n_active + 1;
         b.n_active = ph.n_active;
         b.total_tiles = ph.total;
+        b.grid = ph.grid;
         b.m = method_dev(c->p, ph.t);
         b.t = ph.t;
         b.colour = ph.colour;

@@ -74,7 +74,9 @@ struct BatchPhaseArgs {
     const int *tile_start;       // [n_active + 1] prefix sums of the active jobs' tile counts
     const int *job_of;           // [n_active] job index of each active entry
     const int *is_last;          // [n_active] 1 if this phase is the job's last one
+    const int *xcd_start;        // [9] per-XCD tile ranges of equal work (tile order 0)
     int n_active, total_tiles;
+    int grid;                    // workgroups of the launch
     MethodDev m;
     int t, colour, kind;         // kind 0: init, 1: half-pass
     int order;

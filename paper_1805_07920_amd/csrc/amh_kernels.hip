@@ -852,8 +852,18 @@ template <int HALF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
 void batch_kernel(BatchPhaseArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int g = tile_of_block(b.total_tiles, b.order);
-    if (g < 0) return;
+    // order 0: XCD x walks the tile range [xcd_start[x], xcd_start[x+1]) of the concatenated list,
+    // the ranges cut at equal shares of work (tiles weighted by their job's view count);
+    // order 1: hardware order
+    int g;
+    if (b.order == 0) {
+        const int x = blockIdx.x & 7;
+        g = b.xcd_start[x] + (int)(blockIdx.x >> 3);
+        if (g >= b.xcd_start[x + 1]) return;
+    } else {
+        g = blockIdx.x;
+        if (g >= b.total_tiles) return;
+    }
     int lo = 0, hi = b.n_active;  // tile_start[lo] <= g < tile_start[hi]
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -1012,8 +1022,8 @@ hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
 hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s) {
     if (b.total_tiles == 0) return hipSuccess;
     const size_t lds = pass_lds_bytes(max_src);
-    if (half) AMH_LAUNCH(batch_kernel<1>, dim3(grid_for(b.total_tiles)), dim3(256), lds, s, b);
-    else AMH_LAUNCH(batch_kernel<0>, dim3(grid_for(b.total_tiles)), dim3(256), lds, s, b);
+    if (half) AMH_LAUNCH(batch_kernel<1>, dim3(b.grid), dim3(256), lds, s, b);
+    else AMH_LAUNCH(batch_kernel<0>, dim3(b.grid), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
