@@ -1,0 +1,103 @@
+"""CPU oracle for the two method-side steps of the learned proposal.
+
+TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
+
+1. ``sweep_features``: the network's input at 1/4 resolution.  Cell (i, j)
+   covers reference pixels x in [4j, 4j + 4), y in [4i, 4i + 4) and is sampled
+   at pixel (4j + 2, 4i + 2).  Channels:
+     0: (mean of the cell's 16 reference intensities - 127.5) / 64;
+     1: population standard deviation of those 16 intensities / 32;
+     2 + k, k = 0..13: 1 - (mean of the min(k_views, n) lowest matching costs,
+        Eq. 8, of the fronto-parallel plane at inverse depth
+        q_k = 1/d_max + (k + 0.5) (1/d_min - 1/d_max) / 14, over the first
+        n = min(8, N) sources).  The k-lowest mean is the same aggregate as the
+        initial cost of random initialisation.
+2. ``proposal_state``: the initial PatchMatch state built from per-cell
+   predictions (depth, unit normal, confidence) at a resolution whose cell is
+   s x s reference pixels (s = W / w = H / h).  Pixel (x, y) takes the plane of
+   its cell: through the 3-D point at the predicted depth on the ray of the
+   cell's sample pixel (s j + s/2, s i + s/2), with the predicted normal, turned
+   to face the pixel's own ray.  It is used when the confidence is at least
+   ``conf_min``, the normal is non-zero and the plane's depth along the pixel's
+   ray lies in [d_min, d_max]; otherwise the pixel keeps the random plane of
+   random initialisation (Sec. 3: random plane per pixel).  The initial cost is
+   the mean of the k lowest per-view costs over all N sources, S = 0, v = -1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import Params, State, Views, matching_cost, random_plane
+
+N_DEPTH = 14
+N_NET_SRC = 8
+CELL = 4
+
+
+def _kinv(views: Views) -> np.ndarray:
+    return np.linalg.inv(np.array(views.c.Kref[:], np.float64).reshape(3, 3))
+
+
+def sweep_planes(params: Params, n_depth: int = N_DEPTH) -> list:
+    qf, qn = 1.0 / params.d_max, 1.0 / params.d_min
+    return [np.array([0.0, 0.0, -1.0, 1.0 / (qf + (k + 0.5) * (qn - qf) / n_depth)]) for k in range(n_depth)]
+
+
+def sweep_features(views: Views, params: Params, n_depth: int = N_DEPTH) -> np.ndarray:
+    """(H/4, W/4, 2 + n_depth) float64 network input of the reference of ``views``."""
+    H, W = views.H, views.W
+    h4, w4 = H // CELL, W // CELL
+    n = min(N_NET_SRC, views.n_src)
+    kk = min(params.k, n)
+    ref = views.images[0].astype(np.float64)
+    planes = sweep_planes(params, n_depth)
+    F = np.zeros((h4, w4, 2 + n_depth))
+    for i in range(h4):
+        for j in range(w4):
+            blk = ref[CELL * i:CELL * i + CELL, CELL * j:CELL * j + CELL]
+            F[i, j, 0] = (blk.mean() - 127.5) / 64.0
+            F[i, j, 1] = blk.std() / 32.0
+            x, y = CELL * j + CELL // 2, CELL * i + CELL // 2
+            for k, pl in enumerate(planes):
+                c = sorted(matching_cost(views, params, x, y, pl, jv) for jv in range(n))
+                F[i, j, 2 + k] = 1.0 - float(np.mean(c[:kk]))
+    return F
+
+
+def proposal_plane(views: Views, params: Params, x: int, y: int, depth, normal, conf, conf_min: float = 0.5):
+    """(plane, used) for pixel (x, y) from per-cell maps (h, w) and (h, w, 3)."""
+    h, w = np.shape(depth)
+    s = views.W // w
+    i, j = y // s, x // s
+    nv = np.asarray(normal[i, j], np.float64)
+    nn = float(np.linalg.norm(nv))
+    if conf[i, j] >= conf_min and np.isfinite(nn) and nn > 0.0 and np.isfinite(depth[i, j]):
+        Ki = _kinv(views)
+        n = nv / nn
+        Xc = float(depth[i, j]) * (Ki @ np.array([s * j + s // 2, s * i + s // 2, 1.0]))
+        dp = -float(n @ Xc)
+        r = Ki @ np.array([x, y, 1.0])
+        nr = float(n @ r)
+        if nr > 0.0:
+            n, dp, nr = -n, -dp, -nr
+        if nr < 0.0:
+            d = -dp / nr
+            if params.d_min <= d <= params.d_max:
+                return np.array([n[0], n[1], n[2], dp]), True
+    return random_plane(views, params, x, y, 0, 0), False
+
+
+def proposal_state(views: Views, params: Params, depth, normal, conf, conf_min: float = 0.5):
+    """(State, used mask) of proposal initialisation."""
+    H, W, N = views.H, views.W, views.n_src
+    kk = min(params.k, N)
+    st = State.empty(H, W)
+    used = np.zeros((H, W), bool)
+    for y in range(H):
+        for x in range(W):
+            pl, u = proposal_plane(views, params, x, y, depth, normal, conf, conf_min)
+            st.plane[y, x] = pl
+            used[y, x] = u
+            c = sorted(matching_cost(views, params, x, y, pl, jv) for jv in range(N))
+            st.cost[y, x] = float(np.mean(c[:kk]))
+    return st, used
