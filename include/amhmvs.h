@@ -87,6 +87,7 @@ typedef struct {
     int n1, n2, k;                      /* good-view counts and top-k (Sec. 3.2) */
     uint64_t seed;                      /* key of the counter-based random generator */
     int timing;                         /* 1: record per-pass device times (amh_get_stats) */
+    float conf_min;                     /* learned proposal: lowest confidence that replaces a random plane */
 } amh_params;
 
 /* Counters of the work performed since the last amh_begin / amh_run_checkerboard. */
@@ -109,7 +110,7 @@ typedef struct {
 } amh_job;
 
 /* Fills *out with the paper's parameters, depth range [2, 6], refine 1,
- * include_self 1, seed 0, timing 0.  INVALID_ARG if out is NULL. */
+ * include_self 1, seed 0, timing 0, conf_min 0.5.  INVALID_ARG if out is NULL. */
 amh_status amh_params_default(amh_params *out);
 
 /* Creates a context on the current HIP device.  p: parameters (copied).
@@ -195,6 +196,85 @@ amh_status amh_tune(amh_ctx *ctx, int n_jobs, const amh_job *jobs, int *best_con
 
 /* Work counters and timings of the current reference (or of the last batch). */
 amh_status amh_get_stats(const amh_ctx *ctx, amh_stats *out);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal.  Not part of the paper: a small convolutional network
+ * predicts a plane and a confidence per 4 x 4 cell of the reference image, so
+ * that the iterations of Sec. 3 start from it instead of random planes
+ * (random planes stay where the confidence is low).  The confidence target is
+ * C(m) of Eq. 3 applied to the final cost of the plain method.
+ * Network: 4-level encoder-decoder (channels 16/32/48/64, two 3x3
+ * convolutions + ReLU per encoder level, 2x2 average pooling, nearest 2x
+ * upsampling concatenated with the skip, one 3x3 convolution + ReLU per
+ * decoder level, 1x1 head with 5 outputs); bf16 weights and activations, fp32
+ * accumulation on the matrix cores; trained on the device (forward, loss and
+ * gradient, Adam on fp32 master weights).  Parameters in canonical order, layer
+ * by layer (enc0a, enc0b, enc1a, enc1b, enc2a, enc2b, enc3a, enc3b, dec2, dec1,
+ * dec0, head), each the weight [c_out][ky][kx][c_in] then the bias [c_out].
+ * ------------------------------------------------------------------------ */
+
+/* Number of network parameters (196341).  INVALID_ARG if n is NULL. */
+amh_status amh_nn_param_count(int64_t *n);
+
+/* Creates (or re-creates) the network on the context: He-normal weights drawn
+ * from the seed, biases 0 except the head's normal-z bias -1 (the initial
+ * prediction faces the camera), cleared optimiser state. */
+amh_status amh_nn_init(amh_ctx *ctx, uint64_t seed);
+
+/* Host copies of the fp32 master parameters and of the last gradient (n floats,
+ * canonical order; n must equal the parameter count).  set also clears the
+ * optimiser state.  STATE if the network does not exist. */
+amh_status amh_nn_get_params(amh_ctx *ctx, float *out, int64_t n);
+amh_status amh_nn_set_params(amh_ctx *ctx, const float *in, int64_t n);
+amh_status amh_nn_get_grads(amh_ctx *ctx, float *out, int64_t n);
+
+/* Forward pass over n inputs of h x w cells (h, w positive multiples of 8):
+ * feats (device, bf16 bit patterns, [n][h][w][16]) -> out (device, float,
+ * [n][h][w][5]: depth in [depth_min, depth_max], unit normal, confidence in
+ * (0, 1)); out may be NULL.  The input is copied and the activations are kept
+ * for amh_nn_backward. */
+amh_status amh_nn_forward(amh_ctx *ctx, const void *feats, int n, int h, int w, float *out);
+
+/* Loss of the last forward pass against target (device, float, [n][h][w][6]:
+ * depth, normal (3), confidence target, weight of the depth and normal terms):
+ * the mean over cells of weight * (|s - t| + 1 - n_hat . n_target) plus the
+ * binary cross-entropy of the confidence, with s and t the predicted and target
+ * depth mapped linearly from [depth_min, depth_max] to [0, 1].  Computes the
+ * gradient of every parameter; *loss (host, may be NULL) receives the loss,
+ * which synchronises the stream.  STATE without a forward pass. */
+amh_status amh_nn_backward(amh_ctx *ctx, const float *target, float *loss);
+
+/* One Adam step (Kingma & Ba, bias-corrected) with the last gradient. */
+amh_status amh_nn_adam_step(amh_ctx *ctx, float lr, float beta1, float beta2, float eps);
+
+/* Saves / loads the parameters: 8-byte magic "AMHNN001", int64 count, count
+ * little-endian floats in canonical order.  load creates the network if needed. */
+amh_status amh_nn_save(amh_ctx *ctx, const char *path);
+amh_status amh_nn_load(amh_ctx *ctx, const char *path);
+
+/* Network input of the current reference (amh_begin), one 16-channel vector per
+ * 4 x 4 cell: (mean of its 16 reference intensities - 127.5) / 64, their
+ * standard deviation / 32, and for 14 fronto-parallel planes at inverse depths
+ * 1/depth_max + (k + 1/2) (1/depth_min - 1/depth_max) / 14, one minus the mean
+ * of the k lowest matching costs (Eq. 8) at the cell's pixel (4j + 2, 4i + 2)
+ * over the first min(8, n_src) sources.  feats: device, bf16 bit patterns,
+ * [H/4][W/4][16].  UNSUPPORTED unless W and H are multiples of 32. */
+amh_status amh_sweep_features(amh_ctx *ctx, void *feats);
+
+/* Initialisation from per-cell predictions pred (device, float, [h][w][5] as
+ * amh_nn_forward writes them; cell size s = W/w = H/h, an integer): pixel
+ * (x, y) takes the plane through the point at the predicted depth on the ray
+ * of its cell's pixel (s j + s/2, s i + s/2) with the predicted normal, when
+ * the confidence is at least conf_min and that plane's depth along the pixel's
+ * ray lies in [depth_min, depth_max]; otherwise the random plane of
+ * amh_init_hypotheses.  Initial cost, S and v as there.  Replaces
+ * amh_init_hypotheses after amh_begin. */
+amh_status amh_init_from_proposal(amh_ctx *ctx, const float *pred, int h, int w);
+
+/* amh_begin + amh_sweep_features + amh_nn_forward + amh_init_from_proposal +
+ * iters x (red pass, black pass).  The network reads the first min(8, n_src)
+ * sources.  STATE if the network does not exist. */
+amh_status amh_run_proposal(amh_ctx *ctx, int ref, const int *srcs, int n_src, int iters);
 
 const char *amh_status_str(amh_status s);
 const char *amh_last_error(const amh_ctx *ctx);

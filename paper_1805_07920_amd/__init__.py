@@ -24,7 +24,12 @@ EXPORTS = [
     "amh_pass", "amh_run_checkerboard", "amh_get_depth_normal_cost", "amh_get_state", "amh_set_state",
     "amh_score_fixed", "amh_run_batch", "amh_get_job_result", "amh_get_job_times", "amh_tune", "amh_get_stats",
     "amh_status_str", "amh_last_error", "amh_destroy",
+    "amh_nn_param_count", "amh_nn_init", "amh_nn_get_params", "amh_nn_set_params", "amh_nn_get_grads",
+    "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
+    "amh_init_from_proposal", "amh_run_proposal",
 ]
+NET_CELL = 4  # reference pixels per proposal cell side
+NET_IN, NET_OUT = 16, 5
 N_TUNE_CONFIGS = 4  # tile order {XCD bands, hardware} x job order {given, largest first}
 
 
@@ -48,7 +53,7 @@ class amh_params(C.Structure):
     _fields_ = [("refine", C.c_int), ("include_self", C.c_int), ("depth_min", C.c_float), ("depth_max", C.c_float),
                 ("sigma_color", C.c_float), ("sigma_spatial", C.c_float), ("tau_mc_init", C.c_float),
                 ("alpha", C.c_float), ("beta", C.c_float), ("tau_up", C.c_float), ("n1", C.c_int), ("n2", C.c_int),
-                ("k", C.c_int), ("seed", C.c_uint64), ("timing", C.c_int)]
+                ("k", C.c_int), ("seed", C.c_uint64), ("timing", C.c_int), ("conf_min", C.c_float)]
 
 
 class amh_stats(C.Structure):
@@ -95,6 +100,19 @@ def lib():
         L.amh_last_error.restype = C.c_char_p
         L.amh_destroy.argtypes = [vp]
         L.amh_destroy.restype = None
+        L.amh_nn_param_count.argtypes = [C.POINTER(C.c_int64)]
+        L.amh_nn_init.argtypes = [vp, C.c_uint64]
+        L.amh_nn_get_params.argtypes = [vp, vp, C.c_int64]
+        L.amh_nn_set_params.argtypes = [vp, vp, C.c_int64]
+        L.amh_nn_get_grads.argtypes = [vp, vp, C.c_int64]
+        L.amh_nn_forward.argtypes = [vp, vp, ip, ip, ip, vp]
+        L.amh_nn_backward.argtypes = [vp, vp, C.POINTER(C.c_float)]
+        L.amh_nn_adam_step.argtypes = [vp, fp, fp, fp, fp]
+        L.amh_nn_save.argtypes = [vp, C.c_char_p]
+        L.amh_nn_load.argtypes = [vp, C.c_char_p]
+        L.amh_sweep_features.argtypes = [vp, vp]
+        L.amh_init_from_proposal.argtypes = [vp, vp, ip, ip]
+        L.amh_run_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
         _lib = L
     return _lib
 
@@ -319,3 +337,77 @@ class Context:
         return dict(evals_total=s.evals_total, evals_init=s.evals_init, evals_propagation=s.evals_propagation,
                     evals_refine=s.evals_refine, n_passes=s.n_passes,
                     ms_per_pass=list(s.ms_per_pass[:s.n_passes]), ms_init=s.ms_init)
+
+    # --- learned proposal ----------------------------------------------------------------
+    @staticmethod
+    def nn_param_count() -> int:
+        n = C.c_int64()
+        rc = lib().amh_nn_param_count(C.byref(n))
+        if rc != AMH_OK:
+            raise AmhError(rc, "amh_nn_param_count")
+        return int(n.value)
+
+    def nn_init(self, seed: int = 0):
+        self._check(self.L.amh_nn_init(self.h, int(seed)), "amh_nn_init")
+
+    def nn_get_params(self) -> np.ndarray:
+        out = np.zeros(self.nn_param_count(), np.float32)
+        self._check(self.L.amh_nn_get_params(self.h, out.ctypes.data, out.size), "amh_nn_get_params")
+        return out
+
+    def nn_set_params(self, theta):
+        theta = np.ascontiguousarray(theta, np.float32)
+        self._check(self.L.amh_nn_set_params(self.h, theta.ctypes.data, theta.size), "amh_nn_set_params")
+
+    def nn_get_grads(self) -> np.ndarray:
+        out = np.zeros(self.nn_param_count(), np.float32)
+        self._check(self.L.amh_nn_get_grads(self.h, out.ctypes.data, out.size), "amh_nn_get_grads")
+        return out
+
+    def nn_forward(self, feats, out=None):
+        """feats: device tensor (n, h, w, 16) of bfloat16; returns device (n, h, w, 5) float32."""
+        import torch
+
+        if feats.dtype != torch.bfloat16 or not feats.is_cuda or feats.dim() != 4 or feats.shape[3] != NET_IN:
+            raise ValueError("feats must be a device bfloat16 tensor (n, h, w, 16)")
+        n, h, w, _ = feats.shape
+        if out is None:
+            out = torch.empty((n, h, w, NET_OUT), dtype=torch.float32, device=feats.device)
+        self._check(self.L.amh_nn_forward(self.h, _ptr(feats)[0], n, h, w, _ptr(out)[0]), "amh_nn_forward")
+        return out
+
+    def nn_backward(self, target, want_loss: bool = True):
+        """target: device float32 tensor (n, h, w, 6); returns the loss (host float) or None."""
+        loss = C.c_float(0.0)
+        self._check(self.L.amh_nn_backward(self.h, _ptr(target)[0], C.byref(loss) if want_loss else None),
+                    "amh_nn_backward")
+        return float(loss.value) if want_loss else None
+
+    def nn_adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._check(self.L.amh_nn_adam_step(self.h, lr, beta1, beta2, eps), "amh_nn_adam_step")
+
+    def nn_save(self, path: str):
+        self._check(self.L.amh_nn_save(self.h, os.fsencode(path)), "amh_nn_save")
+
+    def nn_load(self, path: str):
+        self._check(self.L.amh_nn_load(self.h, os.fsencode(path)), "amh_nn_load")
+
+    def sweep_features(self, out=None):
+        """Network input of the current reference: device bfloat16 (H/4, W/4, 16)."""
+        import torch
+
+        if out is None:
+            out = torch.empty((self.H // NET_CELL, self.W // NET_CELL, NET_IN), dtype=torch.bfloat16, device="cuda")
+        self._check(self.L.amh_sweep_features(self.h, _ptr(out)[0]), "amh_sweep_features")
+        return out
+
+    def init_from_proposal(self, pred):
+        """pred: device float32 (h, w, 5) per-cell depth, normal, confidence."""
+        h, w = int(pred.shape[0]), int(pred.shape[1])
+        self._check(self.L.amh_init_from_proposal(self.h, _ptr(pred)[0], h, w), "amh_init_from_proposal")
+
+    def run_proposal(self, ref: int, srcs, iters: int):
+        s = (C.c_int * len(srcs))(*[int(v) for v in srcs])
+        self._check(self.L.amh_run_proposal(self.h, ref, s, len(srcs), iters), "amh_run_proposal")
+        self.H, self.W = self._views_shape[ref]
+        self.n_src = len(srcs)

@@ -13,82 +13,14 @@
 #include <string>
 #include <vector>
 
-#include "amh_internal.h"
-#include "amhmvs.h"
+#include "amh_ctx.h"
 
 using namespace amh;
 
-namespace {
+namespace amh {
 
-struct View {
-    int W = 0, H = 0;
-    float *img = nullptr;   // float32 copy (reference use)
-    void *quads = nullptr;  // gather layout (source use)
-    int half = 0;
-    double K[9], R[9], t[3];
-};
+static int g_alloc_count = 0;
 
-struct JobResult {
-    int W = 0, H = 0;
-    RefDev ref{};
-    float4 *planes = nullptr;
-    float *cost = nullptr;
-    uint32_t *S = nullptr;
-    int32_t *v = nullptr;
-};
-
-}  // namespace
-
-struct amh_ctx {
-    amh_params p;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    std::string err;
-    int half = 0;
-    std::vector<View> views;
-    // current reference
-    int ref = -1;
-    std::vector<int> srcs;
-    std::vector<ViewDev> h_viewc;
-    ViewDev *d_viewc = nullptr;
-    size_t viewc_cap = 0;
-    RefDev refdev{};
-    float4 *planes = nullptr;
-    float *cost = nullptr;
-    uint32_t *S = nullptr;
-    int32_t *v = nullptr;
-    size_t state_cap = 0;
-    bool have_state = false;
-    unsigned long long *counters = nullptr;
-    // timing
-    std::vector<hipEvent_t> ev;  // pairs: [2i] start, [2i+1] stop
-    int n_timed = 0;
-    hipEvent_t ev_init[2] = {nullptr, nullptr};
-    bool init_timed = false;
-    // launch configuration (autotuned): tile order of a launch, job order of a batch
-    int cfg_order = 0;
-    int cfg_job_order = 1;
-    // batch: per-job state, device tables and the captured graph of the last job list
-    std::vector<JobResult> jobs;
-    std::vector<int> batch_key;       // serialized job list of the captured graph
-    hipStream_t cap_stream = nullptr;  // private stream for graph capture
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    BatchJobDev *d_jobs = nullptr;
-    ViewDev *d_bviews = nullptr;
-    int *d_tables = nullptr;
-    unsigned long long *d_bcount = nullptr;  // [3 * kCounterSlots] evals, [n_jobs] tiles done, [n_jobs + 1] clocks
-    int batch_jobs = 0;
-    bool batch_ran = false;
-    bool batch_stats = false;
-    unsigned long long batch_counts[3] = {0, 0, 0};
-};
-
-namespace {
-
-int g_alloc_count = 0;
-
-amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) {
     if (c) {
         char buf[512];
@@ -101,13 +33,6 @@ amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) {
     return s;
 }
 
-#define HIPCHK(c, expr)                                                                          \
-    do {                                                                                         \
-        hipError_t e_ = (expr);                                                                  \
-        if (e_ != hipSuccess) return fail((c), AMH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-// device allocation with an optional injected failure (AMH_FAIL_ALLOC_AT=n fails the n-th call, 1-based)
 amh_status dalloc(amh_ctx *c, void **ptr, size_t bytes) {
     ++g_alloc_count;
     const char *inj = getenv("AMH_FAIL_ALLOC_AT");
@@ -118,6 +43,10 @@ amh_status dalloc(amh_ctx *c, void **ptr, size_t bytes) {
     if (e != hipSuccess) return fail(c, AMH_E_HIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     return AMH_OK;
 }
+
+}  // namespace amh
+
+namespace {
 
 bool finite_all(const double *a, int n) {
     for (int i = 0; i < n; ++i)
@@ -139,6 +68,7 @@ amh_status check_params(amh_ctx *c, const amh_params *p) {
     if ((p->refine != 0 && p->refine != 1) || (p->include_self != 0 && p->include_self != 1) ||
         (p->timing != 0 && p->timing != 1))
         return fail(c, AMH_E_INVALID_ARG, "refine, include_self and timing are 0 or 1");
+    if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(c, AMH_E_INVALID_ARG, "conf_min must be in [0, 1]");
     return AMH_OK;
 }
 
@@ -242,6 +172,30 @@ PassArgs pass_args(amh_ctx *c, int t, int colour) {
     a.counters = c->counters;
     a.order = c->cfg_order;
     return a;
+}
+
+// initialisation of both colours: random planes, or per-cell predictions where usable
+amh_status init_state(amh_ctx *c, const float *pred, int pred_w, int cell) {
+    const int half = c->half;
+    if (c->p.timing) {
+        for (int i = 0; i < 2; ++i)
+            if (!c->ev_init[i]) HIPCHK(c, hipEventCreate(&c->ev_init[i]));
+        HIPCHK(c, hipEventRecord(c->ev_init[0], c->stream));
+    }
+    for (int colour = 0; colour < 2; ++colour) {
+        PassArgs a = pass_args(c, 0, colour);
+        a.prop = pred;
+        a.prop_w = pred_w;
+        a.prop_s = cell;
+        a.conf_min = c->p.conf_min;
+        HIPCHK(c, launch_init(a, half, c->stream));
+    }
+    if (c->p.timing) {
+        HIPCHK(c, hipEventRecord(c->ev_init[1], c->stream));
+        c->init_timed = true;
+    }
+    c->have_state = true;
+    return AMH_OK;
 }
 
 amh_status ensure_events(amh_ctx *c, int n) {
@@ -496,6 +450,7 @@ amh_status amh_params_default(amh_params *out) {
     out->k = 4;
     out->seed = 0;
     out->timing = 0;
+    out->conf_min = 0.5f;
     return AMH_OK;
 }
 
@@ -703,22 +658,7 @@ amh_status amh_begin(amh_ctx *c, int ref, const int *srcs, int n_src) {
 amh_status amh_init_hypotheses(amh_ctx *c) {
     if (!c) return AMH_E_INVALID_ARG;
     if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
-    const int half = c->half;
-    if (c->p.timing) {
-        for (int i = 0; i < 2; ++i)
-            if (!c->ev_init[i]) HIPCHK(c, hipEventCreate(&c->ev_init[i]));
-        HIPCHK(c, hipEventRecord(c->ev_init[0], c->stream));
-    }
-    for (int colour = 0; colour < 2; ++colour) {
-        PassArgs a = pass_args(c, 0, colour);
-        HIPCHK(c, launch_init(a, half, c->stream));
-    }
-    if (c->p.timing) {
-        HIPCHK(c, hipEventRecord(c->ev_init[1], c->stream));
-        c->init_timed = true;
-    }
-    c->have_state = true;
-    return AMH_OK;
+    return init_state(c, nullptr, 0, 0);
 }
 
 amh_status amh_pass(amh_ctx *c, int t, int colour) {
@@ -982,6 +922,68 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
     return AMH_OK;
 }
 
+amh_status amh_sweep_features(amh_ctx *c, void *feats) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (!feats) return fail(c, AMH_E_INVALID_ARG, "feats is NULL");
+    if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
+    const int W = c->refdev.W, H = c->refdev.H;
+    if (W % 32 || H % 32)
+        return fail(c, AMH_E_UNSUPPORTED, "the proposal needs width and height multiples of 32 (got %dx%d)", W, H);
+    SweepArgs a;
+    a.ref = c->refdev;
+    a.views = c->d_viewc;
+    a.n_net = std::min(kNetSrc, (int)c->srcs.size());
+    a.m = method_dev(c->p, 0);
+    a.h4 = H / kCell;
+    a.w4 = W / kCell;
+    const double qf = 1.0 / (double)c->p.depth_max, qn = 1.0 / (double)c->p.depth_min;
+    for (int d = 0; d < kSweepDepths; ++d) a.depth[d] = (float)(1.0 / (qf + (d + 0.5) * (qn - qf) / kSweepDepths));
+    a.feats = static_cast<unsigned short *>(feats);
+    a.counters = c->counters;
+    HIPCHK(c, launch_sweep(a, c->half, c->stream));
+    return AMH_OK;
+}
+
+amh_status amh_init_from_proposal(amh_ctx *c, const float *pred, int h, int w) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (!pred || h < 1 || w < 1) return fail(c, AMH_E_INVALID_ARG, "need pred and a positive cell grid");
+    if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
+    const int W = c->refdev.W, H = c->refdev.H;
+    if (W % w || H % h || W / w != H / h)
+        return fail(c, AMH_E_INVALID_ARG, "a %dx%d cell grid does not tile a %dx%d image with square cells", w, h, W, H);
+    return init_state(c, pred, w, W / w);
+}
+
+amh_status amh_run_proposal(amh_ctx *c, int ref, const int *srcs, int n_src, int iters) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (iters < 0 || iters > 1000) return fail(c, AMH_E_INVALID_ARG, "iters must be in 0..1000");
+    if (!c->net) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
+    amh_status st = amh_begin(c, ref, srcs, n_src);
+    if (st != AMH_OK) return st;
+    const int W = c->refdev.W, H = c->refdev.H;
+    if (W % 32 || H % 32)
+        return fail(c, AMH_E_UNSUPPORTED, "the proposal needs width and height multiples of 32 (got %dx%d)", W, H);
+    const int h4 = H / kCell, w4 = W / kCell;
+    const size_t cells = (size_t)h4 * w4;
+    if (cells > c->prop_cap) {
+        if (c->prop_feats) (void)hipFree(c->prop_feats);
+        if (c->prop_pred) (void)hipFree(c->prop_pred);
+        c->prop_feats = nullptr;
+        c->prop_pred = nullptr;
+        c->prop_cap = 0;
+        if ((st = dalloc(c, &c->prop_feats, cells * 16 * 2)) != AMH_OK) return st;
+        if ((st = dalloc(c, (void **)&c->prop_pred, cells * 5 * sizeof(float))) != AMH_OK) return st;
+        c->prop_cap = cells;
+    }
+    if ((st = amh_sweep_features(c, c->prop_feats)) != AMH_OK) return st;
+    if ((st = amh_nn_forward(c, c->prop_feats, 1, h4, w4, c->prop_pred)) != AMH_OK) return st;
+    if ((st = amh_init_from_proposal(c, c->prop_pred, h4, w4)) != AMH_OK) return st;
+    for (int t = 0; t < iters; ++t)
+        for (int colour = 0; colour < 2; ++colour)
+            if ((st = amh_pass(c, t, colour)) != AMH_OK) return st;
+    return AMH_OK;
+}
+
 amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
     amh_ctx *c = const_cast<amh_ctx *>(cc);
     if (!c || !out) return AMH_E_INVALID_ARG;
@@ -1026,6 +1028,7 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
 void amh_destroy(amh_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    free_net(c);
     for (auto &v : c->views) free_view(v);
     for (auto &j : c->jobs) free_job(j);
     free_batch(c);
@@ -1036,6 +1039,8 @@ void amh_destroy(amh_ctx *c) {
     if (c->S) (void)hipFree(c->S);
     if (c->v) (void)hipFree(c->v);
     if (c->counters) (void)hipFree(c->counters);
+    if (c->prop_feats) (void)hipFree(c->prop_feats);
+    if (c->prop_pred) (void)hipFree(c->prop_pred);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     for (auto e : c->ev_init)
         if (e) (void)hipEventDestroy(e);

@@ -57,6 +57,10 @@ struct PassArgs {
     int tiles_x, n_tiles;        // tile grid of this colour
     unsigned long long *counters;  // [3][kCounterSlots]: init, propagation, refinement evals
     int order;                   // tile order: 0 XCD bands, 1 hardware order
+    // initialisation from per-cell predictions (NULL: random initialisation)
+    const float *prop = nullptr;  // [prop_h][prop_w][5]: depth, normal (3), confidence
+    int prop_w = 0, prop_s = 0;   // cell grid width, cell size in reference pixels
+    float conf_min = 0.5f;
 };
 
 // one reference image of a batch
@@ -85,6 +89,22 @@ struct BatchPhaseArgs {
     unsigned long long *job_end; // [n_jobs] device clock at the job's completion
 };
 
+constexpr int kSweepDepths = 14;  // fronto-parallel planes of the proposal's input sweep
+constexpr int kNetSrc = 8;        // sources the proposal network reads
+constexpr int kCell = 4;          // reference pixels per feature cell side
+
+// plane-sweep input of the proposal network: one 16-channel bf16 vector per 4x4 cell
+struct SweepArgs {
+    RefDev ref;
+    const ViewDev *views;
+    int n_net;                   // sources used (first min(8, n_src))
+    MethodDev m;
+    int h4, w4;                  // cell grid
+    float depth[kSweepDepths];   // plane depths
+    unsigned short *feats;       // [h4 * w4][16] bf16
+    unsigned long long *counters;
+};
+
 struct ScoreArgs {
     RefDev ref;
     const ViewDev *views;
@@ -108,6 +128,7 @@ hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, f
                           hipStream_t s);
 hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *p, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs &a, int half, hipStream_t s);
 size_t pass_lds_bytes(int n_src);
 
 }  // namespace amh

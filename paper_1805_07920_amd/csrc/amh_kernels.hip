@@ -14,6 +14,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include "amh_bf16.h"
 #include "amh_internal.h"
 
 // Minimum waves per SIMD the pass kernels are compiled for (a register budget
@@ -494,8 +495,44 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 }
 
 // ---------------------------------------------------------------------------
-// Random initialisation (PatchMatch random planes; initial cost = mean of the
-// k lowest per-view costs).  Same tile mapping as the pass, one launch per
+// Plane of pixel (x, y) from the per-cell prediction of its cell: through the
+// point at the predicted depth on the ray of the cell's sample pixel, with the
+// predicted normal turned to face the pixel's ray.  False (keep the random
+// plane) when the confidence is below conf_min, the normal is zero or not
+// finite, or the plane's depth along the pixel's ray leaves [d_min, d_max].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int x, int y, float4 &pl) {
+    const int s = a.prop_s;
+    const int i = y / s, j = x / s;
+    const float *pp = a.prop + ((size_t)i * a.prop_w + j) * 5;
+    const float depth = pp[0], conf = pp[4];
+    float nx = pp[1], ny = pp[2], nz = pp[3];
+    const float nn = __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
+    if (!(conf >= a.conf_min) || !(nn > 0.f) || !__builtin_isfinite(nn) || !__builtin_isfinite(depth)) return false;
+    nx /= nn;
+    ny /= nn;
+    nz /= nn;
+    const float2 rc = ref_ray(a.ref, s * j + s / 2, s * i + s / 2);
+    float dp = -depth * (nx * rc.x + ny * rc.y + nz);
+    float nr = nx * r.x + ny * r.y + nz;
+    if (nr > 0.f) {
+        nx = -nx;
+        ny = -ny;
+        nz = -nz;
+        dp = -dp;
+        nr = -nr;
+    }
+    if (!(nr < 0.f)) return false;
+    const float d = -dp / nr;
+    if (!(d >= a.m.d_min && d <= a.m.d_max)) return false;
+    pl = make_float4(nx, ny, nz, dp);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: a random plane per pixel (PatchMatch random init), or the
+// proposal's plane where one is given and usable; initial cost = mean of the k
+// lowest per-view costs.  Same tile mapping as the pass, one launch per
 // colour.  Lane r of a pixel scores views r, r+9, r+18, r+27.
 // ---------------------------------------------------------------------------
 template <int HALF>
@@ -524,12 +561,14 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
     float *mcol = S.ms + wave * N * 64;  // m of view j for group g at mcol[j * 64 + g * 9]
     int n_eval = 0;
     if (pix_ok) {
-        float u[4], nx, ny, nz;
-        philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
         const float2 r = ref_ray(a.ref, x, y);
-        const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
-        normal_from_uniforms(u[1], u[2], nx, ny, nz);
-        pl = plane_from(r, depth, nx, ny, nz);
+        if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
+            float u[4], nx, ny, nz;
+            philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
+            const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
+            normal_from_uniforms(u[1], u[2], nx, ny, nz);
+            pl = plane_from(r, depth, nx, ny, nz);
+        }
         const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
         for (int j = row; j < N; j += kRows) {
             const float c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
@@ -921,6 +960,82 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Plane-sweep input of the proposal network.  A workgroup of 64 lanes takes 8
+// cells x 8 sources: each lane builds the window of its cell's sample pixel
+// (4j + 2, 4i + 2) and scores the 14 fronto-parallel planes on its source;
+// then each cell's channels are written: normalised mean and deviation of its
+// 4 x 4 reference pixels, and 1 - (mean of the k lowest costs over the
+// sources) per plane, the aggregate of random initialisation's initial cost.
+// ---------------------------------------------------------------------------
+template <int HALF>
+__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
+    __shared__ __align__(16) float2 rwbuf[64 * kWinStride];
+    __shared__ float cst[8][kSweepDepths][kNetSrc];
+    const int lane = threadIdx.x, cl = lane >> 3, j = lane & 7;
+    const int n_cells = a.h4 * a.w4;
+    const int cell = blockIdx.x * 8 + cl;
+    const bool ok = cell < n_cells && j < a.n_net;
+    if (ok) {
+        const int ci = cell / a.w4, cj = cell - ci * a.w4;
+        const int x = kCell * cj + kCell / 2, y = kCell * ci + kCell / 2;
+        float2 *rw = rwbuf + lane * kWinStride;
+        GlobalReader rd{&a.ref, x, y};
+        const WinStats ws = build_window(rd, a.m, rw, 0, 1);
+        for (int d = 0; d < kSweepDepths; ++d) {
+            const PlaneQ q = plane_q(a.ref, a.m, make_float4(0.f, 0.f, -1.f, a.depth[d]), x, y);
+            cst[cl][d][j] = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+        }
+    }
+    count_evals(a.counters, 0, ok ? (unsigned long long)kSweepDepths : 0ull);
+    __syncthreads();
+    for (int o = lane; o < 8 * 16; o += 64) {
+        const int c2 = o >> 4, ch = o & 15;
+        const int cell2 = blockIdx.x * 8 + c2;
+        if (cell2 >= n_cells) continue;
+        float val;
+        if (ch >= 2) {
+            const int d = ch - 2, n = a.n_net, kk = a.m.k < n ? a.m.k : n;
+            uint32_t taken = 0;
+            float sum = 0.f;
+            for (int r = 0; r < kk; ++r) {
+                int best = -1;
+                float bc = 0.f;
+                for (int jj = 0; jj < n; ++jj) {
+                    if ((taken >> jj) & 1u) continue;
+                    const float c = cst[c2][d][jj];
+                    if (best < 0 || c < bc) {
+                        best = jj;
+                        bc = c;
+                    }
+                }
+                taken |= 1u << best;
+                sum += bc;
+            }
+            val = 1.f - sum / (float)kk;
+        } else {
+            const int ci = cell2 / a.w4, cj = cell2 - ci * a.w4;
+            const float *img = a.ref.img + (size_t)(kCell * ci) * a.ref.W + kCell * cj;
+            float mu = 0.f;
+            for (int yy = 0; yy < kCell; ++yy)
+                for (int xx = 0; xx < kCell; ++xx) mu += img[(size_t)yy * a.ref.W + xx];
+            mu *= 1.f / (kCell * kCell);
+            if (ch == 0) {
+                val = (mu - 127.5f) * (1.f / 64.f);
+            } else {
+                float var = 0.f;
+                for (int yy = 0; yy < kCell; ++yy)
+                    for (int xx = 0; xx < kCell; ++xx) {
+                        const float dlt = img[(size_t)yy * a.ref.W + xx] - mu;
+                        var = fmaf(dlt, dlt, var);
+                    }
+                val = __builtin_sqrtf(var * (1.f / (kCell * kCell))) * (1.f / 32.f);
+            }
+        }
+        a.feats[(size_t)cell2 * 16 + ch] = f2bf(val);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Layout kernels
 // ---------------------------------------------------------------------------
 __global__ void convert_kernel(const void *src, int dtype, int64_t pitch, int W, int H, float *dst) {
@@ -1029,6 +1144,15 @@ hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStrea
 
 hipError_t launch_stamp(unsigned long long *p, hipStream_t s) {
     AMH_LAUNCH(stamp_kernel, dim3(1), dim3(64), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepArgs &a, int half, hipStream_t s) {
+    const int n_cells = a.h4 * a.w4;
+    if (n_cells == 0) return hipSuccess;
+    dim3 grid((n_cells + 7) / 8);
+    if (half) AMH_LAUNCH(sweep_kernel<1>, grid, dim3(64), 0, s, a);
+    else AMH_LAUNCH(sweep_kernel<0>, grid, dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,142 @@
+"""Trains the learned proposal on the GPU with the library's own kernels.
+
+Data: seeded 640x480 scenes with 8 sources (scene seeds 1000 onwards).  For each
+scene the plain method (random initialisation, 3 iterations with refinement)
+produces the labels: at the pixel (4j + 2, 4i + 2) of every 4 x 4 cell its
+depth, normal and final cost m; the confidence target is C(m) =
+exp(-m^2 / (2 beta^2)) of Eq. 3, which also weights the depth and normal terms,
+so cells the plain method did not resolve count little.  The network input is
+the library's plane-sweep features of the same scene.  Training: Adam with a
+cosine-decayed learning rate over shuffled mini-batches; forward, loss,
+backward and the update all run in the library (amh_nn_*).
+
+    python -m paper_1805_07920_amd.train_proposal --scenes 2000 --out paper_1805_07920_amd/weights/proposal.bin
+
+Prints one line per 100 scenes and per epoch.  Needs a GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import paper_1805_07920_amd as amh  # noqa: E402
+import scenegen  # noqa: E402
+
+DEFAULT_OUT = os.path.join(HERE, "weights", "proposal.bin")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def scene_views(ctx, sc):
+    ctx.init_views([torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in sc.images], sc.cams)
+
+
+def labels_of(depth, normal, cost, beta: float):
+    """(h, w, 6) targets at the cell pixels (4j + 2, 4i + 2) of device maps."""
+    c = amh.NET_CELL
+    d = depth[c // 2::c, c // 2::c]
+    n = normal[c // 2::c, c // 2::c]
+    m = cost[c // 2::c, c // 2::c]
+    conf = torch.exp(-m * m / (2.0 * beta * beta))
+    return torch.cat([d[..., None], n, conf[..., None], conf[..., None]], -1).contiguous()
+
+
+def make_dataset(ctx, seeds, iters: int = 3, n_src: int = 8):
+    feats, targets = [], []
+    t0 = time.time()
+    srcs = list(range(1, n_src + 1))
+    for k, seed in enumerate(seeds):
+        sc = scenegen.config_scene("c5", seed, device="cuda", n_src=n_src)
+        scene_views(ctx, sc)
+        ctx.run_checkerboard(0, srcs, iters)
+        H, W = sc.height, sc.width
+        depth = torch.empty((H, W), device="cuda")
+        normal = torch.empty((H, W, 3), device="cuda")
+        cost = torch.empty((H, W), device="cuda")
+        ctx.get_depth_normal_cost(depth, normal, cost)
+        targets.append(labels_of(depth, normal, cost, ctx.p.beta))
+        feats.append(ctx.sweep_features().clone())
+        if (k + 1) % 100 == 0 or k + 1 == len(seeds):
+            torch.cuda.synchronize()
+            log(f"data: {k + 1}/{len(seeds)} scenes, {time.time() - t0:.1f} s")
+    return torch.stack(feats), torch.stack(targets)
+
+
+def train(ctx, feats, targets, epochs: int, batch: int, lr: float, seed: int):
+    S = feats.shape[0]
+    steps_per_epoch = S // batch
+    total = epochs * steps_per_epoch
+    rng = np.random.default_rng(seed)
+    history = []
+    step = 0
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(S)).cuda()
+        losses = []
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            x = feats.index_select(0, idx).contiguous()
+            t = targets.index_select(0, idx).contiguous()
+            ctx.nn_forward(x)
+            want = b % 20 == 0
+            loss = ctx.nn_backward(t, want_loss=want)
+            if want:
+                losses.append(loss)
+            lr_t = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * step / max(total, 1))))
+            ctx.nn_adam_step(lr_t)
+            step += 1
+        torch.cuda.synchronize()
+        history.append(float(np.mean(losses)))
+        log(f"epoch {ep + 1}/{epochs}: loss {history[-1]:.4f}, {time.time() - t0:.1f} s")
+    return history
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--scenes", type=int, default=2000)
+    ap.add_argument("--seed0", type=int, default=1000)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--report", default=None, help="JSON file for the loss history")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        raise SystemExit("training runs on the GPU")
+    torch.cuda.init()
+    ctx = amh.Context(seed=args.init_seed)
+    t0 = time.time()
+    feats, targets = make_dataset(ctx, range(args.seed0, args.seed0 + args.scenes))
+    t_data = time.time() - t0
+    ctx.nn_init(args.init_seed)
+    t1 = time.time()
+    hist = train(ctx, feats, targets, args.epochs, args.batch, args.lr, args.init_seed)
+    t_train = time.time() - t1
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    ctx.nn_save(args.out)
+    rep = dict(scenes=args.scenes, seed0=args.seed0, epochs=args.epochs, batch=args.batch, lr=args.lr,
+               loss_per_epoch=hist, data_seconds=t_data, train_seconds=t_train, out=os.path.relpath(args.out, ROOT))
+    log(json.dumps(rep))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(rep, f, indent=1)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -174,15 +174,18 @@ def _hash32(x: torch.Tensor) -> torch.Tensor:
     return x
 
 
-def _lattice_value(seed: int, pid: int, i: torch.Tensor, j: torch.Tensor) -> torch.Tensor:
-    salt = int(_hash32(torch.tensor((seed * 0x27D4EB2F + pid * 0x165667B1) & _M32)).item())
+def _salt(seed: int, pid: int) -> int:
+    return int(_hash32(torch.tensor((seed * 0x27D4EB2F + pid * 0x165667B1) & _M32)).item())
+
+
+def _lattice_value(salt: torch.Tensor, i: torch.Tensor, j: torch.Tensor) -> torch.Tensor:
     h = _hash32(i ^ salt)
     h = _hash32(h ^ (j & _M32))
     h = _hash32(h + 0x5BD1E995)
     return h.to(torch.float64) * (255.0 / 4294967295.0)
 
 
-def _texture(seed: int, pid: int, u: torch.Tensor, v: torch.Tensor, spacing: float) -> torch.Tensor:
+def _texture(salt: torch.Tensor, u: torch.Tensor, v: torch.Tensor, spacing: float) -> torch.Tensor:
     su = u / spacing
     sv = v / spacing
     fi = torch.floor(su)
@@ -191,10 +194,10 @@ def _texture(seed: int, pid: int, u: torch.Tensor, v: torch.Tensor, spacing: flo
     fv = sv - fj
     i = fi.to(torch.int64) + (1 << 30)
     j = fj.to(torch.int64) + (1 << 30)
-    v00 = _lattice_value(seed, pid, i, j)
-    v10 = _lattice_value(seed, pid, i + 1, j)
-    v01 = _lattice_value(seed, pid, i, j + 1)
-    v11 = _lattice_value(seed, pid, i + 1, j + 1)
+    v00 = _lattice_value(salt, i, j)
+    v10 = _lattice_value(salt, i + 1, j)
+    v01 = _lattice_value(salt, i, j + 1)
+    v11 = _lattice_value(salt, i + 1, j + 1)
     return (v00 * (1 - fu) + v10 * fu) * (1 - fv) + (v01 * (1 - fu) + v11 * fu) * fv
 
 
@@ -202,71 +205,97 @@ def _texture(seed: int, pid: int, u: torch.Tensor, v: torch.Tensor, spacing: flo
 # ray casting
 # --------------------------------------------------------------------------------------
 
-def _cast(cam: Camera, planes: list, xs: torch.Tensor, ys: torch.Tensor, seed: int, spacing: float):
-    """Intersect camera rays through pixel coords (xs, ys) with the world.
+def _cast(cams: list, planes: list, xs: torch.Tensor, ys: torch.Tensor, ci: torch.Tensor, seed: int,
+          spacing: float):
+    """Intersect the rays through pixel coords (xs, ys) of cameras cams[ci] with the world (flat tensors).
 
     Returns (intensity, camera z-depth, plane id) tensors shaped like xs.  Element-wise arithmetic on
-    the three coordinates (no small matrix products)."""
+    the three coordinates (no small matrix products); per-camera and per-plane constants are gathered
+    per ray, so one call covers every camera and every plane."""
     dev = xs.device
-    Ki = np.linalg.inv(cam.K)
-    R = cam.R
-    C = cam.center
+    nc = len(cams)
+
+    def per_cam(vals):
+        return torch.tensor(vals, dtype=torch.float64, device=dev)[ci]
+
+    Kis = [np.linalg.inv(c.K) for c in cams]
+    Cs = [c.center for c in cams]
     # camera-frame ray with z = 1, then its world direction R^T r (the hit distance is the camera z)
-    rx = Ki[0, 0] * xs + Ki[0, 1] * ys + Ki[0, 2]
-    ry = Ki[1, 1] * ys + Ki[1, 2]
-    dw = [R[0, i] * rx + R[1, i] * ry + R[2, i] for i in range(3)]
+    rx = per_cam([K[0, 0] for K in Kis]) * xs + per_cam([K[0, 1] for K in Kis]) * ys + per_cam([K[0, 2] for K in Kis])
+    ry = per_cam([K[1, 1] for K in Kis]) * ys + per_cam([K[1, 2] for K in Kis])
+    dw = [per_cam([c.R[0, i] for c in cams]) * rx + per_cam([c.R[1, i] for c in cams]) * ry
+          + per_cam([c.R[2, i] for c in cams]) for i in range(3)]
+    del rx, ry
     best_t = torch.full_like(xs, math.inf)
     best_id = torch.full(xs.shape, -1, dtype=torch.int64, device=dev)
     for pid, pl in enumerate(planes):
         den = pl.n[0] * dw[0] + pl.n[1] * dw[1] + pl.n[2] * dw[2]
-        num = -(float(pl.n @ C) + pl.o)
+        num = per_cam([-(float(pl.n @ C) + pl.o) for C in Cs])
         tt = num / den
         ok = (tt > 1e-6) & (tt < best_t)
         if math.isfinite(pl.hu):
-            d = [C[i] - pl.p0[i] + tt * dw[i] for i in range(3)]
+            d = [per_cam([C[i] - pl.p0[i] for C in Cs]) + tt * dw[i] for i in range(3)]
             u = pl.e1[0] * d[0] + pl.e1[1] * d[1] + pl.e1[2] * d[2]
             v = pl.e2[0] * d[0] + pl.e2[1] * d[1] + pl.e2[2] * d[2]
             ok = ok & (u.abs() <= pl.hu) & (v.abs() <= pl.hv)
         best_t = torch.where(ok, tt, best_t)
         best_id = torch.where(ok, torch.full_like(best_id, pid), best_id)
     tcl = best_t.clamp(max=1e6)
-    inten = torch.zeros_like(xs)
-    for pid, pl in enumerate(planes):
-        m = best_id == pid
-        if not bool(m.any()):
-            continue
-        tm = tcl[m]
-        d = [C[i] - pl.p0[i] + tm * dw[i][m] for i in range(3)]
-        u = pl.e1[0] * d[0] + pl.e1[1] * d[1] + pl.e1[2] * d[2]
-        v = pl.e2[0] * d[0] + pl.e2[1] * d[1] + pl.e2[2] * d[2]
-        if pl.const >= 0:
-            val = torch.full_like(u, pl.const)
-        else:
-            val = _texture(seed, pid, u, v, spacing)
-        inten[m] = val
+    # texture of the plane each ray hit, with that plane's constants gathered per ray
+    hit = best_id.clamp(min=0)
+    slot = hit * nc + ci
+
+    def per_plane(vals):
+        return torch.tensor(vals, dtype=torch.float64, device=dev)[hit]
+
+    d = [torch.tensor([C[i] - pl.p0[i] for pl in planes for C in Cs], dtype=torch.float64, device=dev)[slot]
+         + tcl * dw[i] for i in range(3)]
+    u = per_plane([pl.e1[0] for pl in planes]) * d[0] + per_plane([pl.e1[1] for pl in planes]) * d[1] \
+        + per_plane([pl.e1[2] for pl in planes]) * d[2]
+    v = per_plane([pl.e2[0] for pl in planes]) * d[0] + per_plane([pl.e2[1] for pl in planes]) * d[1] \
+        + per_plane([pl.e2[2] for pl in planes]) * d[2]
+    del d
+    salt = torch.tensor([_salt(seed, pid) for pid in range(len(planes))], dtype=torch.int64, device=dev)[hit]
+    const = per_plane([pl.const for pl in planes])
+    val = torch.where(const >= 0, const, _texture(salt, u, v, spacing))
+    inten = torch.where(best_id >= 0, val, torch.zeros_like(val))
     return inten, best_t, best_id
 
 
-def _render(cam: Camera, planes: list, seed: int, spacing: float, ss: int, device) -> tuple:
-    """Render a camera with ss x ss supersampling. Returns (image, depth at pixel centres, id at centres)."""
-    W, H = cam.width, cam.height
-    img = torch.zeros((H, W), dtype=torch.float64, device=device)
+def _render(cams: list, planes: list, seed: int, spacing: float, ss: int, device) -> list:
+    """Render every camera (same size) with ss x ss supersampling.
+    Returns [(image, depth at pixel centres, id at centres)] per camera."""
+    W, H = cams[0].width, cams[0].height
+    nc = len(cams)
+    imgs = [torch.zeros((H, W), dtype=torch.float64, device=device) for _ in cams]
+    depths = [torch.zeros((H, W), dtype=torch.float64, device=device) for _ in cams]
+    ids = [torch.zeros((H, W), dtype=torch.int64, device=device) for _ in cams]
     xs0 = torch.arange(W, dtype=torch.float64, device=device)
-    rows_per_chunk = max(1, (1 << 21) // max(1, W * ss * ss))
     offs = [(k + 0.5) / ss - 0.5 for k in range(ss)]
+    grid = [(oy, ox) for oy in offs for ox in offs] + [(0.0, 0.0)]  # samples, then the pixel centre
+    ng = len(grid)
+    rows_per_chunk = max(1, (1 << 23) // max(1, W * ng * nc))
     for y0 in range(0, H, rows_per_chunk):
         y1 = min(H, y0 + rows_per_chunk)
         ys0 = torch.arange(y0, y1, dtype=torch.float64, device=device)
-        acc = torch.zeros((y1 - y0, W), dtype=torch.float64, device=device)
-        for oy in offs:
-            for ox in offs:
-                ys, xs = torch.meshgrid(ys0 + oy, xs0 + ox, indexing="ij")
-                val, _, _ = _cast(cam, planes, xs, ys, seed, spacing)
-                acc += val
-        img[y0:y1] = acc / (ss * ss)
-    ys, xs = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=device), xs0, indexing="ij")
-    _, depth, ids = _cast(cam, planes, xs, ys, seed, spacing)
-    return img, depth, ids
+        # ray layout (camera, grid point, row, column)
+        ys = torch.stack([ys0 + oy for oy, _ in grid])[:, :, None].expand(ng, y1 - y0, W)
+        xs = torch.stack([xs0 + ox for _, ox in grid])[:, None, :].expand(ng, y1 - y0, W)
+        ys = ys[None].expand(nc, ng, y1 - y0, W).reshape(-1)
+        xs = xs[None].expand(nc, ng, y1 - y0, W).reshape(-1)
+        ci = torch.arange(nc, device=device)[:, None].expand(nc, ng * (y1 - y0) * W).reshape(-1)
+        val, dep, pid = _cast(cams, planes, xs, ys, ci, seed, spacing)
+        val = val.view(nc, ng, y1 - y0, W)
+        dep = dep.view(nc, ng, y1 - y0, W)
+        pid = pid.view(nc, ng, y1 - y0, W)
+        for c in range(nc):
+            acc = torch.zeros((y1 - y0, W), dtype=torch.float64, device=device)
+            for g in range(ng - 1):
+                acc += val[c, g]
+            imgs[c][y0:y1] = acc / (ss * ss)
+            depths[c][y0:y1] = dep[c, ng - 1]
+            ids[c][y0:y1] = pid[c, ng - 1]
+    return list(zip(imgs, depths, ids))
 
 
 def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: int, seed: int, *,
@@ -285,7 +314,8 @@ def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: in
     ys, xs = torch.meshgrid(torch.arange(height, dtype=torch.float64, device=device),
                             torch.arange(width, dtype=torch.float64, device=device), indexing="ij")
     if low_texture_frac > 0:
-        _, _, ids0 = _cast(ref_cam, planes, xs, ys, seed, spacing)
+        ci0 = torch.zeros(width * height, dtype=torch.int64, device=device)
+        _, _, ids0 = _cast([ref_cam], planes, xs.reshape(-1), ys.reshape(-1), ci0, seed, spacing)
         counts = torch.bincount(ids0.flatten().clamp(min=0), minlength=len(planes)).cpu().numpy()
         covered = 0
         for pid in range(len(planes) - 1):
@@ -301,8 +331,9 @@ def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: in
     images = []
     ref_depth = ref_ids = None
     src_depths = []
+    rendered = _render(cams, planes, seed, spacing, supersample, device)
     for vi, cam in enumerate(cams):
-        img, depth, ids = _render(cam, planes, seed, spacing, supersample, device)
+        img, depth, ids = rendered[vi]
         if low_ids:
             noise_gen = torch.Generator(device="cpu").manual_seed(seed * 1000 + vi + 7)
             noise = (torch.rand((height, width), generator=noise_gen, dtype=torch.float64) * 2 - 1).to(device)
@@ -364,6 +395,9 @@ CONFIGS = {
     # 3200x2130, 20 sources stored fp16, 30 % low texture, 4 iterations + refinement
     "c3": dict(width=3200, height=2130, n_src=20, arc_deg=40.0, n_planes=20, gain=0.0, low_texture_frac=0.30,
                src_dtype="f16", supersample=2, iters=4, refine=1),
+    # training scenes of the learned proposal (seeds 1000-2999): 640x480, 8 sources, the 1920x1280 recipe
+    "c5": dict(width=640, height=480, n_src=8, arc_deg=40.0, n_planes=20, gain=0.05, low_texture_frac=0.0,
+               src_dtype="f32", supersample=2, iters=3, refine=1),
 }
 
 

@@ -90,3 +90,25 @@ def test_no_gpu_means_hip_error(amh):
     with pytest.raises(amh.AmhError) as e:
         amh.Context()
     assert e.value.status == amh.AMH_E_HIP
+
+
+def test_nn_null_arguments_and_count(amh):
+    L = amh.lib()
+    n = C.c_int64()
+    assert L.amh_nn_param_count(C.byref(n)) == 0 and n.value == 196341
+    assert L.amh_nn_param_count(None) == amh.AMH_E_INVALID_ARG
+    for call in (lambda: L.amh_nn_init(None, 0), lambda: L.amh_nn_get_params(None, None, 0),
+                 lambda: L.amh_nn_set_params(None, None, 0), lambda: L.amh_nn_get_grads(None, None, 0),
+                 lambda: L.amh_nn_forward(None, None, 1, 8, 8, None), lambda: L.amh_nn_backward(None, None, None),
+                 lambda: L.amh_nn_adam_step(None, 1e-3, 0.9, 0.999, 1e-8), lambda: L.amh_nn_save(None, b"x"),
+                 lambda: L.amh_nn_load(None, b"x"), lambda: L.amh_sweep_features(None, None),
+                 lambda: L.amh_init_from_proposal(None, None, 1, 1), lambda: L.amh_run_proposal(None, 0, None, 1, 1)):
+        assert call() == amh.AMH_E_INVALID_ARG
+
+
+def test_conf_min_validated(amh):
+    p = amh.params_default()
+    assert p.conf_min == 0.5
+    for bad in (-0.1, 1.5, float("nan")):
+        p.conf_min = bad
+        assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(p), None) == amh.AMH_E_INVALID_ARG
