@@ -4,14 +4,17 @@ TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
 
 1. ``sweep_features``: the network's input at 1/4 resolution.  Cell (i, j)
    covers reference pixels x in [4j, 4j + 4), y in [4i, 4i + 4) and is sampled
-   at pixel (4j + 2, 4i + 2).  Channels:
+   at pixel (4j + 2, 4i + 2).  A plane sweep scores D = 12 m fronto-parallel
+   planes, m = max(1, round(W / 160)) sub-planes per coarse bin (so one step
+   moves a near source's warp by ~2 px at any image width), at inverse depths
+   q_i = 1/d_max + (i + 0.5) (1/d_min - 1/d_max) / D; the aggregated cost of
+   plane i is the mean of the min(2, n) lowest matching costs (Eq. 8) over the
+   first n = min(4, N) sources.  Channels:
      0: (mean of the cell's 16 reference intensities - 127.5) / 64;
      1: population standard deviation of those 16 intensities / 32;
-     2 + k, k = 0..13: 1 - (mean of the min(k_views, n) lowest matching costs,
-        Eq. 8, of the fronto-parallel plane at inverse depth
-        q_k = 1/d_max + (k + 0.5) (1/d_min - 1/d_max) / 14, over the first
-        n = min(8, N) sources).  The k-lowest mean is the same aggregate as the
-        initial cost of random initialisation.
+     2: position of the lowest aggregated cost, 2 (i* + 0.5) / D - 1 (ties: lowest i);
+     3: 1 - that lowest aggregated cost;
+     4 + c, c = 0..11: 1 - the lowest aggregated cost among planes c m .. c m + m - 1.
 2. ``proposal_state``: the initial PatchMatch state built from per-cell
    predictions (depth, unit normal, confidence) at a resolution whose cell is
    s x s reference pixels (s = W / w = H / h).  Pixel (x, y) takes the plane of
@@ -29,8 +32,9 @@ import numpy as np
 
 from . import Params, State, Views, matching_cost, random_plane
 
-N_DEPTH = 14
-N_NET_SRC = 8
+N_COARSE = 12
+N_NET_SRC = 4
+K_SWEEP = 2
 CELL = 4
 
 
@@ -38,29 +42,45 @@ def _kinv(views: Views) -> np.ndarray:
     return np.linalg.inv(np.array(views.c.Kref[:], np.float64).reshape(3, 3))
 
 
-def sweep_planes(params: Params, n_depth: int = N_DEPTH) -> list:
+def sub_bins(width: int) -> int:
+    return max(1, int(round(width / 160.0)))
+
+
+def sweep_planes(params: Params, width: int) -> list:
+    D = N_COARSE * sub_bins(width)
     qf, qn = 1.0 / params.d_max, 1.0 / params.d_min
-    return [np.array([0.0, 0.0, -1.0, 1.0 / (qf + (k + 0.5) * (qn - qf) / n_depth)]) for k in range(n_depth)]
+    return [np.array([0.0, 0.0, -1.0, 1.0 / (qf + (i + 0.5) * (qn - qf) / D)]) for i in range(D)]
 
 
-def sweep_features(views: Views, params: Params, n_depth: int = N_DEPTH) -> np.ndarray:
-    """(H/4, W/4, 2 + n_depth) float64 network input of the reference of ``views``."""
+def sweep_costs(views: Views, params: Params, x: int, y: int) -> np.ndarray:
+    """Aggregated cost of every sweep plane at reference pixel (x, y)."""
+    n = min(N_NET_SRC, views.n_src)
+    kk = min(K_SWEEP, n)
+    out = []
+    for pl in sweep_planes(params, views.W):
+        c = sorted(matching_cost(views, params, x, y, pl, jv) for jv in range(n))
+        out.append(float(np.mean(c[:kk])))
+    return np.array(out)
+
+
+def sweep_features(views: Views, params: Params) -> np.ndarray:
+    """(H/4, W/4, 16) float64 network input of the reference of ``views``."""
     H, W = views.H, views.W
     h4, w4 = H // CELL, W // CELL
-    n = min(N_NET_SRC, views.n_src)
-    kk = min(params.k, n)
+    m = sub_bins(W)
+    D = N_COARSE * m
     ref = views.images[0].astype(np.float64)
-    planes = sweep_planes(params, n_depth)
-    F = np.zeros((h4, w4, 2 + n_depth))
+    F = np.zeros((h4, w4, 4 + N_COARSE))
     for i in range(h4):
         for j in range(w4):
             blk = ref[CELL * i:CELL * i + CELL, CELL * j:CELL * j + CELL]
             F[i, j, 0] = (blk.mean() - 127.5) / 64.0
             F[i, j, 1] = blk.std() / 32.0
-            x, y = CELL * j + CELL // 2, CELL * i + CELL // 2
-            for k, pl in enumerate(planes):
-                c = sorted(matching_cost(views, params, x, y, pl, jv) for jv in range(n))
-                F[i, j, 2 + k] = 1.0 - float(np.mean(c[:kk]))
+            a = sweep_costs(views, params, CELL * j + CELL // 2, CELL * i + CELL // 2)
+            best = int(np.argmin(a))
+            F[i, j, 2] = 2.0 * (best + 0.5) / D - 1.0
+            F[i, j, 3] = 1.0 - a[best]
+            F[i, j, 4:] = 1.0 - a.reshape(N_COARSE, m).min(axis=1)
     return F
 
 

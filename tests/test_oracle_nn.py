@@ -230,20 +230,27 @@ def disparity_pair(oracle_mod, W=64, H=40, Z=4.0):
     return oracle_mod.Views([ref, src], [cam(K, np.eye(3), np.zeros(3), W, H), cam(K, np.eye(3), [-B, 0, 0], W, H)])
 
 
-def test_sweep_features_peak_at_the_true_depth(oracle_mod):
+@pytest.mark.parametrize("W,fine", [(64, 5), (320, 11)])
+def test_sweep_features_find_the_true_depth(oracle_mod, W, fine):
+    """Exact case of Eq. 8: the sweep plane through the true depth costs 0, so it wins."""
     from oracle import proposal
 
-    V = disparity_pair(oracle_mod)
-    # choose the depth range so that bin 5's centre is exactly Z = 4
+    V = disparity_pair(oracle_mod, W=W)
+    m = proposal.sub_bins(W)
+    D = 12 * m
+    assert (m, D) == ((1, 12) if W == 64 else (2, 24))
+    # depth range chosen so that sweep plane `fine` sits exactly at Z = 4
     qz, span = 0.25, 0.14
-    qf = qz - 5.5 * span / 14
+    qf = qz - (fine + 0.5) * span / D
     P = oracle_mod.Params(d_min=1.0 / (qf + span), d_max=1.0 / qf)
-    assert proposal.sweep_planes(P)[5][3] == pytest.approx(4.0, rel=1e-12)
+    assert proposal.sweep_planes(P, W)[fine][3] == pytest.approx(4.0, rel=1e-12)
     Fm = proposal.sweep_features(V, P)
-    assert Fm.shape == (10, 16, 16)
-    inner = Fm[2:8, 2:11]  # cells whose window and warped window stay inside both images
-    np.testing.assert_allclose(inner[..., 2 + 5], 1.0, atol=1e-9)
-    assert np.all(np.argmax(inner[..., 2:], axis=-1) == 5)
+    assert Fm.shape == (10, W // 4, 16)
+    inner = Fm[2:8, 2:W // 4 - 5]  # cells whose window and warped window stay inside both images
+    np.testing.assert_allclose(inner[..., 2], 2.0 * (fine + 0.5) / D - 1.0, atol=1e-12)
+    np.testing.assert_allclose(inner[..., 3], 1.0, atol=1e-9)
+    np.testing.assert_allclose(inner[..., 4 + fine // m], 1.0, atol=1e-9)
+    assert np.all(np.argmax(inner[..., 4:], axis=-1) == fine // m)
     ref = V.images[0].astype(np.float64)
     blk = ref[12:16, 20:24]
     assert Fm[3, 5, 0] == pytest.approx((blk.mean() - 127.5) / 64, rel=1e-12)
