@@ -143,6 +143,69 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_learned(args):
+    """Seconds per depth map at equal accuracy: learned proposal + 1 iteration against the plain method
+    (random initialisation + 3 iterations), 1920x1280 with 10 sources, held-out scene seeds."""
+    import torch
+
+    import paper_1805_07920_amd as amh
+    import scenegen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    weights = args.weights or os.path.join(ROOT, "paper_1805_07920_amd", "weights", "proposal.bin")
+    seeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_scenes))
+    ctx = amh.Context(refine=1, seed=args.seed)
+    ctx.nn_load(weights)
+    runs = {"proposal+1": [], "random+1": [], "random+3": []}
+    H = W = 0
+    for seed in seeds:
+        sc = scenegen.config_scene("c2", seed, device="cuda")
+        H, W = sc.height, sc.width
+        ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
+        srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]  # nearest sources first
+        imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images]
+        ctx.init_views(imgs, sc.cams)
+        vis = sc.vis_count >= 2
+        depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        for name, fn in (("proposal+1", lambda: ctx.run_proposal(0, srcs, 1)),
+                         ("random+1", lambda: ctx.run_checkerboard(0, srcs, 1)),
+                         ("random+3", lambda: ctx.run_checkerboard(0, srcs, 3))):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+                ctx.get_depth_normal_cost(depth=depth)
+            torch.cuda.synchronize()
+            ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+            evals = ctx.get_stats()["evals_total"]
+            d = depth.cpu().numpy()
+            e = np.abs(d - sc.depth_gt)[vis]
+            gt = sc.depth_gt[vis]
+            runs[name].append(dict(ms=ms, evals=evals, rel1=float((e < 0.01 * gt).mean()),
+                                   cm2=float((e < 0.02).mean()), cm10=float((e < 0.10).mean())))
+            log(f"seed {seed} {name}: {runs[name][-1]}")
+    ctx.close()
+    mean = {k: {f: float(np.mean([r[f] for r in v])) for f in ("ms", "evals", "rel1", "cm2", "cm10")}
+            for k, v in runs.items()}
+    p, plain = mean["proposal+1"], mean["random+3"]
+    equal = p["cm10"] >= plain["cm10"] and p["cm2"] >= plain["cm2"] - 0.005
+    out = {
+        "metric": METRIC, "value": p["ms"] / 1000.0, "unit": "s per depth map", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": p["ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (network bf16 on MFMA, fp32 accumulation)", "data": "synthetic",
+        "config": {"workload": f"learned proposal + 1 iteration vs plain 3 iterations, {W}x{H}, 10 sources, "
+                               f"held-out scene seeds {seeds[0]}-{seeds[-1]}", "parallelism": "single GPU"},
+        "plain_s_per_depth_map": plain["ms"] / 1000.0, "speedup_vs_plain": plain["ms"] / p["ms"],
+        "equal_accuracy": bool(equal),
+        "equal_accuracy_rule": "proposal >= plain within 10 cm and no more than 0.5 points below it within 2 cm",
+        "accuracy": mean, "per_scene": runs,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,9 +216,18 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="the batched workload instead: 32 reference images of uneven sizes (640x480..3200x2130) "
                          "and 4-16 sources, one captured graph per batch")
+    ap.add_argument("--learned", action="store_true",
+                    help="seconds per depth map of the learned proposal + 1 iteration against the plain method")
+    ap.add_argument("--weights", default=None, help="proposal network parameters (--learned)")
+    ap.add_argument("--eval-seed0", type=int, default=1, help="first held-out scene seed (--learned)")
+    ap.add_argument("--eval-scenes", type=int, default=3, help="held-out scenes (--learned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB element-wise copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+              "Reference images shard across GPUs with no exchange; see the design notes.", file=sys.stderr)
+        sys.exit(2)
     if args.calibrate_copy:
         import torch
 
@@ -168,10 +240,8 @@ def main():
         return
     if args.batch:
         return bench_batch(args)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
-              "Reference images shard across GPUs with no exchange; see the design notes.", file=sys.stderr)
-        sys.exit(2)
+    if args.learned:
+        return bench_learned(args)
 
     import torch
 

@@ -253,11 +253,15 @@ amh_status amh_nn_save(amh_ctx *ctx, const char *path);
 amh_status amh_nn_load(amh_ctx *ctx, const char *path);
 
 /* Network input of the current reference (amh_begin), one 16-channel vector per
- * 4 x 4 cell: (mean of its 16 reference intensities - 127.5) / 64, their
- * standard deviation / 32, and for 14 fronto-parallel planes at inverse depths
- * 1/depth_max + (k + 1/2) (1/depth_min - 1/depth_max) / 14, one minus the mean
- * of the k lowest matching costs (Eq. 8) at the cell's pixel (4j + 2, 4i + 2)
- * over the first min(8, n_src) sources.  feats: device, bf16 bit patterns,
+ * 4 x 4 cell.  A plane sweep at the cell's pixel (4j + 2, 4i + 2) scores
+ * D = 12 m fronto-parallel planes, m = max(1, (W + 80) / 160) (integer
+ * division), at inverse depths 1/depth_max + (i + 1/2) (1/depth_min -
+ * 1/depth_max) / D; a plane's aggregate is the mean of the min(2, n) lowest
+ * matching costs (Eq. 8) over the first n = min(4, n_src) sources.  Channels:
+ * (mean of the cell's 16 reference intensities - 127.5) / 64, their standard
+ * deviation / 32, 2 (i* + 1/2) / D - 1 for the lowest aggregate i* (first on
+ * ties), 1 - that aggregate, and 1 - the lowest aggregate of each of the 12
+ * coarse bins of m consecutive planes.  feats: device, bf16 bit patterns,
  * [H/4][W/4][16].  UNSUPPORTED unless W and H are multiples of 32. */
 amh_status amh_sweep_features(amh_ctx *ctx, void *feats);
 
@@ -272,8 +276,9 @@ amh_status amh_sweep_features(amh_ctx *ctx, void *feats);
 amh_status amh_init_from_proposal(amh_ctx *ctx, const float *pred, int h, int w);
 
 /* amh_begin + amh_sweep_features + amh_nn_forward + amh_init_from_proposal +
- * iters x (red pass, black pass).  The network reads the first min(8, n_src)
- * sources.  STATE if the network does not exist. */
+ * iters x (red pass, black pass).  The sweep reads the first min(4, n_src)
+ * sources (list the nearest first); the iterations use all of them.  STATE if
+ * the network does not exist. */
 amh_status amh_run_proposal(amh_ctx *ctx, int ref, const int *srcs, int n_src, int iters);
 
 const char *amh_status_str(amh_status s);

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
 1. ``sweep_features``: the network's input at 1/4 resolution.  Cell (i, j)
    covers reference pixels x in [4j, 4j + 4), y in [4i, 4i + 4) and is sampled
    at pixel (4j + 2, 4i + 2).  A plane sweep scores D = 12 m fronto-parallel
-   planes, m = max(1, round(W / 160)) sub-planes per coarse bin (so one step
+   planes, m = max(1, floor((W + 80) / 160)) sub-planes per coarse bin (so one step
    moves a near source's warp by ~2 px at any image width), at inverse depths
    q_i = 1/d_max + (i + 0.5) (1/d_min - 1/d_max) / D; the aggregated cost of
    plane i is the mean of the min(2, n) lowest matching costs (Eq. 8) over the
@@ -43,7 +43,7 @@ def _kinv(views: Views) -> np.ndarray:
 
 
 def sub_bins(width: int) -> int:
-    return max(1, int(round(width / 160.0)))
+    return max(1, (width + 80) // 160)
 
 
 def sweep_planes(params: Params, width: int) -> list:

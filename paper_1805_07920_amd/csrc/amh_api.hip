@@ -936,8 +936,10 @@ amh_status amh_sweep_features(amh_ctx *c, void *feats) {
     a.m = method_dev(c->p, 0);
     a.h4 = H / kCell;
     a.w4 = W / kCell;
+    a.sub = std::max(1, (W + 80) / 160);  // one sweep step moves a near source's warp by ~2 px
     const double qf = 1.0 / (double)c->p.depth_max, qn = 1.0 / (double)c->p.depth_min;
-    for (int d = 0; d < kSweepDepths; ++d) a.depth[d] = (float)(1.0 / (qf + (d + 0.5) * (qn - qf) / kSweepDepths));
+    a.q_far = (float)qf;
+    a.q_step = (float)((qn - qf) / (kSweepCoarse * a.sub));
     a.feats = static_cast<unsigned short *>(feats);
     a.counters = c->counters;
     HIPCHK(c, launch_sweep(a, c->half, c->stream));

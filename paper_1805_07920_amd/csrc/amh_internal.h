@@ -89,18 +89,20 @@ struct BatchPhaseArgs {
     unsigned long long *job_end; // [n_jobs] device clock at the job's completion
 };
 
-constexpr int kSweepDepths = 14;  // fronto-parallel planes of the proposal's input sweep
-constexpr int kNetSrc = 8;        // sources the proposal network reads
+constexpr int kSweepCoarse = 12;  // coarse inverse-depth bins of the proposal's input sweep
+constexpr int kNetSrc = 4;        // sources the sweep reads
+constexpr int kSweepK = 2;        // aggregate: mean of the kSweepK lowest costs
 constexpr int kCell = 4;          // reference pixels per feature cell side
 
 // plane-sweep input of the proposal network: one 16-channel bf16 vector per 4x4 cell
 struct SweepArgs {
     RefDev ref;
     const ViewDev *views;
-    int n_net;                   // sources used (first min(8, n_src))
+    int n_net;                   // sources used (first min(4, n_src))
     MethodDev m;
     int h4, w4;                  // cell grid
-    float depth[kSweepDepths];   // plane depths
+    int sub;                     // sweep planes per coarse bin (12 * sub planes)
+    float q_far, q_step;         // inverse depth of plane i: q_far + (i + 1/2) q_step
     unsigned short *feats;       // [h4 * w4][16] bf16
     unsigned long long *counters;
 };

@@ -960,78 +960,84 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Plane-sweep input of the proposal network.  A workgroup of 64 lanes takes 8
-// cells x 8 sources: each lane builds the window of its cell's sample pixel
-// (4j + 2, 4i + 2) and scores the 14 fronto-parallel planes on its source;
-// then each cell's channels are written: normalised mean and deviation of its
-// 4 x 4 reference pixels, and 1 - (mean of the k lowest costs over the
-// sources) per plane, the aggregate of random initialisation's initial cost.
+// Plane-sweep input of the proposal network.  A workgroup of 64 lanes takes 16
+// cells x 4 sources; each lane builds the window of its cell's sample pixel
+// (4j + 2, 4i + 2) and scores the fronto-parallel sweep planes on its source.
+// After every plane the 4 lanes of a cell exchange their costs (lane
+// shuffles) and form the aggregate (mean of the min(2, n) lowest); each lane
+// keeps the running winner and the best aggregate of every coarse bin.
+// Channels: normalised mean and deviation of the cell's 4 x 4 reference
+// pixels, winning plane position, 1 - its cost, 1 - best cost per coarse bin.
 // ---------------------------------------------------------------------------
 template <int HALF>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     __shared__ __align__(16) float2 rwbuf[64 * kWinStride];
-    __shared__ float cst[8][kSweepDepths][kNetSrc];
-    const int lane = threadIdx.x, cl = lane >> 3, j = lane & 7;
+    const int lane = threadIdx.x, cl = lane >> 2, j = lane & 3;
     const int n_cells = a.h4 * a.w4;
-    const int cell = blockIdx.x * 8 + cl;
-    const bool ok = cell < n_cells && j < a.n_net;
+    const int cell = blockIdx.x * 16 + cl;
+    const bool cell_ok = cell < n_cells;
+    const bool ok = cell_ok && j < a.n_net;
+    const int ci = cell_ok ? cell / a.w4 : 0, cj = cell_ok ? cell - ci * a.w4 : 0;
+    const int x = kCell * cj + kCell / 2, y = kCell * ci + kCell / 2;
+    float2 *rw = rwbuf + lane * kWinStride;
+    WinStats ws = {1.f, 0.f};
     if (ok) {
-        const int ci = cell / a.w4, cj = cell - ci * a.w4;
-        const int x = kCell * cj + kCell / 2, y = kCell * ci + kCell / 2;
-        float2 *rw = rwbuf + lane * kWinStride;
         GlobalReader rd{&a.ref, x, y};
-        const WinStats ws = build_window(rd, a.m, rw, 0, 1);
-        for (int d = 0; d < kSweepDepths; ++d) {
-            const PlaneQ q = plane_q(a.ref, a.m, make_float4(0.f, 0.f, -1.f, a.depth[d]), x, y);
-            cst[cl][d][j] = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
-        }
+        ws = build_window(rd, a.m, rw, 0, 1);
     }
-    count_evals(a.counters, 0, ok ? (unsigned long long)kSweepDepths : 0ull);
-    __syncthreads();
-    for (int o = lane; o < 8 * 16; o += 64) {
-        const int c2 = o >> 4, ch = o & 15;
-        const int cell2 = blockIdx.x * 8 + c2;
-        if (cell2 >= n_cells) continue;
-        float val;
-        if (ch >= 2) {
-            const int d = ch - 2, n = a.n_net, kk = a.m.k < n ? a.m.k : n;
-            uint32_t taken = 0;
-            float sum = 0.f;
-            for (int r = 0; r < kk; ++r) {
-                int best = -1;
-                float bc = 0.f;
-                for (int jj = 0; jj < n; ++jj) {
-                    if ((taken >> jj) & 1u) continue;
-                    const float c = cst[c2][d][jj];
-                    if (best < 0 || c < bc) {
-                        best = jj;
-                        bc = c;
-                    }
-                }
-                taken |= 1u << best;
-                sum += bc;
-            }
-            val = 1.f - sum / (float)kk;
-        } else {
-            const int ci = cell2 / a.w4, cj = cell2 - ci * a.w4;
-            const float *img = a.ref.img + (size_t)(kCell * ci) * a.ref.W + kCell * cj;
-            float mu = 0.f;
-            for (int yy = 0; yy < kCell; ++yy)
-                for (int xx = 0; xx < kCell; ++xx) mu += img[(size_t)yy * a.ref.W + xx];
-            mu *= 1.f / (kCell * kCell);
-            if (ch == 0) {
-                val = (mu - 127.5f) * (1.f / 64.f);
-            } else {
-                float var = 0.f;
-                for (int yy = 0; yy < kCell; ++yy)
-                    for (int xx = 0; xx < kCell; ++xx) {
-                        const float dlt = img[(size_t)yy * a.ref.W + xx] - mu;
-                        var = fmaf(dlt, dlt, var);
-                    }
-                val = __builtin_sqrtf(var * (1.f / (kCell * kCell))) * (1.f / 32.f);
-            }
+    const float inf = __builtin_inff();
+    const int kk = a.n_net < kSweepK ? a.n_net : kSweepK;
+    float best = inf, coarse[kSweepCoarse];
+    int best_i = 0;
+#pragma unroll
+    for (int c = 0; c < kSweepCoarse; ++c) coarse[c] = inf;
+    const int D = kSweepCoarse * a.sub;
+    for (int i = 0; i < D; ++i) {
+        // every lane runs the loop (the shuffles need the whole wave); idle lanes contribute +inf
+        const float qi = a.q_far + ((float)i + 0.5f) * a.q_step;
+        float c = inf;
+        if (ok) {
+            const PlaneQ q = plane_q(a.ref, a.m, make_float4(0.f, 0.f, -1.f, 1.f / qi), x, y);
+            c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
         }
-        a.feats[(size_t)cell2 * 16 + ch] = f2bf(val);
+        // the 4 costs of this cell: lanes 4 cl .. 4 cl + 3
+        const float c1 = __shfl_xor(c, 1, 64), c2 = __shfl_xor(c, 2, 64), c3 = __shfl_xor(c1, 2, 64);
+        const float lo01 = fminf(c, c1), hi01 = fmaxf(c, c1), lo23 = fminf(c2, c3), hi23 = fmaxf(c2, c3);
+        const float m1 = fminf(lo01, lo23), m2 = fminf(fmaxf(lo01, lo23), fminf(hi01, hi23));
+        const float agg = kk >= 2 ? 0.5f * (m1 + m2) : m1;
+        if (agg < best) {
+            best = agg;
+            best_i = i;
+        }
+        const int cb = i / a.sub;
+#pragma unroll
+        for (int cc = 0; cc < kSweepCoarse; ++cc)
+            if (cc == cb) coarse[cc] = fminf(coarse[cc], agg);
+    }
+    count_evals(a.counters, 0, ok ? (unsigned long long)D : 0ull);
+    if (!cell_ok) return;  // no barrier follows
+    unsigned short *out = a.feats + (size_t)cell * 16;
+    if (j == 0) {
+        const float *img = a.ref.img + (size_t)(kCell * ci) * a.ref.W + kCell * cj;
+        float mu = 0.f;
+        for (int yy = 0; yy < kCell; ++yy)
+            for (int xx = 0; xx < kCell; ++xx) mu += img[(size_t)yy * a.ref.W + xx];
+        mu *= 1.f / (kCell * kCell);
+        float var = 0.f;
+        for (int yy = 0; yy < kCell; ++yy)
+            for (int xx = 0; xx < kCell; ++xx) {
+                const float dlt = img[(size_t)yy * a.ref.W + xx] - mu;
+                var = fmaf(dlt, dlt, var);
+            }
+        out[0] = f2bf((mu - 127.5f) * (1.f / 64.f));
+        out[1] = f2bf(__builtin_sqrtf(var * (1.f / (kCell * kCell))) * (1.f / 32.f));
+        out[2] = f2bf(2.f * ((float)best_i + 0.5f) / (float)D - 1.f);
+        out[3] = f2bf(1.f - best);
+    } else {
+        // lanes 1..3 write 4 coarse channels each
+#pragma unroll
+        for (int cc = 0; cc < kSweepCoarse; ++cc)
+            if (cc / 4 == j - 1) out[4 + cc] = f2bf(1.f - coarse[cc]);
     }
 }
 
@@ -1150,7 +1156,7 @@ hipError_t launch_stamp(unsigned long long *p, hipStream_t s) {
 hipError_t launch_sweep(const SweepArgs &a, int half, hipStream_t s) {
     const int n_cells = a.h4 * a.w4;
     if (n_cells == 0) return hipSuccess;
-    dim3 grid((n_cells + 7) / 8);
+    dim3 grid((n_cells + 15) / 16);
     if (half) AMH_LAUNCH(sweep_kernel<1>, grid, dim3(64), 0, s, a);
     else AMH_LAUNCH(sweep_kernel<0>, grid, dim3(64), 0, s, a);
     return hipGetLastError();

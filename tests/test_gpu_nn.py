@@ -20,7 +20,8 @@ relative error of at most 2^-9 per stored activation or gradient):
   * Adam: the first step moves every parameter whose gradient is not tiny by
     exactly -lr sign(g) (bias-corrected first step), to 1e-6;
   * sweep features: within a bf16 rounding (2^-8 relative) plus 2e-4 (the
-    matching cost's 1e-4 bar, twice);
+    matching cost's 1e-4 bar, twice); the winning sweep plane exactly wherever
+    it leads the runner-up by more than 2e-4 in the oracle;
   * proposal initialisation: the same plane as the oracle (2e-5) on pixels away
     from the depth-range and confidence thresholds, costs within 1e-4 on 99.9 %.
 """
@@ -292,36 +293,54 @@ def make_ctx(amh, sc, **kw):
     return ctx
 
 
-def test_sweep_features_match_oracle(amh, oracle_mod, scene_c1):
-    say("case sweep features c1")
+def check_features(f, V, P):
+    """Every channel within a bf16 rounding plus 2e-4 (twice the cost bar); the winning plane
+    (channel 2) exactly, on cells whose winner leads the runner-up by more than 2e-4."""
     from oracle import proposal
 
+    fo = proposal.sweep_features(V, P)
+    assert f.shape == fo.shape
+    err = np.abs(f - fo)
+    bound = 2.0 ** -8 * np.abs(fo) + 2e-4
+    rest = np.ones(16, bool)
+    rest[2] = False
+    say(f"  max err {err[..., rest].max():.2e}, worst ratio {(err / bound)[..., rest].max():.3f}")
+    assert np.all(err[..., rest] <= bound[..., rest])
+    robust = 0
+    for i in range(fo.shape[0]):
+        for j in range(fo.shape[1]):
+            a = np.sort(proposal.sweep_costs(V, P, 4 * j + 2, 4 * i + 2))
+            if a[1] - a[0] > 2e-4:
+                robust += 1
+                assert abs(f[i, j, 2] - fo[i, j, 2]) <= 2.0 ** -8 * abs(fo[i, j, 2]) + 1e-6, (i, j)
+    say(f"  winning plane compared on {robust} of {fo.shape[0] * fo.shape[1]} cells")
+    assert robust >= 0.9 * fo.shape[0] * fo.shape[1]
+
+
+def test_sweep_features_match_oracle(amh, oracle_mod, scene_c1):
+    say("case sweep features c1")
     sc = scene_c1
     with make_ctx(amh, sc) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
         f = ctx.sweep_features().float().cpu().numpy().astype(np.float64)
         st = ctx.get_stats()
-    fo = proposal.sweep_features(oracle_mod.Views.from_scene(sc), oracle_mod.Params())
-    assert f.shape == fo.shape == (24, 32, 16)
-    err = np.abs(f - fo)
-    bound = 2.0 ** -8 * np.abs(fo) + 2e-4
-    say(f"  max err {err.max():.2e}, worst ratio {(err / bound).max():.3f}")
-    assert np.all(err <= bound)
-    assert st["evals_init"] == 24 * 32 * 14 * 4
+    assert f.shape == (24, 32, 16)
+    check_features(f, oracle_mod.Views.from_scene(sc), oracle_mod.Params())
+    assert st["evals_init"] == 24 * 32 * 12 * 4
 
 
-def test_sweep_features_use_the_first_eight_sources(amh, oracle_mod):
-    say("case sweep features 10 sources")
+def test_sweep_features_two_sub_planes_ten_sources(amh, oracle_mod):
+    """320 px wide: two sweep planes per coarse bin; the sweep reads the first four of ten sources."""
+    say("case sweep features 320x64, 10 sources")
     import scenegen
-    from oracle import proposal
 
-    sc = scenegen.make_scene(64, 32, 10, 40.0, 3, 5, supersample=1)
+    sc = scenegen.make_scene(320, 64, 10, 40.0, 4, 5, supersample=1)
     with make_ctx(amh, sc) as ctx:
         ctx.begin(0, list(range(1, 11)))
         f = ctx.sweep_features().float().cpu().numpy().astype(np.float64)
-    V = oracle_mod.Views(sc.images[:9], sc.cams[:9])
-    fo = proposal.sweep_features(V, oracle_mod.Params())
-    assert np.all(np.abs(f - fo) <= 2.0 ** -8 * np.abs(fo) + 2e-4)
+        st = ctx.get_stats()
+    check_features(f, oracle_mod.Views(sc.images[:5], sc.cams[:5]), oracle_mod.Params())
+    assert st["evals_init"] == 16 * 80 * 24 * 4
 
 
 def proposal_maps(sc, seed, h, w):
@@ -395,5 +414,5 @@ def test_run_proposal_equals_its_steps(amh, scene_c1):
         b = ctx.get_state()
     for u, w in zip(a, b):
         np.testing.assert_array_equal(u, w)
-    assert st["evals_init"] == 24 * 32 * 14 * 4 + 128 * 96 * 4
+    assert st["evals_init"] == 24 * 32 * 12 * 4 + 128 * 96 * 4
     assert np.isfinite(a[1]).all()
