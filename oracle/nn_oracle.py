@@ -14,7 +14,9 @@ What this module computes, in plain float64 with no blocking or fusion:
   * 3x3 convolution with zero padding (and 1x1 for the head), bias, ReLU;
   * 2x2 average pooling, nearest 2x upsampling, channel concatenation;
   * the 4-level encoder-decoder built from them (channels 16/32/48/64);
-  * the decoded outputs (depth in [d_min, d_max], unit normal, confidence);
+  * the decoded outputs: depth as a bounded correction of the plane sweep's
+    winning inverse depth (a refinement head over the sweep, in [d_min, d_max]),
+    unit normal, confidence;
   * the training loss: L1 on normalised depth + (1 - n_hat . n) + binary
     cross-entropy of the confidence, its gradient, the backward pass of every
     layer, and one Adam step (Kingma and Ba, 2015) on float64 master weights.
@@ -202,12 +204,25 @@ def sigmoid(z):
     return 1.0 / (1.0 + np.exp(-z))
 
 
-def decode(z, d_min: float, d_max: float):
-    """(depth, unit normal, confidence) from the head output."""
-    depth = d_min + sigmoid(z[..., 0]) * (d_max - d_min)
+def inverse_depth(z0, q_ref, d_min: float, d_max: float):
+    """Depth head: the sweep's winning inverse depth q_ref moved by at most one twelfth of
+    the inverse-depth range, q = clamp(q_ref + R tanh(z0), 1/d_max, 1/d_min), R = (1/d_min
+    - 1/d_max) / 12.  Returns (q, dq/dz0) with the derivative 0 where the clamp binds."""
+    qf, qn = 1.0 / d_max, 1.0 / d_min
+    R = (qn - qf) / 12.0
+    th = np.tanh(z0)
+    u = q_ref + R * th
+    q = np.clip(u, qf, qn)
+    dq = np.where((u > qf) & (u < qn), R * (1.0 - th * th), 0.0)
+    return q, dq
+
+
+def decode(z, q_ref, d_min: float, d_max: float):
+    """(depth, unit normal, confidence) from the head output and the sweep's inverse depth."""
+    q, _ = inverse_depth(z[..., 0], q_ref, d_min, d_max)
     nv = z[..., 1:4]
     normal = nv / np.linalg.norm(nv, axis=-1, keepdims=True)
-    return depth, normal, sigmoid(z[..., 4])
+    return 1.0 / q, normal, sigmoid(z[..., 4])
 
 
 def confidence_target(cost, beta: float = 0.3):
@@ -215,15 +230,18 @@ def confidence_target(cost, beta: float = 0.3):
     return np.exp(-np.asarray(cost, np.float64) ** 2 / (2.0 * beta * beta))
 
 
-def loss(z, target, d_min: float, d_max: float):
+def loss(z, q_ref, target, d_min: float, d_max: float):
     """Mean over pixels of  w (|s - t_d| + 1 - n_hat . n_t) + BCE(sigmoid(z4), t_c).
 
     target (n, h, w, 6): depth, normal (3), confidence target, weight w of the
-    depth and normal terms.  s = sigmoid(z0) and t_d = (depth - d_min) / (d_max
-    - d_min).  Returns (loss, dL/dz); the gradient of |.| at 0 is taken as 0."""
+    depth and normal terms.  s = (depth - d_min) / (d_max - d_min) of the decoded
+    depth, t_d the same of the target depth.  Returns (loss, dL/dz); the gradient
+    of |.| at 0 is taken as 0."""
     P = z.shape[0] * z.shape[1] * z.shape[2]
-    s = sigmoid(z[..., 0])
-    td = (target[..., 0] - d_min) / (d_max - d_min)
+    q, dq = inverse_depth(z[..., 0], q_ref, d_min, d_max)
+    span = d_max - d_min
+    s = (1.0 / q - d_min) / span
+    td = (target[..., 0] - d_min) / span
     w = target[..., 5]
     nv = z[..., 1:4]
     nn = np.linalg.norm(nv, axis=-1)
@@ -234,17 +252,17 @@ def loss(z, target, d_min: float, d_max: float):
     bce = np.logaddexp(0.0, z4) - tc * z4
     L = (w * (np.abs(s - td) + 1.0 - cosang) + bce).sum() / P
     dz = np.zeros_like(z)
-    dz[..., 0] = w * np.sign(s - td) * s * (1.0 - s)
+    dz[..., 0] = w * np.sign(s - td) * (-1.0 / (q * q * span)) * dq
     dz[..., 1:4] = -(w / nn)[..., None] * (nt - cosang[..., None] * nh)
     dz[..., 4] = sigmoid(z4) - tc
     return L, dz / P
 
 
-def loss_and_grads(theta, x, target, d_min: float, d_max: float):
+def loss_and_grads(theta, x, q_ref, target, d_min: float, d_max: float):
     """Loss and flat canonical gradient of the whole network at parameters ``theta``."""
     params = unflatten(theta)
     z, a = forward(params, x)
-    L, dz = loss(z, target, d_min, d_max)
+    L, dz = loss(z, q_ref, target, d_min, d_max)
     return L, flatten(backward(params, a, dz))
 
 

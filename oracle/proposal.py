@@ -15,6 +15,8 @@ TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
      2: position of the lowest aggregated cost, 2 (i* + 0.5) / D - 1 (ties: lowest i);
      3: 1 - that lowest aggregated cost;
      4 + c, c = 0..11: 1 - the lowest aggregated cost among planes c m .. c m + m - 1.
+   ``sweep_reference_q`` gives the winning plane's inverse depth, the base that
+   the network's depth head corrects.
 2. ``proposal_state``: the initial PatchMatch state built from per-cell
    predictions (depth, unit normal, confidence) at a resolution whose cell is
    s x s reference pixels (s = W / w = H / h).  Pixel (x, y) takes the plane of
@@ -82,6 +84,19 @@ def sweep_features(views: Views, params: Params) -> np.ndarray:
             F[i, j, 3] = 1.0 - a[best]
             F[i, j, 4:] = 1.0 - a.reshape(N_COARSE, m).min(axis=1)
     return F
+
+
+def sweep_reference_q(views: Views, params: Params) -> np.ndarray:
+    """(H/4, W/4) inverse depth of each cell's winning sweep plane (the network's depth base)."""
+    H, W = views.H, views.W
+    D = N_COARSE * sub_bins(W)
+    qf, qn = 1.0 / params.d_max, 1.0 / params.d_min
+    out = np.zeros((H // CELL, W // CELL))
+    for i in range(H // CELL):
+        for j in range(W // CELL):
+            best = int(np.argmin(sweep_costs(views, params, CELL * j + CELL // 2, CELL * i + CELL // 2)))
+            out[i, j] = qf + (best + 0.5) * (qn - qf) / D
+    return out
 
 
 def proposal_plane(views: Views, params: Params, x: int, y: int, depth, normal, conf, conf_min: float = 0.5):

@@ -91,13 +91,14 @@ def small_batch(seed, n=1, h=8, w=16):
     t[..., 1:4] = nt / np.linalg.norm(nt, axis=-1, keepdims=True)
     t[..., 4] = rng.uniform(0, 1, (n, h, w))
     t[..., 5] = (rng.uniform(0, 1, (n, h, w)) < 0.8).astype(float)
-    return x, t
+    q_ref = rng.uniform(1.0 / 6.0, 0.5, (n, h, w))
+    return x, q_ref, t
 
 
 def test_network_gradient_matches_finite_differences():
-    x, t = small_batch(1)
+    x, q_ref, t = small_batch(1)
     theta = nn.flatten(rand_params(2))
-    L, g = nn.loss_and_grads(theta, x, t, 2.0, 6.0)
+    L, g = nn.loss_and_grads(theta, x, q_ref, t, 2.0, 6.0)
     rng = np.random.default_rng(4)
     # a few parameters of every layer
     offs, o = [], 0
@@ -110,17 +111,16 @@ def test_network_gradient_matches_finite_differences():
         tp, tm = theta.copy(), theta.copy()
         tp[i] += h
         tm[i] -= h
-        fd = (nn.loss_and_grads(tp, x, t, 2.0, 6.0)[0] - nn.loss_and_grads(tm, x, t, 2.0, 6.0)[0]) / (2 * h)
+        fd = (nn.loss_and_grads(tp, x, q_ref, t, 2.0, 6.0)[0] - nn.loss_and_grads(tm, x, q_ref, t, 2.0, 6.0)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=2e-4, abs=1e-8), i
 
 
 def test_network_gradient_matches_autograd():
     """Whole network in torch float64 autograd (a second, library implementation)."""
-    x, t = small_batch(7, n=2, h=16, w=8)
+    x, q_ref, t = small_batch(7, n=2, h=16, w=8)
     params = rand_params(8)
-    L, dz = None, None
     z, a = nn.forward(params, x)
-    L, dz = nn.loss(z, t, 2.0, 6.0)
+    L, dz = nn.loss(z, q_ref, t, 2.0, 6.0)
     grads = nn.backward(params, a, dz)
     tp = {k: (torch_w(W).requires_grad_(), torch.from_numpy(b).requires_grad_()) for k, (W, b) in params.items()}
 
@@ -140,7 +140,9 @@ def test_network_gradient_matches_autograd():
     zt = c("head", d0, act=False)
     np.testing.assert_allclose(nhwc(zt), z, rtol=1e-10, atol=1e-10)
     T = nchw(t)
-    s = torch.sigmoid(zt[:, 0])
+    R = (0.5 - 1.0 / 6.0) / 12.0
+    q = torch.clamp(torch.from_numpy(q_ref) + R * torch.tanh(zt[:, 0]), 1.0 / 6.0, 0.5)
+    s = (1.0 / q - 2.0) / 4.0
     td = (T[:, 0] - 2.0) / 4.0
     nh = zt[:, 1:4] / zt[:, 1:4].norm(dim=1, keepdim=True)
     w = T[:, 5]
@@ -155,30 +157,43 @@ def test_network_gradient_matches_autograd():
 def test_loss_closed_forms_and_gradient():
     z = np.zeros((1, 1, 2, 5))
     z[0, 0, :, 1:4] = [0.0, 0.0, -2.0]
+    q_ref = np.full((1, 1, 2), 0.25)  # z0 = 0 keeps the sweep's inverse depth: depth 4
     t = np.zeros((1, 1, 2, 6))
-    t[..., 0] = 4.0  # sigmoid(0) maps to the middle of [2, 6]
+    t[..., 0] = 4.0
     t[..., 1:4] = [0.0, 0.0, -1.0]
     t[..., 4] = 0.0
     t[..., 5] = 1.0
-    L, dz = nn.loss(z, t, 2.0, 6.0)
+    L, dz = nn.loss(z, q_ref, t, 2.0, 6.0)
     assert L == pytest.approx(np.log(2.0), abs=1e-15)  # depth and normal terms vanish; BCE(1/2, 0) = log 2
     assert np.all(dz[..., 0] == 0) and np.allclose(dz[..., 1:4], 0) and np.allclose(dz[..., 4], 0.25)
+    d, _, _ = nn.decode(z, q_ref, 2.0, 6.0)
+    np.testing.assert_allclose(d, 4.0, rtol=1e-15)
+    # the correction saturates at one twelfth of the inverse-depth range, and the range clamps it
+    zbig = z.copy()
+    zbig[..., 0] = 50.0
+    d, _, _ = nn.decode(zbig, q_ref, 2.0, 6.0)
+    np.testing.assert_allclose(d, 1.0 / (0.25 + (0.5 - 1.0 / 6.0) / 12.0), rtol=1e-12)
+    d, _, _ = nn.decode(zbig, np.full((1, 1, 2), 0.49), 2.0, 6.0)
+    np.testing.assert_allclose(d, 2.0, rtol=1e-15)
+    q, dq = nn.inverse_depth(np.array([3.0]), np.array([0.49]), 2.0, 6.0)
+    assert q[0] == 0.5 and dq[0] == 0.0
     rng = np.random.default_rng(9)
     z = rng.standard_normal((1, 3, 4, 5))
-    _, t = small_batch(10, 1, 3, 4)
-    L, dz = nn.loss(z, t, 2.0, 6.0)
+    _, q_ref, t = small_batch(10, 1, 3, 4)
+    L, dz = nn.loss(z, q_ref, t, 2.0, 6.0)
     h = 1e-6
-    for idx in [(0, 0, 0, 0), (0, 1, 2, 1), (0, 2, 3, 3), (0, 1, 1, 4), (0, 2, 0, 2)]:
+    for idx in [(0, 0, 0, 0), (0, 1, 2, 0), (0, 2, 1, 0), (0, 1, 2, 1), (0, 2, 3, 3), (0, 1, 1, 4), (0, 2, 0, 2)]:
         zp, zm = z.copy(), z.copy()
         zp[idx] += h
         zm[idx] -= h
-        fd = (nn.loss(zp, t, 2.0, 6.0)[0] - nn.loss(zm, t, 2.0, 6.0)[0]) / (2 * h)
+        fd = (nn.loss(zp, q_ref, t, 2.0, 6.0)[0] - nn.loss(zm, q_ref, t, 2.0, 6.0)[0]) / (2 * h)
         assert dz[idx] == pytest.approx(fd, rel=1e-6, abs=1e-10)
 
 
 def test_decode_ranges():
-    z = np.random.default_rng(0).standard_normal((2, 4, 4, 5)) * 5
-    d, n, c = nn.decode(z, 2.0, 6.0)
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal((2, 4, 4, 5)) * 5
+    d, n, c = nn.decode(z, rng.uniform(1 / 6, 0.5, (2, 4, 4)), 2.0, 6.0)
     assert d.min() >= 2.0 and d.max() <= 6.0
     np.testing.assert_allclose(np.linalg.norm(n, axis=-1), 1.0, rtol=1e-14)
     assert c.min() > 0 and c.max() < 1
