@@ -229,11 +229,14 @@ amh_status amh_nn_set_params(amh_ctx *ctx, const float *in, int64_t n);
 amh_status amh_nn_get_grads(amh_ctx *ctx, float *out, int64_t n);
 
 /* Forward pass over n inputs of h x w cells (h, w positive multiples of 8):
- * feats (device, bf16 bit patterns, [n][h][w][16]) -> out (device, float,
- * [n][h][w][5]: depth in [depth_min, depth_max], unit normal, confidence in
- * (0, 1)); out may be NULL.  The input is copied and the activations are kept
- * for amh_nn_backward. */
-amh_status amh_nn_forward(amh_ctx *ctx, const void *feats, int n, int h, int w, float *out);
+ * feats (device, bf16 bit patterns, [n][h][w][16]) and q_ref (device, float,
+ * [n][h][w], the sweep's winning inverse depth, amh_sweep_features) -> out
+ * (device, float, [n][h][w][5]: depth, unit normal, confidence in (0, 1));
+ * out may be NULL.  The depth head corrects q_ref by at most a twelfth of the
+ * inverse-depth range: depth = 1 / clamp(q_ref + R tanh(z0), 1/depth_max,
+ * 1/depth_min), R = (1/depth_min - 1/depth_max) / 12.  The inputs are copied
+ * and the activations kept for amh_nn_backward. */
+amh_status amh_nn_forward(amh_ctx *ctx, const void *feats, const float *q_ref, int n, int h, int w, float *out);
 
 /* Loss of the last forward pass against target (device, float, [n][h][w][6]:
  * depth, normal (3), confidence target, weight of the depth and normal terms):
@@ -262,8 +265,9 @@ amh_status amh_nn_load(amh_ctx *ctx, const char *path);
  * deviation / 32, 2 (i* + 1/2) / D - 1 for the lowest aggregate i* (first on
  * ties), 1 - that aggregate, and 1 - the lowest aggregate of each of the 12
  * coarse bins of m consecutive planes.  feats: device, bf16 bit patterns,
- * [H/4][W/4][16].  UNSUPPORTED unless W and H are multiples of 32. */
-amh_status amh_sweep_features(amh_ctx *ctx, void *feats);
+ * [H/4][W/4][16]; q_ref (device, float, [H/4][W/4], may be NULL): the winning
+ * plane's inverse depth.  UNSUPPORTED unless W and H are multiples of 32. */
+amh_status amh_sweep_features(amh_ctx *ctx, void *feats, float *q_ref);
 
 /* Initialisation from per-cell predictions pred (device, float, [h][w][5] as
  * amh_nn_forward writes them; cell size s = W/w = H/h, an integer): pixel

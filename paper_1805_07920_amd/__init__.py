@@ -105,12 +105,12 @@ def lib():
         L.amh_nn_get_params.argtypes = [vp, vp, C.c_int64]
         L.amh_nn_set_params.argtypes = [vp, vp, C.c_int64]
         L.amh_nn_get_grads.argtypes = [vp, vp, C.c_int64]
-        L.amh_nn_forward.argtypes = [vp, vp, ip, ip, ip, vp]
+        L.amh_nn_forward.argtypes = [vp, vp, vp, ip, ip, ip, vp]
         L.amh_nn_backward.argtypes = [vp, vp, C.POINTER(C.c_float)]
         L.amh_nn_adam_step.argtypes = [vp, fp, fp, fp, fp]
         L.amh_nn_save.argtypes = [vp, C.c_char_p]
         L.amh_nn_load.argtypes = [vp, C.c_char_p]
-        L.amh_sweep_features.argtypes = [vp, vp]
+        L.amh_sweep_features.argtypes = [vp, vp, vp]
         L.amh_init_from_proposal.argtypes = [vp, vp, ip, ip]
         L.amh_run_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
         _lib = L
@@ -364,16 +364,20 @@ class Context:
         self._check(self.L.amh_nn_get_grads(self.h, out.ctypes.data, out.size), "amh_nn_get_grads")
         return out
 
-    def nn_forward(self, feats, out=None):
-        """feats: device tensor (n, h, w, 16) of bfloat16; returns device (n, h, w, 5) float32."""
+    def nn_forward(self, feats, q_ref, out=None):
+        """feats: device bfloat16 (n, h, w, 16); q_ref: device float32 (n, h, w) sweep inverse depth.
+        Returns device (n, h, w, 5) float32: depth, unit normal, confidence."""
         import torch
 
         if feats.dtype != torch.bfloat16 or not feats.is_cuda or feats.dim() != 4 or feats.shape[3] != NET_IN:
             raise ValueError("feats must be a device bfloat16 tensor (n, h, w, 16)")
         n, h, w, _ = feats.shape
+        if q_ref.dtype != torch.float32 or not q_ref.is_cuda or tuple(q_ref.shape) != (n, h, w):
+            raise ValueError("q_ref must be a device float32 tensor (n, h, w)")
         if out is None:
             out = torch.empty((n, h, w, NET_OUT), dtype=torch.float32, device=feats.device)
-        self._check(self.L.amh_nn_forward(self.h, _ptr(feats)[0], n, h, w, _ptr(out)[0]), "amh_nn_forward")
+        self._check(self.L.amh_nn_forward(self.h, _ptr(feats)[0], _ptr(q_ref)[0], n, h, w, _ptr(out)[0]),
+                    "amh_nn_forward")
         return out
 
     def nn_backward(self, target, want_loss: bool = True):
@@ -392,14 +396,18 @@ class Context:
     def nn_load(self, path: str):
         self._check(self.L.amh_nn_load(self.h, os.fsencode(path)), "amh_nn_load")
 
-    def sweep_features(self, out=None):
-        """Network input of the current reference: device bfloat16 (H/4, W/4, 16)."""
+    def sweep_features(self, out=None, q_ref=None):
+        """Network input of the current reference: (device bfloat16 (H/4, W/4, 16), device float32 (H/4, W/4)
+        inverse depth of the winning sweep plane)."""
         import torch
 
+        shape = (self.H // NET_CELL, self.W // NET_CELL)
         if out is None:
-            out = torch.empty((self.H // NET_CELL, self.W // NET_CELL, NET_IN), dtype=torch.bfloat16, device="cuda")
-        self._check(self.L.amh_sweep_features(self.h, _ptr(out)[0]), "amh_sweep_features")
-        return out
+            out = torch.empty(shape + (NET_IN,), dtype=torch.bfloat16, device="cuda")
+        if q_ref is None:
+            q_ref = torch.empty(shape, dtype=torch.float32, device="cuda")
+        self._check(self.L.amh_sweep_features(self.h, _ptr(out)[0], _ptr(q_ref)[0]), "amh_sweep_features")
+        return out, q_ref
 
     def init_from_proposal(self, pred):
         """pred: device float32 (h, w, 5) per-cell depth, normal, confidence."""

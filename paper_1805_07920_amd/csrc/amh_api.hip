@@ -922,7 +922,7 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
     return AMH_OK;
 }
 
-amh_status amh_sweep_features(amh_ctx *c, void *feats) {
+amh_status amh_sweep_features(amh_ctx *c, void *feats, float *q_ref) {
     if (!c) return AMH_E_INVALID_ARG;
     if (!feats) return fail(c, AMH_E_INVALID_ARG, "feats is NULL");
     if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
@@ -941,6 +941,7 @@ amh_status amh_sweep_features(amh_ctx *c, void *feats) {
     a.q_far = (float)qf;
     a.q_step = (float)((qn - qf) / (kSweepCoarse * a.sub));
     a.feats = static_cast<unsigned short *>(feats);
+    a.q_ref = q_ref;
     a.counters = c->counters;
     HIPCHK(c, launch_sweep(a, c->half, c->stream));
     return AMH_OK;
@@ -970,15 +971,18 @@ amh_status amh_run_proposal(amh_ctx *c, int ref, const int *srcs, int n_src, int
     if (cells > c->prop_cap) {
         if (c->prop_feats) (void)hipFree(c->prop_feats);
         if (c->prop_pred) (void)hipFree(c->prop_pred);
+        if (c->prop_qref) (void)hipFree(c->prop_qref);
         c->prop_feats = nullptr;
         c->prop_pred = nullptr;
+        c->prop_qref = nullptr;
         c->prop_cap = 0;
         if ((st = dalloc(c, &c->prop_feats, cells * 16 * 2)) != AMH_OK) return st;
         if ((st = dalloc(c, (void **)&c->prop_pred, cells * 5 * sizeof(float))) != AMH_OK) return st;
+        if ((st = dalloc(c, (void **)&c->prop_qref, cells * sizeof(float))) != AMH_OK) return st;
         c->prop_cap = cells;
     }
-    if ((st = amh_sweep_features(c, c->prop_feats)) != AMH_OK) return st;
-    if ((st = amh_nn_forward(c, c->prop_feats, 1, h4, w4, c->prop_pred)) != AMH_OK) return st;
+    if ((st = amh_sweep_features(c, c->prop_feats, c->prop_qref)) != AMH_OK) return st;
+    if ((st = amh_nn_forward(c, c->prop_feats, c->prop_qref, 1, h4, w4, c->prop_pred)) != AMH_OK) return st;
     if ((st = amh_init_from_proposal(c, c->prop_pred, h4, w4)) != AMH_OK) return st;
     for (int t = 0; t < iters; ++t)
         for (int colour = 0; colour < 2; ++colour)
@@ -1043,6 +1047,7 @@ void amh_destroy(amh_ctx *c) {
     if (c->counters) (void)hipFree(c->counters);
     if (c->prop_feats) (void)hipFree(c->prop_feats);
     if (c->prop_pred) (void)hipFree(c->prop_pred);
+    if (c->prop_qref) (void)hipFree(c->prop_qref);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     for (auto e : c->ev_init)
         if (e) (void)hipEventDestroy(e);

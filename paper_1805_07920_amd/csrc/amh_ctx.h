@@ -81,6 +81,7 @@ struct amh_ctx {
     amh::NetState *net = nullptr;
     void *prop_feats = nullptr;   // amh_run_proposal: network input and prediction of the reference
     float *prop_pred = nullptr;
+    float *prop_qref = nullptr;
     size_t prop_cap = 0;          // cells
 };
 

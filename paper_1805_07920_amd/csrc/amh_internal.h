@@ -104,6 +104,7 @@ struct SweepArgs {
     int sub;                     // sweep planes per coarse bin (12 * sub planes)
     float q_far, q_step;         // inverse depth of plane i: q_far + (i + 1/2) q_step
     unsigned short *feats;       // [h4 * w4][16] bf16
+    float *q_ref;                // [h4 * w4] inverse depth of the winning plane, or NULL
     unsigned long long *counters;
 };
 

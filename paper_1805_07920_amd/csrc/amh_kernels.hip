@@ -961,63 +961,80 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
 
 // ---------------------------------------------------------------------------
 // Plane-sweep input of the proposal network.  A workgroup of 64 lanes takes 16
-// cells x 4 sources; each lane builds the window of its cell's sample pixel
-// (4j + 2, 4i + 2) and scores the fronto-parallel sweep planes on its source.
-// After every plane the 4 lanes of a cell exchange their costs (lane
-// shuffles) and form the aggregate (mean of the min(2, n) lowest); each lane
-// keeps the running winner and the best aggregate of every coarse bin.
+// cells x 4 consecutive sweep planes: lane (cell, k) scores planes k, k + 4,
+// k + 8, ... of its cell on every source in turn, so at any instruction the
+// whole wave gathers from one source, and the 4 lanes of a cell warp to
+// positions ~2 px apart (consecutive planes) that share texel lines.  A lane
+// aggregates its plane's costs (mean of the min(2, n) lowest), keeps its best
+// plane and the best aggregate of every coarse bin; the 4 lanes of a cell
+// merge these with shuffles at the end (ties: lowest plane index).  The
+// window of the cell's sample pixel (4j + 2, 4i + 2) is built once per cell.
 // Channels: normalised mean and deviation of the cell's 4 x 4 reference
-// pixels, winning plane position, 1 - its cost, 1 - best cost per coarse bin.
+// pixels, winning plane position, 1 - its cost, 1 - best cost per coarse bin;
+// the winner's inverse depth is also written in fp32 (the depth base of the
+// network's refinement head).
 // ---------------------------------------------------------------------------
 template <int HALF>
 __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
-    __shared__ __align__(16) float2 rwbuf[64 * kWinStride];
-    const int lane = threadIdx.x, cl = lane >> 2, j = lane & 3;
+    // one window block per cell, written a quarter by each of its 4 lanes
+    __shared__ __align__(16) float2 rwbuf[16 * kWinStride];
+    const int lane = threadIdx.x, cl = lane >> 2, k = lane & 3;
     const int n_cells = a.h4 * a.w4;
     const int cell = blockIdx.x * 16 + cl;
     const bool cell_ok = cell < n_cells;
-    const bool ok = cell_ok && j < a.n_net;
     const int ci = cell_ok ? cell / a.w4 : 0, cj = cell_ok ? cell - ci * a.w4 : 0;
     const int x = kCell * cj + kCell / 2, y = kCell * ci + kCell / 2;
-    float2 *rw = rwbuf + lane * kWinStride;
+    float2 *rw = rwbuf + cl * kWinStride;
     WinStats ws = {1.f, 0.f};
-    if (ok) {
+    if (cell_ok) {
         GlobalReader rd{&a.ref, x, y};
-        ws = build_window(rd, a.m, rw, 0, 1);
+        ws = build_window(rd, a.m, rw, k, 4);
     }
+    __syncthreads();
     const float inf = __builtin_inff();
-    const int kk = a.n_net < kSweepK ? a.n_net : kSweepK;
+    const int n = a.n_net;
     float best = inf, coarse[kSweepCoarse];
-    int best_i = 0;
+    int best_i = 0x7fffffff;
 #pragma unroll
     for (int c = 0; c < kSweepCoarse; ++c) coarse[c] = inf;
-    const int D = kSweepCoarse * a.sub;
-    for (int i = 0; i < D; ++i) {
-        // every lane runs the loop (the shuffles need the whole wave); idle lanes contribute +inf
-        const float qi = a.q_far + ((float)i + 0.5f) * a.q_step;
-        float c = inf;
-        if (ok) {
+    const int D = kSweepCoarse * a.sub;  // a multiple of 4
+    if (cell_ok) {
+        for (int i = k; i < D; i += 4) {
+            const float qi = a.q_far + ((float)i + 0.5f) * a.q_step;
             const PlaneQ q = plane_q(a.ref, a.m, make_float4(0.f, 0.f, -1.f, 1.f / qi), x, y);
-            c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
-        }
-        // the 4 costs of this cell: lanes 4 cl .. 4 cl + 3
-        const float c1 = __shfl_xor(c, 1, 64), c2 = __shfl_xor(c, 2, 64), c3 = __shfl_xor(c1, 2, 64);
-        const float lo01 = fminf(c, c1), hi01 = fmaxf(c, c1), lo23 = fminf(c2, c3), hi23 = fmaxf(c2, c3);
-        const float m1 = fminf(lo01, lo23), m2 = fminf(fmaxf(lo01, lo23), fminf(hi01, hi23));
-        const float agg = kk >= 2 ? 0.5f * (m1 + m2) : m1;
-        if (agg < best) {
-            best = agg;
-            best_i = i;
-        }
-        const int cb = i / a.sub;
+            float m1 = inf, m2 = inf;  // two lowest costs over the sources
+            for (int j = 0; j < n; ++j) {
+                const float c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+                m2 = fminf(m2, fmaxf(m1, c));
+                m1 = fminf(m1, c);
+            }
+            const float agg = n >= kSweepK ? 0.5f * (m1 + m2) : m1;
+            if (agg < best) {
+                best = agg;
+                best_i = i;
+            }
+            const int cb = i / a.sub;
 #pragma unroll
-        for (int cc = 0; cc < kSweepCoarse; ++cc)
-            if (cc == cb) coarse[cc] = fminf(coarse[cc], agg);
+            for (int cc = 0; cc < kSweepCoarse; ++cc)
+                if (cc == cb) coarse[cc] = fminf(coarse[cc], agg);
+        }
     }
-    count_evals(a.counters, 0, ok ? (unsigned long long)D : 0ull);
+    count_evals(a.counters, 0, cell_ok ? (unsigned long long)(D / 4) * n : 0ull);
+    // merge the 4 lanes of the cell (lanes 4 cl .. 4 cl + 3)
+#pragma unroll
+    for (int off = 1; off <= 2; off <<= 1) {
+        const float ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(best_i, off, 64);
+        if (ob < best || (ob == best && oi < best_i)) {
+            best = ob;
+            best_i = oi;
+        }
+#pragma unroll
+        for (int cc = 0; cc < kSweepCoarse; ++cc) coarse[cc] = fminf(coarse[cc], __shfl_xor(coarse[cc], off, 64));
+    }
     if (!cell_ok) return;  // no barrier follows
     unsigned short *out = a.feats + (size_t)cell * 16;
-    if (j == 0) {
+    if (k == 0) {
         const float *img = a.ref.img + (size_t)(kCell * ci) * a.ref.W + kCell * cj;
         float mu = 0.f;
         for (int yy = 0; yy < kCell; ++yy)
@@ -1033,11 +1050,12 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
         out[1] = f2bf(__builtin_sqrtf(var * (1.f / (kCell * kCell))) * (1.f / 32.f));
         out[2] = f2bf(2.f * ((float)best_i + 0.5f) / (float)D - 1.f);
         out[3] = f2bf(1.f - best);
+        if (a.q_ref) a.q_ref[cell] = a.q_far + ((float)best_i + 0.5f) * a.q_step;
     } else {
         // lanes 1..3 write 4 coarse channels each
 #pragma unroll
         for (int cc = 0; cc < kSweepCoarse; ++cc)
-            if (cc / 4 == j - 1) out[4 + cc] = f2bf(1.f - coarse[cc]);
+            if (cc / 4 == k - 1) out[4 + cc] = f2bf(1.f - coarse[cc]);
     }
 }
 

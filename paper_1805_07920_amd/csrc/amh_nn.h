@@ -33,6 +33,11 @@ struct WgradArgs {
     int chunk;             // pixels per split (multiple of 32)
 };
 
+// depth head: depth = 1 / clamp(q_ref + R tanh(z0), q_far, q_near)
+struct DepthHead {
+    float d_min, d_max, q_far, q_near, R;
+};
+
 hipError_t launch_conv(const ConvArgs &a, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs &a, float *gw, float *gb, int splits, hipStream_t s);
 hipError_t launch_transpose_w(const bf16_t *w, int cin, int cout_pad, int kpad, int ks, bf16_t *wt, int kpad_t,
@@ -44,10 +49,10 @@ hipError_t launch_enc_grad(const bf16_t *dp, const bf16_t *dcat, int Ccat, int o
                            int w, int C, bf16_t *g, hipStream_t s);
 hipError_t launch_up_grad(const bf16_t *dcat, int Ccat, const bf16_t *act, int n, int h, int w, int C1, bf16_t *g,
                           hipStream_t s);
-hipError_t launch_decode(const float *z, int P, float d_min, float d_max, float *out, hipStream_t s);
+hipError_t launch_decode(const float *z, const float *q_ref, int P, const DepthHead &dh, float *out, hipStream_t s);
 int loss_blocks(int P);
-hipError_t launch_loss(const float *z, const float *target, int P, float d_min, float d_max, bf16_t *dz, float *part,
-                       float *loss, hipStream_t s);
+hipError_t launch_loss(const float *z, const float *q_ref, const float *target, int P, const DepthHead &dh, bf16_t *dz,
+                       float *part, float *loss, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, bf16_t *pb, int n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);
 hipError_t launch_to_bf16(const float *src, int n, bf16_t *dst, hipStream_t s);

@@ -299,15 +299,25 @@ __global__ void up_grad_kernel(const bf16_t *dcat, int Ccat, const bf16_t *act, 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
 
+// depth head: q = clamp(q_ref + R tanh(z0), q_far, q_near); returns q and dq/dz0 (0 where clamped)
+__device__ __forceinline__ float head_q(float z0, float q_ref, const DepthHead &dh, float &dq) {
+    const float th = tanhf(z0);
+    const float u = fmaf(dh.R, th, q_ref);
+    const bool inside = u > dh.q_far && u < dh.q_near;
+    dq = inside ? dh.R * (1.f - th * th) : 0.f;
+    return fminf(fmaxf(u, dh.q_far), dh.q_near);
+}
+
 // z: [P][16] head output (channels 0..4 used) -> out [P][5]: depth, unit normal, confidence
-__global__ void decode_kernel(const float *z, int P, float d_min, float d_max, float *out) {
+__global__ void decode_kernel(const float *z, const float *q_ref, int P, DepthHead dh, float *out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const float *zp = z + (size_t)p * 16;
     const float nx = zp[1], ny = zp[2], nz = zp[3];
     const float inv = 1.f / __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
+    float dq;
     float *o = out + (size_t)p * 5;
-    o[0] = d_min + sigmoidf(zp[0]) * (d_max - d_min);
+    o[0] = 1.f / head_q(zp[0], q_ref[p], dh, dq);
     o[1] = nx * inv;
     o[2] = ny * inv;
     o[3] = nz * inv;
@@ -315,8 +325,8 @@ __global__ void decode_kernel(const float *z, int P, float d_min, float d_max, f
 }
 
 // per pixel: w (|s - t_d| + 1 - n_hat . n_t) + softplus(z4) - t_c z4, and dL/dz / P
-__global__ __launch_bounds__(256) void loss_kernel(const float *z, const float *target, int P, float d_min,
-                                                   float d_max, bf16_t *dz, float *part) {
+__global__ __launch_bounds__(256) void loss_kernel(const float *z, const float *q_ref, const float *target, int P,
+                                                   DepthHead dh, bf16_t *dz, float *part) {
     __shared__ float red[256];
     const int p = blockIdx.x * 256 + threadIdx.x;
     float L = 0.f;
@@ -324,8 +334,11 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *z, const float *
         const float *zp = z + (size_t)p * 16;
         const float *tp = target + (size_t)p * 6;
         const float invP = 1.f / (float)P;
-        const float s = sigmoidf(zp[0]);
-        const float td = (tp[0] - d_min) / (d_max - d_min);
+        const float span = dh.d_max - dh.d_min;
+        float dq;
+        const float q = head_q(zp[0], q_ref[p], dh, dq);
+        const float s = (1.f / q - dh.d_min) / span;
+        const float td = (tp[0] - dh.d_min) / span;
         const float wdn = tp[5];
         const float nx = zp[1], ny = zp[2], nz = zp[3];
         const float nn = __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
@@ -340,7 +353,7 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *z, const float *
 #pragma unroll
         for (int k = 0; k < 16; ++k) g[k] = 0.f;
         const float sg = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
-        g[0] = wdn * sg * s * (1.f - s) * invP;
+        g[0] = wdn * sg * (-1.f / (q * q * span)) * dq * invP;
         const float wn = -wdn * inv * invP;
         g[1] = wn * (tp[1] - cosang * hx);
         g[2] = wn * (tp[2] - cosang * hy);
@@ -463,17 +476,17 @@ hipError_t launch_up_grad(const bf16_t *dcat, int Ccat, const bf16_t *act, int n
     return hipGetLastError();
 }
 
-hipError_t launch_decode(const float *z, int P, float d_min, float d_max, float *out, hipStream_t s) {
-    NN_LAUNCH(decode_kernel, grid1(P), dim3(256), 0, s, z, P, d_min, d_max, out);
+hipError_t launch_decode(const float *z, const float *q_ref, int P, const DepthHead &dh, float *out, hipStream_t s) {
+    NN_LAUNCH(decode_kernel, grid1(P), dim3(256), 0, s, z, q_ref, P, dh, out);
     return hipGetLastError();
 }
 
 int loss_blocks(int P) { return (P + 255) / 256; }
 
-hipError_t launch_loss(const float *z, const float *target, int P, float d_min, float d_max, bf16_t *dz, float *part,
-                       float *loss, hipStream_t s) {
+hipError_t launch_loss(const float *z, const float *q_ref, const float *target, int P, const DepthHead &dh, bf16_t *dz,
+                       float *part, float *loss, hipStream_t s) {
     const int nb = loss_blocks(P);
-    NN_LAUNCH(loss_kernel, dim3(nb), dim3(256), 0, s, z, target, P, d_min, d_max, dz, part);
+    NN_LAUNCH(loss_kernel, dim3(nb), dim3(256), 0, s, z, q_ref, target, P, dh, dz, part);
     NN_LAUNCH(loss_reduce_kernel, dim3(1), dim3(256), 0, s, part, nb, P, loss);
     return hipGetLastError();
 }

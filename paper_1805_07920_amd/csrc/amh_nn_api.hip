@@ -64,6 +64,7 @@ struct NetState {
     // activations and gradients, sized for cap_px level-0 cells
     size_t cap_px = 0;
     std::vector<void *> bufs;
+    float *qref;                         // depth base of the kept forward pass
     bf16_t *x, *e0a, *e0, *p0, *e1a, *e1, *p1, *e2a, *e2, *p2, *e3a, *e3, *c2, *d2, *c1, *d1, *c0, *d0;
     float *z;
     bf16_t *dz, *g_d0, *dc0, *g_d1, *dc1, *g_d2, *dc2, *g_e3, *g_e3a, *dp2, *g_e2, *g_e2a, *dp1, *g_e1, *g_e1a, *dp0,
@@ -110,6 +111,7 @@ amh_status ensure_acts(amh_ctx *c, size_t P0) {
         N->bufs.push_back(p);
         return static_cast<bf16_t *>(p);
     };
+    N->qref = reinterpret_cast<float *>(get(P0, 2));  // one float per cell
     N->x = get(P0, 16);
     N->e0a = get(P0, 16);
     N->e0 = get(P0, 16);
@@ -335,6 +337,17 @@ amh_status conv_bwd(amh_ctx *c, int li, const bf16_t *x, const bf16_t *g, bf16_t
     return AMH_OK;
 }
 
+DepthHead depth_head(const amh_params &p) {
+    DepthHead dh;
+    dh.d_min = p.depth_min;
+    dh.d_max = p.depth_max;
+    const double qf = 1.0 / (double)p.depth_max, qn = 1.0 / (double)p.depth_min;
+    dh.q_far = (float)qf;
+    dh.q_near = (float)qn;
+    dh.R = (float)((qn - qf) / 12.0);
+    return dh;
+}
+
 amh_status check_net(amh_ctx *c) {
     if (!c->net) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
     return AMH_OK;
@@ -405,8 +418,9 @@ amh_status amh_nn_get_grads(amh_ctx *c, float *out, int64_t n) {
     return AMH_OK;
 }
 
-amh_status amh_nn_forward(amh_ctx *c, const void *feats, int n, int h, int w, float *out) {
+amh_status amh_nn_forward(amh_ctx *c, const void *feats, const float *q_ref, int n, int h, int w, float *out) {
     if (!c) return AMH_E_INVALID_ARG;
+    if (!q_ref) return fail(c, AMH_E_INVALID_ARG, "q_ref is NULL");
     if (!feats || n < 1 || h < 8 || w < 8 || h % 8 || w % 8 || (int64_t)n * h * w > (1ll << 28))
         return fail(c, AMH_E_INVALID_ARG, "need feats and n >= 1, h and w positive multiples of 8");
     amh_status st = check_net(c);
@@ -416,6 +430,7 @@ amh_status amh_nn_forward(amh_ctx *c, const void *feats, int n, int h, int w, fl
     if ((st = ensure_acts(c, P0)) != AMH_OK) return st;
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemcpyAsync(N->x, feats, P0 * kIn * sizeof(bf16_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(N->qref, q_ref, P0 * sizeof(float), hipMemcpyDeviceToDevice, s));
     const int h1 = h / 2, w1 = w / 2, h2 = h / 4, w2 = w / 4, h3 = h / 8, w3 = w / 8;
 #define FWD(li, in, outb, hh, ww)                                                         \
     if ((st = conv_fwd(c, li, in, outb, n, hh, ww, false)) != AMH_OK) return st
@@ -438,7 +453,7 @@ amh_status amh_nn_forward(amh_ctx *c, const void *feats, int n, int h, int w, fl
     FWD(DEC0, N->c0, N->d0, h, w);
 #undef FWD
     if ((st = conv_fwd(c, HEAD, N->d0, N->z, n, h, w, true)) != AMH_OK) return st;
-    if (out) HIPCHK(c, launch_decode(N->z, (int)P0, c->p.depth_min, c->p.depth_max, out, s));
+    if (out) HIPCHK(c, launch_decode(N->z, N->qref, (int)P0, depth_head(c->p), out, s));
     N->n = n;
     N->h = h;
     N->w = w;
@@ -466,7 +481,7 @@ amh_status amh_nn_backward(amh_ctx *c, const float *target, float *loss) {
         if ((st = dalloc(c, (void **)&N->loss_part, (size_t)nb * 4)) != AMH_OK) return st;
         N->loss_cap = nb;
     }
-    HIPCHK(c, launch_loss(N->z, target, P0, c->p.depth_min, c->p.depth_max, N->dz, N->loss_part, N->loss_dev, s));
+    HIPCHK(c, launch_loss(N->z, N->qref, target, P0, depth_head(c->p), N->dz, N->loss_part, N->loss_dev, s));
 #define BWD(li, x, g, dx, mask, hh, ww)                                          \
     if ((st = conv_bwd(c, li, x, g, dx, mask, n, hh, ww)) != AMH_OK) return st
     BWD(HEAD, N->d0, N->dz, N->g_d0, N->d0, h, w);          // dL/d(d0 pre-activation)

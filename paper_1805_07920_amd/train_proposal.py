@@ -6,7 +6,8 @@ produces the labels: at the pixel (4j + 2, 4i + 2) of every 4 x 4 cell its
 depth, normal and final cost m; the confidence target is C(m) =
 exp(-m^2 / (2 beta^2)) of Eq. 3, which also weights the depth and normal terms,
 so cells the plain method did not resolve count little.  The network input is
-the library's plane-sweep features of the same scene.  Training: Adam with a
+the library's plane-sweep features of the same scene, and its depth head
+corrects the sweep's winning inverse depth.  Training: Adam with a
 cosine-decayed learning rate over shuffled mini-batches; forward, loss,
 backward and the update all run in the library (amh_nn_*).
 
@@ -56,7 +57,7 @@ def labels_of(depth, normal, cost, beta: float):
 
 
 def make_dataset(ctx, seeds, iters: int = 3, n_src: int = 8):
-    feats, targets = [], []
+    feats, qrefs, targets = [], [], []
     t0 = time.time()
     srcs = list(range(1, n_src + 1))
     for k, seed in enumerate(seeds):
@@ -69,14 +70,16 @@ def make_dataset(ctx, seeds, iters: int = 3, n_src: int = 8):
         cost = torch.empty((H, W), device="cuda")
         ctx.get_depth_normal_cost(depth, normal, cost)
         targets.append(labels_of(depth, normal, cost, ctx.p.beta))
-        feats.append(ctx.sweep_features().clone())
+        f, q = ctx.sweep_features()
+        feats.append(f)
+        qrefs.append(q)
         if (k + 1) % 100 == 0 or k + 1 == len(seeds):
             torch.cuda.synchronize()
             log(f"data: {k + 1}/{len(seeds)} scenes, {time.time() - t0:.1f} s")
-    return torch.stack(feats), torch.stack(targets)
+    return torch.stack(feats), torch.stack(qrefs), torch.stack(targets)
 
 
-def train(ctx, feats, targets, epochs: int, batch: int, lr: float, seed: int):
+def train(ctx, feats, qrefs, targets, epochs: int, batch: int, lr: float, seed: int):
     S = feats.shape[0]
     steps_per_epoch = S // batch
     total = epochs * steps_per_epoch
@@ -90,8 +93,9 @@ def train(ctx, feats, targets, epochs: int, batch: int, lr: float, seed: int):
         for b in range(steps_per_epoch):
             idx = perm[b * batch:(b + 1) * batch]
             x = feats.index_select(0, idx).contiguous()
+            q = qrefs.index_select(0, idx).contiguous()
             t = targets.index_select(0, idx).contiguous()
-            ctx.nn_forward(x)
+            ctx.nn_forward(x, q)
             want = b % 20 == 0
             loss = ctx.nn_backward(t, want_loss=want)
             if want:
@@ -109,7 +113,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--scenes", type=int, default=2000)
     ap.add_argument("--seed0", type=int, default=1000)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=0)
@@ -121,11 +125,11 @@ def main(argv=None):
     torch.cuda.init()
     ctx = amh.Context(seed=args.init_seed)
     t0 = time.time()
-    feats, targets = make_dataset(ctx, range(args.seed0, args.seed0 + args.scenes))
+    feats, qrefs, targets = make_dataset(ctx, range(args.seed0, args.seed0 + args.scenes))
     t_data = time.time() - t0
     ctx.nn_init(args.init_seed)
     t1 = time.time()
-    hist = train(ctx, feats, targets, args.epochs, args.batch, args.lr, args.init_seed)
+    hist = train(ctx, feats, qrefs, targets, args.epochs, args.batch, args.lr, args.init_seed)
     t_train = time.time() - t1
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     ctx.nn_save(args.out)

@@ -41,3 +41,9 @@ def random_targets(seed: int, n: int, h: int, w: int, d_min: float = 2.0, d_max:
     t[..., 4] = rng.uniform(0, 1, (n, h, w))
     t[..., 5] = (rng.uniform(0, 1, (n, h, w)) < 0.8)
     return t
+
+
+def random_q_ref(seed: int, n: int, h: int, w: int, d_min: float = 2.0, d_max: float = 6.0) -> np.ndarray:
+    """(n, h, w) float32 inverse depths inside [1/d_max, 1/d_min] (a plane sweep's winners)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(1.0 / d_max, 1.0 / d_min, (n, h, w)).astype(np.float32)

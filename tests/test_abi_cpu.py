@@ -99,9 +99,9 @@ def test_nn_null_arguments_and_count(amh):
     assert L.amh_nn_param_count(None) == amh.AMH_E_INVALID_ARG
     for call in (lambda: L.amh_nn_init(None, 0), lambda: L.amh_nn_get_params(None, None, 0),
                  lambda: L.amh_nn_set_params(None, None, 0), lambda: L.amh_nn_get_grads(None, None, 0),
-                 lambda: L.amh_nn_forward(None, None, 1, 8, 8, None), lambda: L.amh_nn_backward(None, None, None),
+                 lambda: L.amh_nn_forward(None, None, None, 1, 8, 8, None), lambda: L.amh_nn_backward(None, None, None),
                  lambda: L.amh_nn_adam_step(None, 1e-3, 0.9, 0.999, 1e-8), lambda: L.amh_nn_save(None, b"x"),
-                 lambda: L.amh_nn_load(None, b"x"), lambda: L.amh_sweep_features(None, None),
+                 lambda: L.amh_nn_load(None, b"x"), lambda: L.amh_sweep_features(None, None, None),
                  lambda: L.amh_init_from_proposal(None, None, 1, 1), lambda: L.amh_run_proposal(None, 0, None, 1, 1)):
         assert call() == amh.AMH_E_INVALID_ARG
 

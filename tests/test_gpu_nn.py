@@ -63,7 +63,7 @@ def logit(p):
     return np.log(p / (1 - p))
 
 
-def emulated(theta, x, t=None, d_min=2.0, d_max=6.0):
+def emulated(theta, x, q_ref=None, t=None, d_min=2.0, d_max=6.0):
     """The oracle's layers with every stored activation and activation gradient
     rounded to bf16 at the points where the device stores them.  Returns the head
     output z, and with targets t also the loss and the flat gradient."""
@@ -96,7 +96,7 @@ def emulated(theta, x, t=None, d_min=2.0, d_max=6.0):
     z = nn.conv(A["d0"], W, b)
     if t is None:
         return z
-    L, dz = nn.loss(z, t, d_min, d_max)
+    L, dz = nn.loss(z, q_ref, t, d_min, d_max)
     G = {}
 
     def bwd(name, xin, g, mask=None):
@@ -125,17 +125,21 @@ def emulated(theta, x, t=None, d_min=2.0, d_max=6.0):
     return z, L, nn.flatten(G)
 
 
-def compare_predictions(out, z, tol_logit, tol_deg):
+def compare_predictions(out, z, q_ref, tol, tol_deg):
+    """Normwise relative error of (depth correction in units of its bound, confidence logit), and
+    the normal angle, between device predictions and the head output z of a reference."""
     depth, normal, conf = out[..., 0], out[..., 1:4], out[..., 4]
-    zl = np.stack([z[..., 0], z[..., 4]], -1)
-    gl = np.stack([logit((depth - 2.0) / 4.0), logit(conf)], -1)
+    R = (0.5 - 1.0 / 6.0) / 12.0
+    dref, nref, _ = nn.decode(z, q_ref, 2.0, 6.0)
+    zl = np.stack([(1.0 / dref - q_ref) / R, z[..., 4]], -1)
+    gl = np.stack([(1.0 / depth - q_ref) / R, logit(conf)], -1)
     rel = np.linalg.norm(gl - zl) / np.linalg.norm(zl)
-    _, nref, _ = nn.decode(z, 2.0, 6.0)
     ang = np.degrees(np.arccos(np.clip((normal * nref).sum(-1), -1, 1)))
-    say(f"  logit rel err {rel:.2e}, normal angle max {ang.max():.3f} deg")
-    assert rel <= tol_logit
+    say(f"  head rel err {rel:.2e}, normal angle max {ang.max():.3f} deg")
+    assert rel <= tol
     assert ang.max() <= tol_deg
     np.testing.assert_allclose(np.linalg.norm(normal, axis=-1), 1.0, atol=1e-5)
+    assert depth.min() >= 2.0 - 1e-5 and depth.max() <= 6.0 + 1e-4
 
 
 def test_param_count_and_roundtrip(amh):
@@ -169,15 +173,17 @@ def test_forward_matches_oracle(amh, shape):
     n, h, w = shape
     theta = ng.random_params(10 + h, nn.LAYERS)
     x = ng.random_features(20 + w, n, h, w)
+    q = ng.random_q_ref(30 + n, n, h, w)
     import torch
 
     with amh.Context() as ctx:
         ctx.nn_set_params(theta)
-        out = ctx.nn_forward(dev(x, torch.bfloat16)).cpu().numpy().astype(np.float64)
-    z_emu = emulated(theta.astype(np.float64), x.astype(np.float64))
-    compare_predictions(out, z_emu, 1e-2, 1.0)
-    z64, _ = nn.forward(nn.unflatten(theta.astype(np.float64)), x.astype(np.float64))
-    compare_predictions(out, z64, 3e-2, 3.0)
+        out = ctx.nn_forward(dev(x, torch.bfloat16), dev(q, torch.float32)).cpu().numpy().astype(np.float64)
+    f64 = lambda a: a.astype(np.float64)
+    z_emu = emulated(f64(theta), f64(x))
+    compare_predictions(out, z_emu, f64(q), 1e-2, 1.0)
+    z64, _ = nn.forward(nn.unflatten(f64(theta)), f64(x))
+    compare_predictions(out, z64, f64(q), 3e-2, 3.0)
 
 
 def test_backward_matches_oracle(amh):
@@ -189,14 +195,15 @@ def test_backward_matches_oracle(amh):
     theta = ng.random_params(31, nn.LAYERS)
     x = ng.random_features(32, n, h, w)
     t = ng.random_targets(33, n, h, w)
+    q = ng.random_q_ref(34, n, h, w)
     with amh.Context() as ctx:
         ctx.nn_set_params(theta)
-        ctx.nn_forward(dev(x, torch.bfloat16))
+        ctx.nn_forward(dev(x, torch.bfloat16), dev(q, torch.float32))
         loss = ctx.nn_backward(dev(t, torch.float32))
         g = ctx.nn_get_grads().astype(np.float64)
     f64 = lambda a: a.astype(np.float64)
-    _, Le, ge = emulated(f64(theta), f64(x), f64(t))
-    L, go = nn.loss_and_grads(f64(theta), f64(x), f64(t), 2.0, 6.0)
+    _, Le, ge = emulated(f64(theta), f64(x), f64(q), f64(t))
+    L, go = nn.loss_and_grads(f64(theta), f64(x), f64(q), f64(t), 2.0, 6.0)
     say(f"  loss gpu {loss:.6f} bf16-storage oracle {Le:.6f} float64 oracle {L:.6f}")
     assert loss == pytest.approx(Le, rel=1e-4)
     assert loss == pytest.approx(L, rel=1e-2)
@@ -223,12 +230,14 @@ def test_adam_first_step_and_training_reduces_loss(amh):
     theta = ng.random_params(41, nn.LAYERS)
     x = ng.random_features(42, n, h, w)
     t = ng.random_targets(43, n, h, w)
-    _, go = nn.loss_and_grads(theta.astype(np.float64), x.astype(np.float64), t.astype(np.float64), 2.0, 6.0)
-    xd, td = dev(x, torch.bfloat16), dev(t, torch.float32)
+    q = ng.random_q_ref(44, n, h, w)
+    f64 = lambda a: a.astype(np.float64)
+    _, go = nn.loss_and_grads(f64(theta), f64(x), f64(q), f64(t), 2.0, 6.0)
+    xd, qd, td = dev(x, torch.bfloat16), dev(q, torch.float32), dev(t, torch.float32)
     lr = 1e-3
     with amh.Context() as ctx:
         ctx.nn_set_params(theta)
-        ctx.nn_forward(xd)
+        ctx.nn_forward(xd, qd)
         l0 = ctx.nn_backward(td)
         ctx.nn_adam_step(lr, 0.9, 0.999, 1e-8)
         step = ctx.nn_get_params().astype(np.float64) - theta
@@ -237,10 +246,10 @@ def test_adam_first_step_and_training_reduces_loss(amh):
         # bias-corrected first step: -lr g / (|g| + eps) = -lr sign(g) where |g| >> eps
         np.testing.assert_allclose(step[big], -lr * np.sign(go[big]), rtol=1e-3, atol=1e-6)
         for _ in range(60):
-            ctx.nn_forward(xd)
+            ctx.nn_forward(xd, qd)
             ctx.nn_backward(td, want_loss=False)
             ctx.nn_adam_step(lr)
-        ctx.nn_forward(xd)
+        ctx.nn_forward(xd, qd)
         l1 = ctx.nn_backward(td)
     say(f"  loss {l0:.4f} -> {l1:.4f}")
     assert l1 < 0.8 * l0
@@ -251,15 +260,17 @@ def test_nn_errors(amh):
     import torch
 
     with amh.Context() as ctx:
+        q8 = torch.full((1, 8, 8), 0.25, device="cuda")
         with pytest.raises(amh.AmhError) as e:
-            ctx.nn_forward(torch.zeros((1, 8, 8, 16), dtype=torch.bfloat16, device="cuda"))
+            ctx.nn_forward(torch.zeros((1, 8, 8, 16), dtype=torch.bfloat16, device="cuda"), q8)
         assert e.value.status == amh.AMH_E_STATE
         ctx.nn_init(0)
         with pytest.raises(amh.AmhError) as e:
             ctx.nn_backward(torch.zeros((1, 8, 8, 6), device="cuda"))
         assert e.value.status == amh.AMH_E_STATE
         with pytest.raises(amh.AmhError) as e:
-            ctx.nn_forward(torch.zeros((1, 12, 8, 16), dtype=torch.bfloat16, device="cuda"))
+            ctx.nn_forward(torch.zeros((1, 12, 8, 16), dtype=torch.bfloat16, device="cuda"),
+                           torch.full((1, 12, 8), 0.25, device="cuda"))
         assert e.value.status == amh.AMH_E_INVALID_ARG
         with pytest.raises(amh.AmhError) as e:
             ctx.nn_adam_step(1e-3)
@@ -293,11 +304,13 @@ def make_ctx(amh, sc, **kw):
     return ctx
 
 
-def check_features(f, V, P):
+def check_features(f, q, V, P):
     """Every channel within a bf16 rounding plus 2e-4 (twice the cost bar); the winning plane
-    (channel 2) exactly, on cells whose winner leads the runner-up by more than 2e-4."""
+    (channel 2, and its fp32 inverse depth q) exactly, on cells whose winner leads the runner-up
+    by more than 2e-4."""
     from oracle import proposal
 
+    qo = proposal.sweep_reference_q(V, P)
     fo = proposal.sweep_features(V, P)
     assert f.shape == fo.shape
     err = np.abs(f - fo)
@@ -313,6 +326,7 @@ def check_features(f, V, P):
             if a[1] - a[0] > 2e-4:
                 robust += 1
                 assert abs(f[i, j, 2] - fo[i, j, 2]) <= 2.0 ** -8 * abs(fo[i, j, 2]) + 1e-6, (i, j)
+                assert q[i, j] == pytest.approx(qo[i, j], rel=1e-6), (i, j)
     say(f"  winning plane compared on {robust} of {fo.shape[0] * fo.shape[1]} cells")
     assert robust >= 0.9 * fo.shape[0] * fo.shape[1]
 
@@ -322,10 +336,11 @@ def test_sweep_features_match_oracle(amh, oracle_mod, scene_c1):
     sc = scene_c1
     with make_ctx(amh, sc) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
-        f = ctx.sweep_features().float().cpu().numpy().astype(np.float64)
+        fd, qd = ctx.sweep_features()
+        f, q = fd.float().cpu().numpy().astype(np.float64), qd.cpu().numpy().astype(np.float64)
         st = ctx.get_stats()
     assert f.shape == (24, 32, 16)
-    check_features(f, oracle_mod.Views.from_scene(sc), oracle_mod.Params())
+    check_features(f, q, oracle_mod.Views.from_scene(sc), oracle_mod.Params())
     assert st["evals_init"] == 24 * 32 * 12 * 4
 
 
@@ -337,9 +352,10 @@ def test_sweep_features_two_sub_planes_ten_sources(amh, oracle_mod):
     sc = scenegen.make_scene(320, 64, 10, 40.0, 4, 5, supersample=1)
     with make_ctx(amh, sc) as ctx:
         ctx.begin(0, list(range(1, 11)))
-        f = ctx.sweep_features().float().cpu().numpy().astype(np.float64)
+        fd, qd = ctx.sweep_features()
+        f, q = fd.float().cpu().numpy().astype(np.float64), qd.cpu().numpy().astype(np.float64)
         st = ctx.get_stats()
-    check_features(f, oracle_mod.Views(sc.images[:5], sc.cams[:5]), oracle_mod.Params())
+    check_features(f, q, oracle_mod.Views(sc.images[:5], sc.cams[:5]), oracle_mod.Params())
     assert st["evals_init"] == 16 * 80 * 24 * 4
 
 
@@ -406,8 +422,8 @@ def test_run_proposal_equals_its_steps(amh, scene_c1):
         a = ctx.get_state()
         st = ctx.get_stats()
         ctx.begin(0, srcs)
-        f = ctx.sweep_features()
-        pred = ctx.nn_forward(f[None])[0].contiguous()
+        f, q = ctx.sweep_features()
+        pred = ctx.nn_forward(f[None], q[None])[0].contiguous()
         ctx.init_from_proposal(pred)
         ctx.pass_(0, 0)
         ctx.pass_(0, 1)
