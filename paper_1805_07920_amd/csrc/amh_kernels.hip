@@ -12,6 +12,8 @@
 // not used: the work is per-sample gathers and scalar arithmetic, bounded by
 // the vector ALU.
 #include <hip/hip_fp16.h>
+
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include "amh_bf16.h"
@@ -603,6 +605,79 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
 }
 
 // ---------------------------------------------------------------------------
+// Initialisation of one colour with one lane per (pixel, source): a
+// workgroup holds G = min(64, 256 / N) pixels of the colour in row-major order
+// x N lanes, so nearly every lane evaluates (the tiled body above leaves most
+// lanes of its second round idle when N is not a multiple of 9).  The N lanes
+// of a pixel build its window block together, score the same plane on their
+// sources, and the pixel's first lane takes the mean of the k lowest costs.
+// Same arithmetic as init_body, so the two give identical states.
+// ---------------------------------------------------------------------------
+constexpr int kInitMaxPix = 64;
+
+template <int HALF>
+__global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
+    __shared__ __align__(16) float2 rwbuf[kInitMaxPix * kWinStride];
+    __shared__ float cst[256];
+    const int N = a.n_src;
+    const int G = min(kInitMaxPix, 256 / N);
+    const int t = threadIdx.x, g = t / N, j = t - g * N;
+    const bool lane_ok = g < G;
+    const int per_row = (a.ref.W + 1) / 2;  // slots per row; x beyond the image is skipped
+    const long long pc = (long long)blockIdx.x * G + g;
+    const int y = (int)(pc / per_row);
+    const int x = 2 * (int)(pc - (long long)y * per_row) + ((y + a.colour) & 1);
+    const bool pix_ok = lane_ok && y < a.ref.H && x < a.ref.W;
+    float2 *rw = rwbuf + (lane_ok ? g : 0) * kWinStride;
+    WinStats ws = {1.f, 0.f};
+    if (pix_ok) {
+        GlobalReader rd{&a.ref, x, y};
+        ws = build_window(rd, a.m, rw, j, N);
+    }
+    __syncthreads();
+    float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
+    if (pix_ok) {
+        const float2 r = ref_ray(a.ref, x, y);
+        if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
+            float u[4], nx, ny, nz;
+            philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
+            const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
+            normal_from_uniforms(u[1], u[2], nx, ny, nz);
+            pl = plane_from(r, depth, nx, ny, nz);
+        }
+        const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
+        cst[t] = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+    }
+    count_evals(a.counters, 0, pix_ok ? 1ull : 0ull);
+    __syncthreads();
+    if (pix_ok && j == 0) {
+        // mean of the k lowest costs, in ascending order
+        const float *c = cst + g * N;
+        const int kk = a.m.k < N ? a.m.k : N;
+        uint32_t taken = 0;
+        float sum = 0.f;
+        for (int r = 0; r < kk; ++r) {
+            int best = -1;
+            float bc = 0.f;
+            for (int v = 0; v < N; ++v) {
+                if ((taken >> v) & 1u) continue;
+                if (best < 0 || c[v] < bc) {
+                    best = v;
+                    bc = c[v];
+                }
+            }
+            taken |= 1u << best;
+            sum += bc;
+        }
+        const size_t p = (size_t)y * a.ref.W + x;
+        a.st.planes[p] = pl;
+        a.st.cost[p] = sum / (float)kk;
+        a.st.S[p] = 0u;
+        a.st.v[p] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One checkerboard half-pass (Sec. 3.1 - 3.3).
 // ---------------------------------------------------------------------------
 template <int HALF>
@@ -859,17 +934,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
 }
 
 // ---------------------------------------------------------------------------
-// Single-image launches: one workgroup per tile of the colour.
+// Single-image half-pass: one workgroup per tile of the colour.
 // ---------------------------------------------------------------------------
-template <int HALF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
-void init_kernel(PassArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int L = tile_of_block(a.n_tiles, a.order);
-    if (L < 0) return;
-    init_body<HALF>(a, L, smem);
-}
-
 template <int HALF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
 void pass_kernel(PassArgs a) {
@@ -1145,9 +1211,11 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
-    const size_t lds = pass_lds_bytes(a.n_src);
-    if (half) AMH_LAUNCH(init_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
-    else AMH_LAUNCH(init_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    const int G = std::min(kInitMaxPix, 256 / a.n_src);
+    const long long slots = (long long)a.ref.H * ((a.ref.W + 1) / 2);
+    const dim3 grid((unsigned)((slots + G - 1) / G));
+    if (half) AMH_LAUNCH(init_pix_kernel<1>, grid, dim3(256), 0, s, a);
+    else AMH_LAUNCH(init_pix_kernel<0>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
