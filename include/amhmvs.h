@@ -87,7 +87,9 @@ typedef struct {
     int n1, n2, k;                      /* good-view counts and top-k (Sec. 3.2) */
     uint64_t seed;                      /* key of the counter-based random generator */
     int timing;                         /* 1: record per-pass device times (amh_get_stats) */
-    float conf_min;                     /* learned proposal: lowest confidence that replaces a random plane */
+    float conf_min;                     /* learned proposal: lowest confidence that replaces a random plane
+                                         * (default 0: on held-out 1920x1280 scenes every in-range predicted
+                                         * plane beat a random one after one iteration) */
 } amh_params;
 
 /* Counters of the work performed since the last amh_begin / amh_run_checkerboard. */
@@ -110,7 +112,7 @@ typedef struct {
 } amh_job;
 
 /* Fills *out with the paper's parameters, depth range [2, 6], refine 1,
- * include_self 1, seed 0, timing 0, conf_min 0.5.  INVALID_ARG if out is NULL. */
+ * include_self 1, seed 0, timing 0, conf_min 0.  INVALID_ARG if out is NULL. */
 amh_status amh_params_default(amh_params *out);
 
 /* Creates a context on the current HIP device.  p: parameters (copied).
@@ -184,15 +186,21 @@ amh_status amh_get_job_result(amh_ctx *ctx, int job, float *depth, float *normal
  * n must equal the batch's job count.  Synchronises the stream. */
 amh_status amh_get_job_times(amh_ctx *ctx, int n, float *job_ms);
 
-/* Autotuner: times the batch under each launch configuration (tile order:
- * XCD bands or hardware order, x job order: as given or largest first;
- * configuration = tile_order + 2 * job_order), keeps the fastest for the
- * following launches of this context (single images included) and returns
- * it in *best_config (may be NULL) with the measured ms in ms_per_config[4]
- * (may be NULL; -1 where not measured).  If the environment variable
- * AMH_TUNE_CACHE names a file, the choice is looked up there by shape bucket
- * (job count, largest view count, pixel count) and appended after tuning. */
+/* Autotuner: times the batch under each launch configuration -- tile order (XCD
+ * bands or hardware order) x job order (as given or largest first) x tile shape
+ * of the half-pass (4 or 2 image rows per workgroup); configuration =
+ * tile_order + 2 * job_order + 4 * (two-row tiles) -- keeps the fastest for the
+ * following launches of this context (single images included) and returns it in
+ * *best_config (may be NULL) with the measured ms in ms_per_config[8] (may be
+ * NULL; -1 where not measured).  If the environment variable AMH_TUNE_CACHE
+ * names a file, the choice is looked up there by shape bucket (job count,
+ * largest view count, pixel count) and appended after tuning. */
 amh_status amh_tune(amh_ctx *ctx, int n_jobs, const amh_job *jobs, int *best_config, float *ms_per_config);
+
+/* Sets the launch configuration (0..7, numbered as for amh_tune) for the
+ * following launches of this context; results do not depend on it.
+ * INVALID_ARG outside 0..7. */
+amh_status amh_set_launch_config(amh_ctx *ctx, int config);
 
 /* Work counters and timings of the current reference (or of the last batch). */
 amh_status amh_get_stats(const amh_ctx *ctx, amh_stats *out);

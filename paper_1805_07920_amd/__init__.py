@@ -26,11 +26,11 @@ EXPORTS = [
     "amh_status_str", "amh_last_error", "amh_destroy",
     "amh_nn_param_count", "amh_nn_init", "amh_nn_get_params", "amh_nn_set_params", "amh_nn_get_grads",
     "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
-    "amh_init_from_proposal", "amh_run_proposal",
+    "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config",
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
-N_TUNE_CONFIGS = 4  # tile order {XCD bands, hardware} x job order {given, largest first}
+N_TUNE_CONFIGS = 8  # tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2}
 
 
 class AmhError(RuntimeError):
@@ -113,6 +113,7 @@ def lib():
         L.amh_sweep_features.argtypes = [vp, vp, vp]
         L.amh_init_from_proposal.argtypes = [vp, vp, ip, ip]
         L.amh_run_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
+        L.amh_set_launch_config.argtypes = [vp, ip]
         _lib = L
     return _lib
 
@@ -312,6 +313,10 @@ class Context:
         self._check(self.L.amh_tune(self.h, len(jobs), arr, C.byref(best), ms), "amh_tune")
         self._jobs_shape = [self._views_shape[int(jb["ref"])] for jb in jobs]
         return int(best.value), list(ms)
+
+    def set_launch_config(self, config: int):
+        """Launch configuration 0..7 (tile order + 2 job order + 4 two-row tiles); results do not depend on it."""
+        self._check(self.L.amh_set_launch_config(self.h, int(config)), "amh_set_launch_config")
 
     def get_job_times(self):
         n = len(self._jobs_shape)

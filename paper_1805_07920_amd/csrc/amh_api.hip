@@ -167,10 +167,11 @@ PassArgs pass_args(amh_ctx *c, int t, int colour) {
     const int W = c->refdev.W, H = c->refdev.H;
     const int per_row = (W + 1) / 2;  // same-colour pixels per row (upper bound)
     a.tiles_x = (per_row + kTilePix - 1) / kTilePix;
-    const int tiles_y = (H + kTileRows - 1) / kTileRows;
+    const int tiles_y = (H + c->cfg_waves - 1) / c->cfg_waves;
     a.n_tiles = a.tiles_x * tiles_y;
     a.counters = c->counters;
     a.order = c->cfg_order;
+    a.waves = c->cfg_waves;
     return a;
 }
 
@@ -208,7 +209,15 @@ amh_status ensure_events(amh_ctx *c, int n) {
 }
 
 
-constexpr int kTuneConfigs = 4;  // tile order {XCD bands, hardware} x job order {given, largest first}
+// launch configurations: tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2};
+// configuration = tile_order + 2 job_order + 4 (tile rows == 2)
+constexpr int kTuneConfigs = 8;
+
+void apply_config(amh_ctx *c, int cfg) {
+    c->cfg_order = cfg & 1;
+    c->cfg_job_order = (cfg >> 1) & 1;
+    c->cfg_waves = (cfg & 4) ? 2 : kDefaultTileRows;
+}
 
 amh_status check_jobs(amh_ctx *c, int n_jobs, const amh_job *jobs) {
     if (!jobs || n_jobs < 1 || n_jobs > 4096) return fail(c, AMH_E_INVALID_ARG, "need 1 <= n_jobs <= 4096 jobs");
@@ -296,7 +305,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         b.n_src = jobs[j].n_src;
         b.st = StateDev{c->jobs[j].planes, c->jobs[j].cost, c->jobs[j].S, c->jobs[j].v};
         b.tiles_x = ((r.W + 1) / 2 + kTilePix - 1) / kTilePix;
-        b.n_tiles = b.tiles_x * ((r.H + kTileRows - 1) / kTileRows);
+        b.n_tiles = b.tiles_x * ((r.H + c->cfg_waves - 1) / c->cfg_waves);
         so += jobs[j].n_src;
     }
     // job order within a phase: as given, or the largest first (shorter tail)
@@ -398,6 +407,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         b.colour = ph.colour;
         b.kind = ph.kind;
         b.order = c->cfg_order;
+        b.waves = c->cfg_waves;
         b.counters = c->d_bcount;
         b.tiles_done = tiles_done;
         b.job_end = clocks;
@@ -450,7 +460,7 @@ amh_status amh_params_default(amh_params *out) {
     out->k = 4;
     out->seed = 0;
     out->timing = 0;
-    out->conf_min = 0.5f;
+    out->conf_min = 0.0f;  // measured best after one iteration (see amhmvs.h)
     return AMH_OK;
 }
 
@@ -794,7 +804,7 @@ amh_status amh_run_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
     if (!c) return AMH_E_INVALID_ARG;
     amh_status st = check_jobs(c, n_jobs, jobs);
     if (st != AMH_OK) return st;
-    std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order};
+    std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order, c->cfg_waves};
     for (int j = 0; j < n_jobs; ++j) {
         key.push_back(jobs[j].ref);
         key.push_back(jobs[j].n_src);
@@ -856,6 +866,14 @@ amh_status amh_get_job_times(amh_ctx *c, int n, float *job_ms) {
     return AMH_OK;
 }
 
+amh_status amh_set_launch_config(amh_ctx *c, int config) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (config < 0 || config >= kTuneConfigs)
+        return fail(c, AMH_E_INVALID_ARG, "launch configuration %d outside 0..%d", config, kTuneConfigs - 1);
+    apply_config(c, config);
+    return AMH_OK;
+}
+
 amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_config, float *ms_per_config) {
     if (!c) return AMH_E_INVALID_ARG;
     amh_status st = check_jobs(c, n_jobs, jobs);
@@ -868,8 +886,8 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
         px += (double)c->views[jobs[j].ref].W * c->views[jobs[j].ref].H;
     }
     char bucket[128];
-    snprintf(bucket, sizeof bucket, "gfx950/jobs%d/src%d/px2^%d/half%d", n_jobs, max_src, (int)std::ceil(std::log2(px + 1)),
-             c->half);
+    snprintf(bucket, sizeof bucket, "gfx950/cfg8/jobs%d/src%d/px2^%d/half%d", n_jobs, max_src,
+             (int)std::ceil(std::log2(px + 1)), c->half);
     const char *path = getenv("AMH_TUNE_CACHE");
     int cached = -1;
     if (path) {
@@ -891,8 +909,7 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
         HIPCHK(c, hipEventCreate(&e1));
         float best_ms = 0.f;
         for (int cfg = 0; cfg < kTuneConfigs; ++cfg) {
-            c->cfg_order = cfg & 1;
-            c->cfg_job_order = (cfg >> 1) & 1;
+            apply_config(c, cfg);
             if ((st = amh_run_batch(c, n_jobs, jobs)) != AMH_OK) return st;  // build + warm
             HIPCHK(c, hipEventRecord(e0, c->stream));
             if ((st = amh_run_batch(c, n_jobs, jobs)) != AMH_OK) return st;  // replay, timed
@@ -914,8 +931,7 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
             }
         }
     }
-    c->cfg_order = best & 1;
-    c->cfg_job_order = (best >> 1) & 1;
+    apply_config(c, best);
     if (best_config) *best_config = best;
     if (ms_per_config)
         for (int i = 0; i < kTuneConfigs; ++i) ms_per_config[i] = ms[i];

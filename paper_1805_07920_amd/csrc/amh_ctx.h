@@ -63,6 +63,7 @@ struct amh_ctx {
     // launch configuration (autotuned): tile order of a launch, job order of a batch
     int cfg_order = 0;
     int cfg_job_order = 1;
+    int cfg_waves = kDefaultTileRows;  // tile rows of the half-pass (2 or 4)
     // batch: per-job state, device tables and the captured graph of the last job list
     std::vector<JobResult> jobs;
     std::vector<int> batch_key;       // serialized job list of the captured graph

@@ -8,11 +8,12 @@ namespace amh {
 
 constexpr int kMaxSrc = 32;
 constexpr int kCounterSlots = 256;    // eval counters are spread over slots to avoid one hot atomic
-constexpr int kWaves = 4;             // waves per workgroup of the pass kernels
 constexpr int kGroups = 7;            // pixels per wave (7 groups x 9 lanes = 63 lanes)
 constexpr int kRows = 9;              // 8 propagated hypotheses + the pixel's own
-constexpr int kTileRows = kWaves;     // image rows per workgroup tile
 constexpr int kTilePix = kGroups;     // same-colour pixels per tile row
+// image rows per workgroup tile of the half-pass (one wave per row): 4 by default, 2 as the
+// autotuner's alternative tile shape
+constexpr int kDefaultTileRows = 4;
 
 // One source view relative to the current reference (Sec. 3.3: plane-induced warp).
 // Homogeneous source pixel of reference pixel (x, y) on the plane with inverse
@@ -57,10 +58,11 @@ struct PassArgs {
     int tiles_x, n_tiles;        // tile grid of this colour
     unsigned long long *counters;  // [3][kCounterSlots]: init, propagation, refinement evals
     int order;                   // tile order: 0 XCD bands, 1 hardware order
+    int waves = kDefaultTileRows;  // tile rows = waves per workgroup (2 or 4)
     // initialisation from per-cell predictions (NULL: random initialisation)
     const float *prop = nullptr;  // [prop_h][prop_w][5]: depth, normal (3), confidence
     int prop_w = 0, prop_s = 0;   // cell grid width, cell size in reference pixels
-    float conf_min = 0.5f;
+    float conf_min = 0.f;
 };
 
 // one reference image of a batch
@@ -84,6 +86,7 @@ struct BatchPhaseArgs {
     MethodDev m;
     int t, colour, kind;         // kind 0: init, 1: half-pass
     int order;
+    int waves;                   // tile rows = waves per workgroup (2 or 4)
     unsigned long long *counters;
     unsigned long long *tiles_done;  // [n_jobs] tiles finished in the job's last phase
     unsigned long long *job_end; // [n_jobs] device clock at the job's completion
@@ -132,6 +135,6 @@ hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, f
 hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *p, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs &a, int half, hipStream_t s);
-size_t pass_lds_bytes(int n_src);
+size_t pass_lds_bytes(int n_src, int waves);
 
 }  // namespace amh

@@ -402,7 +402,7 @@ __device__ __forceinline__ int tile_of_block(int n_tiles, int order) {
 
 // LDS carve-up of the pass / init kernels
 struct PassLds {
-    float *tile;     // kTileRows + 10 rows x (2 * kTilePix + 10) cols of reference intensities
+    float *tile;     // WAVES + 10 rows x (2 * kTilePix + 10) cols of reference intensities
     float2 *rw;      // [wave][group][kWinStride] window blocks
     float4 *pl;      // [256] hypothesis of each lane
     float *ms;       // [wave][n_src][64] costs, reused for refinement results
@@ -414,34 +414,34 @@ struct PassLds {
     float *wgt;      // [wave][group][32] view weights of each pixel
 };
 
-constexpr int kTileH = kTileRows + 10;
 constexpr int kTileW = 2 * kTilePix + 10;
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t lds_layout(int n_src, size_t off[10]) {
+// LDS of a workgroup of `waves` waves (one image row of the tile per wave)
+__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[10]) {
     size_t o = 0;
-    off[0] = o; o = align16(o + sizeof(float) * kTileH * kTileW);
-    off[1] = o; o = align16(o + sizeof(float2) * kWaves * kGroups * kWinStride);
-    off[2] = o; o = align16(o + sizeof(float4) * 256);
-    off[3] = o; o = align16(o + sizeof(float) * kWaves * (n_src > 7 ? n_src : 7) * 64);
-    off[4] = o; o = align16(o + sizeof(float) * 256);
-    off[5] = o; o = align16(o + sizeof(float) * kWaves * kGroups * kMaxSrc);
-    off[6] = o; o = align16(o + sizeof(int) * 256);
-    off[7] = o; o = align16(o + kWaves * kGroups * kMaxSrc);
-    off[8] = o; o = align16(o + sizeof(float4) * kWaves * kGroups * 6);
-    off[9] = o; o = align16(o + sizeof(float) * kWaves * kGroups * kMaxSrc);
+    off[0] = o; o = align16(o + sizeof(float) * (waves + 10) * kTileW);
+    off[1] = o; o = align16(o + sizeof(float2) * waves * kGroups * kWinStride);
+    off[2] = o; o = align16(o + sizeof(float4) * waves * 64);
+    off[3] = o; o = align16(o + sizeof(float) * waves * (n_src > 7 ? n_src : 7) * 64);
+    off[4] = o; o = align16(o + sizeof(float) * waves * 64);
+    off[5] = o; o = align16(o + sizeof(float) * waves * kGroups * kMaxSrc);
+    off[6] = o; o = align16(o + sizeof(int) * waves * 64);
+    off[7] = o; o = align16(o + waves * kGroups * kMaxSrc);
+    off[8] = o; o = align16(o + sizeof(float4) * waves * kGroups * 6);
+    off[9] = o; o = align16(o + sizeof(float) * waves * kGroups * kMaxSrc);
     return o;
 }
 
-size_t pass_lds_bytes(int n_src) {
+size_t pass_lds_bytes(int n_src, int waves) {
     size_t off[10];
-    return lds_layout(n_src, off);
+    return lds_layout(n_src, waves, off);
 }
 
-__device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src) {
+__device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int waves) {
     size_t off[10];
-    lds_layout(n_src, off);
+    lds_layout(n_src, waves, off);
     PassLds L;
     L.tile = reinterpret_cast<float *>(smem + off[0]);
     L.rw = reinterpret_cast<float2 *>(smem + off[1]);
@@ -456,9 +456,10 @@ __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src) {
     return L;
 }
 
-// reference tile of a workgroup: rows y0-5 .. y0+kTileRows+4, cols x0-5 .. x0+2*kTilePix+4, clamped
+// reference tile of a workgroup: rows y0-5 .. y0+WAVES+4, cols x0-5 .. x0+2*kTilePix+4, clamped
+template <int WAVES>
 __device__ __forceinline__ void stage_tile(const RefDev &ref, float *tile, int y0, int x0) {
-    for (int i = threadIdx.x; i < kTileH * kTileW; i += blockDim.x) {
+    for (int i = threadIdx.x; i < (WAVES + 10) * kTileW; i += blockDim.x) {
         const int ty = i / kTileW, tx = i - ty * kTileW;
         const int gy = min(max(y0 - 5 + ty, 0), ref.H - 1);
         const int gx = min(max(x0 - 5 + tx, 0), ref.W - 1);
@@ -493,7 +494,8 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
     unsigned long long tot = n;
     for (int off = 32; off > 0; off >>= 1) tot += __shfl_down(tot, off, 64);
     if (lane == 0 && tot)
-        atomicAdd(&counters[kind * kCounterSlots + ((blockIdx.x * kWaves + (threadIdx.x >> 6)) % kCounterSlots)], tot);
+        atomicAdd(&counters[kind * kCounterSlots + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCounterSlots)],
+                  tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,18 +539,18 @@ __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int 
 // lowest per-view costs.  Same tile mapping as the pass, one launch per
 // colour.  Lane r of a pixel scores views r, r+9, r+18, r+27.
 // ---------------------------------------------------------------------------
-template <int HALF>
+template <int HALF, int WAVES>
 __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned char *smem) {
-    PassLds S = carve(smem, a.n_src);
+    PassLds S = carve(smem, a.n_src, WAVES);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int grp = lane / kRows, row = lane - grp * kRows;
     const int ty = L / a.tiles_x, tx = L - ty * a.tiles_x;
-    const int y0 = ty * kTileRows, x0 = tx * 2 * kTilePix;
+    const int y0 = ty * WAVES, x0 = tx * 2 * kTilePix;
     const int y = y0 + wave;
     const int x = 2 * (tx * kTilePix + grp) + ((y + a.colour) & 1);
     const bool pix_ok = grp < kGroups && y < a.ref.H && x < a.ref.W;
 
-    stage_tile(a.ref, S.tile, y0, x0);
+    stage_tile<WAVES>(a.ref, S.tile, y0, x0);
     __syncthreads();
     float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * kWinStride;
     WinStats ws = {1.f, 0.f};
@@ -680,14 +682,14 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
 // ---------------------------------------------------------------------------
 // One checkerboard half-pass (Sec. 3.1 - 3.3).
 // ---------------------------------------------------------------------------
-template <int HALF>
+template <int HALF, int WAVES>
 __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned char *smem) {
-    PassLds S = carve(smem, a.n_src);
+    PassLds S = carve(smem, a.n_src, WAVES);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int grp = lane / kRows, row = lane - grp * kRows;
     const int g = grp < kGroups ? grp : 0;
     const int ty = L / a.tiles_x, tx = L - ty * a.tiles_x;
-    const int y0 = ty * kTileRows, x0 = tx * 2 * kTilePix;
+    const int y0 = ty * WAVES, x0 = tx * 2 * kTilePix;
     const int y = y0 + wave;
     const int x = 2 * (tx * kTilePix + grp) + ((y + a.colour) & 1);
     const int W = a.ref.W, H = a.ref.H;
@@ -696,7 +698,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     const int N = a.n_src;
     const MethodDev &m = a.m;
 
-    stage_tile(a.ref, S.tile, y0, x0);
+    stage_tile<WAVES>(a.ref, S.tile, y0, x0);
 
     // (1) asymmetric propagation: lane r < 8 takes the lowest-cost candidate of region r
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
@@ -936,13 +938,13 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
 // ---------------------------------------------------------------------------
 // Single-image half-pass: one workgroup per tile of the colour.
 // ---------------------------------------------------------------------------
-template <int HALF>
+template <int HALF, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
 void pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = tile_of_block(a.n_tiles, a.order);
     if (L < 0) return;
-    pass_body<HALF>(a, L, smem);
+    pass_body<HALF, WAVES>(a, L, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -953,7 +955,7 @@ void pass_kernel(PassArgs a) {
 // workgroup that finishes the last tile of a job's last phase stamps the
 // device clock (per-job completion time within the batch).
 // ---------------------------------------------------------------------------
-template <int HALF>
+template <int HALF, int WAVES>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
 void batch_kernel(BatchPhaseArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -990,8 +992,8 @@ void batch_kernel(BatchPhaseArgs b) {
     a.counters = b.counters;
     a.order = b.order;
     const int L = g - b.tile_start[lo];
-    if (b.kind == 0) init_body<HALF>(a, L, smem);
-    else pass_body<HALF>(a, L, smem);
+    if (b.kind == 0) init_body<HALF, WAVES>(a, L, smem);
+    else pass_body<HALF, WAVES>(a, L, smem);
     if (b.is_last[lo]) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1220,17 +1222,33 @@ hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
 }
 
 hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
-    const size_t lds = pass_lds_bytes(a.n_src);
-    if (half) AMH_LAUNCH(pass_kernel<1>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
-    else AMH_LAUNCH(pass_kernel<0>, dim3(grid_for(a.n_tiles)), dim3(256), lds, s, a);
+    const size_t lds = pass_lds_bytes(a.n_src, a.waves);
+    const dim3 grid(grid_for(a.n_tiles)), block(64 * a.waves);
+    if (a.waves == 2) {
+        if (half) AMH_LAUNCH((pass_kernel<1, 2>), grid, block, lds, s, a);
+        else AMH_LAUNCH((pass_kernel<0, 2>), grid, block, lds, s, a);
+    } else if (a.waves == 4) {
+        if (half) AMH_LAUNCH((pass_kernel<1, 4>), grid, block, lds, s, a);
+        else AMH_LAUNCH((pass_kernel<0, 4>), grid, block, lds, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s) {
     if (b.total_tiles == 0) return hipSuccess;
-    const size_t lds = pass_lds_bytes(max_src);
-    if (half) AMH_LAUNCH(batch_kernel<1>, dim3(b.grid), dim3(256), lds, s, b);
-    else AMH_LAUNCH(batch_kernel<0>, dim3(b.grid), dim3(256), lds, s, b);
+    const size_t lds = pass_lds_bytes(max_src, b.waves);
+    const dim3 grid(b.grid), block(64 * b.waves);
+    if (b.waves == 2) {
+        if (half) AMH_LAUNCH((batch_kernel<1, 2>), grid, block, lds, s, b);
+        else AMH_LAUNCH((batch_kernel<0, 2>), grid, block, lds, s, b);
+    } else if (b.waves == 4) {
+        if (half) AMH_LAUNCH((batch_kernel<1, 4>), grid, block, lds, s, b);
+        else AMH_LAUNCH((batch_kernel<0, 4>), grid, block, lds, s, b);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

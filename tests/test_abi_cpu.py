@@ -69,7 +69,7 @@ def test_null_arguments(amh):
                  lambda: L.amh_score_fixed(None, None, None, 0, None, 0), lambda: L.amh_run_batch(None, 0, None),
                  lambda: L.amh_get_job_result(None, 0, None, None, None, 0),
                  lambda: L.amh_get_job_times(None, 0, None), lambda: L.amh_tune(None, 0, None, None, None),
-                 lambda: L.amh_get_stats(None, None)):
+                 lambda: L.amh_get_stats(None, None), lambda: L.amh_set_launch_config(None, 0)):
         assert call() == amh.AMH_E_INVALID_ARG
     L.amh_destroy(None)
     assert L.amh_last_error(None) == b"NULL context"
@@ -108,7 +108,7 @@ def test_nn_null_arguments_and_count(amh):
 
 def test_conf_min_validated(amh):
     p = amh.params_default()
-    assert p.conf_min == 0.5
+    assert p.conf_min == 0.0
     for bad in (-0.1, 1.5, float("nan")):
         p.conf_min = bad
         assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(p), None) == amh.AMH_E_INVALID_ARG

@@ -143,3 +143,23 @@ def test_batch_errors(amh, batch_setup):
         with pytest.raises(amh.AmhError) as e:
             ctx.run_batch(bad)
         assert e.value.status == amh.AMH_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("config", [1, 4, 5])
+def test_single_image_launch_configurations_agree(amh, batch_setup, config):
+    """Tile order and tile shape (4- or 2-row workgroups) change only the launch, not the result."""
+    say(f"case launch config {config}")
+    images, cams, jobs = batch_setup
+    jb = jobs[0]
+    with amh.Context(refine=1, seed=3) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_checkerboard(jb["ref"], jb["srcs"], 2)
+        ref = ctx.get_state()
+        ctx.set_launch_config(config)
+        ctx.run_checkerboard(jb["ref"], jb["srcs"], 2)
+        out = ctx.get_state()
+        with pytest.raises(amh.AmhError) as e:
+            ctx.set_launch_config(8)
+        assert e.value.status == amh.AMH_E_INVALID_ARG
+    for x, y in zip(ref, out):
+        assert np.array_equal(x, y)

@@ -359,6 +359,22 @@ def test_sweep_features_two_sub_planes_ten_sources(amh, oracle_mod):
     assert st["evals_init"] == 16 * 80 * 24 * 4
 
 
+def test_sweep_features_fp16_sources(amh, oracle_mod):
+    """Sources stored as float16: the sweep reads the texel quads of the half-precision layout; the
+    oracle reads the same fp16-rounded values."""
+    say("case sweep features 96x64, fp16 sources")
+    import scenegen
+
+    sc = scenegen.make_scene(96, 64, 6, 30.0, 3, 3, src_dtype="f16", supersample=2)
+    ctx = amh.Context()
+    ctx.init_views([np.ascontiguousarray(im) for im in sc.images], sc.cams, store_as=amh.AMH_F16)
+    with ctx:
+        ctx.begin(0, list(range(1, 7)))
+        fd, qd = ctx.sweep_features()
+        f, q = fd.float().cpu().numpy().astype(np.float64), qd.cpu().numpy().astype(np.float64)
+    check_features(f, q, oracle_mod.Views(sc.images[:5], sc.cams[:5]), oracle_mod.Params())
+
+
 def proposal_maps(sc, seed, h, w):
     rng = np.random.default_rng(seed)
     depth = rng.uniform(2.3, 5.7, (h, w)).astype(np.float32)
@@ -377,7 +393,7 @@ def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
 
     sc = scene_c1
     pred = proposal_maps(sc, 4, 24, 32)
-    with make_ctx(amh, sc, seed=13) as ctx:
+    with make_ctx(amh, sc, seed=13, conf_min=0.5) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
         ctx.init_from_proposal(dev(pred, torch.float32))
         pl, cost, S, v = ctx.get_state()
