@@ -1,0 +1,169 @@
+"""GPU parity of the learned proposal at the measured size (1920x1280, 10 sources,
+held-out scene, the trained weights), in the launch configuration bench.py times.
+
+The oracle recomputes what it can one by one: the sweep of sampled cells, the
+network's forward on the whole 480 x 320 input (float64 NumPy, with the
+device's bf16 storage points), and the proposal initialisation of sampled
+pixels from the device's own prediction.  Bars as in tests/test_gpu_nn.py,
+except the network forward, which is held per cell to the method's depth
+parity bar (see test_network_forward_full_input).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as nn
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_1805_07920_amd", "weights", "proposal.bin")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1805_07920_amd as amh
+    import scenegen
+
+    say("rendering c2 seed 1")
+    sc = scenegen.config_scene("c2", 1, device="cuda")
+    ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
+    srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]
+    ctx = amh.Context(seed=5)
+    ctx.init_views([torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in sc.images], sc.cams)
+    best, _ = ctx.tune([dict(ref=0, srcs=srcs, iters=3)])  # as bench.py does
+    ctx.init_views([torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in sc.images], sc.cams)
+    ctx.nn_load(WEIGHTS)
+    ctx.begin(0, srcs)
+    f, q = ctx.sweep_features()
+    pred = ctx.nn_forward(f[None], q[None])[0].contiguous()
+    out = dict(amh=amh, sc=sc, srcs=srcs, ctx=ctx, f=f.float().cpu().numpy().astype(np.float64),
+               q=q.cpu().numpy().astype(np.float64), pred=pred, config=best)
+    yield out
+    ctx.close()
+
+
+def oracle_views(sc, srcs, n=None):
+    import oracle
+
+    order = srcs if n is None else srcs[:n]
+    return oracle.Views([sc.images[0]] + [sc.images[j] for j in order], [sc.cams[0]] + [sc.cams[j] for j in order])
+
+
+def test_sweep_sampled_cells(setup):
+    import oracle
+    from oracle import proposal
+
+    sc, f, q = setup["sc"], setup["f"], setup["q"]
+    say(f"case fullsize sweep, launch config {setup['config']}")
+    V = oracle_views(sc, setup["srcs"], 4)
+    P = oracle.Params()
+    rng = np.random.default_rng(0)
+    h4, w4 = f.shape[:2]
+    cells = [(int(rng.integers(0, h4)), int(rng.integers(0, w4))) for _ in range(48)]
+    cells += [(0, 0), (h4 - 1, w4 - 1), (0, w4 - 1), (h4 - 1, 0)]
+    D = 12 * proposal.sub_bins(sc.width)
+    qf, qn = 1.0 / P.d_max, 1.0 / P.d_min
+    robust = 0
+    for i, j in cells:
+        a = proposal.sweep_costs(V, P, 4 * j + 2, 4 * i + 2)
+        k = int(np.argmin(a))
+        want = np.r_[1.0 - a[k], 1.0 - a.reshape(12, -1).min(axis=1)]
+        got = np.r_[f[i, j, 3], f[i, j, 4:]]
+        assert np.all(np.abs(got - want) <= 2.0 ** -8 * np.abs(want) + 2e-4), (i, j)
+        srt = np.sort(a)
+        if srt[1] - srt[0] > 2e-4:
+            robust += 1
+            assert q[i, j] == pytest.approx(qf + (k + 0.5) * (qn - qf) / D, rel=1e-6), (i, j)
+            assert f[i, j, 2] == pytest.approx(2.0 * (k + 0.5) / D - 1.0, rel=2.0 ** -8, abs=1e-6)
+    say(f"  {len(cells)} cells, winner compared on {robust}")
+    assert robust >= 0.8 * len(cells)
+
+
+def test_network_forward_full_input(setup):
+    """The whole 480 x 320 forward against the oracle with the device's bf16 storage points."""
+    import paper_1805_07920_amd as amh
+
+    say("case fullsize network forward 480x320")
+    ctx = setup["ctx"]
+    theta = ctx.nn_get_params().astype(np.float64)
+    r = nn.bf16_round
+    # the device multiplies by the bf16 copy of the fp32 master weights (biases stay fp32)
+    P = {k: (r(W), b) for k, (W, b) in nn.unflatten(theta).items()}
+    x = setup["f"][None]
+
+    def cr(name, inp):
+        W, b = P[name]
+        return r(nn.relu(nn.conv(inp, W, b)))
+
+    e0 = cr("enc0b", cr("enc0a", x))
+    e1 = cr("enc1b", cr("enc1a", r(nn.pool(e0))))
+    e2 = cr("enc2b", cr("enc2a", r(nn.pool(e1))))
+    e3 = cr("enc3b", cr("enc3a", r(nn.pool(e2))))
+    d2 = cr("dec2", np.concatenate([nn.up(e3), e2], 3))
+    d1 = cr("dec1", np.concatenate([nn.up(d2), e1], 3))
+    d0 = cr("dec0", np.concatenate([nn.up(d1), e0], 3))
+    W, b = P["head"]
+    z = nn.conv(d0, W, b)[0]
+    depth, normal, conf = nn.decode(z, setup["q"], 2.0, 6.0)
+    out = setup["pred"].cpu().numpy().astype(np.float64)
+    rel = np.abs(out[..., 0] - depth) / depth
+    ang = np.degrees(np.arccos(np.clip((out[..., 1:4] * normal).sum(-1), -1, 1)))
+    dc = np.abs(out[..., 4] - conf)
+    say(f"  depth rel err median {np.median(rel):.1e} p99 {np.percentile(rel, 99):.1e} max {rel.max():.1e}; "
+        f"normal p99 {np.percentile(ang, 99):.3f} max {ang.max():.3f} deg; confidence max {dc.max():.2e}")
+    # Most cells agree to fp32 rounding; where fp32 and float64 put a stored activation on different
+    # sides of a bf16 rounding boundary, the one-step difference spreads over the receptive field of
+    # the later layers (one step of a large last-layer activation moves the head's depth output by
+    # up to ~0.3 %).  Bound: the full-run depth bar of the method, for the same reason (discrete
+    # decisions may flip): >= 99.5 % of the cells within 0.1 %, and every cell within 1 %.
+    assert np.median(rel) <= 1e-5
+    assert (rel <= 1e-3).mean() >= 0.995
+    assert rel.max() <= 1e-2
+    assert np.percentile(ang, 99) <= 0.5 and ang.max() <= 2.0 and dc.max() <= 2e-2
+    assert amh.NET_OUT == 5
+
+
+def test_proposal_init_sampled_pixels(setup):
+    """Initialisation from the device's own prediction, recomputed by the oracle pixel by pixel."""
+    import oracle
+    from oracle import proposal
+
+    say("case fullsize proposal init")
+    ctx, sc = setup["ctx"], setup["sc"]
+    ctx.begin(0, setup["srcs"])
+    ctx.init_from_proposal(setup["pred"])
+    pl, cost, S, v = ctx.get_state()
+    pred = setup["pred"].cpu().numpy().astype(np.float64)
+    V = oracle_views(sc, setup["srcs"])
+    P = oracle.Params(seed=5, d_min=2.0, d_max=6.0)
+    rng = np.random.default_rng(1)
+    H, W = sc.height, sc.width
+    pts = [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(160)] + [(0, 0), (W - 1, H - 1)]
+    kk = min(P.k, V.n_src)
+    near, checked = 0, 0
+    for x, y in pts:
+        want, used = proposal.proposal_plane(V, P, x, y, pred[..., 0], pred[..., 1:4], pred[..., 4], 0.0)
+        if used:
+            nr = want[:3] @ (proposal._kinv(V) @ [x, y, 1.0])
+            d = -want[3] / nr
+            if min(abs(d - 2.0), abs(d - 6.0)) < 6e-4:
+                near += 1
+                continue
+        checked += 1
+        np.testing.assert_allclose(pl[y, x], want, atol=2e-5, rtol=2e-5)
+        c = sorted(oracle.matching_cost(V, P, x, y, want, j) for j in range(V.n_src))
+        assert abs(cost[y, x] - np.mean(c[:kk])) <= 1e-4, (x, y)
+    say(f"  {checked} pixels checked, {near} at a range end skipped")
+    assert np.all(S == 0) and np.all(v == -1)

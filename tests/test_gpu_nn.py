@@ -68,7 +68,8 @@ def emulated(theta, x, q_ref=None, t=None, d_min=2.0, d_max=6.0):
     rounded to bf16 at the points where the device stores them.  Returns the head
     output z, and with targets t also the loss and the flat gradient."""
     r = nn.bf16_round
-    P = nn.unflatten(theta)
+    # weights are multiplied in their bf16 copy (biases stay fp32)
+    P = {k: (r(W), b) for k, (W, b) in nn.unflatten(theta).items()}
     A = {"x": x}
 
     def cr(name, inp):
