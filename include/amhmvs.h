@@ -264,7 +264,9 @@ amh_status amh_nn_save(amh_ctx *ctx, const char *path);
 amh_status amh_nn_load(amh_ctx *ctx, const char *path);
 
 /* Network input of the current reference (amh_begin), one 16-channel vector per
- * 4 x 4 cell.  A plane sweep at the cell's pixel (4j + 2, 4i + 2) scores
+ * cell of 4 x 4 pixels on a grid of h4 = 8 ceil(H/32) rows x w4 = 8 ceil(W/32)
+ * columns (cells past the image repeat its edge: coordinates are clamped).  A
+ * plane sweep at the cell's pixel (min(4j + 2, W - 1), min(4i + 2, H - 1)) scores
  * D = 12 m fronto-parallel planes, m = max(1, (W + 80) / 160) (integer
  * division), at inverse depths 1/depth_max + (i + 1/2) (1/depth_min -
  * 1/depth_max) / D; a plane's aggregate is the mean of the min(2, n) lowest
@@ -273,14 +275,15 @@ amh_status amh_nn_load(amh_ctx *ctx, const char *path);
  * deviation / 32, 2 (i* + 1/2) / D - 1 for the lowest aggregate i* (first on
  * ties), 1 - that aggregate, and 1 - the lowest aggregate of each of the 12
  * coarse bins of m consecutive planes.  feats: device, bf16 bit patterns,
- * [H/4][W/4][16]; q_ref (device, float, [H/4][W/4], may be NULL): the winning
- * plane's inverse depth.  UNSUPPORTED unless W and H are multiples of 32. */
+ * [h4][w4][16]; q_ref (device, float, [h4][w4], may be NULL): the winning
+ * plane's inverse depth. */
 amh_status amh_sweep_features(amh_ctx *ctx, void *feats, float *q_ref);
 
 /* Initialisation from per-cell predictions pred (device, float, [h][w][5] as
- * amh_nn_forward writes them; cell size s = W/w = H/h, an integer): pixel
- * (x, y) takes the plane through the point at the predicted depth on the ray
- * of its cell's pixel (s j + s/2, s i + s/2) with the predicted normal, when
+ * amh_nn_forward writes them) on a grid of 4 x 4 cells covering the image
+ * (4 w >= W, 4 h >= H): pixel (x, y) takes the plane through the point at the
+ * predicted depth on the ray of its cell's pixel (min(4j + 2, W - 1),
+ * min(4i + 2, H - 1)), (i, j) = (y / 4, x / 4), with the predicted normal, when
  * the confidence is at least conf_min and that plane's depth along the pixel's
  * ray lies in [depth_min, depth_max]; otherwise the random plane of
  * amh_init_hypotheses.  Initial cost, S and v as there.  Replaces

@@ -2,9 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
 
-1. ``sweep_features``: the network's input at 1/4 resolution.  Cell (i, j)
-   covers reference pixels x in [4j, 4j + 4), y in [4i, 4i + 4) and is sampled
-   at pixel (4j + 2, 4i + 2).  A plane sweep scores D = 12 m fronto-parallel
+1. ``sweep_features``: the network's input at 1/4 resolution, on a grid of
+   8 ceil(H / 32) x 8 ceil(W / 32) cells (the network halves it three times).
+   Cell (i, j) covers reference pixels x in [4j, 4j + 4), y in [4i, 4i + 4),
+   coordinates clamped to the image (cells past the right or bottom edge repeat
+   the edge pixels), and is sampled at pixel (min(4j + 2, W - 1),
+   min(4i + 2, H - 1)).  A plane sweep scores D = 12 m fronto-parallel
    planes, m = max(1, floor((W + 80) / 160)) sub-planes per coarse bin (so one step
    moves a near source's warp by ~2 px at any image width), at inverse depths
    q_i = 1/d_max + (i + 0.5) (1/d_min - 1/d_max) / D; the aggregated cost of
@@ -18,11 +21,10 @@ TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
    ``sweep_reference_q`` gives the winning plane's inverse depth, the base that
    the network's depth head corrects.
 2. ``proposal_state``: the initial PatchMatch state built from per-cell
-   predictions (depth, unit normal, confidence) at a resolution whose cell is
-   s x s reference pixels (s = W / w = H / h).  Pixel (x, y) takes the plane of
-   its cell: through the 3-D point at the predicted depth on the ray of the
-   cell's sample pixel (s j + s/2, s i + s/2), with the predicted normal, turned
-   to face the pixel's own ray.  It is used when the confidence is at least
+   predictions (depth, unit normal, confidence) on the same grid of 4 x 4 cells.
+   Pixel (x, y) takes the plane of its cell (y // 4, x // 4): through the 3-D
+   point at the predicted depth on the ray of the cell's sample pixel, with the
+   predicted normal, turned to face the pixel's own ray.  It is used when the confidence is at least
    ``conf_min``, the normal is non-zero and the plane's depth along the pixel's
    ray lies in [d_min, d_max]; otherwise the pixel keeps the random plane of
    random initialisation (Sec. 3: random plane per pixel).  The initial cost is
@@ -42,6 +44,15 @@ CELL = 4
 
 def _kinv(views: Views) -> np.ndarray:
     return np.linalg.inv(np.array(views.c.Kref[:], np.float64).reshape(3, 3))
+
+
+def grid(H: int, W: int):
+    """Cell grid (h4, w4) of an H x W reference: 1/4 resolution rounded up to multiples of 8."""
+    return 8 * -(-H // 32), 8 * -(-W // 32)
+
+
+def sample_pixel(H: int, W: int, i: int, j: int):
+    return min(CELL * j + CELL // 2, W - 1), min(CELL * i + CELL // 2, H - 1)
 
 
 def sub_bins(width: int) -> int:
@@ -66,19 +77,21 @@ def sweep_costs(views: Views, params: Params, x: int, y: int) -> np.ndarray:
 
 
 def sweep_features(views: Views, params: Params) -> np.ndarray:
-    """(H/4, W/4, 16) float64 network input of the reference of ``views``."""
+    """(h4, w4, 16) float64 network input of the reference of ``views``."""
     H, W = views.H, views.W
-    h4, w4 = H // CELL, W // CELL
+    h4, w4 = grid(H, W)
     m = sub_bins(W)
     D = N_COARSE * m
     ref = views.images[0].astype(np.float64)
     F = np.zeros((h4, w4, 4 + N_COARSE))
     for i in range(h4):
         for j in range(w4):
-            blk = ref[CELL * i:CELL * i + CELL, CELL * j:CELL * j + CELL]
+            ys = np.minimum(np.arange(CELL * i, CELL * i + CELL), H - 1)
+            xs = np.minimum(np.arange(CELL * j, CELL * j + CELL), W - 1)
+            blk = ref[np.ix_(ys, xs)]
             F[i, j, 0] = (blk.mean() - 127.5) / 64.0
             F[i, j, 1] = blk.std() / 32.0
-            a = sweep_costs(views, params, CELL * j + CELL // 2, CELL * i + CELL // 2)
+            a = sweep_costs(views, params, *sample_pixel(H, W, i, j))
             best = int(np.argmin(a))
             F[i, j, 2] = 2.0 * (best + 0.5) / D - 1.0
             F[i, j, 3] = 1.0 - a[best]
@@ -87,29 +100,30 @@ def sweep_features(views: Views, params: Params) -> np.ndarray:
 
 
 def sweep_reference_q(views: Views, params: Params) -> np.ndarray:
-    """(H/4, W/4) inverse depth of each cell's winning sweep plane (the network's depth base)."""
+    """(h4, w4) inverse depth of each cell's winning sweep plane (the network's depth base)."""
     H, W = views.H, views.W
+    h4, w4 = grid(H, W)
     D = N_COARSE * sub_bins(W)
     qf, qn = 1.0 / params.d_max, 1.0 / params.d_min
-    out = np.zeros((H // CELL, W // CELL))
-    for i in range(H // CELL):
-        for j in range(W // CELL):
-            best = int(np.argmin(sweep_costs(views, params, CELL * j + CELL // 2, CELL * i + CELL // 2)))
+    out = np.zeros((h4, w4))
+    for i in range(h4):
+        for j in range(w4):
+            x, y = sample_pixel(H, W, i, j)
+            best = int(np.argmin(sweep_costs(views, params, x, y)))
             out[i, j] = qf + (best + 0.5) * (qn - qf) / D
     return out
 
 
 def proposal_plane(views: Views, params: Params, x: int, y: int, depth, normal, conf, conf_min: float = 0.5):
-    """(plane, used) for pixel (x, y) from per-cell maps (h, w) and (h, w, 3)."""
-    h, w = np.shape(depth)
-    s = views.W // w
-    i, j = y // s, x // s
+    """(plane, used) for pixel (x, y) from per-cell maps (h4, w4) and (h4, w4, 3)."""
+    H, W = views.H, views.W
+    i, j = y // CELL, x // CELL
     nv = np.asarray(normal[i, j], np.float64)
     nn = float(np.linalg.norm(nv))
     if conf[i, j] >= conf_min and np.isfinite(nn) and nn > 0.0 and np.isfinite(depth[i, j]):
         Ki = _kinv(views)
         n = nv / nn
-        Xc = float(depth[i, j]) * (Ki @ np.array([s * j + s // 2, s * i + s // 2, 1.0]))
+        Xc = float(depth[i, j]) * (Ki @ np.array([*sample_pixel(H, W, i, j), 1.0]))
         dp = -float(n @ Xc)
         r = Ki @ np.array([x, y, 1.0])
         nr = float(n @ r)

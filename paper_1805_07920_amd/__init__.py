@@ -402,11 +402,11 @@ class Context:
         self._check(self.L.amh_nn_load(self.h, os.fsencode(path)), "amh_nn_load")
 
     def sweep_features(self, out=None, q_ref=None):
-        """Network input of the current reference: (device bfloat16 (H/4, W/4, 16), device float32 (H/4, W/4)
-        inverse depth of the winning sweep plane)."""
+        """Network input of the current reference on its grid of 4x4 cells (8 ceil(H/32) x 8 ceil(W/32)):
+        (device bfloat16 (h4, w4, 16), device float32 (h4, w4) inverse depth of the winning sweep plane)."""
         import torch
 
-        shape = (self.H // NET_CELL, self.W // NET_CELL)
+        shape = (8 * -(-self.H // 32), 8 * -(-self.W // 32))
         if out is None:
             out = torch.empty(shape + (NET_IN,), dtype=torch.bfloat16, device="cuda")
         if q_ref is None:

@@ -175,6 +175,9 @@ PassArgs pass_args(amh_ctx *c, int t, int colour) {
     return a;
 }
 
+// cells of the proposal grid along a side of n pixels: 1/4 resolution rounded up to a multiple of 8
+int cell_rows(int n) { return 8 * ((n + 31) / 32); }
+
 // initialisation of both colours: random planes, or per-cell predictions where usable
 amh_status init_state(amh_ctx *c, const float *pred, int pred_w, int cell) {
     const int half = c->half;
@@ -943,15 +946,13 @@ amh_status amh_sweep_features(amh_ctx *c, void *feats, float *q_ref) {
     if (!feats) return fail(c, AMH_E_INVALID_ARG, "feats is NULL");
     if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
     const int W = c->refdev.W, H = c->refdev.H;
-    if (W % 32 || H % 32)
-        return fail(c, AMH_E_UNSUPPORTED, "the proposal needs width and height multiples of 32 (got %dx%d)", W, H);
     SweepArgs a;
     a.ref = c->refdev;
     a.views = c->d_viewc;
     a.n_net = std::min(kNetSrc, (int)c->srcs.size());
     a.m = method_dev(c->p, 0);
-    a.h4 = H / kCell;
-    a.w4 = W / kCell;
+    a.h4 = cell_rows(H);
+    a.w4 = cell_rows(W);
     a.sub = std::max(1, (W + 80) / 160);  // one sweep step moves a near source's warp by ~2 px
     const double qf = 1.0 / (double)c->p.depth_max, qn = 1.0 / (double)c->p.depth_min;
     a.q_far = (float)qf;
@@ -968,9 +969,9 @@ amh_status amh_init_from_proposal(amh_ctx *c, const float *pred, int h, int w) {
     if (!pred || h < 1 || w < 1) return fail(c, AMH_E_INVALID_ARG, "need pred and a positive cell grid");
     if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
     const int W = c->refdev.W, H = c->refdev.H;
-    if (W % w || H % h || W / w != H / h)
-        return fail(c, AMH_E_INVALID_ARG, "a %dx%d cell grid does not tile a %dx%d image with square cells", w, h, W, H);
-    return init_state(c, pred, w, W / w);
+    if ((int64_t)w * kCell < W || (int64_t)h * kCell < H)
+        return fail(c, AMH_E_INVALID_ARG, "a %dx%d grid of 4x4 cells does not cover a %dx%d image", w, h, W, H);
+    return init_state(c, pred, w, kCell);
 }
 
 amh_status amh_run_proposal(amh_ctx *c, int ref, const int *srcs, int n_src, int iters) {
@@ -979,10 +980,7 @@ amh_status amh_run_proposal(amh_ctx *c, int ref, const int *srcs, int n_src, int
     if (!c->net) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
     amh_status st = amh_begin(c, ref, srcs, n_src);
     if (st != AMH_OK) return st;
-    const int W = c->refdev.W, H = c->refdev.H;
-    if (W % 32 || H % 32)
-        return fail(c, AMH_E_UNSUPPORTED, "the proposal needs width and height multiples of 32 (got %dx%d)", W, H);
-    const int h4 = H / kCell, w4 = W / kCell;
+    const int h4 = cell_rows(c->refdev.H), w4 = cell_rows(c->refdev.W);
     const size_t cells = (size_t)h4 * w4;
     if (cells > c->prop_cap) {
         if (c->prop_feats) (void)hipFree(c->prop_feats);

@@ -499,15 +499,15 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 }
 
 // ---------------------------------------------------------------------------
-// Plane of pixel (x, y) from the per-cell prediction of its cell: through the
-// point at the predicted depth on the ray of the cell's sample pixel, with the
-// predicted normal turned to face the pixel's ray.  False (keep the random
+// Plane of pixel (x, y) from the per-cell prediction of its 4 x 4 cell: through
+// the point at the predicted depth on the ray of the cell's sample pixel
+// (4j + 2, 4i + 2, clamped to the image), with the predicted normal turned to
+// face the pixel's ray.  False (keep the random
 // plane) when the confidence is below conf_min, the normal is zero or not
 // finite, or the plane's depth along the pixel's ray leaves [d_min, d_max].
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int x, int y, float4 &pl) {
-    const int s = a.prop_s;
-    const int i = y / s, j = x / s;
+    const int i = y / kCell, j = x / kCell;
     const float *pp = a.prop + ((size_t)i * a.prop_w + j) * 5;
     const float depth = pp[0], conf = pp[4];
     float nx = pp[1], ny = pp[2], nz = pp[3];
@@ -516,7 +516,7 @@ __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int 
     nx /= nn;
     ny /= nn;
     nz /= nn;
-    const float2 rc = ref_ray(a.ref, s * j + s / 2, s * i + s / 2);
+    const float2 rc = ref_ray(a.ref, min(kCell * j + kCell / 2, a.ref.W - 1), min(kCell * i + kCell / 2, a.ref.H - 1));
     float dp = -depth * (nx * rc.x + ny * rc.y + nz);
     float nr = nx * r.x + ny * r.y + nz;
     if (nr > 0.f) {
@@ -1028,7 +1028,8 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Plane-sweep input of the proposal network.  A workgroup of 64 lanes takes 16
+// Plane-sweep input of the proposal network, on a grid of 8 ceil(H/32) x
+// 8 ceil(W/32) cells of 4 x 4 pixels.  A workgroup of 64 lanes takes 16
 // cells x 4 consecutive sweep planes: lane (cell, k) scores planes k, k + 4,
 // k + 8, ... of its cell on every source in turn, so at any instruction the
 // whole wave gathers from one source, and the 4 lanes of a cell warp to
@@ -1036,7 +1037,8 @@ __global__ __launch_bounds__(64) void score_kernel(ScoreArgs a) {
 // aggregates its plane's costs (mean of the min(2, n) lowest), keeps its best
 // plane and the best aggregate of every coarse bin; the 4 lanes of a cell
 // merge these with shuffles at the end (ties: lowest plane index).  The
-// window of the cell's sample pixel (4j + 2, 4i + 2) is built once per cell.
+// window of the cell's sample pixel (4j + 2, 4i + 2; clamped to the image) is
+// built once per cell.
 // Channels: normalised mean and deviation of the cell's 4 x 4 reference
 // pixels, winning plane position, 1 - its cost, 1 - best cost per coarse bin;
 // the winner's inverse depth is also written in fp32 (the depth base of the
@@ -1051,7 +1053,8 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     const int cell = blockIdx.x * 16 + cl;
     const bool cell_ok = cell < n_cells;
     const int ci = cell_ok ? cell / a.w4 : 0, cj = cell_ok ? cell - ci * a.w4 : 0;
-    const int x = kCell * cj + kCell / 2, y = kCell * ci + kCell / 2;
+    // sample pixel, clamped to the image (cells past the right or bottom edge repeat the edge)
+    const int x = min(kCell * cj + kCell / 2, a.ref.W - 1), y = min(kCell * ci + kCell / 2, a.ref.H - 1);
     float2 *rw = rwbuf + cl * kWinStride;
     WinStats ws = {1.f, 0.f};
     if (cell_ok) {
@@ -1103,17 +1106,20 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs a) {
     if (!cell_ok) return;  // no barrier follows
     unsigned short *out = a.feats + (size_t)cell * 16;
     if (k == 0) {
-        const float *img = a.ref.img + (size_t)(kCell * ci) * a.ref.W + kCell * cj;
-        float mu = 0.f;
+        // the cell's 4 x 4 pixels, coordinates clamped to the image
+        float px[kCell * kCell];
         for (int yy = 0; yy < kCell; ++yy)
-            for (int xx = 0; xx < kCell; ++xx) mu += img[(size_t)yy * a.ref.W + xx];
+            for (int xx = 0; xx < kCell; ++xx)
+                px[yy * kCell + xx] = a.ref.img[(size_t)min(kCell * ci + yy, a.ref.H - 1) * a.ref.W +
+                                                min(kCell * cj + xx, a.ref.W - 1)];
+        float mu = 0.f;
+        for (int e = 0; e < kCell * kCell; ++e) mu += px[e];
         mu *= 1.f / (kCell * kCell);
         float var = 0.f;
-        for (int yy = 0; yy < kCell; ++yy)
-            for (int xx = 0; xx < kCell; ++xx) {
-                const float dlt = img[(size_t)yy * a.ref.W + xx] - mu;
-                var = fmaf(dlt, dlt, var);
-            }
+        for (int e = 0; e < kCell * kCell; ++e) {
+            const float dlt = px[e] - mu;
+            var = fmaf(dlt, dlt, var);
+        }
         out[0] = f2bf((mu - 127.5f) * (1.f / 64.f));
         out[1] = f2bf(__builtin_sqrtf(var * (1.f / (kCell * kCell))) * (1.f / 32.f));
         out[2] = f2bf(2.f * ((float)best_i + 0.5f) / (float)D - 1.f);

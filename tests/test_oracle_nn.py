@@ -260,7 +260,7 @@ def test_sweep_features_find_the_true_depth(oracle_mod, W, fine):
     P = oracle_mod.Params(d_min=1.0 / (qf + span), d_max=1.0 / qf)
     assert proposal.sweep_planes(P, W)[fine][3] == pytest.approx(4.0, rel=1e-12)
     Fm = proposal.sweep_features(V, P)
-    assert Fm.shape == (10, W // 4, 16)
+    assert Fm.shape == proposal.grid(40, W) + (16,) == (16, 8 * -(-W // 32), 16)
     inner = Fm[2:8, 2:W // 4 - 5]  # cells whose window and warped window stay inside both images
     np.testing.assert_allclose(inner[..., 2], 2.0 * (fine + 0.5) / D - 1.0, atol=1e-12)
     np.testing.assert_allclose(inner[..., 3], 1.0, atol=1e-9)
@@ -314,3 +314,20 @@ def test_proposal_at_the_true_plane(oracle_mod):
         if used3[y, x]:
             assert st3.plane[y, x, :3] @ Xc + st3.plane[y, x, 3] == pytest.approx(0.0, abs=1e-12)
             assert st3.plane[y, x, :3] @ (Ki @ np.array([x, y, 1.0])) < 0
+
+
+def test_sweep_grid_of_a_ragged_image(oracle_mod):
+    """Grid 8 ceil(H/32) x 8 ceil(W/32): cells past the image repeat its edge (clamped sample pixel and block)."""
+    from oracle import proposal
+
+    V = disparity_pair(oracle_mod, W=70, H=36)
+    P = oracle_mod.Params()
+    Fm = proposal.sweep_features(V, P)
+    assert Fm.shape == (16, 24, 16)
+    assert proposal.sample_pixel(36, 70, 15, 23) == (69, 35)
+    # the last column of cells inside the image ends at x = 69: cells 17.. repeat column 69 / row 35
+    ref = V.images[0].astype(np.float64)
+    blk = ref[np.ix_([35, 35, 35, 35], [69, 69, 69, 69])]
+    assert Fm[12, 20, 0] == pytest.approx((blk.mean() - 127.5) / 64, rel=1e-12)
+    assert Fm[12, 20, 1] == 0.0
+    np.testing.assert_array_equal(Fm[12, 20], Fm[15, 23])
