@@ -178,6 +178,14 @@ amh_status amh_score_fixed(amh_ctx *ctx, const float *planes, const int *pix, in
  * INVALID_ARG on bad jobs (checked before any HIP call), STATE without views. */
 amh_status amh_run_batch(amh_ctx *ctx, int n_jobs, const amh_job *jobs);
 
+/* amh_run_batch with every job initialised from the learned proposal instead of
+ * random planes: the plane sweep and the network's forward pass of each job
+ * (amh_sweep_features, amh_nn_forward; sweep on the job's first min(4, n_src)
+ * sources) and the proposal initialisation (amh_init_from_proposal) are
+ * captured in the same graph ahead of the iterations.  STATE if the network
+ * does not exist. */
+amh_status amh_run_batch_proposal(amh_ctx *ctx, int n_jobs, const amh_job *jobs);
+
 /* Depth / normal / cost of job `job` of the last batch (as amh_get_depth_normal_cost). */
 amh_status amh_get_job_result(amh_ctx *ctx, int job, float *depth, float *normal, float *cost, int dst_on_device);
 

@@ -26,7 +26,7 @@ EXPORTS = [
     "amh_status_str", "amh_last_error", "amh_destroy",
     "amh_nn_param_count", "amh_nn_init", "amh_nn_get_params", "amh_nn_set_params", "amh_nn_get_grads",
     "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
-    "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config",
+    "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config", "amh_run_batch_proposal",
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
@@ -114,6 +114,7 @@ def lib():
         L.amh_init_from_proposal.argtypes = [vp, vp, ip, ip]
         L.amh_run_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
         L.amh_set_launch_config.argtypes = [vp, ip]
+        L.amh_run_batch_proposal.argtypes = [vp, ip, C.POINTER(amh_job)]
         _lib = L
     return _lib
 
@@ -303,6 +304,12 @@ class Context:
     def run_batch(self, jobs):
         arr, keep = self._jobs(jobs)
         self._check(self.L.amh_run_batch(self.h, len(jobs), arr), "amh_run_batch")
+        self._jobs_shape = [self._views_shape[int(jb["ref"])] for jb in jobs]
+
+    def run_batch_proposal(self, jobs):
+        """The batch with every job initialised from the learned proposal (network must be loaded)."""
+        arr, keep = self._jobs(jobs)
+        self._check(self.L.amh_run_batch_proposal(self.h, len(jobs), arr), "amh_run_batch_proposal")
         self._jobs_shape = [self._views_shape[int(jb["ref"])] for jb in jobs]
 
     def tune(self, jobs):

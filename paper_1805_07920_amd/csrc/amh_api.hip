@@ -148,10 +148,8 @@ void free_view(View &v) {
 }
 
 void free_job(JobResult &j) {
-    if (j.planes) (void)hipFree(j.planes);
-    if (j.cost) (void)hipFree(j.cost);
-    if (j.S) (void)hipFree(j.S);
-    if (j.v) (void)hipFree(j.v);
+    for (void *p : {(void *)j.planes, (void *)j.cost, (void *)j.S, (void *)j.v, j.feats, (void *)j.qref, (void *)j.pred})
+        if (p) (void)hipFree(p);
     j = JobResult{};
 }
 
@@ -177,6 +175,26 @@ PassArgs pass_args(amh_ctx *c, int t, int colour) {
 
 // cells of the proposal grid along a side of n pixels: 1/4 resolution rounded up to a multiple of 8
 int cell_rows(int n) { return 8 * ((n + 31) / 32); }
+
+// plane-sweep arguments of a reference (proposal input)
+SweepArgs sweep_args(amh_ctx *c, const RefDev &ref, const ViewDev *views, int n_src, void *feats, float *q_ref,
+                     unsigned long long *counters) {
+    SweepArgs a;
+    a.ref = ref;
+    a.views = views;
+    a.n_net = std::min(kNetSrc, n_src);
+    a.m = method_dev(c->p, 0);
+    a.h4 = cell_rows(ref.H);
+    a.w4 = cell_rows(ref.W);
+    a.sub = std::max(1, (ref.W + 80) / 160);  // one sweep step moves a near source's warp by ~2 px
+    const double qf = 1.0 / (double)c->p.depth_max, qn = 1.0 / (double)c->p.depth_min;
+    a.q_far = (float)qf;
+    a.q_step = (float)((qn - qf) / (kSweepCoarse * a.sub));
+    a.feats = static_cast<unsigned short *>(feats);
+    a.q_ref = q_ref;
+    a.counters = counters;
+    return a;
+}
 
 // initialisation of both colours: random planes, or per-cell predictions where usable
 amh_status init_state(amh_ctx *c, const float *pred, int pred_w, int cell) {
@@ -261,7 +279,7 @@ void free_batch(amh_ctx *c) {
 // Builds the device tables of a batch and captures its phases into a graph:
 // zero counters, stamp the start clock, init (2 colours), then per iteration
 // the red and the black half-pass over the jobs that still iterate.
-amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
+amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposal) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     free_batch(c);
     c->batch_ran = false;
@@ -282,6 +300,21 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
             if ((st = dalloc(c, (void **)&jr.v, P * sizeof(int32_t))) != AMH_OK) return st;
             jr.W = r.W;
             jr.H = r.H;
+        }
+        if (proposal) {
+            const size_t cells = (size_t)cell_rows(r.H) * cell_rows(r.W);
+            if (cells > jr.cells) {
+                for (void *p : {jr.feats, (void *)jr.qref, (void *)jr.pred})
+                    if (p) (void)hipFree(p);
+                jr.feats = nullptr;
+                jr.qref = jr.pred = nullptr;
+                jr.cells = 0;
+                amh_status st;
+                if ((st = dalloc(c, &jr.feats, cells * 16 * sizeof(uint16_t))) != AMH_OK) return st;
+                if ((st = dalloc(c, (void **)&jr.qref, cells * sizeof(float))) != AMH_OK) return st;
+                if ((st = dalloc(c, (void **)&jr.pred, cells * 5 * sizeof(float))) != AMH_OK) return st;
+                jr.cells = cells;
+            }
         }
         jr.ref.img = r.img;
         jr.ref.W = r.W;
@@ -309,6 +342,8 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         b.st = StateDev{c->jobs[j].planes, c->jobs[j].cost, c->jobs[j].S, c->jobs[j].v};
         b.tiles_x = ((r.W + 1) / 2 + kTilePix - 1) / kTilePix;
         b.n_tiles = b.tiles_x * ((r.H + c->cfg_waves - 1) / c->cfg_waves);
+        b.prop = proposal ? c->jobs[j].pred : nullptr;
+        b.prop_w = proposal ? cell_rows(r.W) : 0;
         so += jobs[j].n_src;
     }
     // job order within a phase: as given, or the largest first (shorter tail)
@@ -386,6 +421,11 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
     HIPCHK(c, hipMemcpyAsync(c->d_bviews, hv.data(), sizeof(ViewDev) * total_src, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_jobs, hj.data(), sizeof(BatchJobDev) * n_jobs, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_tables, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, c->stream));
+    if (proposal) {
+        size_t most = 0;
+        for (int j = 0; j < n_jobs; ++j) most = std::max(most, c->jobs[j].cells);
+        if ((st = nn_reserve(c, most)) != AMH_OK) return st;  // before capture: may allocate
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     // capture (kernels only: counters are cleared by a kernel, not a memset)
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -394,6 +434,15 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_zero_u64(c->d_bcount, 3 * kCounterSlots + n_jobs, c->cap_stream);
     if (e == hipSuccess) e = launch_stamp(clocks + n_jobs, c->cap_stream);
+    // learned proposal: sweep and network forward of every job before its initialisation
+    for (int j = 0; proposal && j < n_jobs && e == hipSuccess; ++j) {
+        const JobResult &jr = c->jobs[j];
+        SweepArgs sa = sweep_args(c, jr.ref, hj[j].views, jobs[j].n_src, jr.feats, jr.qref, c->d_bcount);
+        e = launch_sweep(sa, c->half, c->cap_stream);
+        if (e == hipSuccess &&
+            nn_forward_stream(c, jr.feats, jr.qref, 1, sa.h4, sa.w4, jr.pred, c->cap_stream) != AMH_OK)
+            e = hipErrorLaunchFailure;
+    }
     for (const Phase &ph : phases) {
         if (e != hipSuccess) break;
         BatchPhaseArgs b;
@@ -411,6 +460,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         b.kind = ph.kind;
         b.order = c->cfg_order;
         b.waves = c->cfg_waves;
+        b.conf_min = c->p.conf_min;
         b.counters = c->d_bcount;
         b.tiles_done = tiles_done;
         b.job_end = clocks;
@@ -803,11 +853,11 @@ amh_status amh_score_fixed(amh_ctx *c, const float *planes, const int *pix, int 
     return AMH_OK;
 }
 
-amh_status amh_run_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
-    if (!c) return AMH_E_INVALID_ARG;
+static amh_status run_batch_impl(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposal) {
     amh_status st = check_jobs(c, n_jobs, jobs);
     if (st != AMH_OK) return st;
-    std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order, c->cfg_waves};
+    if (proposal && !c->net) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
+    std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order, c->cfg_waves, proposal ? 1 : 0};
     for (int j = 0; j < n_jobs; ++j) {
         key.push_back(jobs[j].ref);
         key.push_back(jobs[j].n_src);
@@ -815,7 +865,7 @@ amh_status amh_run_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
         key.insert(key.end(), jobs[j].srcs, jobs[j].srcs + jobs[j].n_src);
     }
     if (!(c->graph_exec && key == c->batch_key)) {
-        st = build_batch(c, n_jobs, jobs);
+        st = build_batch(c, n_jobs, jobs, proposal);
         if (st != AMH_OK) return st;
         c->batch_key = key;
     }
@@ -824,6 +874,16 @@ amh_status amh_run_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
     c->batch_stats = true;
     c->batch_jobs = n_jobs;
     return AMH_OK;
+}
+
+amh_status amh_run_batch(amh_ctx *c, int n_jobs, const amh_job *jobs) {
+    if (!c) return AMH_E_INVALID_ARG;
+    return run_batch_impl(c, n_jobs, jobs, false);
+}
+
+amh_status amh_run_batch_proposal(amh_ctx *c, int n_jobs, const amh_job *jobs) {
+    if (!c) return AMH_E_INVALID_ARG;
+    return run_batch_impl(c, n_jobs, jobs, true);
 }
 
 amh_status amh_get_job_result(amh_ctx *c, int job, float *depth, float *normal, float *cost, int dst_on_device) {
@@ -946,20 +1006,7 @@ amh_status amh_sweep_features(amh_ctx *c, void *feats, float *q_ref) {
     if (!feats) return fail(c, AMH_E_INVALID_ARG, "feats is NULL");
     if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
     const int W = c->refdev.W, H = c->refdev.H;
-    SweepArgs a;
-    a.ref = c->refdev;
-    a.views = c->d_viewc;
-    a.n_net = std::min(kNetSrc, (int)c->srcs.size());
-    a.m = method_dev(c->p, 0);
-    a.h4 = cell_rows(H);
-    a.w4 = cell_rows(W);
-    a.sub = std::max(1, (W + 80) / 160);  // one sweep step moves a near source's warp by ~2 px
-    const double qf = 1.0 / (double)c->p.depth_max, qn = 1.0 / (double)c->p.depth_min;
-    a.q_far = (float)qf;
-    a.q_step = (float)((qn - qf) / (kSweepCoarse * a.sub));
-    a.feats = static_cast<unsigned short *>(feats);
-    a.q_ref = q_ref;
-    a.counters = c->counters;
+    const SweepArgs a = sweep_args(c, c->refdev, c->d_viewc, (int)c->srcs.size(), feats, q_ref, c->counters);
     HIPCHK(c, launch_sweep(a, c->half, c->stream));
     return AMH_OK;
 }

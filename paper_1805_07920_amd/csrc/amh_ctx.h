@@ -28,6 +28,11 @@ struct JobResult {
     float *cost = nullptr;
     uint32_t *S = nullptr;
     int32_t *v = nullptr;
+    // learned-proposal batches: network input, depth base and prediction of the job
+    void *feats = nullptr;
+    float *qref = nullptr;
+    float *pred = nullptr;
+    size_t cells = 0;
 };
 
 }  // namespace amh
@@ -100,5 +105,11 @@ amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) __attribute__((f
 
 // device allocation with an optional injected failure (AMH_FAIL_ALLOC_AT=n fails the n-th call, 1-based)
 amh_status dalloc(amh_ctx *c, void **ptr, size_t bytes);
+
+// proposal network (amh_nn_api.hip): reserve activations for `cells` level-0 cells, and a forward pass
+// on an explicit stream that neither allocates nor synchronises (capturable)
+amh_status nn_reserve(amh_ctx *c, size_t cells);
+amh_status nn_forward_stream(amh_ctx *c, const void *feats, const float *q_ref, int n, int h, int w, float *out,
+                             hipStream_t s);
 
 }  // namespace amh

@@ -72,6 +72,8 @@ struct BatchJobDev {
     int n_src;
     StateDev st;
     int tiles_x, n_tiles;        // tile grid of one colour
+    const float *prop;           // per-cell predictions for the initialisation, or NULL (random)
+    int prop_w;                  // cell grid width
 };
 
 // one phase (init of a colour, or a half-pass) over the active jobs of a batch
@@ -87,6 +89,7 @@ struct BatchPhaseArgs {
     int t, colour, kind;         // kind 0: init, 1: half-pass
     int order;
     int waves;                   // tile rows = waves per workgroup (2 or 4)
+    float conf_min;              // proposal initialisation threshold
     unsigned long long *counters;
     unsigned long long *tiles_done;  // [n_jobs] tiles finished in the job's last phase
     unsigned long long *job_end; // [n_jobs] device clock at the job's completion

@@ -507,18 +507,20 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 // finite, or the plane's depth along the pixel's ray leaves [d_min, d_max].
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int x, int y, float4 &pl) {
+    // explicit fused multiply-adds: the two initialisation kernels inline this function, and the
+    // result must not depend on how the compiler contracts it at each call site
     const int i = y / kCell, j = x / kCell;
     const float *pp = a.prop + ((size_t)i * a.prop_w + j) * 5;
     const float depth = pp[0], conf = pp[4];
     float nx = pp[1], ny = pp[2], nz = pp[3];
-    const float nn = __builtin_sqrtf(nx * nx + ny * ny + nz * nz);
+    const float nn = __builtin_sqrtf(fmaf(nx, nx, fmaf(ny, ny, __fmul_rn(nz, nz))));
     if (!(conf >= a.conf_min) || !(nn > 0.f) || !__builtin_isfinite(nn) || !__builtin_isfinite(depth)) return false;
     nx /= nn;
     ny /= nn;
     nz /= nn;
     const float2 rc = ref_ray(a.ref, min(kCell * j + kCell / 2, a.ref.W - 1), min(kCell * i + kCell / 2, a.ref.H - 1));
-    float dp = -depth * (nx * rc.x + ny * rc.y + nz);
-    float nr = nx * r.x + ny * r.y + nz;
+    float dp = __fmul_rn(-depth, fmaf(nx, rc.x, fmaf(ny, rc.y, nz)));
+    float nr = fmaf(nx, r.x, fmaf(ny, r.y, nz));
     if (nr > 0.f) {
         nx = -nx;
         ny = -ny;
@@ -991,6 +993,11 @@ void batch_kernel(BatchPhaseArgs b) {
     a.n_tiles = J.n_tiles;
     a.counters = b.counters;
     a.order = b.order;
+    a.waves = WAVES;
+    a.prop = J.prop;
+    a.prop_w = J.prop_w;
+    a.prop_s = kCell;
+    a.conf_min = b.conf_min;
     const int L = g - b.tile_start[lo];
     if (b.kind == 0) init_body<HALF, WAVES>(a, L, smem);
     else pass_body<HALF, WAVES>(a, L, smem);

@@ -266,11 +266,11 @@ ConvArgs conv_args(const Layer &l, const bf16_t *x, const bf16_t *w, const float
     return a;
 }
 
-amh_status conv_fwd(amh_ctx *c, int li, const bf16_t *x, void *y, int n, int h, int w, bool head) {
+amh_status conv_fwd(amh_ctx *c, int li, const bf16_t *x, void *y, int n, int h, int w, bool head, hipStream_t s) {
     NetState *N = c->net;
     const Layer &l = N->L[li];
     const ConvArgs a = conv_args(l, x, N->pb + l.w_off, N->p32 + l.b_off, y, n, h, w, head ? 0 : 1, head ? 1 : 0);
-    HIPCHK(c, launch_conv(a, c->stream));
+    HIPCHK(c, launch_conv(a, s));
     return AMH_OK;
 }
 
@@ -355,6 +355,53 @@ amh_status check_net(amh_ctx *c) {
 
 }  // namespace
 
+namespace amh {
+
+amh_status nn_reserve(amh_ctx *c, size_t cells) { return ensure_acts(c, cells); }
+
+// forward pass on stream s; activations must be reserved (no allocation or synchronisation here,
+// so that it can be captured into a graph)
+amh_status nn_forward_stream(amh_ctx *c, const void *feats, const float *q_ref, int n, int h, int w, float *out,
+                             hipStream_t s) {
+    NetState *N = c->net;
+    if (!N) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
+    const size_t P0 = (size_t)n * h * w;
+    if (P0 > N->cap_px) return fail(c, AMH_E_STATE, "network activations not reserved for %zu cells", P0);
+    amh_status st;
+    HIPCHK(c, hipMemcpyAsync(N->x, feats, P0 * kIn * sizeof(bf16_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(N->qref, q_ref, P0 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    const int h1 = h / 2, w1 = w / 2, h2 = h / 4, w2 = w / 4, h3 = h / 8, w3 = w / 8;
+#define FWD(li, in, outb, hh, ww)                                                \
+    if ((st = conv_fwd(c, li, in, outb, n, hh, ww, false, s)) != AMH_OK) return st
+    FWD(ENC0A, N->x, N->e0a, h, w);
+    FWD(ENC0B, N->e0a, N->e0, h, w);
+    HIPCHK(c, launch_pool(N->e0, n, h1, w1, 16, N->p0, s));
+    FWD(ENC1A, N->p0, N->e1a, h1, w1);
+    FWD(ENC1B, N->e1a, N->e1, h1, w1);
+    HIPCHK(c, launch_pool(N->e1, n, h2, w2, 32, N->p1, s));
+    FWD(ENC2A, N->p1, N->e2a, h2, w2);
+    FWD(ENC2B, N->e2a, N->e2, h2, w2);
+    HIPCHK(c, launch_pool(N->e2, n, h3, w3, 48, N->p2, s));
+    FWD(ENC3A, N->p2, N->e3a, h3, w3);
+    FWD(ENC3B, N->e3a, N->e3, h3, w3);
+    HIPCHK(c, launch_upcat(N->e3, 64, N->e2, 48, n, h2, w2, N->c2, s));
+    FWD(DEC2, N->c2, N->d2, h2, w2);
+    HIPCHK(c, launch_upcat(N->d2, 48, N->e1, 32, n, h1, w1, N->c1, s));
+    FWD(DEC1, N->c1, N->d1, h1, w1);
+    HIPCHK(c, launch_upcat(N->d1, 32, N->e0, 16, n, h, w, N->c0, s));
+    FWD(DEC0, N->c0, N->d0, h, w);
+#undef FWD
+    if ((st = conv_fwd(c, HEAD, N->d0, N->z, n, h, w, true, s)) != AMH_OK) return st;
+    if (out) HIPCHK(c, launch_decode(N->z, N->qref, (int)P0, depth_head(c->p), out, s));
+    N->n = n;
+    N->h = h;
+    N->w = w;
+    N->have_fwd = true;
+    return AMH_OK;
+}
+
+}  // namespace amh
+
 extern "C" {
 
 amh_status amh_nn_param_count(int64_t *n) {
@@ -425,40 +472,8 @@ amh_status amh_nn_forward(amh_ctx *c, const void *feats, const float *q_ref, int
         return fail(c, AMH_E_INVALID_ARG, "need feats and n >= 1, h and w positive multiples of 8");
     amh_status st = check_net(c);
     if (st != AMH_OK) return st;
-    NetState *N = c->net;
-    const size_t P0 = (size_t)n * h * w;
-    if ((st = ensure_acts(c, P0)) != AMH_OK) return st;
-    hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(N->x, feats, P0 * kIn * sizeof(bf16_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(N->qref, q_ref, P0 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    const int h1 = h / 2, w1 = w / 2, h2 = h / 4, w2 = w / 4, h3 = h / 8, w3 = w / 8;
-#define FWD(li, in, outb, hh, ww)                                                         \
-    if ((st = conv_fwd(c, li, in, outb, n, hh, ww, false)) != AMH_OK) return st
-    FWD(ENC0A, N->x, N->e0a, h, w);
-    FWD(ENC0B, N->e0a, N->e0, h, w);
-    HIPCHK(c, launch_pool(N->e0, n, h1, w1, 16, N->p0, s));
-    FWD(ENC1A, N->p0, N->e1a, h1, w1);
-    FWD(ENC1B, N->e1a, N->e1, h1, w1);
-    HIPCHK(c, launch_pool(N->e1, n, h2, w2, 32, N->p1, s));
-    FWD(ENC2A, N->p1, N->e2a, h2, w2);
-    FWD(ENC2B, N->e2a, N->e2, h2, w2);
-    HIPCHK(c, launch_pool(N->e2, n, h3, w3, 48, N->p2, s));
-    FWD(ENC3A, N->p2, N->e3a, h3, w3);
-    FWD(ENC3B, N->e3a, N->e3, h3, w3);
-    HIPCHK(c, launch_upcat(N->e3, 64, N->e2, 48, n, h2, w2, N->c2, s));
-    FWD(DEC2, N->c2, N->d2, h2, w2);
-    HIPCHK(c, launch_upcat(N->d2, 48, N->e1, 32, n, h1, w1, N->c1, s));
-    FWD(DEC1, N->c1, N->d1, h1, w1);
-    HIPCHK(c, launch_upcat(N->d1, 32, N->e0, 16, n, h, w, N->c0, s));
-    FWD(DEC0, N->c0, N->d0, h, w);
-#undef FWD
-    if ((st = conv_fwd(c, HEAD, N->d0, N->z, n, h, w, true)) != AMH_OK) return st;
-    if (out) HIPCHK(c, launch_decode(N->z, N->qref, (int)P0, depth_head(c->p), out, s));
-    N->n = n;
-    N->h = h;
-    N->w = w;
-    N->have_fwd = true;
-    return AMH_OK;
+    if ((st = nn_reserve(c, (size_t)n * h * w)) != AMH_OK) return st;
+    return nn_forward_stream(c, feats, q_ref, n, h, w, out, c->stream);
 }
 
 amh_status amh_nn_backward(amh_ctx *c, const float *target, float *loss) {

@@ -69,7 +69,8 @@ def test_null_arguments(amh):
                  lambda: L.amh_score_fixed(None, None, None, 0, None, 0), lambda: L.amh_run_batch(None, 0, None),
                  lambda: L.amh_get_job_result(None, 0, None, None, None, 0),
                  lambda: L.amh_get_job_times(None, 0, None), lambda: L.amh_tune(None, 0, None, None, None),
-                 lambda: L.amh_get_stats(None, None), lambda: L.amh_set_launch_config(None, 0)):
+                 lambda: L.amh_get_stats(None, None), lambda: L.amh_set_launch_config(None, 0),
+                 lambda: L.amh_run_batch_proposal(None, 0, None)):
         assert call() == amh.AMH_E_INVALID_ARG
     L.amh_destroy(None)
     assert L.amh_last_error(None) == b"NULL context"

@@ -163,3 +163,34 @@ def test_single_image_launch_configurations_agree(amh, batch_setup, config):
         assert e.value.status == amh.AMH_E_INVALID_ARG
     for x, y in zip(ref, out):
         assert np.array_equal(x, y)
+
+
+def test_batched_proposal_equals_single_proposal_runs(amh, batch_setup):
+    """Each job of a learned-proposal batch ends bitwise equal to amh_run_proposal of that job alone."""
+    say("case batched proposal")
+    import os
+
+    weights = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_07920_amd",
+                           "weights", "proposal.bin")
+    images, cams, jobs = batch_setup
+    with amh.Context(refine=1, seed=7) as ctx:
+        ctx.init_views(images, cams)
+        with pytest.raises(amh.AmhError) as e:
+            ctx.run_batch_proposal(jobs)
+        assert e.value.status == amh.AMH_E_STATE
+        ctx.nn_load(weights)
+        ctx.run_batch_proposal(jobs)
+        got = [ctx.get_job_result(i) for i in range(len(jobs))]
+        st = ctx.get_stats()
+        ctx.run_batch_proposal(jobs)  # replay
+        again = [ctx.get_job_result(i) for i in range(len(jobs))]
+        singles = []
+        evals = 0
+        for jb in jobs:
+            ctx.run_proposal(jb["ref"], jb["srcs"], jb["iters"])
+            singles.append(ctx.get_depth_normal_cost())
+            evals += ctx.get_stats()["evals_total"]
+    assert st["evals_total"] == evals
+    for a, b, c in zip(got, again, singles):
+        for x, y, z in zip(a, b, c):
+            assert np.array_equal(x, y) and np.array_equal(x, z)
