@@ -1,7 +1,8 @@
 """Trains the learned proposal on the GPU with the library's own kernels.
 
-Data: seeded 640x480 scenes with 8 sources (scene seeds 1000 onwards).  For each
-scene the plain method (random initialisation, 3 iterations with refinement)
+Data: seeded 640x480 scenes (scene seeds 1000 onwards) with a source count drawn
+from 4..16 per scene (--n-src), sources listed nearest first as at inference.
+For each scene the plain method (random initialisation, 3 iterations with refinement)
 produces the labels: at the pixel (4j + 2, 4i + 2) of every 4 x 4 cell its
 depth, normal and final cost m; the confidence target is C(m) =
 exp(-m^2 / (2 beta^2)) of Eq. 3, which also weights the depth and normal terms,
@@ -56,12 +57,20 @@ def labels_of(depth, normal, cost, beta: float):
     return torch.cat([d[..., None], n, conf[..., None], conf[..., None]], -1).contiguous()
 
 
-def make_dataset(ctx, seeds, iters: int = 3, n_src: int = 8):
+def nearest_first(sc):
+    """Source indices by angular distance from the reference camera: the sweep reads the first few."""
+    ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
+    return [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]
+
+
+def make_dataset(ctx, seeds, iters: int = 3, n_src=(8, 8)):
+    """n_src: (lo, hi) -- each scene draws its source count uniformly from lo..hi (seeded by the scene)."""
     feats, qrefs, targets = [], [], []
     t0 = time.time()
-    srcs = list(range(1, n_src + 1))
     for k, seed in enumerate(seeds):
-        sc = scenegen.config_scene("c5", seed, device="cuda", n_src=n_src)
+        n = int(np.random.default_rng(seed).integers(n_src[0], n_src[1] + 1))
+        sc = scenegen.config_scene("c5", seed, device="cuda", n_src=n)
+        srcs = nearest_first(sc)
         scene_views(ctx, sc)
         ctx.run_checkerboard(0, srcs, iters)
         H, W = sc.height, sc.width
@@ -117,6 +126,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--init-seed", type=int, default=0)
+    ap.add_argument("--n-src", type=int, nargs=2, default=(4, 16), metavar=("LO", "HI"),
+                    help="source count per training scene, drawn uniformly from LO..HI")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--report", default=None, help="JSON file for the loss history")
     args = ap.parse_args(argv)
@@ -125,7 +136,7 @@ def main(argv=None):
     torch.cuda.init()
     ctx = amh.Context(seed=args.init_seed)
     t0 = time.time()
-    feats, qrefs, targets = make_dataset(ctx, range(args.seed0, args.seed0 + args.scenes))
+    feats, qrefs, targets = make_dataset(ctx, range(args.seed0, args.seed0 + args.scenes), n_src=tuple(args.n_src))
     t_data = time.time() - t0
     ctx.nn_init(args.init_seed)
     t1 = time.time()
@@ -133,7 +144,8 @@ def main(argv=None):
     t_train = time.time() - t1
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     ctx.nn_save(args.out)
-    rep = dict(scenes=args.scenes, seed0=args.seed0, epochs=args.epochs, batch=args.batch, lr=args.lr,
+    rep = dict(scenes=args.scenes, seed0=args.seed0, n_src=list(args.n_src), epochs=args.epochs, batch=args.batch,
+               lr=args.lr,
                loss_per_epoch=hist, data_seconds=t_data, train_seconds=t_train, out=os.path.relpath(args.out, ROOT))
     log(json.dumps(rep))
     if args.report:
