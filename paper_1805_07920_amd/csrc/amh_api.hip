@@ -19,8 +19,6 @@ using namespace amh;
 
 namespace amh {
 
-static int g_alloc_count = 0;
-
 amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) {
     if (c) {
         char buf[512];
@@ -34,9 +32,8 @@ amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) {
 }
 
 amh_status dalloc(amh_ctx *c, void **ptr, size_t bytes) {
-    ++g_alloc_count;
-    const char *inj = getenv("AMH_FAIL_ALLOC_AT");
-    if (inj && atoi(inj) == g_alloc_count) return fail(c, AMH_E_OOM, "injected allocation failure (%zu bytes)", bytes);
+    if (++c->alloc_count == c->fail_alloc_at)
+        return fail(c, AMH_E_OOM, "injected allocation failure (%zu bytes)", bytes);
     hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
         return fail(c, AMH_E_OOM, "hipMalloc(%zu) failed: out of memory", bytes);
@@ -528,6 +525,8 @@ amh_status amh_create(amh_ctx **out, const amh_params *p, void *hip_stream) {
     if (!c) return AMH_E_OOM;
     c->p = *p;
     c->stream = (hipStream_t)hip_stream;
+    const char *inj = getenv("AMH_FAIL_ALLOC_AT");  // test hook: fail this context's n-th device allocation
+    c->fail_alloc_at = inj ? atoi(inj) : 0;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return AMH_E_HIP;

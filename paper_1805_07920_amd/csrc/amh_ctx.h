@@ -41,6 +41,8 @@ using namespace amh;  // private header: the library's own translation units onl
 
 struct amh_ctx {
     amh_params p;
+    int alloc_count = 0;      // device allocations made by this context
+    int fail_alloc_at = 0;    // AMH_FAIL_ALLOC_AT at creation: that allocation reports out-of-memory (test hook)
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
@@ -103,7 +105,8 @@ amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) __attribute__((f
         if (e_ != hipSuccess) return fail((c), AMH_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// device allocation with an optional injected failure (AMH_FAIL_ALLOC_AT=n fails the n-th call, 1-based)
+// device allocation with an optional injected failure (AMH_FAIL_ALLOC_AT=n at amh_create: the context's
+// n-th allocation fails, 1-based)
 amh_status dalloc(amh_ctx *c, void **ptr, size_t bytes);
 
 // proposal network (amh_nn_api.hip): reserve activations for `cells` level-0 cells, and a forward pass

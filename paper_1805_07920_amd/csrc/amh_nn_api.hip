@@ -179,16 +179,21 @@ amh_status create_net(amh_ctx *c) {
         wt_max = std::max(wt_max, (size_t)l.cin * round_up(l.ks * l.ks * l.cout_pad, 32));
     }
     N->n_pad = off;
-    amh_status st;
-    if ((st = dalloc(c, (void **)&N->p32, off * 4)) != AMH_OK) return st;
-    if ((st = dalloc(c, (void **)&N->g32, off * 4)) != AMH_OK) return st;
-    if ((st = dalloc(c, (void **)&N->m, off * 4)) != AMH_OK) return st;
-    if ((st = dalloc(c, (void **)&N->v, off * 4)) != AMH_OK) return st;
-    if ((st = dalloc(c, (void **)&N->pb, off * 2)) != AMH_OK) return st;
-    if ((st = dalloc(c, (void **)&N->wt, wt_max * 2)) != AMH_OK) return st;
+    amh_status st = AMH_OK;
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->p32, off * 4);
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->g32, off * 4);
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->m, off * 4);
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->v, off * 4);
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->pb, off * 2);
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->wt, wt_max * 2);
+    if (st == AMH_OK) st = dalloc(c, (void **)&N->loss_dev, 64);
+    if (st == AMH_OK && hipMemsetAsync(N->g32, 0, off * 4, c->stream) != hipSuccess)
+        st = fail(c, AMH_E_HIP, "hipMemsetAsync of the gradient buffer failed");
+    if (st != AMH_OK) {
+        free_net(c);  // no half-built network stays on the context
+        return st;
+    }
     N->wt_cap = wt_max;
-    if ((st = dalloc(c, (void **)&N->loss_dev, 64)) != AMH_OK) return st;
-    HIPCHK(c, hipMemsetAsync(N->g32, 0, off * 4, c->stream));
     return AMH_OK;
 }
 

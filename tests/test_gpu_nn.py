@@ -491,3 +491,21 @@ def test_run_proposal_equals_its_steps(amh, scene_c1):
         np.testing.assert_array_equal(u, w)
     assert st["evals_init"] == 24 * 32 * 12 * 4 + 128 * 96 * 4
     assert np.isfinite(a[1]).all()
+
+
+def test_allocation_failure_leaves_no_half_network(amh, monkeypatch):
+    """An allocation failing inside amh_nn_init (injected with AMH_FAIL_ALLOC_AT, read at context
+    creation) reports out-of-memory and leaves the context without a network, usable afterwards."""
+    say("case nn allocation failure")
+    monkeypatch.setenv("AMH_FAIL_ALLOC_AT", "3")  # 1: work counters, 2: parameters, 3: gradients
+    ctx = amh.Context()
+    monkeypatch.delenv("AMH_FAIL_ALLOC_AT")
+    with ctx:
+        with pytest.raises(amh.AmhError) as e:
+            ctx.nn_init(0)
+        assert e.value.status == amh.AMH_E_OOM
+        with pytest.raises(amh.AmhError) as e:
+            ctx.nn_get_params()
+        assert e.value.status == amh.AMH_E_STATE
+        ctx.nn_init(1)  # later allocations succeed: a complete network
+        assert ctx.nn_get_params().size == 196341
