@@ -37,23 +37,28 @@ OPS_PER_EVAL = 1160
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # Bytes the half-pass kernel moves between L2 and memory per launch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean of the 6 half-passes of one depth map) scaled by
-# what the same counters read for a plain 256 MiB copy (bench.py --calibrate-copy: FETCH_SIZE 131081 KiB
+# what the same counters read for a plain 256 MiB copy (bench.py --calibrate-copy: FETCH_SIZE 131080 KiB
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
-# profiles/pass_kernel_1920x1280_n10_traffic.md.  Valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"fetch_kib": 1174383.5, "write_kib": 82066.6, "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "1cfc7ed05d19a6a7a93a3bdfed9a98edaf71288b5d46bdb4684d36c8f40a24c8"}
+# profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
+# autotuner picks, and valid only for the kernel source they were taken on.
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 1989588.1, "write_kib": 84938.2}},
+                "fetch_scale": 2.0, "write_scale": 1.0,
+                "kernel_sha256": "37b3a2c48b5eee33a754df1c450ebcbe2f9529d7c372a582ab280072878b26a1"}
 
 
-def pass_traffic_bytes():
-    """HBM-side bytes per half-pass launch, or None once the kernel source has changed since the counters."""
+def pass_traffic_bytes(tile_rows: int):
+    """HBM-side bytes per half-pass launch of the variant with `tile_rows` rows per workgroup, or None
+    when not measured for it or once the kernel source has changed since the counters."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1805_07920_amd", "csrc", "amh_kernels.hip")
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != PASS_TRAFFIC["kernel_sha256"]:
             return None
-    return 1024.0 * (PASS_TRAFFIC["fetch_kib"] * PASS_TRAFFIC["fetch_scale"]
-                     + PASS_TRAFFIC["write_kib"] * PASS_TRAFFIC["write_scale"])
+    c = PASS_TRAFFIC["by_tile_rows"].get(tile_rows)
+    if c is None:
+        return None
+    return 1024.0 * (c["fetch_kib"] * PASS_TRAFFIC["fetch_scale"] + c["write_kib"] * PASS_TRAFFIC["write_scale"])
 
 
 def log(*a):
@@ -374,9 +379,10 @@ def main():
         "init_ms": ev["ms_init"],
         "accuracy_within_1pct_of_ground_truth": acc,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                     "frac": achieved / VALU_PEAK_OPS, "traffic": pass_traffic_bytes(),
+                     "frac": achieved / VALU_PEAK_OPS, "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4),
                      "traffic_unit": "bytes per launch (L2 <-> memory, calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                     "kernel": "pass_kernel<0> (fused checkerboard half-pass)",
+                     "kernel": f"pass_kernel<0, {2 if best_cfg & 4 else 4}> (fused checkerboard half-pass, "
+                               f"{2 if best_cfg & 4 else 4}-row tiles)",
                      "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals_per_pass},
         "cpu_baseline": cpu,
         "autotune": {"best_config": best_cfg, "ms_per_config": tune_ms,
