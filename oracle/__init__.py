@@ -51,7 +51,7 @@ class _Params(C.Structure):
                 ("sigma_spatial", C.c_double), ("tau_mc_init", C.c_double), ("alpha", C.c_double),
                 ("beta", C.c_double), ("tau_up", C.c_double),
                 ("n1", C.c_int), ("n2", C.c_int), ("k", C.c_int), ("seed", C.c_uint64),
-                ("view_mode", C.c_int)]
+                ("view_mode", C.c_int), ("prop_mode", C.c_int)]
 
 
 class _State(C.Structure):
@@ -83,6 +83,8 @@ def lib():
         L.orc_u24.restype = C.c_double
         L.orc_acp_offsets.argtypes = [ip, ip, ip]
         L.orc_acp_offsets.restype = C.c_int
+        L.orc_scp_offsets.argtypes = [ip, ip, ip]
+        L.orc_scp_offsets.restype = C.c_int
         L.orc_project.argtypes = [C.POINTER(_Views), C.c_double, C.c_double, dp, C.c_int, dp]
         L.orc_matching_cost.argtypes = [C.POINTER(_Views), C.POINTER(_Params), C.c_int, C.c_int, dp, C.c_int]
         L.orc_matching_cost.restype = C.c_double
@@ -130,12 +132,14 @@ class Params:
     n2: int = 3
     k: int = 4
     seed: int = 0
-    view_mode: int = 0  # 1: plain mean over all views (static objective for the sweep pin)
+    view_mode: int = 0  # 1: plain mean over all views (static objective for the sweep pin); 2: heuristic best-k
+    prop_mode: int = 0  # 1: symmetric fast checkerboard propagation (ablation)
 
     def c(self) -> _Params:
         return _Params(self.refine, self.include_self, self.d_min, self.d_max, self.sigma_color,
                        self.sigma_spatial, self.tau_mc_init, self.alpha, self.beta, self.tau_up,
-                       self.n1, self.n2, self.k, self.seed & 0xFFFFFFFFFFFFFFFF, self.view_mode)
+                       self.n1, self.n2, self.k, self.seed & 0xFFFFFFFFFFFFFFFF, self.view_mode,
+                       self.prop_mode)
 
 
 class Views:
@@ -214,6 +218,14 @@ def acp_offsets():
     dy = np.zeros(N_OFFSETS, np.int32)
     reg = np.zeros(N_OFFSETS, np.int32)
     n = lib().orc_acp_offsets(_iptr(dx), _iptr(dy), _iptr(reg))
+    return dx[:n], dy[:n], reg[:n]
+
+
+def scp_offsets():
+    dx = np.zeros(8, np.int32)
+    dy = np.zeros(8, np.int32)
+    reg = np.zeros(8, np.int32)
+    n = lib().orc_scp_offsets(_iptr(dx), _iptr(dy), _iptr(reg))
     return dx[:n], dy[:n], reg[:n]
 
 

@@ -38,6 +38,13 @@
  *   R12 if every weight is 0 the cost is the plain mean over all views.
  *   R13 refinement: perturbed depth/normal candidates in the first 3
  *       iterations, plus random ones afterwards; strictly lower cost wins.
+ *   R15 symmetric checkerboard propagation of the ablation (the figure that
+ *       fixes Gipuma's patterns is missing): the fast version, 8 fixed
+ *       neighbours at distances 1 and 5 up/down/left/right, one per row of the
+ *       8-row cost matrix, so the joint view selection sees the same shape.
+ *   R16 heuristic view selection of the ablation: each hypothesis (and each
+ *       refinement candidate) costs the mean of its own k lowest per-view
+ *       costs; no view-selection memory is kept (S = 0, v = -1).
  */
 #include "amh_oracle.h"
 
@@ -113,6 +120,20 @@ int orc_acp_offsets(int *dx, int *dy, int *region)
         }
     }
     return n;
+}
+
+/* Symmetric checkerboard propagation of the ablation (Sec. 3.1, Fig. 2(c),  */
+/* Sec. 4; R15): region r holds the single neighbour at distance 1 (r < 4) or */
+/* 5 (r >= 4) in direction up, down, left, right.                             */
+int orc_scp_offsets(int *dx, int *dy, int *region)
+{
+    for (int r = 0; r < 8; ++r) {
+        int u = r < 4 ? 1 : 5, dir = r & 3;
+        dx[r] = dir == 2 ? -u : (dir == 3 ? u : 0);
+        dy[r] = dir == 0 ? -u : (dir == 1 ? u : 0);
+        region[r] = r;
+    }
+    return 8;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -433,19 +454,31 @@ void orc_init(const orc_views *V, const orc_params *p, orc_state *s)
 /* refines it.  Updates in place; reads only the other colour and the pixel   */
 /* itself, so the order of the pixels does not matter.                        */
 /* ------------------------------------------------------------------------ */
+static double mean_k_lowest(const double *c, int n, int k)
+{
+    double tmp[ORC_MAX_SRC];
+    memcpy(tmp, c, sizeof(double) * (size_t)n);
+    qsort(tmp, (size_t)n, sizeof(double), cmp_double);
+    int kk = k < n ? k : n;
+    double sum = 0;
+    for (int j = 0; j < kk; ++j) sum += tmp[j];
+    return sum / kk;
+}
+
 static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, int t, long idx,
-                         const int *odx, const int *ody, const int *oreg, double delta, orc_diag *dg)
+                         const int *odx, const int *ody, const int *oreg, int n_off, double delta, orc_diag *dg)
 {
     const int N = V->n_src;
     int x = (int)(idx % V->W), y = (int)(idx / V->W);
     double planes[9][4];
     int valid[9];
     int cidx[8];
-    /* asymmetric checkerboard propagation: per region, the neighbour with the lowest current cost */
+    /* checkerboard propagation: per region, the neighbour with the lowest current cost
+       (one neighbour per region in the symmetric pattern) */
     for (int r = 0; r < 8; ++r) {
         int best = -1;
         double bc = 0;
-        for (int e = 0; e < ORC_N_OFFSETS; ++e) {
+        for (int e = 0; e < n_off; ++e) {
             if (oreg[e] != r) continue;
             int nx = x + odx[e], ny = y + ody[e];
             if (nx < 0 || nx >= V->W || ny < 0 || ny >= V->H) continue;
@@ -472,19 +505,22 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
     int v;
     double w[ORC_MAX_SRC];
     orc_view_selection(p, t, Mflat, valid, N, s->S[idx], s->v[idx], &S, &v, w);
-    if (p->view_mode == 1) {
+    if (p->view_mode != 0) {
         S = 0;
         v = -1;
         for (int j = 0; j < N; ++j) w[j] = 1.0;
     }
+    const int heuristic = p->view_mode == 2;
 
-    /* unified cost of every hypothesis (Eq. 7) and the minimum; ties keep self, then region order */
+    /* unified cost of every hypothesis (Eq. 7; R16 in the heuristic mode) and the minimum;
+       ties keep self, then region order */
     double sw = 0;
     for (int j = 0; j < N; ++j) sw += w[j];
     double mf[9];
     for (int r = 0; r < 9; ++r) {
         mf[r] = INFINITY;
         if (!valid[r]) continue;
+        if (heuristic) { mf[r] = mean_k_lowest(M[r], N, p->k); continue; }
         double acc = 0;
         for (int j = 0; j < N; ++j) acc += w[j] * M[r][j];
         mf[r] = acc / sw;
@@ -500,8 +536,9 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
     memcpy(cur, planes[best], sizeof(cur));
     double cur_cost = mf[best];
     int chosen = best;
-    int robust = view_selection_robust(p, t, Mflat, valid, N, S, s->v[idx], delta) | ORC_ROBUST_ARGMIN |
-                 ORC_ROBUST_REFINE;
+    int robust = (p->view_mode != 0 ? ORC_ROBUST_S | ORC_ROBUST_V | ORC_ROBUST_TOPK
+                                     : view_selection_robust(p, t, Mflat, valid, N, S, s->v[idx], delta)) |
+                 ORC_ROBUST_ARGMIN | ORC_ROBUST_REFINE;
     if (!(robust & ORC_ROBUST_S)) robust = 0;
     for (int r = 0; r < 9; ++r)
         if (valid[r] && r != best && fabs(mf[r] - mf[best]) < 4 * delta &&
@@ -539,10 +576,16 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
             plane_from(rr, drnd, nrnd, cand[n_cand++]);
         }
         for (int c = 0; c < n_cand; ++c) {
-            double acc = 0;
-            for (int j = 0; j < N; ++j)
-                if (w[j] > 0.0) acc += w[j] * orc_matching_cost(V, p, x, y, cand[c], j);
-            cand_cost[c] = acc / sw;
+            if (heuristic) {
+                double cc[ORC_MAX_SRC];
+                for (int j = 0; j < N; ++j) cc[j] = orc_matching_cost(V, p, x, y, cand[c], j);
+                cand_cost[c] = mean_k_lowest(cc, N, p->k);
+            } else {
+                double acc = 0;
+                for (int j = 0; j < N; ++j)
+                    if (w[j] > 0.0) acc += w[j] * orc_matching_cost(V, p, x, y, cand[c], j);
+                cand_cost[c] = acc / sw;
+            }
             if (fabs(cand_cost[c] - cur_cost) < 4 * delta) robust &= ~ORC_ROBUST_REFINE;
             if (cand_cost[c] < cur_cost) {
                 cur_cost = cand_cost[c];
@@ -581,7 +624,7 @@ void orc_pass(const orc_views *V, const orc_params *p, orc_state *s, int t, int 
               const int *order, int n_order, double delta, orc_diag *diag)
 {
     int odx[ORC_N_OFFSETS], ody[ORC_N_OFFSETS], oreg[ORC_N_OFFSETS];
-    orc_acp_offsets(odx, ody, oreg);
+    int n_off = p->prop_mode == 1 ? orc_scp_offsets(odx, ody, oreg) : orc_acp_offsets(odx, ody, oreg);
     long P = (long)V->W * V->H;
     if (order) {
 #pragma omp parallel for schedule(dynamic, 16)
@@ -590,14 +633,14 @@ void orc_pass(const orc_views *V, const orc_params *p, orc_state *s, int t, int 
             if (idx < 0 || idx >= P) continue;
             int x = (int)(idx % V->W), y = (int)(idx / V->W);
             if (((x + y) & 1) != colour) continue;
-            update_pixel(V, p, s, t, idx, odx, ody, oreg, delta, diag ? &diag[q] : NULL);
+            update_pixel(V, p, s, t, idx, odx, ody, oreg, n_off, delta, diag ? &diag[q] : NULL);
         }
     } else {
 #pragma omp parallel for schedule(dynamic, 16)
         for (long idx = 0; idx < P; ++idx) {
             int x = (int)(idx % V->W), y = (int)(idx / V->W);
             if (((x + y) & 1) != colour) continue;
-            update_pixel(V, p, s, t, idx, odx, ody, oreg, delta, NULL);
+            update_pixel(V, p, s, t, idx, odx, ody, oreg, n_off, delta, NULL);
         }
     }
 }

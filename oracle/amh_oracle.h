@@ -16,6 +16,9 @@
  *                          exact integer-disparity case)
  *   orc_view_selection     pinned (hand-computed matrices, closed forms of Eq. 2-4)
  *   orc_acp_offsets        pinned (invariants of the region table)
+ *   orc_scp_offsets        pinned (symmetry, colour and subset invariants)
+ *   heuristic view mode    pinned (mean of the k lowest against numpy sorts; k >= N
+ *                          equals the plain mean, k = 1 the minimum)
  *   orc_pass / orc_run     pinned by recovery of rendered ground truth, brute-force
  *                          plane sweep and order independence; the refinement step,
  *                          the initial cost and the empty-selection fallback are
@@ -51,7 +54,10 @@ typedef struct {
     int n1, n2, k;
     uint64_t seed;
     int view_mode;   /* 0: joint view selection (the method); 1: plain mean over all views
-                        (a static objective, used only by the brute-force sweep pin) */
+                        (a static objective, used only by the brute-force sweep pin);
+                        2: heuristic selection, mean of each hypothesis' k lowest costs */
+    int prop_mode;   /* 0: asymmetric checkerboard propagation (the method);
+                        1: symmetric fast checkerboard propagation (ablation) */
 } orc_params;
 
 typedef struct {
@@ -79,6 +85,7 @@ typedef struct {
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 double orc_u24(uint64_t w);
 int orc_acp_offsets(int *dx, int *dy, int *region);
+int orc_scp_offsets(int *dx, int *dy, int *region);
 void orc_project(const orc_views *V, double sx, double sy, const double plane[4], int j, double out[3]);
 double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, const double plane[4], int j);
 double orc_tau(const orc_params *p, int t);
