@@ -41,9 +41,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 1989588.1, "write_kib": 84938.2}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 1998659.8, "write_kib": 85000.4},
+                                 4: {"fetch_kib": 1172383.3, "write_kib": 82094.5}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "37b3a2c48b5eee33a754df1c450ebcbe2f9529d7c372a582ab280072878b26a1"}
+                "kernel_sha256": "23a440e5bf5b86f6e42ed9f98ffbd8f61315b487a5c76026ddc32079007f0345"}
 
 
 def pass_traffic_bytes(tile_rows: int):
@@ -262,6 +263,99 @@ def bench_learned(args):
     print(json.dumps(out))
 
 
+ABLATION_VARIANTS = (("full", 0, 0), ("no_acp", 1, 0), ("no_mhj", 0, 1), ("neither", 1, 1))
+
+
+def bench_ablation(args):
+    """Ablation of Sec. 4 on 1920x1280 scenes with 10 sources (scene seeds --eval-seed0..): the method,
+    symmetric checkerboard propagation instead of ACP (no_acp), heuristic best-k view selection instead of
+    the joint one (no_mhj), and both.  Per variant: the fraction of visible pixels whose depth is within
+    2 cm and 10 cm of the rendered truth (scene units are metres) after each iteration (Fig. 4, Table 1),
+    the time per depth map at --ablation-iters iterations, and the device time per half-pass."""
+    import torch
+
+    import paper_1805_07920_amd as amh
+    import scenegen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    iters = args.ablation_iters
+    seeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_scenes))
+    ctx = amh.Context(refine=1, seed=args.seed)
+    res = {name: dict(cm2=np.zeros((len(seeds), iters)), cm10=np.zeros((len(seeds), iters)), ms=[], pass_ms=[],
+                      evals=[]) for name, _, _ in ABLATION_VARIANTS}
+    H = W = 0
+    tuned = None
+    for si, seed in enumerate(seeds):
+        sc = scenegen.config_scene("c2", seed, device="cuda")
+        H, W = sc.height, sc.width
+        ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
+        srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]  # nearest sources first
+        imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images]
+        ctx.set_params(amh.params_default(refine=1, seed=args.seed))
+        ctx.init_views(imgs, sc.cams)
+        if tuned is None:
+            tuned = ctx.tune([dict(ref=0, srcs=srcs, iters=3)])  # launch configuration of the method
+            ctx.init_views(imgs, sc.cams)
+        vis = torch.from_numpy(sc.vis_count >= 2).to(dev)
+        gt = torch.from_numpy(sc.depth_gt).to(dev)
+        depth = torch.empty((H, W), dtype=torch.float32, device=dev)
+        for name, sym, heur in ABLATION_VARIANTS:
+            r = res[name]
+            # accuracy after every iteration
+            ctx.set_params(amh.params_default(refine=1, seed=args.seed, sym_prop=sym, heuristic_views=heur,
+                                              timing=1))
+            ctx.begin(0, srcs)
+            ctx.init_hypotheses()
+            for t in range(iters):
+                ctx.pass_(t, 0)
+                ctx.pass_(t, 1)
+                ctx.get_depth_normal_cost(depth=depth)
+                e = (depth - gt).abs()[vis]
+                r["cm2"][si, t] = float((e < 0.02).float().mean())
+                r["cm10"][si, t] = float((e < 0.10).float().mean())
+            st = ctx.get_stats()
+            r["pass_ms"].append(float(np.mean(st["ms_per_pass"])))
+            r["evals"].append(st["evals_total"])
+            # time per depth map (no per-pass events)
+            ctx.set_params(amh.params_default(refine=1, seed=args.seed, sym_prop=sym, heuristic_views=heur))
+            for _ in range(max(1, args.warmup)):
+                ctx.run_checkerboard(0, srcs, iters)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.run_checkerboard(0, srcs, iters)
+            torch.cuda.synchronize()
+            r["ms"].append(1000.0 * (time.perf_counter() - t0) / args.steps)
+            log(f"seed {seed} {name}: cm2 {np.round(r['cm2'][si], 4).tolist()} cm10 {np.round(r['cm10'][si], 4).tolist()}"
+                f" {r['ms'][-1]:.1f} ms/depth map, {r['pass_ms'][-1]:.3f} ms/half-pass")
+    ctx.close()
+    summary = {}
+    for name, sym, heur in ABLATION_VARIANTS:
+        r = res[name]
+        ms = float(np.mean(r["ms"]))
+        summary[name] = {
+            "sym_prop": sym, "heuristic_views": heur,
+            "cm2_per_iteration": r["cm2"].mean(0).round(5).tolist(),
+            "cm10_per_iteration": r["cm10"].mean(0).round(5).tolist(),
+            "ms_per_depth_map": ms, "ms_per_half_pass": float(np.mean(r["pass_ms"])),
+            "evals_per_s": float(np.mean(r["evals"])) / (ms / 1000.0),
+            "per_scene_cm2_final": r["cm2"][:, -1].round(5).tolist(),
+        }
+    full = summary["full"]
+    out = {
+        "metric": "ablation (Sec. 4): pixels within 2 cm / 10 cm of the truth per iteration, time per depth map",
+        "value": full["cm2_per_iteration"][-1], "unit": "fraction of visible pixels within 2 cm (method)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": full["ms_per_depth_map"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{W}x{H}, 10 sources nearest first, {iters} iterations with refinement, "
+                               f"scene seeds {seeds[0]}-{seeds[-1]}", "parallelism": "single GPU"},
+        "variants": summary,
+        "autotune": {"best_config": tuned[0], "ms_per_config": tuned[1]},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +371,12 @@ def main():
     ap.add_argument("--weights", default=None, help="proposal network parameters (--learned)")
     ap.add_argument("--eval-seed0", type=int, default=1, help="first held-out scene seed (--learned)")
     ap.add_argument("--eval-scenes", type=int, default=3, help="held-out scenes (--learned)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="accuracy per iteration and time of the method and its ablations (symmetric propagation, "
+                         "heuristic view selection)")
+    ap.add_argument("--ablation-iters", type=int, default=6, help="iterations per depth map (--ablation)")
+    ap.add_argument("--launch-config", type=int, default=None, choices=range(8),
+                    help="skip the autotuner and run this launch configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB element-wise copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -298,6 +398,8 @@ def main():
         return bench_batch(args)
     if args.learned:
         return bench_learned(args)
+    if args.ablation:
+        return bench_ablation(args)
 
     import torch
 
@@ -323,8 +425,12 @@ def main():
     # launch configuration (tile order, tile rows) picked by the library's autotuner on this workload,
     # before the timed region
     ctx.init_views(imgs, sc.cams, store_as=amh.AMH_F32)
-    best_cfg, tune_ms = ctx.tune([dict(ref=0, srcs=srcs, iters=cfg["iters"])])
-    log(f"autotune: config {best_cfg}, ms per configuration {np.round(tune_ms, 2).tolist()}")
+    if args.launch_config is None:
+        best_cfg, tune_ms = ctx.tune([dict(ref=0, srcs=srcs, iters=cfg["iters"])])
+        log(f"autotune: config {best_cfg}, ms per configuration {np.round(tune_ms, 2).tolist()}")
+    else:  # a fixed configuration (per-tile-shape counter runs)
+        best_cfg, tune_ms = args.launch_config, None
+        ctx.set_launch_config(best_cfg)
 
     def step():
         ctx.init_views(imgs, sc.cams, store_as=amh.AMH_F32)

@@ -90,6 +90,15 @@ typedef struct {
     float conf_min;                     /* learned proposal: lowest confidence that replaces a random plane
                                          * (default 0: on held-out 1920x1280 scenes every in-range predicted
                                          * plane beat a random one after one iteration) */
+    int sym_prop;        /* ablation of Sec. 4 (default 0): 1 replaces the asymmetric propagation by the
+                          * symmetric checkerboard of Gipuma's fast version (Fig. 2(c)): row r of the cost
+                          * matrix takes the one neighbour at distance 1 (r < 4) or 5 (r >= 4) up, down,
+                          * left, right */
+    int heuristic_views; /* ablation of Sec. 4 (default 0): 1 replaces the joint view selection by the
+                          * heuristic one (Sec. 3.2): each hypothesis and each refinement candidate costs
+                          * the mean of its own k lowest per-view costs; S = 0 and v = -1 are kept.
+                          * Either ablation runs on the single-image path only (amh_pass and the calls
+                          * built on it); the batched calls return UNSUPPORTED. */
 } amh_params;
 
 /* Counters of the work performed since the last amh_begin / amh_run_checkerboard. */
@@ -112,7 +121,7 @@ typedef struct {
 } amh_job;
 
 /* Fills *out with the paper's parameters, depth range [2, 6], refine 1,
- * include_self 1, seed 0, timing 0, conf_min 0.  INVALID_ARG if out is NULL. */
+ * include_self 1, seed 0, timing 0, conf_min 0, no ablation.  INVALID_ARG if out is NULL. */
 amh_status amh_params_default(amh_params *out);
 
 /* Creates a context on the current HIP device.  p: parameters (copied).

@@ -65,6 +65,8 @@ amh_status check_params(amh_ctx *c, const amh_params *p) {
     if ((p->refine != 0 && p->refine != 1) || (p->include_self != 0 && p->include_self != 1) ||
         (p->timing != 0 && p->timing != 1))
         return fail(c, AMH_E_INVALID_ARG, "refine, include_self and timing are 0 or 1");
+    if ((p->sym_prop != 0 && p->sym_prop != 1) || (p->heuristic_views != 0 && p->heuristic_views != 1))
+        return fail(c, AMH_E_INVALID_ARG, "sym_prop and heuristic_views are 0 or 1");
     if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(c, AMH_E_INVALID_ARG, "conf_min must be in [0, 1]");
     return AMH_OK;
 }
@@ -94,6 +96,8 @@ MethodDev method_dev(const amh_params &p, int t) {
     m.include_self = p.include_self;
     m.refine = p.refine;
     m.seed = p.seed;
+    m.sym_prop = p.sym_prop;
+    m.heuristic = p.heuristic_views;
     return m;
 }
 
@@ -511,6 +515,8 @@ amh_status amh_params_default(amh_params *out) {
     out->seed = 0;
     out->timing = 0;
     out->conf_min = 0.0f;  // measured best after one iteration (see amhmvs.h)
+    out->sym_prop = 0;
+    out->heuristic_views = 0;
     return AMH_OK;
 }
 
@@ -856,6 +862,8 @@ static amh_status run_batch_impl(amh_ctx *c, int n_jobs, const amh_job *jobs, bo
     amh_status st = check_jobs(c, n_jobs, jobs);
     if (st != AMH_OK) return st;
     if (proposal && !c->net) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
+    if (c->p.sym_prop || c->p.heuristic_views)
+        return fail(c, AMH_E_UNSUPPORTED, "the ablation modes run on the single-image path only");
     std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order, c->cfg_waves, proposal ? 1 : 0};
     for (int j = 0; j < n_jobs; ++j) {
         key.push_back(jobs[j].ref);

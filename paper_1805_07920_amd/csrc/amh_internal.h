@@ -39,6 +39,7 @@ struct MethodDev {
     int n1, n2, k;
     int include_self, refine;
     uint64_t seed;
+    int sym_prop, heuristic;     // ablation switches (symmetric propagation, heuristic views)
 };
 
 struct StateDev {

@@ -684,7 +684,30 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
 // ---------------------------------------------------------------------------
 // One checkerboard half-pass (Sec. 3.1 - 3.3).
 // ---------------------------------------------------------------------------
-template <int HALF, int WAVES>
+// Mean of the kk lowest of n values at stride `stride` (heuristic view selection of the ablation).
+__device__ __forceinline__ float mean_k_lowest(const float *c, int stride, int n, int kk) {
+    uint32_t taken = 0;
+    float sum = 0.f;
+    for (int r = 0; r < kk; ++r) {
+        int bj = -1;
+        float bv = 0.f;
+        for (int j = 0; j < n; ++j) {
+            if ((taken >> j) & 1u) continue;
+            const float v = c[j * stride];
+            if (bj < 0 || v < bv) { bj = j; bv = v; }
+        }
+        taken |= 1u << bj;
+        sum += bv;
+    }
+    return sum / (float)kk;
+}
+
+// ABL: the ablation build of the pass, with the two switches of Sec. 4 read at run
+// time: m.sym_prop (symmetric checkerboard propagation: region r holds the one
+// neighbour at distance 1 (r < 4) or 5 (r >= 4) up/down/left/right, the fast
+// pattern of Fig. 2(c)) and m.heuristic (each hypothesis, and each refinement
+// candidate, costs the mean of its own k lowest per-view costs; no selection memory).
+template <int HALF, int WAVES, bool ABL = false>
 __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned char *smem) {
     PassLds S = carve(smem, a.n_src, WAVES);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -706,7 +729,15 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
     bool valid = false;
     if (pix_ok) {
-        if (row < 8) {
+        if (ABL && m.sym_prop && row < 8) {
+            const int u = row < 4 ? 1 : 5, dir = row & 3;
+            const int nx = x + (dir == 2 ? -u : (dir == 3 ? u : 0));
+            const int ny = y + (dir == 0 ? -u : (dir == 1 ? u : 0));
+            if (nx >= 0 && nx < W && ny >= 0 && ny < H) {
+                valid = true;
+                pl = a.st.planes[(size_t)ny * W + nx];
+            }
+        } else if (row < 8) {
             int bx = -1, by = -1;
             float bc = 0.f;
             const int ne = region_size(row);
@@ -758,10 +789,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     //     good view: more than n1 costs below tau and fewer than n2 above tau_up;
     //     importance: mean confidence exp(-m^2 / (2 beta^2)) over the valid rows
     float *psi = S.psi + (wave * kGroups + g) * kMaxSrc;
+    const bool heur = ABL && m.heuristic;  // uniform over the launch
     int nv = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) nv += S.valid[wave * 64 + g * kRows + i];
-    if (pix_ok) {
+    if (pix_ok && !heur) {
         for (int j = row; j < N; j += kRows) {
             int lt = 0, gt = 0;
             float sc = 0.f;
@@ -785,8 +817,9 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     int vprev = -1;
     uint32_t Sprev = 0;
     float wsum = 0.f;
-    bool uniform = false;
-    if (pix_ok) {
+    bool uniform = heur;
+    if (heur) wsum = (float)N;
+    if (pix_ok && !heur) {
         vprev = a.st.v[p];
         Sprev = a.st.S[p];
         float best = 0.f;
@@ -831,9 +864,13 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     // (6) unified cost of the lane's hypothesis (Eq. 7)
     float mfin = __builtin_inff();
     if (valid) {
-        float acc = 0.f;
-        for (int j = 0; j < N; ++j) acc = fmaf(wgt[j], mcol[j * 64 + lane], acc);
-        mfin = acc / wsum;
+        if (heur) {
+            mfin = mean_k_lowest(mcol + lane, 64, N, min(m.k, N));
+        } else {
+            float acc = 0.f;
+            for (int j = 0; j < N; ++j) acc = fmaf(wgt[j], mcol[j * 64 + lane], acc);
+            mfin = acc / wsum;
+        }
     }
     S.mf[tid] = mfin;
     __syncthreads();
@@ -915,9 +952,14 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
         __syncthreads();
         if (pix_ok) {
             for (int c = 0; c < ncand; ++c) {
-                float acc = 0.f;
-                for (int i = 0; i < nw; ++i) acc += res[c * nw + i];
-                const float cc = acc / wsum;
+                float cc;
+                if (heur) {
+                    cc = mean_k_lowest(res + c * nw, 1, nw, min(m.k, nw));
+                } else {
+                    float acc = 0.f;
+                    for (int i = 0; i < nw; ++i) acc += res[c * nw + i];
+                    cc = acc / wsum;
+                }
                 if (cc < bcost) {
                     bcost = cc;
                     best = cand[c];
@@ -940,13 +982,13 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
 // ---------------------------------------------------------------------------
 // Single-image half-pass: one workgroup per tile of the colour.
 // ---------------------------------------------------------------------------
-template <int HALF, int WAVES>
+template <int HALF, int WAVES, bool ABL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
 void pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = tile_of_block(a.n_tiles, a.order);
     if (L < 0) return;
-    pass_body<HALF, WAVES>(a, L, smem);
+    pass_body<HALF, WAVES, ABL>(a, L, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1237,12 +1279,23 @@ hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
 hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
     const size_t lds = pass_lds_bytes(a.n_src, a.waves);
     const dim3 grid(grid_for(a.n_tiles)), block(64 * a.waves);
+    const bool abl = a.m.sym_prop || a.m.heuristic;
     if (a.waves == 2) {
-        if (half) AMH_LAUNCH((pass_kernel<1, 2>), grid, block, lds, s, a);
-        else AMH_LAUNCH((pass_kernel<0, 2>), grid, block, lds, s, a);
+        if (abl) {
+            if (half) AMH_LAUNCH((pass_kernel<1, 2, true>), grid, block, lds, s, a);
+            else AMH_LAUNCH((pass_kernel<0, 2, true>), grid, block, lds, s, a);
+        } else {
+            if (half) AMH_LAUNCH((pass_kernel<1, 2, false>), grid, block, lds, s, a);
+            else AMH_LAUNCH((pass_kernel<0, 2, false>), grid, block, lds, s, a);
+        }
     } else if (a.waves == 4) {
-        if (half) AMH_LAUNCH((pass_kernel<1, 4>), grid, block, lds, s, a);
-        else AMH_LAUNCH((pass_kernel<0, 4>), grid, block, lds, s, a);
+        if (abl) {
+            if (half) AMH_LAUNCH((pass_kernel<1, 4, true>), grid, block, lds, s, a);
+            else AMH_LAUNCH((pass_kernel<0, 4, true>), grid, block, lds, s, a);
+        } else {
+            if (half) AMH_LAUNCH((pass_kernel<1, 4, false>), grid, block, lds, s, a);
+            else AMH_LAUNCH((pass_kernel<0, 4, false>), grid, block, lds, s, a);
+        }
     } else {
         return hipErrorInvalidValue;
     }

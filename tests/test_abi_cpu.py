@@ -113,3 +113,12 @@ def test_conf_min_validated(amh):
     for bad in (-0.1, 1.5, float("nan")):
         p.conf_min = bad
         assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(p), None) == amh.AMH_E_INVALID_ARG
+
+
+def test_ablation_switches_validated(amh):
+    p = amh.params_default()
+    assert p.sym_prop == 0 and p.heuristic_views == 0
+    for field in ("sym_prop", "heuristic_views"):
+        for bad in (-1, 2):
+            q = amh.params_default(**{field: bad})
+            assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(q), None) == amh.AMH_E_INVALID_ARG

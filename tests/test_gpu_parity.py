@@ -131,11 +131,13 @@ def test_init_matches_oracle(amh, oracle_mod, scene_c1):
     assert st["evals_init"] == sc.width * sc.height * 4
 
 
-def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1):
+def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1, sym_prop=0, heuristic=0):
     n = len(sc.srcs) if n_src is None else n_src
     V = O.Views(sc.images[: n + 1], sc.cams[: n + 1])
-    P = O.Params(refine=refine, seed=seed, include_self=include_self)
-    with make_ctx(amh, sc, refine=refine, seed=seed, include_self=include_self) as ctx:
+    P = O.Params(refine=refine, seed=seed, include_self=include_self, prop_mode=sym_prop,
+                 view_mode=2 if heuristic else 0)
+    with make_ctx(amh, sc, refine=refine, seed=seed, include_self=include_self, sym_prop=sym_prop,
+                  heuristic_views=heuristic) as ctx:
         ctx.begin(0, list(range(1, n + 1)))
         ctx.init_hypotheses()
         # earlier passes give a realistic state (non-empty S, v)
@@ -203,6 +205,46 @@ def test_single_pass_without_self_row(amh, oracle_mod, scene_c1):
     say("case pass include_self=0")
     _pass_parity(amh, oracle_mod, scene_c1, 0, 0, seed=2, refine=0, include_self=0)
 
+
+
+# ablation modes of Sec. 4 (symmetric propagation, heuristic best-k view selection), same bars
+@pytest.mark.parametrize("sym,heur,t,colour,refine", [(1, 0, 0, 0, 1), (1, 0, 1, 1, 1), (0, 1, 0, 1, 0),
+                                                      (0, 1, 1, 0, 1), (1, 1, 3, 1, 1)])
+def test_ablation_pass_matches_oracle(amh, oracle_mod, scene_c1, sym, heur, t, colour, refine):
+    say("case ablation pass c1", sym, heur, t, colour, refine)
+    _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=6, refine=refine, sym_prop=sym, heuristic=heur)
+
+
+@pytest.mark.parametrize("key,sym,heur", [("ragged_131x77_n5", 1, 1), ("fp16_96x64_n6", 0, 1)])
+def test_ablation_pass_other_shapes(amh, oracle_mod, key, sym, heur):
+    say("case ablation pass", key, sym, heur)
+    _pass_parity(amh, oracle_mod, build_scene(SCENES[key]), 1, 1, seed=8, refine=1, sym_prop=sym, heuristic=heur)
+
+
+@pytest.mark.parametrize("sym,heur", [(1, 0), (0, 1), (1, 1)])
+def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_c1, sym, heur):
+    say("case ablation full run c1", sym, heur)
+    O = oracle_mod
+    with make_ctx(amh, scene_c1, refine=1, seed=4, sym_prop=sym, heuristic_views=heur) as ctx:
+        ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
+        depth, _, _ = ctx.get_depth_normal_cost()
+        _, _, S, v = ctx.get_state()
+    V = O.Views.from_scene(scene_c1)
+    st = O.run(V, O.Params(refine=1, seed=4, prop_mode=sym, view_mode=2 if heur else 0), 3)
+    od, _ = O.depth_normal(V, st)
+    frac = (np.abs(depth - od) / od <= 1e-3).mean()
+    say(f"  depth agreement {frac:.5f}")
+    assert frac >= 0.995
+    if heur:
+        assert np.all(S == 0) and np.all(v == -1)
+
+
+def test_ablation_rejected_by_the_batched_path(amh, scene_c1):
+    say("case ablation batch rejected")
+    with make_ctx(amh, scene_c1, sym_prop=1) as ctx:
+        with pytest.raises(amh.AmhError) as e:
+            ctx.run_batch([dict(ref=0, srcs=[1, 2, 3, 4], iters=1)])
+        assert e.value.status == amh.AMH_E_UNSUPPORTED
 
 def test_full_run_depth_parity(amh, oracle_mod, scene_c1):
     """3 iterations + refinement: GPU and oracle depth maps agree on >= 99.5 % of pixels (0.1 % relative)."""
