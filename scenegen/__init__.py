@@ -62,6 +62,10 @@ class Scene:
     d_min: float = D_MIN
     d_max: float = D_MAX
     meta: dict = field(default_factory=dict)
+    # with all_views=True: per camera (same order as cams) the z-depth and the unit normal (camera frame,
+    # facing that camera) of the surface at each pixel centre, float32
+    depth_views: list = None
+    normal_views: list = None
 
     @property
     def ref(self) -> np.ndarray:
@@ -300,7 +304,7 @@ def _render(cams: list, planes: list, seed: int, spacing: float, ss: int, device
 
 def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: int, seed: int, *,
                gain: float = 0.0, low_texture_frac: float = 0.0, src_dtype: str = "f32",
-               supersample: int = 4, device="cpu") -> Scene:
+               supersample: int = 4, device="cpu", all_views: bool = False) -> Scene:
     """Render one reference + n_src source views of a seeded piecewise-planar world."""
     rng = np.random.default_rng(seed)
     ref_cam = Camera(_intrinsics(width, height), np.eye(3), np.zeros(3), width, height)
@@ -331,6 +335,7 @@ def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: in
     images = []
     ref_depth = ref_ids = None
     src_depths = []
+    depth_views, normal_views = ([], []) if all_views else (None, None)
     rendered = _render(cams, planes, seed, spacing, supersample, device)
     for vi, cam in enumerate(cams):
         img, depth, ids = rendered[vi]
@@ -349,6 +354,18 @@ def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: in
             ref_depth, ref_ids = depth, ids
         else:
             src_depths.append(depth)
+        if all_views:
+            depth_views.append(depth.to(torch.float32).cpu().numpy())
+            idn = ids.cpu().numpy()
+            nv = np.zeros((height, width, 3))
+            for pid, pl in enumerate(planes):
+                nv[idn == pid] = cam.R @ pl.n
+            Ki = np.linalg.inv(cam.K)
+            gy, gx = np.mgrid[0:height, 0:width]
+            ray = np.stack([Ki[0, 0] * gx + Ki[0, 1] * gy + Ki[0, 2], Ki[1, 1] * gy + Ki[1, 2],
+                            np.ones_like(gx, dtype=np.float64)], -1)
+            nv = np.where(((nv * ray).sum(-1) > 0)[..., None], -nv, nv)
+            normal_views.append(nv.astype(np.float32))
 
     # ground truth for the reference: depth, normal, visibility
     depth_gt = ref_depth.to(torch.float32).cpu().numpy()
@@ -378,7 +395,8 @@ def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: in
     meta = dict(width=width, height=height, n_src=n_src, arc_deg=arc_deg, n_planes=n_planes, seed=seed,
                 gain=gain, low_texture_frac=low_texture_frac, src_dtype=src_dtype, supersample=supersample,
                 gains=gains)
-    return Scene(images, cams, depth_gt, normal_gt, vis.cpu().numpy(), ids_np, low_mask, meta=meta)
+    return Scene(images, cams, depth_gt, normal_gt, vis.cpu().numpy(), ids_np, low_mask, meta=meta,
+                 depth_views=depth_views, normal_views=normal_views)
 
 
 # --------------------------------------------------------------------------------------
