@@ -47,6 +47,24 @@ PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 1998659.8, "write_kib": 85000.
                 "kernel_sha256": "23a440e5bf5b86f6e42ed9f98ffbd8f61315b487a5c76026ddc32079007f0345"}
 
 
+# The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the
+# 44 dispatches of one bench.py --fusion --steps 1 --warmup 0 run); profiles/fuse_kernel_1920x1280_v11.md.
+FUSE_TRAFFIC = {"fetch_kib": 102368.1, "write_kib": 38176.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                "source_sha256": "a3f585a1d4563ea4c7aeb69d172548120645751f61c5d04b8850c1ede7adc101"}
+
+
+def fuse_traffic_bytes():
+    """HBM-side bytes per fusion-kernel launch, or None once the fusion source has changed since."""
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1805_07920_amd", "csrc", "amh_fusion.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != FUSE_TRAFFIC["source_sha256"]:
+            return None
+    return 1024.0 * (FUSE_TRAFFIC["fetch_kib"] * FUSE_TRAFFIC["fetch_scale"]
+                     + FUSE_TRAFFIC["write_kib"] * FUSE_TRAFFIC["write_scale"])
+
+
 def pass_traffic_bytes(tile_rows: int):
     """HBM-side bytes per half-pass launch of the variant with `tile_rows` rows per workgroup, or None
     when not measured for it or once the kernel source has changed since the counters."""
@@ -356,6 +374,123 @@ def bench_ablation(args):
     print(json.dumps(out))
 
 
+def bench_fusion(args):
+    """The stage after the depth maps on one scene: 11 views of 1920x1280 (the measured scene, seed
+    --eval-seed0), each the reference of one depth map with the other 10 as sources (batched, untimed),
+    then per step: the 4x4 median filter of the 11 depth maps and the consistency-check fusion into one
+    point cloud (f_eps 0.3, f_ang 30 deg, f_con 2).  Reports ms per scene, points, accuracy of the points
+    against the rendered surfaces, and the fusion's bytes against the HBM roofline."""
+    import torch
+
+    import paper_1805_07920_amd as amh
+    import scenegen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seed = args.eval_seed0
+    sc = scenegen.config_scene("c2", seed, device="cuda", all_views=True)
+    V = len(sc.images)
+    H, W = sc.height, sc.width
+    ctx = amh.Context(refine=1, seed=args.seed)
+    ctx.init_views([torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images], sc.cams)
+    ctx.run_batch([dict(ref=i, srcs=[j for j in range(V) if j != i], iters=3) for i in range(V)])
+    depths = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(V)]
+    normals = [torch.empty((H, W, 3), dtype=torch.float32, device=dev) for _ in range(V)]
+    for i in range(V):
+        ctx.get_job_result(i, depth=depths[i], normal=normals[i])
+    filt = [torch.empty_like(d) for d in depths]
+    cap = V * H * W
+    views = list(range(V))
+
+    def step():
+        for d, f in zip(depths, filt):
+            ctx.median_filter4(d, f)
+        return ctx.fuse(views, filt, normals, capacity=cap)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P, N, O, total = step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    # the fusion alone, with events on the library's stream (torch's current stream), and the fusion kernel
+    # of each view with the library's own events (timing = 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ctx.fuse(views, filt, normals, capacity=cap)
+    e1.record()
+    torch.cuda.synchronize()
+    fuse_ms = e0.elapsed_time(e1) / args.steps
+    ctx.set_params(amh.params_default(refine=1, seed=args.seed, timing=1))
+    kern_ms = []
+    for _ in range(args.steps):
+        ctx.fuse(views, filt, normals, capacity=cap)
+        st = ctx.get_stats()
+        kern_ms.append(st["ms_fuse_kernels"] / st["n_fuse_kernels"])
+    kernel_ms = float(np.mean(kern_ms))
+    # accuracy: each point against the rendered depth of its origin view at the pixel it projects to
+    O64 = O.long()
+    err = torch.empty(len(P), dtype=torch.float64, device=dev)
+    for i in range(V):
+        m = O64[:, 0] == i
+        cam = sc.cams[i]
+        R = torch.tensor(cam.R, dtype=torch.float64, device=dev)
+        t = torch.tensor(cam.t, dtype=torch.float64, device=dev)
+        K = torch.tensor(cam.K, dtype=torch.float64, device=dev)
+        Xc = P[m].double() @ R.T + t
+        p = Xc @ K.T
+        u = torch.floor(p[:, 0] / p[:, 2] + 0.5).clamp(0, W - 1).long()
+        v = torch.floor(p[:, 1] / p[:, 2] + 0.5).clamp(0, H - 1).long()
+        gt = torch.from_numpy(sc.depth_views[i]).to(dev).double()[v, u]
+        err[m] = (Xc[:, 2] - gt).abs()
+    cm2 = float((err < 0.02).double().mean())
+    cm10 = float((err < 0.10).double().mean())
+    # algorithmic bytes of the fusion kernel of one reference view: its depth, normal and consumed mark
+    # (17 B / px), the other views' depth and normal maps once each (16 B / px), and the view's share of the
+    # points (48 B each: point, normal, origin)
+    px = H * W
+    alg = 17 * px + (V - 1) * 16 * px + 48 * total / V
+    achieved = alg / (kernel_ms / 1000.0)
+    cpu = None
+    if not args.no_cpu:
+        from oracle import fusion
+
+        # bounded sample: the per-pixel definition on random pixels of the first reference view
+        dn = [f.cpu().numpy() for f in filt]
+        nn = [n.cpu().numpy() for n in normals]
+        rng = np.random.default_rng(0)
+        n_pix = 0
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < 10.0:
+            fusion.fuse_pixel(sc.cams, dn, nn, 0, int(rng.integers(0, W)), int(rng.integers(0, H)))
+            n_pix += 1
+        el = time.perf_counter() - t1
+        cpu = {"value": n_pix / el, "unit": "reference pixels fused per s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_pix} random pixels of the first reference view against the other {V - 1} views "
+                         f"(per-pixel definition, float64), {el:.1f} s"}
+    out = {
+        "metric": "depth-map fusion: ms per scene (4x4 median of every map + consistency-check fusion)",
+        "value": ms, "unit": "ms per scene", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{V} views of {W}x{H}, depth maps by the method (3 iterations, 10 sources each), "
+                               f"f_eps 0.3, f_ang 30, f_con 2, scene seed {seed}", "parallelism": "single GPU"},
+        "points": total, "fuse_ms": fuse_ms, "median_ms": ms - fuse_ms,
+        "reference_pixels_fused_per_s": V * px / (fuse_ms / 1000.0),
+        "points_within_2cm": cm2, "points_within_10cm": cm10,
+        "fuse_kernel_ms": kernel_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8e12, "traffic": fuse_traffic_bytes(), "bytes_per_launch": alg,
+                     "kernel": "fuse_kernel (one reference view against the other 10), algorithmic bytes"},
+        "cpu_baseline": cpu,
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +510,8 @@ def main():
                     help="accuracy per iteration and time of the method and its ablations (symmetric propagation, "
                          "heuristic view selection)")
     ap.add_argument("--ablation-iters", type=int, default=6, help="iterations per depth map (--ablation)")
+    ap.add_argument("--fusion", action="store_true",
+                    help="the stage after the depth maps: median filter + consistency-check fusion of 11 views")
     ap.add_argument("--launch-config", type=int, default=None, choices=range(8),
                     help="skip the autotuner and run this launch configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -400,6 +537,8 @@ def main():
         return bench_learned(args)
     if args.ablation:
         return bench_ablation(args)
+    if args.fusion:
+        return bench_fusion(args)
 
     import torch
 

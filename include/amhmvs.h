@@ -110,6 +110,8 @@ typedef struct {
     int n_passes;
     float ms_per_pass[64];      /* device time of each half-pass (timing = 1), else 0 */
     float ms_init;
+    float ms_fuse_kernels;      /* timing = 1: device time of the per-view fusion kernels of the last amh_fuse */
+    int n_fuse_kernels;         /* ... and their number (one per view) */
 } amh_stats;
 
 /* Batched job (see amh_run_batch). */
@@ -312,6 +314,53 @@ amh_status amh_init_from_proposal(amh_ctx *ctx, const float *pred, int h, int w)
  * sources (list the nearest first); the iterations use all of them.  STATE if
  * the network does not exist. */
 amh_status amh_run_proposal(amh_ctx *ctx, int ref, const int *srcs, int n_src, int iters);
+
+/* ------------------------------------------------------------------------ */
+/* After the depth maps (Sec. 3.3, last two paragraphs): the 4 x 4 median     */
+/* filter and the consistency-check fusion into a point cloud.                */
+/* ------------------------------------------------------------------------ */
+
+/* Thresholds of the fusion's consistency check (the check of Gipuma the paper
+ * adopts, with its values): f_eps disparity difference in pixels (0.3), f_ang
+ * normal angle in degrees (30), f_con consistent views needed (2). */
+typedef struct {
+    float f_eps;
+    float f_ang_deg;
+    int f_con;
+} amh_fusion_params;
+
+/* Fills *out with f_eps 0.3, f_ang_deg 30, f_con 2.  INVALID_ARG if out is NULL. */
+amh_status amh_fusion_params_default(amh_fusion_params *out);
+
+/* 4 x 4 median filter of a depth map (Sec. 3.3).  src, dst: device pointers to
+ * width * height floats, row-major, not overlapping (INVALID_ARG if src == dst).
+ * dst(x, y) is the median of src over columns x-1..x+2 and rows y-1..y+2 clipped
+ * to the image; NaN values are skipped (all NaN: NaN); an even count takes the
+ * mean of the two middle values.  Enqueued on the context's stream (no wait). */
+amh_status amh_median_filter4(amh_ctx *ctx, const float *src, float *dst, int width, int height);
+
+/* Consistency-check fusion (Sec. 3.3, fusion paragraph) of n_views (1..128)
+ * depth maps into one point cloud.  views[k]: a view registered with
+ * amh_init_views (its camera and size); depth[k] (H*W floats, camera z; a value
+ * that is not finite or not positive means no depth) and normal[k] (H*W*3
+ * floats, unit, camera frame): device pointers.  Views are taken as references
+ * in the order given.  A pixel p of view k not consumed by an earlier view
+ * back-projects to a world point X; another view j is consistent when X lies in
+ * front of j, projects to a pixel q (nearest, floor(u + 0.5)) inside j where j
+ * has a depth, the disparity difference f_j |C_k - C_j| |1/z_j(X) - 1/d_j(q)|
+ * is below f_eps (f_j = K_j[0][0] / K_j[2][2]) and the angle between the two
+ * world normals is below f_ang.  With at least f_con consistent views p yields
+ * a point (mean of X and the consistent back-projections, normalised sum of the
+ * normals) and its witnesses q are consumed.  Points come in view order, then
+ * raster order: points (capacity * 3 floats, world frame), point_normals
+ * (capacity * 3 floats, or NULL), origin (capacity * 3 int32: view slot k,
+ * pixel index y W + x, number of consistent views; or NULL) -- device pointers;
+ * the first min(total, capacity) points are written and *n_points (host)
+ * receives the total.  Waits for the result.  The context keeps a workspace of
+ * the views' pixel count + 36 bytes per pixel of the largest view. */
+amh_status amh_fuse(amh_ctx *ctx, int n_views, const int *views, const float *const *depth,
+                    const float *const *normal, const amh_fusion_params *fp, float *points, float *point_normals,
+                    int32_t *origin, int64_t capacity, int64_t *n_points);
 
 const char *amh_status_str(amh_status s);
 const char *amh_last_error(const amh_ctx *ctx);

@@ -126,3 +126,55 @@ def fuse(cams, depths, normals, f_eps: float = F_EPS, f_ang_deg: float = F_ANG_D
         nrm.append(Nn)
         org.append(np.stack([np.full(len(idx), i), idx, count.ravel()[idx]], 1))
     return np.concatenate(pts), np.concatenate(nrm), np.concatenate(org).astype(np.int64)
+
+
+def fuse_pixel(cams, depths, normals, i: int, x: int, y: int, used: bool = False, f_eps: float = F_EPS,
+               f_ang_deg: float = F_ANG_DEG, f_con: int = F_CON):
+    """The fusion decision of one pixel (x, y) of reference view i, written out view by view.
+
+    ``used``: whether an earlier view consumed the pixel.  Returns a dict: emitted, point, normal, count,
+    witnesses [(j, q)], and fragile -- whether a decision lies within the margins of a float32 evaluation
+    (disparity within 1e-3 px of f_eps, normal cosine within 1e-5 of cos f_ang, or a projection within
+    1e-3 px of a rounding boundary)."""
+    K, R, t, C = _cam(cams[i])
+    d = float(np.asarray(depths[i])[y, x])
+    out = dict(emitted=False, point=None, normal=None, count=0, witnesses=[], fragile=False)
+    if not (np.isfinite(d) and d > 0) or used:
+        return out
+    X = R.T @ (d * (np.linalg.inv(K) @ [x, y, 1.0]) - t)
+    nw = R.T @ np.asarray(normals[i], np.float64)[y, x]
+    cos_ang = np.cos(np.radians(f_ang_deg))
+    acc, accn = X.copy(), nw.copy()
+    for j in range(len(cams)):
+        if j == i:
+            continue
+        Kj, Rj, tj, Cj = _cam(cams[j])
+        Hj, Wj = np.shape(depths[j])
+        Xj = Rj @ X + tj
+        if not Xj[2] > 0:
+            continue
+        p = Kj @ Xj
+        u, v = p[0] / p[2], p[1] / p[2]
+        for c in (u, v):
+            f = (c + 0.5) - np.floor(c + 0.5)
+            if min(f, 1.0 - f) < 1e-3:
+                out["fragile"] = True
+        ui, vi = int(np.floor(u + 0.5)), int(np.floor(v + 0.5))
+        if not (0 <= ui <= Wj - 1 and 0 <= vi <= Hj - 1):
+            continue
+        dj = float(np.asarray(depths[j])[vi, ui])
+        if not (np.isfinite(dj) and dj > 0):
+            continue
+        nj = Rj.T @ np.asarray(normals[j], np.float64)[vi, ui]
+        disp = Kj[0, 0] / Kj[2, 2] * np.linalg.norm(C - Cj) * abs(1.0 / Xj[2] - 1.0 / dj)
+        cosn = float(nw @ nj)
+        if abs(disp - f_eps) < 1e-3 or abs(cosn - cos_ang) < 1e-5:
+            out["fragile"] = True
+        if disp < f_eps and np.degrees(np.arccos(np.clip(cosn, -1.0, 1.0))) < f_ang_deg:
+            acc += Rj.T @ (dj * (np.linalg.inv(Kj) @ [ui, vi, 1.0]) - tj)
+            accn += nj
+            out["count"] += 1
+            out["witnesses"].append((j, vi * Wj + ui))
+    if out["count"] >= f_con:
+        out.update(emitted=True, point=acc / (out["count"] + 1), normal=accn / np.linalg.norm(accn))
+    return out

@@ -27,6 +27,7 @@ EXPORTS = [
     "amh_nn_param_count", "amh_nn_init", "amh_nn_get_params", "amh_nn_set_params", "amh_nn_get_grads",
     "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
     "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config", "amh_run_batch_proposal",
+    "amh_fusion_params_default", "amh_median_filter4", "amh_fuse",
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
@@ -60,7 +61,11 @@ class amh_params(C.Structure):
 class amh_stats(C.Structure):
     _fields_ = [("evals_total", C.c_uint64), ("evals_init", C.c_uint64), ("evals_propagation", C.c_uint64),
                 ("evals_refine", C.c_uint64), ("n_passes", C.c_int), ("ms_per_pass", C.c_float * 64),
-                ("ms_init", C.c_float)]
+                ("ms_init", C.c_float), ("ms_fuse_kernels", C.c_float), ("n_fuse_kernels", C.c_int)]
+
+
+class amh_fusion_params(C.Structure):
+    _fields_ = [("f_eps", C.c_float), ("f_ang_deg", C.c_float), ("f_con", C.c_int)]
 
 
 class amh_job(C.Structure):
@@ -116,6 +121,10 @@ def lib():
         L.amh_run_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
         L.amh_set_launch_config.argtypes = [vp, ip]
         L.amh_run_batch_proposal.argtypes = [vp, ip, C.POINTER(amh_job)]
+        L.amh_fusion_params_default.argtypes = [C.POINTER(amh_fusion_params)]
+        L.amh_median_filter4.argtypes = [vp, vp, vp, ip, ip]
+        L.amh_fuse.argtypes = [vp, ip, C.POINTER(C.c_int), C.POINTER(vp), C.POINTER(vp),
+                               C.POINTER(amh_fusion_params), vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -349,7 +358,8 @@ class Context:
         self._check(self.L.amh_get_stats(self.h, C.byref(s)), "amh_get_stats")
         return dict(evals_total=s.evals_total, evals_init=s.evals_init, evals_propagation=s.evals_propagation,
                     evals_refine=s.evals_refine, n_passes=s.n_passes,
-                    ms_per_pass=list(s.ms_per_pass[:s.n_passes]), ms_init=s.ms_init)
+                    ms_per_pass=list(s.ms_per_pass[:s.n_passes]), ms_init=s.ms_init,
+                    ms_fuse_kernels=s.ms_fuse_kernels, n_fuse_kernels=s.n_fuse_kernels)
 
     # --- learned proposal ----------------------------------------------------------------
     @staticmethod
@@ -432,3 +442,38 @@ class Context:
         self._check(self.L.amh_run_proposal(self.h, ref, s, len(srcs), iters), "amh_run_proposal")
         self.H, self.W = self._views_shape[ref]
         self.n_src = len(srcs)
+
+    def median_filter4(self, src, dst=None):
+        """4x4 median filter of a device float32 (H, W) depth map into dst (allocated if None)."""
+        import torch
+
+        if dst is None:
+            dst = torch.empty_like(src)
+        H, W = int(src.shape[0]), int(src.shape[1])
+        self._check(self.L.amh_median_filter4(self.h, _ptr(src)[0], _ptr(dst)[0], W, H), "amh_median_filter4")
+        return dst
+
+    def fuse(self, views, depths, normals, f_eps: float = 0.3, f_ang_deg: float = 30.0, f_con: int = 2,
+             capacity: int | None = None):
+        """Point cloud of device depth (H, W) and normal (H, W, 3) maps of the registered ``views``:
+        (points (P, 3), normals (P, 3), origin (P, 3) int32: view slot, pixel index, consistent views),
+        device tensors trimmed to the P points fused."""
+        import torch
+
+        n = len(views)
+        if len(depths) != n or len(normals) != n:
+            raise ValueError("one depth and one normal map per view")
+        if capacity is None:
+            capacity = sum(int(d.numel()) for d in depths)
+        pts = torch.empty((max(capacity, 1), 3), dtype=torch.float32, device="cuda")
+        nrm = torch.empty_like(pts)
+        org = torch.empty((max(capacity, 1), 3), dtype=torch.int32, device="cuda")
+        v = (C.c_int * n)(*[int(x) for x in views])
+        dp = (C.c_void_p * n)(*[_ptr(d)[0] for d in depths])
+        np_ = (C.c_void_p * n)(*[_ptr(x)[0] for x in normals])
+        fp = amh_fusion_params(f_eps, f_ang_deg, f_con)
+        total = C.c_int64(0)
+        self._check(self.L.amh_fuse(self.h, n, v, dp, np_, C.byref(fp), _ptr(pts)[0], _ptr(nrm)[0], _ptr(org)[0],
+                                    capacity, C.byref(total)), "amh_fuse")
+        k = min(int(total.value), capacity)
+        return pts[:k], nrm[:k], org[:k], int(total.value)

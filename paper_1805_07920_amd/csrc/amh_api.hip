@@ -923,6 +923,7 @@ amh_status amh_get_job_times(amh_ctx *c, int n, float *job_ms) {
     if (!c) return AMH_E_INVALID_ARG;
     if (!c->batch_ran) return fail(c, AMH_E_STATE, "no batch has run");
     if (!job_ms || n != c->batch_jobs) return fail(c, AMH_E_INVALID_ARG, "need n == the batch's job count");
+    if (!c->d_bcount) return fail(c, AMH_E_STATE, "the batch's clocks were released (parameters changed)");
     // clocks: [n] job completions then the batch start, after the evaluation counters and tiles-done
     std::vector<unsigned long long> h((size_t)n + 1);
     const size_t off = 3 * (size_t)kCounterSlots + (size_t)n;
@@ -1062,7 +1063,7 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
     amh_ctx *c = const_cast<amh_ctx *>(cc);
     if (!c || !out) return AMH_E_INVALID_ARG;
     memset(out, 0, sizeof *out);
-    if (c->batch_stats) {
+    if (c->batch_stats && c->d_bcount) {
         std::vector<unsigned long long> h(3 * kCounterSlots);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->d_bcount, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1073,7 +1074,7 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
         out->evals_init = c->batch_counts[0];
         out->evals_propagation = c->batch_counts[1];
         out->evals_refine = c->batch_counts[2];
-    } else {
+    } else if (!c->batch_stats && c->counters) {
         std::vector<unsigned long long> h(3 * kCounterSlots);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->counters, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1096,6 +1097,8 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
         HIPCHK(c, hipEventSynchronize(c->ev_init[1]));
         HIPCHK(c, hipEventElapsedTime(&out->ms_init, c->ev_init[0], c->ev_init[1]));
     }
+    out->ms_fuse_kernels = c->fuse_ms;
+    out->n_fuse_kernels = c->fuse_n;
     return AMH_OK;
 }
 
@@ -1103,6 +1106,7 @@ void amh_destroy(amh_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     free_net(c);
+    free_fusion(c);
     for (auto &v : c->views) free_view(v);
     for (auto &j : c->jobs) free_job(j);
     free_batch(c);

@@ -91,11 +91,18 @@ struct amh_ctx {
     float *prop_pred = nullptr;
     float *prop_qref = nullptr;
     size_t prop_cap = 0;          // cells
+    // fusion workspace (amh_fuse): used marks, one view's dense outputs, tables
+    void *fuse_ws = nullptr;
+    size_t fuse_ws_cap = 0;
+    std::vector<hipEvent_t> fuse_ev;  // timing = 1: a start/stop pair per fusion kernel launch
+    float fuse_ms = 0.f;               // their total device time in the last amh_fuse
+    int fuse_n = 0;
 };
 
 namespace amh {
 
 void free_net(amh_ctx *c);
+void free_fusion(amh_ctx *c);
 
 amh_status fail(amh_ctx *c, amh_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 

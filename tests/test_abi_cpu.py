@@ -23,7 +23,7 @@ def amh():
 def header_functions():
     txt = open(os.path.join(ROOT, "include", "amhmvs.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(amh_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(amh_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_exports_every_declared_function(amh):
@@ -122,3 +122,14 @@ def test_ablation_switches_validated(amh):
         for bad in (-1, 2):
             q = amh.params_default(**{field: bad})
             assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(q), None) == amh.AMH_E_INVALID_ARG
+
+
+def test_fusion_arguments_validated(amh):
+    L = amh.lib()
+    fp = amh.amh_fusion_params()
+    assert L.amh_fusion_params_default(C.byref(fp)) == amh.AMH_OK
+    assert (fp.f_eps, fp.f_ang_deg, fp.f_con) == (pytest.approx(0.3), 30.0, 2)
+    assert L.amh_fusion_params_default(None) == amh.AMH_E_INVALID_ARG
+    assert L.amh_median_filter4(None, None, None, 4, 4) == amh.AMH_E_INVALID_ARG
+    n = C.c_int64(0)
+    assert L.amh_fuse(None, 1, None, None, None, C.byref(fp), None, None, None, 0, C.byref(n)) == amh.AMH_E_INVALID_ARG

@@ -145,6 +145,26 @@ def test_batch_errors(amh, batch_setup):
         assert e.value.status == amh.AMH_E_INVALID_ARG
 
 
+
+def test_changed_parameters_release_the_batch(amh, batch_setup):
+    """Changing the parameters drops the captured batch: statistics read as zero, job clocks are a STATE
+    error, and the per-job results stay readable."""
+    say("case set_params after a batch")
+    images, cams, jobs = batch_setup
+    with amh.Context(seed=2) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_batch(jobs[:2])
+        assert ctx.get_stats()["evals_total"] > 0
+        d0, _, _ = ctx.get_job_result(0)
+        ctx.set_params(amh.params_default(seed=2, timing=1))
+        st = ctx.get_stats()
+        assert st["evals_total"] == 0
+        with pytest.raises(amh.AmhError) as e:
+            ctx.get_job_times()
+        assert e.value.status == amh.AMH_E_STATE
+        d1, _, _ = ctx.get_job_result(0)
+        assert np.array_equal(d0, d1)
+
 @pytest.mark.parametrize("config", [1, 4, 5])
 def test_single_image_launch_configurations_agree(amh, batch_setup, config):
     """Tile order and tile shape (4- or 2-row workgroups) change only the launch, not the result."""

@@ -134,3 +134,26 @@ def test_pixels_without_depth():
     for y in (5, 6, 7):
         assert y * 40 + 20 not in from0
     assert 8 * 40 + 20 in from0
+
+
+def test_vectorised_fusion_equals_the_per_pixel_definition():
+    """View 0 (nothing consumed yet) of a rendered scene with noisy depths: both formulations agree."""
+    import scenegen
+
+    sc = scenegen.make_scene(48, 32, 3, 30.0, 3, 2, supersample=2, all_views=True)
+    rng = np.random.default_rng(1)
+    depths = [d * (1 + rng.normal(scale=2e-3, size=d.shape)) for d in sc.depth_views]
+    P, N, O = fusion.fuse(sc.cams, depths, sc.normal_views)
+    first = {int(o[1]): k for k, o in enumerate(O) if o[0] == 0}
+    emitted = 0
+    for y in range(32):
+        for x in range(48):
+            r = fusion.fuse_pixel(sc.cams, depths, sc.normal_views, 0, x, y)
+            k = first.get(y * 48 + x)
+            assert r["emitted"] == (k is not None), (x, y)
+            if k is not None:
+                emitted += 1
+                assert r["count"] == O[k, 2]
+                np.testing.assert_allclose(P[k], r["point"], atol=1e-12)
+                np.testing.assert_allclose(N[k], r["normal"], atol=1e-12)
+    assert 0.3 * 48 * 32 < emitted < 48 * 32
