@@ -25,6 +25,8 @@
  *   R5  bilateral weight exp(-|dI|/(2 sI^2) - |dx|/(2 sx^2)) with the colour
  *       difference and the spatial distance unsquared, as the paper prints it;
  *       weights come from the reference patch and apply to both patches.
+ *       bilateral_sq = 1 takes the usual squared form exp(-dI^2/(2 sI^2) -
+ *       |dx|^2/(2 sx^2)) instead.
  *   R6  a patch with weighted variance below 1e-5 gives cost 2.
  *   R7  the pixel's current plane is scored as a ninth row, excluded from the
  *       view inference, included in the final argmin (ties keep it).
@@ -242,6 +244,7 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             a[n] = ref_at(V, x + dx, y + dy);
             double dcol = fabs(a[n] - ac);
             double dsp = sqrt((double)(dx * dx + dy * dy));
+            if (p->bilateral_sq) { dcol *= dcol; dsp *= dsp; } /* the squared form (R5 alternative) */
             w[n] = exp(-dcol / (2.0 * p->sigma_color * p->sigma_color) - dsp / (2.0 * p->sigma_spatial * p->sigma_spatial));
             /* every sample's ray must meet the plane in front of the reference camera and the
                point must lie in front of the source camera (R3) */

@@ -58,6 +58,7 @@ typedef struct {
                         2: heuristic selection, mean of each hypothesis' k lowest costs */
     int prop_mode;   /* 0: asymmetric checkerboard propagation (the method);
                         1: symmetric fast checkerboard propagation (ablation) */
+    int bilateral_sq; /* 1: squared colour difference and distance in the bilateral weight */
 } orc_params;
 
 typedef struct {

@@ -207,3 +207,28 @@ def test_integer_disparity_true_plane_costs_zero(oracle_mod):
         assert oracle_mod.matching_cost(V, P, x, y, pl, 0) == pytest.approx(0.0, abs=1e-9)
         wrong = np.array([0.0, 0.0, -1.0, Z * 1.2])
         assert oracle_mod.matching_cost(V, P, x, y, wrong, 0) > 0.3
+
+
+def test_squared_bilateral_weights_match_weighted_cov(oracle_mod):
+    """The squared form: sigma_I = 3 and a 6-level step weigh e^-2 (36 / 18); sigma_x = 1 weighs
+    exp(-(dx^2 + dy^2) / 2)."""
+    rng = np.random.default_rng(8)
+    ref = np.full((16, 16), 100.0, np.float32)
+    far = rng.random((16, 16)) < 0.5
+    ref[far] = 106.0
+    ref[8, 8] = 100.0
+    src = rng.uniform(0, 255, (16, 16)).astype(np.float32)
+    V, pl = identity_pair(oracle_mod, ref, src)
+    a, b = window(ref, 8, 8), window(src, 8, 8)
+    P = oracle_mod.Params(sigma_color=3.0, sigma_spatial=1e12, bilateral_sq=1)
+    w = np.where(a == 106.0, math.exp(-2.0), 1.0)
+    c = np.cov(np.stack([a, b]), aweights=w, bias=True)
+    assert oracle_mod.matching_cost(V, P, 8, 8, pl, 0) == pytest.approx(1.0 - c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]),
+                                                                       abs=1e-12)
+    ref2 = rng.uniform(0, 255, (16, 16)).astype(np.float32)
+    V, pl = identity_pair(oracle_mod, ref2, src)
+    P = oracle_mod.Params(sigma_color=1e12, sigma_spatial=1.0, bilateral_sq=1)
+    w = np.array([math.exp(-(dx * dx + dy * dy) / 2.0) for dy in OFFS for dx in OFFS])
+    c = np.cov(np.stack([window(ref2, 8, 8), b]), aweights=w, bias=True)
+    assert oracle_mod.matching_cost(V, P, 8, 8, pl, 0) == pytest.approx(1.0 - c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]),
+                                                                       abs=1e-12)
