@@ -41,10 +41,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 1998659.8, "write_kib": 85000.4},
-                                 4: {"fetch_kib": 1172383.3, "write_kib": 82094.5}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2466812.9, "write_kib": 312246.1},
+                                 4: {"fetch_kib": 1568086.3, "write_kib": 288318.8}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "23a440e5bf5b86f6e42ed9f98ffbd8f61315b487a5c76026ddc32079007f0345"}
+                "kernel_sha256": "730756f184ffd6869aecc5baababfe690f00a9fe4c2bd3af8e1dd77c3bfff45e"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the
@@ -281,15 +281,21 @@ def bench_learned(args):
     print(json.dumps(out))
 
 
-ABLATION_VARIANTS = (("full", 0, 0), ("no_acp", 1, 0), ("no_mhj", 0, 1), ("neither", 1, 1))
+ABLATION_VARIANTS = (("full", dict()), ("no_acp", dict(sym_prop=1)), ("no_mhj", dict(heuristic_views=1)),
+                     ("neither", dict(sym_prop=1, heuristic_views=1)))
+# readings of the paper that the printed text leaves open, against its literal form: the pixel's own plane
+# competing in the final argmin (R7), the unsquared bilateral weight (R5) and the iteration count (R14: the
+# curves run to the paper's 6)
+READING_VARIANTS = (("readings", dict()), ("no_self_row", dict(include_self=0)),
+                    ("squared_weights", dict(bilateral_squared=1)),
+                    ("paper_literal", dict(include_self=0, bilateral_squared=1)))
 
 
-def bench_ablation(args):
-    """Ablation of Sec. 4 on 1920x1280 scenes with 10 sources (scene seeds --eval-seed0..): the method,
-    symmetric checkerboard propagation instead of ACP (no_acp), heuristic best-k view selection instead of
-    the joint one (no_mhj), and both.  Per variant: the fraction of visible pixels whose depth is within
-    2 cm and 10 cm of the rendered truth (scene units are metres) after each iteration (Fig. 4, Table 1),
-    the time per depth map at --ablation-iters iterations, and the device time per half-pass."""
+def bench_variants(args, variants, metric: str):
+    """Method variants on 1920x1280 scenes with 10 sources (scene seeds --eval-seed0..): per variant the
+    fraction of visible pixels whose depth is within 2 cm and 10 cm of the rendered truth (scene units are
+    metres) after each iteration, the time per depth map at --ablation-iters iterations, and the device time
+    per half-pass."""
     import torch
 
     import paper_1805_07920_amd as amh
@@ -301,7 +307,7 @@ def bench_ablation(args):
     seeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_scenes))
     ctx = amh.Context(refine=1, seed=args.seed)
     res = {name: dict(cm2=np.zeros((len(seeds), iters)), cm10=np.zeros((len(seeds), iters)), ms=[], pass_ms=[],
-                      evals=[]) for name, _, _ in ABLATION_VARIANTS}
+                      evals=[]) for name, _ in variants}
     H = W = 0
     tuned = None
     for si, seed in enumerate(seeds):
@@ -318,11 +324,10 @@ def bench_ablation(args):
         vis = torch.from_numpy(sc.vis_count >= 2).to(dev)
         gt = torch.from_numpy(sc.depth_gt).to(dev)
         depth = torch.empty((H, W), dtype=torch.float32, device=dev)
-        for name, sym, heur in ABLATION_VARIANTS:
+        for name, kw in variants:
             r = res[name]
             # accuracy after every iteration
-            ctx.set_params(amh.params_default(refine=1, seed=args.seed, sym_prop=sym, heuristic_views=heur,
-                                              timing=1))
+            ctx.set_params(amh.params_default(refine=1, seed=args.seed, timing=1, **kw))
             ctx.begin(0, srcs)
             ctx.init_hypotheses()
             for t in range(iters):
@@ -336,7 +341,7 @@ def bench_ablation(args):
             r["pass_ms"].append(float(np.mean(st["ms_per_pass"])))
             r["evals"].append(st["evals_total"])
             # time per depth map (no per-pass events)
-            ctx.set_params(amh.params_default(refine=1, seed=args.seed, sym_prop=sym, heuristic_views=heur))
+            ctx.set_params(amh.params_default(refine=1, seed=args.seed, **kw))
             for _ in range(max(1, args.warmup)):
                 ctx.run_checkerboard(0, srcs, iters)
             torch.cuda.synchronize()
@@ -349,22 +354,22 @@ def bench_ablation(args):
                 f" {r['ms'][-1]:.1f} ms/depth map, {r['pass_ms'][-1]:.3f} ms/half-pass")
     ctx.close()
     summary = {}
-    for name, sym, heur in ABLATION_VARIANTS:
+    for name, kw in variants:
         r = res[name]
         ms = float(np.mean(r["ms"]))
         summary[name] = {
-            "sym_prop": sym, "heuristic_views": heur,
+            "params": kw,
             "cm2_per_iteration": r["cm2"].mean(0).round(5).tolist(),
             "cm10_per_iteration": r["cm10"].mean(0).round(5).tolist(),
             "ms_per_depth_map": ms, "ms_per_half_pass": float(np.mean(r["pass_ms"])),
             "evals_per_s": float(np.mean(r["evals"])) / (ms / 1000.0),
             "per_scene_cm2_final": r["cm2"][:, -1].round(5).tolist(),
         }
-    full = summary["full"]
+    first = summary[variants[0][0]]
     out = {
-        "metric": "ablation (Sec. 4): pixels within 2 cm / 10 cm of the truth per iteration, time per depth map",
-        "value": full["cm2_per_iteration"][-1], "unit": "fraction of visible pixels within 2 cm (method)",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": full["ms_per_depth_map"],
+        "metric": metric,
+        "value": first["cm2_per_iteration"][-1], "unit": f"fraction of visible pixels within 2 cm ({variants[0][0]})",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": first["ms_per_depth_map"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{W}x{H}, 10 sources nearest first, {iters} iterations with refinement, "
                                f"scene seeds {seeds[0]}-{seeds[-1]}", "parallelism": "single GPU"},
@@ -373,6 +378,19 @@ def bench_ablation(args):
     }
     print(json.dumps(out))
 
+
+def bench_ablation(args):
+    """Ablation of Sec. 4: the method, symmetric checkerboard propagation instead of ACP (no_acp), heuristic
+    best-k view selection instead of the joint one (no_mhj), and both (Fig. 4, Table 1)."""
+    return bench_variants(args, ABLATION_VARIANTS,
+                          "ablation (Sec. 4): pixels within 2 cm / 10 cm of the truth per iteration, time per depth map")
+
+
+def bench_readings(args):
+    """The readings R5/R7/R14 against the paper's literal text: no self row, squared weights, both."""
+    return bench_variants(args, READING_VARIANTS,
+                          "readings vs literal text: pixels within 2 cm / 10 cm of the truth per iteration, "
+                          "time per depth map")
 
 def bench_fusion(args):
     """The stage after the depth maps on one scene: 11 views of 1920x1280 (the measured scene, seed
@@ -509,7 +527,10 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="accuracy per iteration and time of the method and its ablations (symmetric propagation, "
                          "heuristic view selection)")
-    ap.add_argument("--ablation-iters", type=int, default=6, help="iterations per depth map (--ablation)")
+    ap.add_argument("--readings", action="store_true",
+                    help="accuracy per iteration of the readings against the literal text (self row, squared weights)")
+    ap.add_argument("--ablation-iters", type=int, default=6,
+                    help="iterations per depth map (--ablation, --readings)")
     ap.add_argument("--fusion", action="store_true",
                     help="the stage after the depth maps: median filter + consistency-check fusion of 11 views")
     ap.add_argument("--launch-config", type=int, default=None, choices=range(8),
@@ -539,6 +560,8 @@ def main():
         return bench_ablation(args)
     if args.fusion:
         return bench_fusion(args)
+    if args.readings:
+        return bench_readings(args)
 
     import torch
 

@@ -99,6 +99,9 @@ typedef struct {
                           * the mean of its own k lowest per-view costs; S = 0 and v = -1 are kept.
                           * Either ablation runs on the single-image path only (amh_pass and the calls
                           * built on it); the batched calls return UNSUPPORTED. */
+    int bilateral_squared; /* 1: the bilateral weight of Eq. 8 with squared colour difference and squared
+                            * distance, exp(-dI^2 / (2 sigma_color^2) - |dx|^2 / (2 sigma_spatial^2));
+                            * default 0: unsquared, as the equation is printed */
 } amh_params;
 
 /* Counters of the work performed since the last amh_begin / amh_run_checkerboard. */

@@ -245,7 +245,7 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             double dcol = fabs(a[n] - ac);
             double dsp = sqrt((double)(dx * dx + dy * dy));
             if (p->bilateral_sq) { dcol *= dcol; dsp *= dsp; } /* the squared form (R5 alternative) */
-            w[n] = exp(-dcol / (2.0 * p->sigma_color * p->sigma_color) - dsp / (2.0 * p->sigma_spatial * p->sigma_spatial));
+            w[n] = dcol / (2.0 * p->sigma_color * p->sigma_color) + dsp / (2.0 * p->sigma_spatial * p->sigma_spatial);
             /* every sample's ray must meet the plane in front of the reference camera and the
                point must lie in front of the source camera (R3) */
             double rs[3];
@@ -258,6 +258,11 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             ++n;
         }
     }
+    /* weights exp(-exponent), scaled by exp(min exponent): a common factor, which cancels in the NCC,
+       keeps the largest weight at 1 so that the sum cannot underflow */
+    double emin = w[0];
+    for (int i = 1; i < 36; ++i) emin = fmin(emin, w[i]);
+    for (int i = 0; i < 36; ++i) w[i] = exp(emin - w[i]);
     /* weighted means, then weighted covariances (plain two-pass definition) */
     double sw = 0, sa = 0, sb = 0;
     for (int i = 0; i < 36; ++i) { sw += w[i]; sa += w[i] * a[i]; sb += w[i] * b[i]; }

@@ -65,8 +65,9 @@ amh_status check_params(amh_ctx *c, const amh_params *p) {
     if ((p->refine != 0 && p->refine != 1) || (p->include_self != 0 && p->include_self != 1) ||
         (p->timing != 0 && p->timing != 1))
         return fail(c, AMH_E_INVALID_ARG, "refine, include_self and timing are 0 or 1");
-    if ((p->sym_prop != 0 && p->sym_prop != 1) || (p->heuristic_views != 0 && p->heuristic_views != 1))
-        return fail(c, AMH_E_INVALID_ARG, "sym_prop and heuristic_views are 0 or 1");
+    if ((p->sym_prop != 0 && p->sym_prop != 1) || (p->heuristic_views != 0 && p->heuristic_views != 1) ||
+        (p->bilateral_squared != 0 && p->bilateral_squared != 1))
+        return fail(c, AMH_E_INVALID_ARG, "sym_prop, heuristic_views and bilateral_squared are 0 or 1");
     if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(c, AMH_E_INVALID_ARG, "conf_min must be in [0, 1]");
     return AMH_OK;
 }
@@ -98,6 +99,7 @@ MethodDev method_dev(const amh_params &p, int t) {
     m.seed = p.seed;
     m.sym_prop = p.sym_prop;
     m.heuristic = p.heuristic_views;
+    m.bil_sq = p.bilateral_squared;
     return m;
 }
 
@@ -339,6 +341,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         BatchJobDev &b = hj[j];
         b.ref = c->jobs[j].ref;
         b.views = c->d_bviews + so;
+        b.view_off = so;
         b.n_src = jobs[j].n_src;
         b.st = StateDev{c->jobs[j].planes, c->jobs[j].cost, c->jobs[j].S, c->jobs[j].v};
         b.tiles_x = ((r.W + 1) / 2 + kTilePix - 1) / kTilePix;
@@ -354,17 +357,20 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hj[a].n_tiles > hj[b].n_tiles; });
     // phases and their tables
     struct Phase {
-        int kind, colour, t, n_active, total, off, grid;
+        int kind, colour, t, n_active, total, off, grid, max_src;
     };
     std::vector<Phase> phases;
     std::vector<int> tab;
-    auto add_phase = [&](int kind, int colour, int t) {
-        Phase ph{kind, colour, t, 0, 0, (int)tab.size(), 0};
-        std::vector<int> act;
-        for (int j : order)
-            if (kind == 0 || jobs[j].iters > t) act.push_back(j);
+    // A phase is launched once per LDS class: workgroups whose sources need less LDS fit more of them on
+    // a CU (160 KB), so the jobs of a phase are grouped by how many workgroups per CU their view count
+    // allows (capped at 4 waves per SIMD); one launch per group, largest occupancy first.
+    const int wg_cap = 16 / c->cfg_waves;
+    auto wg_per_cu = [&](int n) { return std::min(wg_cap, (int)((size_t)160 * 1024 / pass_lds_bytes(n, c->cfg_waves))); };
+    auto add_group = [&](int kind, int colour, int t, const std::vector<int> &act) {
+        Phase ph{kind, colour, t, 0, 0, (int)tab.size(), 0, 0};
         ph.n_active = (int)act.size();
         if (ph.n_active == 0) return;
+        for (int j : act) ph.max_src = std::max(ph.max_src, jobs[j].n_src);
         int acc = 0;
         for (int j : act) {
             tab.push_back(acc);
@@ -377,40 +383,33 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
             const bool last = colour == 1 && ((kind == 0 && jobs[j].iters == 0) || (kind == 1 && t == jobs[j].iters - 1));
             tab.push_back(last ? 1 : 0);
         }
-        // per-XCD ranges of the concatenated tiles, cut at equal shares of work (a tile's work is
-        // proportional to its job's view count); the launch gives every XCD as many workgroups as
-        // the longest range
-        double work = 0;
-        for (int j : act) work += (double)hj[j].n_tiles * hj[j].n_src;
-        const size_t xs = tab.size();
-        int x = 1, g0 = 0;
-        double cum = 0;
-        tab.push_back(0);
-        for (int j : act) {
-            const double wt = hj[j].n_src;
-            for (int k = 0; k < hj[j].n_tiles && x < 8;) {
-                // tiles of this job up to the next cut
-                const double need = work * x / 8.0 - cum;
-                const int take = std::min(hj[j].n_tiles - k, (int)std::ceil(need / wt));
-                k += take;
-                g0 += take;
-                cum += take * wt;
-                if (cum >= work * x / 8.0 - 1e-9) {
-                    tab.push_back(g0);
-                    ++x;
-                }
-            }
-            if (x >= 8) break;
-        }
-        while (x < 8) {  // rounding left cuts over
-            tab.push_back(g0);
-            ++x;
-        }
-        tab.push_back(acc);
+        // tile order 0: each job's tiles in 8 contiguous bands [n b / 8, n (b + 1) / 8); XCD x takes band
+        // (x + slot) mod 8 of the job at active slot `slot`; per XCD the prefix sums of its band sizes
         int longest = 1;
-        for (int i = 0; i < 8; ++i) longest = std::max(longest, tab[xs + i + 1] - tab[xs + i]);
+        for (int x = 0; x < 8; ++x) {
+            int acc_x = 0;
+            tab.push_back(0);
+            for (int k = 0; k < (int)act.size(); ++k) {
+                const long long n = hj[act[k]].n_tiles;
+                const int bi = (x + k) & 7;
+                acc_x += (int)((n * (bi + 1)) >> 3) - (int)((n * bi) >> 3);
+                tab.push_back(acc_x);
+            }
+            longest = std::max(longest, acc_x);
+        }
         ph.grid = c->cfg_order == 0 ? 8 * longest : acc;
         phases.push_back(ph);
+    };
+    auto add_phase = [&](int kind, int colour, int t) {
+        std::vector<int> act;
+        for (int j : order)
+            if (kind == 0 || jobs[j].iters > t) act.push_back(j);
+        for (int w = wg_cap; w >= 1; --w) {
+            std::vector<int> grp;
+            for (int j : act)
+                if (std::max(1, wg_per_cu(jobs[j].n_src)) == w) grp.push_back(j);
+            add_group(kind, colour, t, grp);
+        }
     };
     add_phase(0, 0, 0);
     add_phase(0, 1, 0);
@@ -448,10 +447,11 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         if (e != hipSuccess) break;
         BatchPhaseArgs b;
         b.jobs = c->d_jobs;
+        b.views = c->d_bviews;
         b.tile_start = c->d_tables + ph.off;
         b.job_of = c->d_tables + ph.off + ph.n_active + 1;
         b.is_last = c->d_tables + ph.off + 2 * ph.n_active + 1;
-        b.xcd_start = c->d_tables + ph.off + 3 * ph.n_active + 1;
+        b.xcd_pre = c->d_tables + ph.off + 3 * ph.n_active + 1;
         b.n_active = ph.n_active;
         b.total_tiles = ph.total;
         b.grid = ph.grid;
@@ -465,7 +465,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         b.counters = c->d_bcount;
         b.tiles_done = tiles_done;
         b.job_end = clocks;
-        e = launch_batch(b, c->half, max_src, c->cap_stream);
+        e = launch_batch(b, c->half, ph.max_src, c->cap_stream);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
@@ -517,6 +517,7 @@ amh_status amh_params_default(amh_params *out) {
     out->conf_min = 0.0f;  // measured best after one iteration (see amhmvs.h)
     out->sym_prop = 0;
     out->heuristic_views = 0;
+    out->bilateral_squared = 0;
     return AMH_OK;
 }
 

@@ -40,6 +40,7 @@ struct MethodDev {
     int include_self, refine;
     uint64_t seed;
     int sym_prop, heuristic;     // ablation switches (symmetric propagation, heuristic views)
+    int bil_sq;                  // squared colour difference and distance in the bilateral weight
 };
 
 struct StateDev {
@@ -70,6 +71,7 @@ struct PassArgs {
 struct BatchJobDev {
     RefDev ref;
     const ViewDev *views;        // n_src warp constants
+    int view_off;                // ... at BatchPhaseArgs::views + view_off
     int n_src;
     StateDev st;
     int tiles_x, n_tiles;        // tile grid of one colour
@@ -80,10 +82,11 @@ struct BatchJobDev {
 // one phase (init of a colour, or a half-pass) over the active jobs of a batch
 struct BatchPhaseArgs {
     const BatchJobDev *jobs;
+    const ViewDev *views;        // the warp constants of every job's sources
     const int *tile_start;       // [n_active + 1] prefix sums of the active jobs' tile counts
     const int *job_of;           // [n_active] job index of each active entry
     const int *is_last;          // [n_active] 1 if this phase is the job's last one
-    const int *xcd_start;        // [9] per-XCD tile ranges of equal work (tile order 0)
+    const int *xcd_pre;          // [8][n_active + 1] per-XCD prefix sums of the band sizes (tile order 0)
     int n_active, total_tiles;
     int grid;                    // workgroups of the launch
     MethodDev m;

@@ -19,12 +19,17 @@
 #include "amh_bf16.h"
 #include "amh_internal.h"
 
-// Minimum waves per SIMD the pass kernels are compiled for (a register budget
-// of 512 / waves VGPRs).  At 2 the compiler settles at ~165 VGPRs (3 waves per
-// SIMD) with the row pipeline of ncc_cost; forcing 4 waves spills and measured
-// slower on the 1920x1280 / 10-source workload (5.43 vs 5.02 ms per half-pass).
+// Minimum waves per SIMD the kernels are compiled for (a register budget of
+// 512 / waves VGPRs).  The single-image half-pass fits 128 VGPRs (4 waves per
+// SIMD) with a 20-byte spill and runs 8 % faster there than at its natural 132
+// (3 waves): 4.60 vs 5.02 ms per half-pass on the 1920x1280 / 10-source
+// workload.  The batched kernel and the ablation build spill 56-120 bytes at
+// that budget and stay at 2 (~150 VGPRs, 3 waves).
 #ifndef AMH_PASS_WAVES_PER_EU
-#define AMH_PASS_WAVES_PER_EU 2
+#define AMH_PASS_WAVES_PER_EU 4
+#endif
+#ifndef AMH_BATCH_WAVES_PER_EU
+#define AMH_BATCH_WAVES_PER_EU 2
 #endif
 
 namespace amh {
@@ -97,7 +102,29 @@ __device__ __forceinline__ void region_offset(int r, int e, int &dx, int &dy) {
 // a scalar base address).
 // ---------------------------------------------------------------------------
 typedef const __attribute__((address_space(1))) unsigned char gbyte;
+
+// The library's buffers are global memory; a pointer read from a table (batched launches) reaches the
+// kernels as a generic one, so state and reference accesses name the global address space explicitly
+// (global instead of flat instructions).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *glob(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
 typedef float gf4 __attribute__((ext_vector_type(4)));
+
+// planes (float4) through the global address space, as the clang vector type
+__device__ __forceinline__ float4 load_plane(const float4 *base, size_t i) {
+    const gf4 v = ((const __attribute__((address_space(1))) gf4 *)base)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void store_plane(float4 *base, size_t i, float4 p) {
+    gf4 v;
+    v.x = p.x;
+    v.y = p.y;
+    v.z = p.z;
+    v.w = p.w;
+    ((__attribute__((address_space(1))) gf4 *)base)[i] = v;
+}
 typedef _Float16 gh4 __attribute__((ext_vector_type(4)));
 
 template <int HALF>
@@ -150,8 +177,9 @@ __device__ __forceinline__ int med3i(int x, int lo, int hi) {
 // issues their texel loads.  The homogeneous source position of window offset
 // (u, v) is (N0 + u Pu + v Pv) relative to the texel (ix, iy); texel indices
 // are clamped to the image (-1..W-1 in absolute terms, the quad layout holds
-// the clamped footprint).
-template <int HALF>
+// the clamped footprint).  CLAMP = false: the caller has shown that every
+// index is already inside that range, so the clamp would change nothing.
+template <int HALF, bool CLAMP>
 __device__ __forceinline__ void issue_row(const void *quads, float vf, float N0x, float N0y, float Z0, float pux,
                                           float puy, float puz, float pvx, float pvy, float pvz, int xlo, int xhi,
                                           int ylo, int yhi, int row_bytes, int base,
@@ -164,8 +192,8 @@ __device__ __forceinline__ void issue_row(const void *quads, float vf, float N0x
         const float nx = fmaf(uf, pux, rx), ny = fmaf(uf, puy, ry), nz = fmaf(uf, puz, rzz);
         const float r = __builtin_amdgcn_rcpf(nz);
         const float dx = nx * r, dy = ny * r;
-        const int xr = med3i(cvt_floor(dx), xlo, xhi);
-        const int yr = med3i(cvt_floor(dy), ylo, yhi);
+        const int xr = CLAMP ? med3i(cvt_floor(dx), xlo, xhi) : cvt_floor(dx);
+        const int yr = CLAMP ? med3i(cvt_floor(dy), ylo, yhi) : cvt_floor(dy);
         fxs[su] = __builtin_amdgcn_fractf(dx);
         fys[su] = __builtin_amdgcn_fractf(dy);
         // modulo-2^32 arithmetic; the true offset is in [0, (W+1)(H+1) * entry) < 2^32
@@ -198,12 +226,23 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
     const float ac = rd(0, 0);
     float sw = 0.f, swa = 0.f;
     float w[36];
+    // exponents of the weights: unsquared colour difference and distance as printed (Eq. 8), or the
+    // squared form; the weights are scaled by exp(min exponent), a common factor that cancels in the
+    // NCC, so the largest is 1 and the sum never underflows
+    float emin = __builtin_inff();
 #pragma unroll
     for (int s = 0; s < 36; ++s) {
         const int du = -5 + 2 * (s % 6), dv = -5 + 2 * (s / 6);
         a[s] = rd(du, dv);
-        const float dist = __builtin_sqrtf((float)(du * du + dv * dv));
-        w[s] = __expf(-fabsf(a[s] - ac) * m.inv_2sc2 - dist * m.inv_2sx2);
+        const float d2 = (float)(du * du + dv * dv), dc = fabsf(a[s] - ac);
+        const float dist = m.bil_sq ? d2 : __builtin_sqrtf(d2);
+        const float col = m.bil_sq ? dc * dc : dc;
+        w[s] = fmaf(col, m.inv_2sc2, dist * m.inv_2sx2);
+        emin = fminf(emin, w[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 36; ++s) {
+        w[s] = __expf(emin - w[s]);
         sw += w[s];
         swa = fmaf(w[s], a[s], swa);
     }
@@ -227,7 +266,9 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
         }
         const float wprev = wcum;
         wcum += wr;
-        if ((r % write_stride) == write_phase) rowc[r] = make_float4(1.f / wr, wr / wcum, wprev * wr / wcum, ar);
+        // a row whose weights all underflow adds nothing (its constants are 0)
+        if ((r % write_stride) == write_phase)
+            rowc[r] = wr > 0.f ? make_float4(1.f / wr, wr / wcum, wprev * wr / wcum, ar) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     WinStats ws;
     ws.invW = invW;
@@ -244,6 +285,59 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
 //   q0, qu, qv: inverse depth of the plane along the pixel ray and its
 //   change per reference pixel in x and y.
 // ---------------------------------------------------------------------------
+// Source moments of the 36 samples, row by row (see ncc_cost); CLAMP as in issue_row.
+template <int HALF, bool CLAMP>
+__device__ __forceinline__ void window_moments(const void *__restrict__ quads, const float2 *__restrict__ rw,
+                                               float N0x, float N0y, float Z0, float pux, float puy, float puz,
+                                               float pvx, float pvy, float pvz, int xlo, int xhi, int ylo, int yhi,
+                                               int row_bytes, int base, float &m2, float &cab) {
+    // Source moments row by row: the 6 samples of a window row are held, their weighted mean,
+    // centred square sum and cross sum with the reference formed exactly (two passes over the
+    // row), and the rows merged with the parallel-variance update (Chan, Golub, LeVeque):
+    //   mean' = mean + (mu_r - mean) W_r / W_<=r,
+    //   M2'   = M2 + M2_r + (mu_r - mean)^2 W_<r W_r / W_<=r,
+    //   C'    = C + C_r + (mu_r - mean') A_r + (mean - mean') A_<r.
+    // No cancellation at any size of the offsets, and only 6 samples live at a time.
+    const float4 *__restrict__ rowc = reinterpret_cast<const float4 *>(rw + 36);
+    float mu = 0.f, acum = 0.f;
+    m2 = 0.f;
+    cab = 0.f;
+    // software pipeline: the gathers of row sv + 1 are issued before row sv's moments
+    typename QuadT<HALF>::type qd[6];
+    float fxs[6], fys[6];
+    issue_row<HALF, CLAMP>(quads, -5.f, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi, row_bytes,
+                           base, qd, fxs, fys);
+#pragma unroll
+    for (int sv = 0; sv < 6; ++sv) {
+        float v6[6];
+        float srow = 0.f;
+#pragma unroll
+        for (int su = 0; su < 6; ++su) {
+            v6[su] = eval_quad<HALF>(qd[su], fxs[su], fys[su]);
+            srow = fmaf(rw[sv * 6 + su].x, v6[su], srow);
+        }
+        if (sv < 5)
+            issue_row<HALF, CLAMP>(quads, -3.f + 2.f * sv, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo,
+                                   yhi, row_bytes, base, qd, fxs, fys);
+        const float4 rc = rowc[sv];
+        const float mur = srow * rc.x;
+        float m2r = 0.f, cr = 0.f;
+#pragma unroll
+        for (int su = 0; su < 6; ++su) {
+            const float2 wa = rw[sv * 6 + su];
+            const float d = v6[su] - mur;
+            m2r = fmaf(wa.x * d, d, m2r);
+            cr = fmaf(wa.y, d, cr);
+        }
+        const float delta = mur - mu;
+        const float mun = fmaf(delta, rc.y, mu);
+        m2 += fmaf(rc.z * delta, delta, m2r);
+        cab += fmaf(mur - mun, rc.w, fmaf(mu - mun, acum, cr));
+        acum += rc.w;
+        mu = mun;
+    }
+}
+
 template <int HALF>
 __device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__restrict__ rw_in, const WinStats &ws,
                                           int x, int y, double q0, float qu, float qv) {
@@ -279,49 +373,24 @@ __device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__res
     const int row_bytes = (W + 1) * kEntry;
     const int xlo = -1 - ix, xhi = W - 1 - ix, ylo = -1 - iy, yhi = H - 1 - iy;
     const int base = ((iy + 1) * (W + 1) + (ix + 1)) * kEntry;
-    // Source moments row by row: the 6 samples of a window row are held, their weighted mean,
-    // centred square sum and cross sum with the reference formed exactly (two passes over the
-    // row), and the rows merged with the parallel-variance update (Chan, Golub, LeVeque):
-    //   mean' = mean + (mu_r - mean) W_r / W_<=r,
-    //   M2'   = M2 + M2_r + (mu_r - mean)^2 W_<r W_r / W_<=r,
-    //   C'    = C + C_r + (mu_r - mean') A_r + (mean - mean') A_<r.
-    // No cancellation at any size of the offsets, and only 6 samples live at a time.
-    const float4 *__restrict__ rowc = reinterpret_cast<const float4 *>(rw + 36);
-    float mu = 0.f, m2 = 0.f, cab = 0.f, acum = 0.f;
-    // software pipeline: the gathers of row sv + 1 are issued before row sv's moments
-    typename QuadT<HALF>::type qd[6];
-    float fxs[6], fys[6];
-    issue_row<HALF>(quads, -5.f, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi, row_bytes, base,
-                    qd, fxs, fys);
-#pragma unroll
-    for (int sv = 0; sv < 6; ++sv) {
-        float v6[6];
-        float srow = 0.f;
-#pragma unroll
-        for (int su = 0; su < 6; ++su) {
-            v6[su] = eval_quad<HALF>(qd[su], fxs[su], fys[su]);
-            srow = fmaf(rw[sv * 6 + su].x, v6[su], srow);
-        }
-        if (sv < 5)
-            issue_row<HALF>(quads, -3.f + 2.f * sv, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
-                            row_bytes, base, qd, fxs, fys);
-        const float4 rc = rowc[sv];
-        const float mur = srow * rc.x;
-        float m2r = 0.f, cr = 0.f;
-#pragma unroll
-        for (int su = 0; su < 6; ++su) {
-            const float2 wa = rw[sv * 6 + su];
-            const float d = v6[su] - mur;
-            m2r = fmaf(wa.x * d, d, m2r);
-            cr = fmaf(wa.y, d, cr);
-        }
-        const float delta = mur - mu;
-        const float mun = fmaf(delta, rc.y, mu);
-        m2 += fmaf(rc.z * delta, delta, m2r);
-        cab += fmaf(mur - mun, rc.w, fmaf(mu - mun, acum, cr));
-        acum += rc.w;
-        mu = mun;
-    }
+    // Clamp-free fast path: the samples lie in the convex image of the window square (the depth is
+    // positive at its corners, so the warp has no pole inside), hence |dx| <= (|N0x| + 5 |pux| + 5 |pvx|)
+    // / min corner depth, likewise dy.  When that bound (widened by 1 % + 0.01 px, far above the float
+    // rounding of the samples once the min depth exceeds 1e-3 of the centre's) keeps every texel index
+    // inside the clamp range, the clamps are no-ops and are skipped: the same offsets, the same result.
+    const float zmin = fminf(fminf(zc0, zc1), fminf(zc2, zc3));
+    const float rzm = __builtin_amdgcn_rcpf(zmin);
+    const float bx = fmaf(fmaf(5.f, fabsf(pux) + fabsf(pvx), fabsf(N0x)) * rzm, 1.01f, 0.01f);
+    const float by = fmaf(fmaf(5.f, fabsf(puy) + fabsf(pvy), fabsf(N0y)) * rzm, 1.01f, 0.01f);
+    const bool interior = zmin > 1e-3f * Z0 && bx <= (float)(ix + 1) && bx < (float)(W - ix) &&
+                          by <= (float)(iy + 1) && by < (float)(H - iy);
+    float m2, cab;
+    if (interior)
+        window_moments<HALF, false>(quads, rw, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
+                                    row_bytes, base, m2, cab);
+    else
+        window_moments<HALF, true>(quads, rw, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
+                                   row_bytes, base, m2, cab);
     const float var_b = m2 * ws.invW;
     const float cov = cab * ws.invW;
     if (ws.var_a < 1e-5f || var_b < 1e-5f) return 2.f;
@@ -463,7 +532,7 @@ __device__ __forceinline__ void stage_tile(const RefDev &ref, float *tile, int y
         const int ty = i / kTileW, tx = i - ty * kTileW;
         const int gy = min(max(y0 - 5 + ty, 0), ref.H - 1);
         const int gx = min(max(x0 - 5 + tx, 0), ref.W - 1);
-        tile[i] = ref.img[(size_t)gy * ref.W + gx];
+        tile[i] = glob(ref.img)[(size_t)gy * ref.W + gx];
     }
 }
 
@@ -600,10 +669,10 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
             sum += bc;
         }
         const size_t p = (size_t)y * a.ref.W + x;
-        a.st.planes[p] = pl;
-        a.st.cost[p] = sum / (float)kk;
-        a.st.S[p] = 0u;
-        a.st.v[p] = -1;
+        store_plane(a.st.planes, p, pl);
+        glob(a.st.cost)[p] = sum / (float)kk;
+        glob(a.st.S)[p] = 0u;
+        glob(a.st.v)[p] = -1;
     }
     count_evals(a.counters, 0, (unsigned long long)n_eval);
 }
@@ -674,10 +743,10 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
             sum += bc;
         }
         const size_t p = (size_t)y * a.ref.W + x;
-        a.st.planes[p] = pl;
-        a.st.cost[p] = sum / (float)kk;
-        a.st.S[p] = 0u;
-        a.st.v[p] = -1;
+        store_plane(a.st.planes, p, pl);
+        glob(a.st.cost)[p] = sum / (float)kk;
+        glob(a.st.S)[p] = 0u;
+        glob(a.st.v)[p] = -1;
     }
 }
 
@@ -735,7 +804,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             const int ny = y + (dir == 0 ? -u : (dir == 1 ? u : 0));
             if (nx >= 0 && nx < W && ny >= 0 && ny < H) {
                 valid = true;
-                pl = a.st.planes[(size_t)ny * W + nx];
+                pl = load_plane(a.st.planes, (size_t)ny * W + nx);
             }
         } else if (row < 8) {
             int bx = -1, by = -1;
@@ -746,16 +815,16 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                 region_offset(row, e, dx, dy);
                 const int nx = x + dx, ny = y + dy;
                 if (nx < 0 || nx >= W || ny < 0 || ny >= H) continue;
-                const float c = a.st.cost[(size_t)ny * W + nx];
+                const float c = glob(a.st.cost)[(size_t)ny * W + nx];
                 if (bx < 0 || c < bc) { bx = nx; by = ny; bc = c; }
             }
             if (bx >= 0) {
                 valid = true;
-                pl = a.st.planes[(size_t)by * W + bx];
+                pl = load_plane(a.st.planes, (size_t)by * W + bx);
             }
         } else {
             valid = m.include_self != 0;
-            pl = a.st.planes[p];
+            pl = load_plane(a.st.planes, p);
         }
     }
     S.pl[tid] = pl;
@@ -820,8 +889,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     bool uniform = heur;
     if (heur) wsum = (float)N;
     if (pix_ok && !heur) {
-        vprev = a.st.v[p];
-        Sprev = a.st.S[p];
+        vprev = glob(a.st.v)[p];
+        Sprev = glob(a.st.S)[p];
         float best = 0.f;
         for (int j = 0; j < N; ++j) {
             const float ps = psi[j];
@@ -970,10 +1039,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
 
     // (9) write the pixel
     if (pix_ok && row == 0) {
-        a.st.planes[p] = best;
-        a.st.cost[p] = bcost;
-        a.st.S[p] = Sm;
-        a.st.v[p] = vt;
+        store_plane(a.st.planes, p, best);
+        glob(a.st.cost)[p] = bcost;
+        glob(a.st.S)[p] = Sm;
+        glob(a.st.v)[p] = vt;
     }
     count_evals(a.counters, 1, (unsigned long long)n_prop);
     if (m.refine) count_evals(a.counters, 2, (unsigned long long)n_ref);
@@ -983,7 +1052,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
 // Single-image half-pass: one workgroup per tile of the colour.
 // ---------------------------------------------------------------------------
 template <int HALF, int WAVES, bool ABL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ABL ? AMH_BATCH_WAVES_PER_EU : AMH_PASS_WAVES_PER_EU)))
 void pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = tile_of_block(a.n_tiles, a.order);
@@ -999,33 +1068,59 @@ void pass_kernel(PassArgs a) {
 // workgroup that finishes the last tile of a job's last phase stamps the
 // device clock (per-job completion time within the batch).
 // ---------------------------------------------------------------------------
-template <int HALF, int WAVES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+// A workgroup-uniform value read from memory, made visibly uniform (scalar registers), one dword at a time.
+template <typename T>
+__device__ __forceinline__ T make_uniform(const T &v) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized");
+    T r;
+    const int *src = reinterpret_cast<const int *>(&v);
+    int *dst = reinterpret_cast<int *>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return r;
+}
+
+// KIND: 0 initialisation, 1 half-pass (separate kernels, so that each gets its own register budget)
+template <int HALF, int WAVES, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND ? AMH_PASS_WAVES_PER_EU : AMH_BATCH_WAVES_PER_EU)))
 void batch_kernel(BatchPhaseArgs b) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // order 0: XCD x walks the tile range [xcd_start[x], xcd_start[x+1]) of the concatenated list,
-    // the ranges cut at equal shares of work (tiles weighted by their job's view count);
-    // order 1: hardware order
-    int g;
+    // order 0: every job's tiles are cut into 8 contiguous bands; XCD x (workgroups round-robin over
+    // the XCDs) walks one band of each job in job order -- band (x + slot) mod 8 of the job at active
+    // slot `slot`, so that the larger bands of uneven cuts rotate over the XCDs -- and all XCDs move
+    // through the jobs together (one job's sources in the shared cache, neighbouring tiles in each
+    // XCD's L2).  xcd_pre[x][slot] is the prefix sum of XCD x's band sizes.
+    // order 1: hardware order over the concatenated tiles.
+    int lo, L;
     if (b.order == 0) {
-        const int x = blockIdx.x & 7;
-        g = b.xcd_start[x] + (int)(blockIdx.x >> 3);
-        if (g >= b.xcd_start[x + 1]) return;
+        const int x = blockIdx.x & 7, g = (int)(blockIdx.x >> 3);
+        const int *pre = b.xcd_pre + x * (b.n_active + 1);
+        if (g >= pre[b.n_active]) return;
+        int a0 = 0, a1 = b.n_active;  // pre[a0] <= g < pre[a1]
+        while (a1 - a0 > 1) {
+            const int mid = (a0 + a1) >> 1;
+            if (pre[mid] <= g) a0 = mid;
+            else a1 = mid;
+        }
+        lo = a0;
+        const int n = b.tile_start[lo + 1] - b.tile_start[lo];
+        L = (int)(((long long)n * ((x + lo) & 7)) >> 3) + (g - pre[lo]);
     } else {
-        g = blockIdx.x;
+        const int g = blockIdx.x;
         if (g >= b.total_tiles) return;
-    }
-    int lo = 0, hi = b.n_active;  // tile_start[lo] <= g < tile_start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (b.tile_start[mid] <= g) lo = mid;
-        else hi = mid;
+        int a0 = 0, a1 = b.n_active;  // tile_start[a0] <= g < tile_start[a1]
+        while (a1 - a0 > 1) {
+            const int mid = (a0 + a1) >> 1;
+            if (b.tile_start[mid] <= g) a0 = mid;
+            else a1 = mid;
+        }
+        lo = a0;
+        L = g - b.tile_start[lo];
     }
     const int j = b.job_of[lo];
     const BatchJobDev &J = b.jobs[j];
     PassArgs a;
     a.ref = J.ref;
-    a.views = J.views;
     a.n_src = J.n_src;
     a.m = b.m;
     a.st = J.st;
@@ -1040,8 +1135,14 @@ void batch_kernel(BatchPhaseArgs b) {
     a.prop_w = J.prop_w;
     a.prop_s = kCell;
     a.conf_min = b.conf_min;
-    const int L = g - b.tile_start[lo];
-    if (b.kind == 0) init_body<HALF, WAVES>(a, L, smem);
+    // the job's arguments are the same for the whole workgroup: keep them (and the gathers' base
+    // addresses) in scalar registers, as for the single-image kernels' by-value arguments
+    a = make_uniform(a);
+    L = __builtin_amdgcn_readfirstlane(L);
+    // the source table as an offset from the argument's pointer, so that the per-view constants are
+    // read like the single-image kernels read theirs (scalar loads from a kernel-argument buffer)
+    a.views = b.views + __builtin_amdgcn_readfirstlane(J.view_off);
+    if (KIND == 0) init_body<HALF, WAVES>(a, L, smem);
     else pass_body<HALF, WAVES>(a, L, smem);
     if (b.is_last[lo]) {
         __syncthreads();
@@ -1306,15 +1407,21 @@ hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStrea
     if (b.total_tiles == 0) return hipSuccess;
     const size_t lds = pass_lds_bytes(max_src, b.waves);
     const dim3 grid(b.grid), block(64 * b.waves);
+#define AMH_BATCH_LAUNCH(H, WV)                                                  \
+    do {                                                                         \
+        if (b.kind == 0) AMH_LAUNCH((batch_kernel<H, WV, 0>), grid, block, lds, s, b); \
+        else AMH_LAUNCH((batch_kernel<H, WV, 1>), grid, block, lds, s, b);            \
+    } while (0)
     if (b.waves == 2) {
-        if (half) AMH_LAUNCH((batch_kernel<1, 2>), grid, block, lds, s, b);
-        else AMH_LAUNCH((batch_kernel<0, 2>), grid, block, lds, s, b);
+        if (half) AMH_BATCH_LAUNCH(1, 2);
+        else AMH_BATCH_LAUNCH(0, 2);
     } else if (b.waves == 4) {
-        if (half) AMH_LAUNCH((batch_kernel<1, 4>), grid, block, lds, s, b);
-        else AMH_LAUNCH((batch_kernel<0, 4>), grid, block, lds, s, b);
+        if (half) AMH_BATCH_LAUNCH(1, 4);
+        else AMH_BATCH_LAUNCH(0, 4);
     } else {
         return hipErrorInvalidValue;
     }
+#undef AMH_BATCH_LAUNCH
     return hipGetLastError();
 }
 

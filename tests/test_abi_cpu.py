@@ -133,3 +133,10 @@ def test_fusion_arguments_validated(amh):
     assert L.amh_median_filter4(None, None, None, 4, 4) == amh.AMH_E_INVALID_ARG
     n = C.c_int64(0)
     assert L.amh_fuse(None, 1, None, None, None, C.byref(fp), None, None, None, 0, C.byref(n)) == amh.AMH_E_INVALID_ARG
+
+
+def test_bilateral_switch_validated(amh):
+    assert amh.params_default().bilateral_squared == 0
+    for bad in (-1, 2):
+        q = amh.params_default(bilateral_squared=bad)
+        assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(q), None) == amh.AMH_E_INVALID_ARG

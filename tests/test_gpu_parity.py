@@ -131,13 +131,14 @@ def test_init_matches_oracle(amh, oracle_mod, scene_c1):
     assert st["evals_init"] == sc.width * sc.height * 4
 
 
-def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1, sym_prop=0, heuristic=0):
+def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1, sym_prop=0, heuristic=0,
+                 bil_sq=0, delta=1e-5, ctol=1e-4, min_plane=0.99):
     n = len(sc.srcs) if n_src is None else n_src
     V = O.Views(sc.images[: n + 1], sc.cams[: n + 1])
     P = O.Params(refine=refine, seed=seed, include_self=include_self, prop_mode=sym_prop,
-                 view_mode=2 if heuristic else 0)
+                 view_mode=2 if heuristic else 0, bilateral_sq=bil_sq)
     with make_ctx(amh, sc, refine=refine, seed=seed, include_self=include_self, sym_prop=sym_prop,
-                  heuristic_views=heuristic) as ctx:
+                  heuristic_views=heuristic, bilateral_squared=bil_sq) as ctx:
         ctx.begin(0, list(range(1, n + 1)))
         ctx.init_hypotheses()
         # earlier passes give a realistic state (non-empty S, v)
@@ -152,7 +153,7 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
     st = O.State.from_arrays(pl0, c0, S0, v0)
     Wd, Hd = sc.width, sc.height
     order = np.array([i for i in range(Wd * Hd) if ((i % Wd) + (i // Wd)) % 2 == colour], np.int32)
-    dg = O.run_pass(V, P, st, t, colour, order=order, delta=1e-5, diag=True)
+    dg = O.run_pass(V, P, st, t, colour, order=order, delta=delta, diag=True)
     bits = np.array([d.robust for d in dg])
     # the plane and the cost depend on the view tests, the top-k cut, the argmin and refinement;
     # v_t additionally on its own argmax (ORC_ROBUST_* bits of the oracle)
@@ -166,8 +167,7 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
     exact = np.all(gp == op.astype(np.float32), axis=-1)
     close = np.all(np.abs(gp - op) <= 1e-5 * (1 + np.abs(op)), axis=-1)
     ok_plane = np.where(propagated, exact, close)
-    ok = ok_plane & (gS == oS) & (np.abs(gc - oc) <= 1e-4)
-    assert np.all(gv[v_robust] == ov[v_robust])
+    ok = ok_plane & (gS == oS) & (np.abs(gc - oc) <= ctol)
     frac_robust = robust.mean()
     say(f"  t={t} colour={colour}: robust {frac_robust:.4f}, agree on robust {ok[robust].mean():.5f}, "
         f"plane agreement overall {ok_plane.mean():.5f}, S {np.mean(gS == oS):.4f}, v {np.mean(gv == ov):.4f}, "
@@ -178,13 +178,19 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
         say(f"    pixel {order[q] % Wd},{order[q] // Wd}: chosen {d.chosen} gpu cost {gc[q]:.6f} oracle {oc[q]:.6f} "
             f"S {gS[q]:#x}/{oS[q]:#x} v {gv[q]}/{ov[q]} mfinal {[round(d.mfinal[r], 6) for r in range(9)]} "
             f"cand {[round(d.cand_cost[c], 6) for c in range(d.n_cand)]}")
+    vbad = np.nonzero(v_robust & (gv != ov))[0][:5]
+    for q in vbad:
+        d = dg[q]
+        say(f"    v mismatch at {order[q] % Wd},{order[q] // Wd}: gpu {gv[q]} oracle {ov[q]} S {gS[q]:#x}/{oS[q]:#x} "
+            f"M {[[round(d.M[r][j], 5) for j in range(n)] for r in range(9) if d.row_valid[r]]}")
+    assert np.all(gv[v_robust] == ov[v_robust])
     # the other colour is untouched by the pass
     other = ~np.isin(np.arange(Wd * Hd), order)
     assert np.array_equal(pl1.reshape(-1, 4)[other], pl0.reshape(-1, 4)[other])
     # every robust pixel must agree, and almost every pixel keeps the same plane
     assert frac_robust >= 0.5
     assert ok[robust].mean() >= 0.999
-    assert ok_plane.mean() >= 0.99
+    assert ok_plane.mean() >= min_plane
     return ok, robust
 
 
@@ -237,6 +243,41 @@ def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_c1, sym, heur):
     assert frac >= 0.995
     if heur:
         assert np.all(S == 0) and np.all(v == -1)
+
+
+@pytest.mark.parametrize("t,colour,include_self", [(0, 0, 1), (1, 1, 0)])
+def test_squared_bilateral_pass_matches_oracle(amh, oracle_mod, scene_c1, t, colour, include_self):
+    # squared colour differences concentrate the weight on the few samples closest in intensity to the
+    # centre, and the float32 moments of so few effective samples carry cost errors up to ~1e-4 (measured
+    # 8.9e-5, against ~1e-6 with the printed weights): margin and cost bar 2e-4, and >= 98 % of all pixels
+    # keep the oracle's plane
+    say("case pass squared bilateral", t, colour, include_self)
+    _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=9, refine=1, include_self=include_self, bil_sq=1,
+                 delta=2e-4, ctol=2e-4, min_plane=0.98)
+
+
+@pytest.mark.parametrize("include_self", [1, 0])
+def test_squared_bilateral_full_run_accuracy(amh, oracle_mod, scene_c1, include_self):
+    """Full runs with squared weights: the near-ties of a single pass (1.3 % of the pixels keep a different
+    plane, against 0.1 % with the printed weights) spread over the iterations, so depth maps are compared
+    by their accuracy against the rendered depth: within 1 % and within 5 %, GPU and oracle within 2 points."""
+    say("case full run squared bilateral, include_self", include_self)
+    O = oracle_mod
+    sc = scene_c1
+    with make_ctx(amh, sc, refine=1, seed=4, bilateral_squared=1, include_self=include_self) as ctx:
+        ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
+        depth, _, _ = ctx.get_depth_normal_cost()
+    V = O.Views.from_scene(sc)
+    st = O.run(V, O.Params(refine=1, seed=4, bilateral_sq=1, include_self=include_self), 3)
+    od, _ = O.depth_normal(V, st)
+    vis = sc.vis_count >= 2
+    g = np.abs(depth - sc.depth_gt)[vis] / sc.depth_gt[vis]
+    o = np.abs(od - sc.depth_gt)[vis] / sc.depth_gt[vis]
+    for tol in (0.01, 0.05):
+        say(f"  within {tol:.0%}: gpu {(g < tol).mean():.4f} oracle {(o < tol).mean():.4f}")
+        assert abs((g < tol).mean() - (o < tol).mean()) <= 0.02
+    if include_self:  # without the own plane a pixel can be left with a neighbour's plane out of range here
+        assert np.all((depth >= 2.0 - 1e-5) & (depth <= 6.0 + 1e-5))
 
 
 def test_ablation_rejected_by_the_batched_path(amh, scene_c1):
