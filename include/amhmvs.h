@@ -115,6 +115,8 @@ typedef struct {
     float ms_init;
     float ms_fuse_kernels;      /* timing = 1: device time of the per-view fusion kernels of the last amh_fuse */
     int n_fuse_kernels;         /* ... and their number (one per view) */
+    uint64_t fallback_pixels;   /* initialisation from a proposal: pixels that kept the random plane (confidence
+                                 * below conf_min, no normal, or the predicted plane out of range there) */
 } amh_stats;
 
 /* Batched job (see amh_run_batch). */

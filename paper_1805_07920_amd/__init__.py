@@ -61,7 +61,8 @@ class amh_params(C.Structure):
 class amh_stats(C.Structure):
     _fields_ = [("evals_total", C.c_uint64), ("evals_init", C.c_uint64), ("evals_propagation", C.c_uint64),
                 ("evals_refine", C.c_uint64), ("n_passes", C.c_int), ("ms_per_pass", C.c_float * 64),
-                ("ms_init", C.c_float), ("ms_fuse_kernels", C.c_float), ("n_fuse_kernels", C.c_int)]
+                ("ms_init", C.c_float), ("ms_fuse_kernels", C.c_float), ("n_fuse_kernels", C.c_int),
+                ("fallback_pixels", C.c_uint64)]
 
 
 class amh_fusion_params(C.Structure):
@@ -359,7 +360,8 @@ class Context:
         return dict(evals_total=s.evals_total, evals_init=s.evals_init, evals_propagation=s.evals_propagation,
                     evals_refine=s.evals_refine, n_passes=s.n_passes,
                     ms_per_pass=list(s.ms_per_pass[:s.n_passes]), ms_init=s.ms_init,
-                    ms_fuse_kernels=s.ms_fuse_kernels, n_fuse_kernels=s.n_fuse_kernels)
+                    ms_fuse_kernels=s.ms_fuse_kernels, n_fuse_kernels=s.n_fuse_kernels,
+                    fallback_pixels=s.fallback_pixels)
 
     # --- learned proposal ----------------------------------------------------------------
     @staticmethod

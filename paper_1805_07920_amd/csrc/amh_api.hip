@@ -330,7 +330,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
     amh_status st;
     if ((st = dalloc(c, (void **)&c->d_bviews, sizeof(ViewDev) * total_src)) != AMH_OK) return st;
     if ((st = dalloc(c, (void **)&c->d_jobs, sizeof(BatchJobDev) * n_jobs)) != AMH_OK) return st;
-    const size_t ncount = 3 * (size_t)kCounterSlots + (size_t)n_jobs + (size_t)n_jobs + 1;
+    const size_t ncount = kCounterKinds * (size_t)kCounterSlots + (size_t)n_jobs + (size_t)n_jobs + 1;
     if ((st = dalloc(c, (void **)&c->d_bcount, sizeof(unsigned long long) * ncount)) != AMH_OK) return st;
     std::vector<ViewDev> hv(total_src);
     std::vector<BatchJobDev> hj(n_jobs);
@@ -429,10 +429,10 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
     HIPCHK(c, hipStreamSynchronize(c->stream));
     // capture (kernels only: counters are cleared by a kernel, not a memset)
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    unsigned long long *tiles_done = c->d_bcount + 3 * kCounterSlots;
+    unsigned long long *tiles_done = c->d_bcount + kCounterKinds * kCounterSlots;
     unsigned long long *clocks = tiles_done + n_jobs;  // [n_jobs] completion, [n_jobs] start
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_zero_u64(c->d_bcount, 3 * kCounterSlots + n_jobs, c->cap_stream);
+    hipError_t e = launch_zero_u64(c->d_bcount, kCounterKinds * kCounterSlots + n_jobs, c->cap_stream);
     if (e == hipSuccess) e = launch_stamp(clocks + n_jobs, c->cap_stream);
     // learned proposal: sweep and network forward of every job before its initialisation
     for (int j = 0; proposal && j < n_jobs && e == hipSuccess; ++j) {
@@ -538,7 +538,7 @@ amh_status amh_create(amh_ctx **out, const amh_params *p, void *hip_stream) {
         delete c;
         return AMH_E_HIP;
     }
-    st = dalloc(c, (void **)&c->counters, sizeof(unsigned long long) * 3 * kCounterSlots);
+    st = dalloc(c, (void **)&c->counters, sizeof(unsigned long long) * kCounterKinds * kCounterSlots);
     if (st != AMH_OK) {
         delete c;
         return st;
@@ -720,7 +720,7 @@ amh_status amh_begin(amh_ctx *c, int ref, const int *srcs, int n_src) {
     c->n_timed = 0;
     c->init_timed = false;
     c->batch_stats = false;
-    HIPCHK(c, launch_zero_u64(c->counters, 3 * kCounterSlots, c->stream));
+    HIPCHK(c, launch_zero_u64(c->counters, kCounterKinds * kCounterSlots, c->stream));
     return AMH_OK;
 }
 
@@ -927,7 +927,7 @@ amh_status amh_get_job_times(amh_ctx *c, int n, float *job_ms) {
     if (!c->d_bcount) return fail(c, AMH_E_STATE, "the batch's clocks were released (parameters changed)");
     // clocks: [n] job completions then the batch start, after the evaluation counters and tiles-done
     std::vector<unsigned long long> h((size_t)n + 1);
-    const size_t off = 3 * (size_t)kCounterSlots + (size_t)n;
+    const size_t off = kCounterKinds * (size_t)kCounterSlots + (size_t)n;
     HIPCHK(c, hipMemcpyAsync(h.data(), c->d_bcount + off, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     int khz = 0;
@@ -1065,26 +1065,28 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
     if (!c || !out) return AMH_E_INVALID_ARG;
     memset(out, 0, sizeof *out);
     if (c->batch_stats && c->d_bcount) {
-        std::vector<unsigned long long> h(3 * kCounterSlots);
+        std::vector<unsigned long long> h(kCounterKinds * kCounterSlots);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->d_bcount, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kCounterKinds; ++k) {
             c->batch_counts[k] = 0;
             for (int i = 0; i < kCounterSlots; ++i) c->batch_counts[k] += h[k * kCounterSlots + i];
         }
         out->evals_init = c->batch_counts[0];
         out->evals_propagation = c->batch_counts[1];
         out->evals_refine = c->batch_counts[2];
+        out->fallback_pixels = c->batch_counts[3];
     } else if (!c->batch_stats && c->counters) {
-        std::vector<unsigned long long> h(3 * kCounterSlots);
+        std::vector<unsigned long long> h(kCounterKinds * kCounterSlots);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->counters, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        unsigned long long s[3] = {0, 0, 0};
-        for (int k = 0; k < 3; ++k)
+        unsigned long long s[kCounterKinds] = {0, 0, 0, 0};
+        for (int k = 0; k < kCounterKinds; ++k)
             for (int i = 0; i < kCounterSlots; ++i) s[k] += h[k * kCounterSlots + i];
         out->evals_init = s[0];
         out->evals_propagation = s[1];
         out->evals_refine = s[2];
+        out->fallback_pixels = s[3];
     }
     out->evals_total = out->evals_init + out->evals_propagation + out->evals_refine;
     out->n_passes = c->n_timed;

@@ -80,11 +80,11 @@ struct amh_ctx {
     BatchJobDev *d_jobs = nullptr;
     ViewDev *d_bviews = nullptr;
     int *d_tables = nullptr;
-    unsigned long long *d_bcount = nullptr;  // [3 * kCounterSlots] evals, [n_jobs] tiles done, [n_jobs + 1] clocks
+    unsigned long long *d_bcount = nullptr;  // [kCounterKinds * kCounterSlots] counts, [n_jobs] tiles done, [n_jobs + 1] clocks
     int batch_jobs = 0;
     bool batch_ran = false;
     bool batch_stats = false;
-    unsigned long long batch_counts[3] = {0, 0, 0};
+    unsigned long long batch_counts[kCounterKinds] = {0, 0, 0, 0};
     // proposal network (weights, optimiser state, activations), created by amh_nn_init
     amh::NetState *net = nullptr;
     void *prop_feats = nullptr;   // amh_run_proposal: network input and prediction of the reference

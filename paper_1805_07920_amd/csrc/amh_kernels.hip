@@ -635,9 +635,11 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
     float *mcol = S.ms + wave * N * 64;  // m of view j for group g at mcol[j * 64 + g * 9]
     int n_eval = 0;
+    bool fell_back = false;  // a proposal was given but this pixel keeps the random plane
     if (pix_ok) {
         const float2 r = ref_ray(a.ref, x, y);
         if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
+            fell_back = a.prop != nullptr;
             float u[4], nx, ny, nz;
             philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
             const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
@@ -675,6 +677,7 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
         glob(a.st.v)[p] = -1;
     }
     count_evals(a.counters, 0, (unsigned long long)n_eval);
+    if (a.prop) count_evals(a.counters, 3, (fell_back && row == 0) ? 1ull : 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -709,9 +712,11 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
     }
     __syncthreads();
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
+    bool fell_back = false;
     if (pix_ok) {
         const float2 r = ref_ray(a.ref, x, y);
         if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
+            fell_back = a.prop != nullptr;
             float u[4], nx, ny, nz;
             philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
             const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
@@ -722,6 +727,7 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
         cst[t] = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
     }
     count_evals(a.counters, 0, pix_ok ? 1ull : 0ull);
+    if (a.prop) count_evals(a.counters, 3, (fell_back && j == 0) ? 1ull : 0ull);
     __syncthreads();
     if (pix_ok && j == 0) {
         // mean of the k lowest costs, in ascending order

@@ -440,6 +440,7 @@ def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
         ctx.begin(0, [1, 2, 3, 4])
         ctx.init_from_proposal(dev(pred, torch.float32))
         pl, cost, S, v = ctx.get_state()
+        fallbacks = ctx.get_stats()["fallback_pixels"]
     V = oracle_mod.Views.from_scene(sc)
     P = oracle_mod.Params(seed=13)
     ost, used = proposal.proposal_state(V, P, pred[..., 0].astype(np.float64), pred[..., 1:4].astype(np.float64),
@@ -464,6 +465,8 @@ def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
     np.testing.assert_allclose(pl[ok], ost.plane[ok], atol=2e-5, rtol=2e-5)
     assert (np.abs(cost - ost.cost)[ok] <= 1e-4).mean() >= 0.999
     assert np.all(S == 0) and np.all(v == -1)
+    # pixels that kept the random plane, as counted by the library
+    assert abs(int(fallbacks) - int((~used).sum())) <= int(near.sum())
 
 
 def test_run_proposal_equals_its_steps(amh, scene_c1):
@@ -490,6 +493,7 @@ def test_run_proposal_equals_its_steps(amh, scene_c1):
     for u, w in zip(a, b):
         np.testing.assert_array_equal(u, w)
     assert st["evals_init"] == 24 * 32 * 12 * 4 + 128 * 96 * 4
+    assert 0 <= st["fallback_pixels"] <= 128 * 96
     assert np.isfinite(a[1]).all()
 
 
