@@ -117,7 +117,7 @@ def cpu_baseline(sc, params_kw, gpu_state, budget_s=15.0):
         evals += d.n_cand * sum(1 for j in range(n) if d.w[j] > 0)
     return {"value": evals / el, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"one red half-pass (t=0, refinement on) over {len(order)} pixels in rows {y0}..{y0 + rows - 1}"
-                      f" of the 1920x1280 reference, {evals} evaluations in {el:.1f} s"}
+                      f" of the {W}x{H} reference, {evals} evaluations in {el:.1f} s"}
 
 
 def bench_batch(args):
@@ -535,6 +535,9 @@ def main():
                     help="iterations per depth map (--ablation, --readings)")
     ap.add_argument("--fusion", action="store_true",
                     help="the stage after the depth maps: median filter + consistency-check fusion of 11 views")
+    ap.add_argument("--config", default="c2", choices=("c2", "c3"),
+                    help="single-image workload: c2 = 1920x1280, 10 sources (the headline); c3 = 3200x2130, 20 sources "
+                         "stored fp16, 30 %% low texture, 4 iterations")
     ap.add_argument("--launch-config", type=int, default=None, choices=range(8),
                     help="skip the autotuner and run this launch configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -573,9 +576,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = scenegen.CONFIGS["c2"]
+    cfg = scenegen.CONFIGS[args.config]
     t0 = time.time()
-    sc = scenegen.config_scene("c2", args.seed, device="cuda")
+    sc = scenegen.config_scene(args.config, args.seed, device="cuda")
     log(f"scene rendered in {time.time() - t0:.1f} s")
     imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images]
     n = len(imgs) - 1
@@ -588,7 +591,8 @@ def main():
     ctx = amh.Context(refine=cfg["refine"], seed=args.seed, timing=1)
     # launch configuration (tile order, tile rows) picked by the library's autotuner on this workload,
     # before the timed region
-    ctx.init_views(imgs, sc.cams, store_as=amh.AMH_F32)
+    store = amh.AMH_F16 if cfg["src_dtype"] == "f16" else amh.AMH_F32
+    ctx.init_views(imgs, sc.cams, store_as=store)
     if args.launch_config is None:
         best_cfg, tune_ms = ctx.tune([dict(ref=0, srcs=srcs, iters=cfg["iters"])])
         log(f"autotune: config {best_cfg}, ms per configuration {np.round(tune_ms, 2).tolist()}")
@@ -597,7 +601,7 @@ def main():
         ctx.set_launch_config(best_cfg)
 
     def step():
-        ctx.init_views(imgs, sc.cams, store_as=amh.AMH_F32)
+        ctx.init_views(imgs, sc.cams, store_as=store)
         ctx.run_checkerboard(0, srcs, cfg["iters"])
         ctx.get_depth_normal_cost(depth, normal, cost)
 
@@ -638,9 +642,13 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "1920x1280 reference + 10 sources, 20-plane seeded scene with occlusions and "
-                               "+-5% gain, 11x11 window stride 2, 3 iterations + refinement, random init",
+        "vs_baseline": None, "dtype": "f32" if store == amh.AMH_F32 else "f32 (sources stored f16)",
+        "data": "synthetic",
+        "config": {"workload": (f"{W}x{H} reference + {n} sources, 20-plane seeded scene with occlusions and "
+                                "+-5% gain, 11x11 window stride 2, 3 iterations + refinement, random init")
+                   if args.config == "c2" else
+                   (f"{W}x{H} reference + {n} sources stored fp16 (fp32 arithmetic), 20-plane seeded scene, 30% "
+                    f"low-texture area, 11x11 window stride 2, {cfg['iters']} iterations + refinement, random init"),
                    "width": W, "height": H, "n_src": n, "iters": cfg["iters"], "refine": cfg["refine"],
                    "seed": args.seed, "parallelism": "single GPU"},
         "sec_per_depth_map": ms_per_step / 1000.0,
@@ -649,10 +657,12 @@ def main():
         "init_ms": ev["ms_init"],
         "accuracy_within_1pct_of_ground_truth": acc,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                     "frac": achieved / VALU_PEAK_OPS, "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4),
+                     "frac": achieved / VALU_PEAK_OPS,
+                     # the counters were taken on the 1920x1280 workload only
+                     "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4) if args.config == "c2" else None,
                      "traffic_unit": "bytes per launch (L2 <-> memory, calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                     "kernel": f"pass_kernel<0, {2 if best_cfg & 4 else 4}> (fused checkerboard half-pass, "
-                               f"{2 if best_cfg & 4 else 4}-row tiles)",
+                     "kernel": f"pass_kernel<{1 if store == amh.AMH_F16 else 0}, {2 if best_cfg & 4 else 4}> "
+                               f"(fused checkerboard half-pass, {2 if best_cfg & 4 else 4}-row tiles)",
                      "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals_per_pass},
         "cpu_baseline": cpu,
         "autotune": {"best_config": best_cfg, "ms_per_config": tune_ms,
