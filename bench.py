@@ -511,6 +511,57 @@ def bench_fusion(args):
     print(json.dumps(out))
 
 
+def bench_scaling(args):
+    """Time per depth map against image size (the shape of the paper's Table 3: time proportional to the
+    pixel count): the 1920x1280 / 10-source recipe at scales 1, 0.5 and 0.25 (3 iterations + refinement)."""
+    import torch
+
+    import paper_1805_07920_amd as amh
+    import scenegen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    base = scenegen.CONFIGS["c2"]
+    ctx = amh.Context(refine=1, seed=args.seed)
+    rows = []
+    tuned = None
+    for eta in (1.0, 0.5, 0.25):
+        W, H = int(base["width"] * eta), int(base["height"] * eta)
+        sc = scenegen.config_scene("c2", args.seed, device="cuda", width=W, height=H)
+        srcs = list(range(1, len(sc.images)))
+        imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images]
+        ctx.init_views(imgs, sc.cams)
+        if tuned is None:
+            tuned = ctx.tune([dict(ref=0, srcs=srcs, iters=3)])  # the full-size configuration for every scale
+            ctx.init_views(imgs, sc.cams)
+        for _ in range(max(1, args.warmup)):
+            ctx.run_checkerboard(0, srcs, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.run_checkerboard(0, srcs, 3)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        ev = ctx.get_stats()["evals_total"]
+        rows.append(dict(scale=eta, width=W, height=H, ms_per_depth_map=ms, evals=ev, evals_per_s=ev / (ms / 1000.0)))
+        log(f"scale {eta}: {W}x{H} {ms:.2f} ms, {ev / (ms / 1000.0) / 1e9:.2f} G evals/s")
+    ctx.close()
+    out = {
+        "metric": "seconds per depth map against pixel count (Table 3 shape)", "value": rows[0]["ms_per_depth_map"] / 1000.0,
+        "unit": "s per depth map at 1920x1280", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": rows[0]["ms_per_depth_map"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "the 1920x1280 / 10-source recipe at scales 1, 0.5, 0.25, 3 iterations + refinement",
+                   "parallelism": "single GPU"},
+        "sizes": rows,
+        "time_ratio_1_to_0.5": rows[0]["ms_per_depth_map"] / rows[1]["ms_per_depth_map"],
+        "time_ratio_0.5_to_0.25": rows[1]["ms_per_depth_map"] / rows[2]["ms_per_depth_map"],
+        "pixel_ratio": 4.0,
+        "autotune": {"best_config": tuned[0], "ms_per_config": tuned[1]},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +582,8 @@ def main():
                          "heuristic view selection)")
     ap.add_argument("--readings", action="store_true",
                     help="accuracy per iteration of the readings against the literal text (self row, squared weights)")
+    ap.add_argument("--scaling", action="store_true",
+                    help="time per depth map at scales 1, 0.5 and 0.25 of the 1920x1280 workload")
     ap.add_argument("--ablation-iters", type=int, default=6,
                     help="iterations per depth map (--ablation, --readings)")
     ap.add_argument("--fusion", action="store_true",
@@ -567,6 +620,8 @@ def main():
         return bench_fusion(args)
     if args.readings:
         return bench_readings(args)
+    if args.scaling:
+        return bench_scaling(args)
 
     import torch
 
