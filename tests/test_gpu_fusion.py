@@ -224,3 +224,24 @@ def test_fusion_errors(amh):
         # one view, f_con 0: every pixel with a depth yields its own back-projection
         P, N, O, total = ctx.fuse([0], [d], [n], f_con=0)
         assert total == 32 * 24
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 7), (9, 1), (65, 3)])
+def test_fusion_tiny_views(amh, W, H):
+    """Views of 1 to a few pixels (ragged 64-pixel blocks): the cloud equals the vectorised oracle's."""
+    import torch
+
+    import scenegen
+    from oracle import fusion
+
+    say("case fusion tiny", W, H)
+    sc = scenegen.make_scene(W, H, 2, 10.0, 0, 3, supersample=1, all_views=True)
+    with amh.Context() as ctx:
+        ctx.init_views([np.ascontiguousarray(im) for im in sc.images], sc.cams)
+        d = [torch.from_numpy(x).cuda() for x in sc.depth_views]
+        n = [torch.from_numpy(x).cuda() for x in sc.normal_views]
+        P, N, O, total = ctx.fuse([0, 1, 2], d, n, f_con=1)
+    Po, _, Oo = fusion.fuse(sc.cams, sc.depth_views, sc.normal_views, f_con=1)
+    assert total == len(Po)
+    assert np.array_equal(O.cpu().numpy()[:, :2], Oo[:, :2].astype(np.int32))
+    np.testing.assert_allclose(P.cpu().numpy(), Po, atol=1e-4)

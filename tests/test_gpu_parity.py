@@ -329,18 +329,19 @@ def test_run_is_deterministic_and_composes(amh, scene_c1):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("W,H,n", [(1, 1, 1), (2, 3, 2), (7, 5, 3), (16, 1, 2), (30, 30, 1)])
-def test_degenerate_sizes(amh, oracle_mod, W, H, n):
-    say("case tiny", W, H, n)
+@pytest.mark.parametrize("W,H,n,sym,heur", [(1, 1, 1, 0, 0), (2, 3, 2, 0, 0), (7, 5, 3, 0, 0), (16, 1, 2, 0, 0),
+                                           (30, 30, 1, 0, 0), (1, 1, 1, 1, 1), (7, 5, 3, 1, 0), (16, 1, 2, 0, 1)])
+def test_degenerate_sizes(amh, oracle_mod, W, H, n, sym, heur):
+    say("case tiny", W, H, n, "ablation" if sym or heur else "")
     import scenegen
 
     sc = scenegen.make_scene(W, H, n, 15.0, 1, seed=1, supersample=1)
-    with make_ctx(amh, sc, refine=1, seed=1) as ctx:
+    with make_ctx(amh, sc, refine=1, seed=1, sym_prop=sym, heuristic_views=heur) as ctx:
         ctx.run_checkerboard(0, list(range(1, n + 1)), 2)
         d, nn, c = ctx.get_depth_normal_cost()
     O = oracle_mod
     V = O.Views.from_scene(sc)
-    st = O.run(V, O.Params(refine=1, seed=1), 2)
+    st = O.run(V, O.Params(refine=1, seed=1, prop_mode=sym, view_mode=2 if heur else 0), 2)
     od, _ = O.depth_normal(V, st)
     assert np.all(np.isfinite(d)) and np.all(np.isfinite(c))
     assert (np.abs(d - od) / od <= 1e-3).mean() >= 0.9
