@@ -597,7 +597,7 @@ def main():
                     help="only run a plain 256 MiB element-wise copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}). "
               "Reference images shard across GPUs with no exchange; see the design notes.", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:

@@ -51,7 +51,7 @@ typedef enum {
     AMH_E_OOM = -2,         /* a device allocation failed */
     AMH_E_HIP = -3,         /* the HIP runtime reported an error (no device, launch failure, ...) */
     AMH_E_STATE = -4,       /* the call needs an earlier call that has not happened (e.g. views, a run) */
-    AMH_E_UNSUPPORTED = -5  /* a valid request outside what this build supports */
+    AMH_E_UNSUPPORTED = -5  /* a valid request outside what the library supports */
 } amh_status;
 
 typedef enum { AMH_F32 = 0, AMH_F16 = 1 } amh_dtype;

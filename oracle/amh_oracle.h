@@ -4,7 +4,7 @@
  * Multi-Hypothesis Joint View Selection", arXiv 1805.07920).
  *
  * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, double-precision
- * restatement of the method, used to judge the GPU library.  Only the tests,
+ * restatement of the method, used to check the GPU library.  Only the tests,
  * the smoke check and the benchmark's CPU-baseline leg may call it; the
  * library never does.  It shares no code, header, table or constant with the
  * GPU path.

@@ -25,7 +25,7 @@ Pins (tests/test_oracle_nn.py): convolution, pooling and upsampling against
 torch's float64 CPU routines; every backward against torch autograd and central
 finite differences; the loss against finite differences and closed forms; Adam
 against its closed-form first step and torch.optim.Adam.  The network's
-*trained result* is parity unpinned: it is judged against ground-truth depth.
+*trained result* is parity unpinned: it is checked against ground-truth depth.
 
 Layout: activations are NHWC float64 arrays (n, h, w, c); a 3x3 weight is
 (c_out, 3, 3, c_in) with tap (ky, kx) reading input pixel (y + ky - 1,
