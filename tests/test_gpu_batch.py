@@ -37,6 +37,8 @@ SPECS = [  # (W, H, n_src, iters, seed)
     (64, 48, 2, 1, 23),
     (150, 90, 4, 0, 24),
     (40, 30, 6, 3, 25),
+    (48, 40, 12, 2, 26),  # 12 and 16 sources: a second LDS class, launched separately in each phase
+    (56, 36, 16, 1, 27),
 ]
 
 

@@ -245,3 +245,33 @@ def test_fusion_tiny_views(amh, W, H):
     assert total == len(Po)
     assert np.array_equal(O.cpu().numpy()[:, :2], Oo[:, :2].astype(np.int32))
     np.testing.assert_allclose(P.cpu().numpy(), Po, atol=1e-4)
+
+
+def test_fusion_views_of_different_sizes(amh):
+    """Two parallel cameras of different image sizes looking at one fronto-parallel plane: the cloud equals the
+    oracle's, point for point."""
+    import torch
+
+    from oracle import fusion
+
+    class Cam:
+        def __init__(self, K, t, w, h):
+            self.K, self.R, self.t, self.width, self.height = K, np.eye(3), np.asarray(t, float), w, h
+
+    say("case fusion different sizes")
+    cams, depths, normals = [], [], []
+    for (w, h, tx) in ((40, 24, 0.0), (56, 30, -0.52)):
+        K = np.array([[100.0, 0, (w - 1) / 2], [0, 100.0, (h - 1) / 2], [0, 0, 1.0]])
+        cams.append(Cam(K, [tx, 0, 0], w, h))
+        depths.append(np.full((h, w), 4.0, np.float32))
+        normals.append(np.tile(np.array([0, 0, -1], np.float32), (h, w, 1)))
+    imgs = [np.full((c.height, c.width), 100.0, np.float32) for c in cams]
+    with amh.Context() as ctx:
+        ctx.init_views(imgs, cams)
+        P, N, O, total = ctx.fuse([0, 1], [torch.from_numpy(d).cuda() for d in depths],
+                                  [torch.from_numpy(n).cuda() for n in normals], f_con=1)
+    Po, _, Oo = fusion.fuse(cams, depths, normals, f_con=1)
+    say(f"  {total} points, oracle {len(Po)}")
+    assert total == len(Po) > 0
+    assert np.array_equal(O.cpu().numpy()[:, :2], Oo[:, :2].astype(np.int32))
+    np.testing.assert_allclose(P.cpu().numpy(), Po, atol=1e-4)
