@@ -41,10 +41,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2463183.8, "write_kib": 312510.0},
-                                 4: {"fetch_kib": 1565025.9, "write_kib": 288463.0}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2465470.9, "write_kib": 312318.3},
+                                 4: {"fetch_kib": 1570081.3, "write_kib": 288232.4}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "83db525fd2628481ac14ac85f67f3f00b0bd7f79475b5e5de6874638e4579f63"}
+                "kernel_sha256": "ace4f1a29e6dc4b25094d4f7f97ef871f37348be4b8becc085ae05d3749bcb4b"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

@@ -1014,7 +1014,6 @@ amh_status amh_sweep_features(amh_ctx *c, void *feats, float *q_ref) {
     if (!c) return AMH_E_INVALID_ARG;
     if (!feats) return fail(c, AMH_E_INVALID_ARG, "feats is NULL");
     if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
-    const int W = c->refdev.W, H = c->refdev.H;
     const SweepArgs a = sweep_args(c, c->refdev, c->d_viewc, (int)c->srcs.size(), feats, q_ref, c->counters);
     HIPCHK(c, launch_sweep(a, c->half, c->stream));
     return AMH_OK;

@@ -147,9 +147,11 @@ __device__ __forceinline__ float eval_quad_f32(gf4 q, float fx, float fy) {
 }
 
 __device__ __forceinline__ float eval_quad_f16(gh4 q, float fx, float fy) {
+    // a + fx (b - a) as fma(b, fx, fma(-a, fx, a)): the halves enter mixed-precision FMAs directly
+    // (exact conversion inside the instruction), which saves the separate conversions and differences
     const float a = (float)q.x, b = (float)q.y, c = (float)q.z, d = (float)q.w;
-    const float top = fmaf(fx, b - a, a);
-    const float bot = fmaf(fx, d - c, c);
+    const float top = fmaf(b, fx, fmaf(-a, fx, a));
+    const float bot = fmaf(d, fx, fmaf(-c, fx, c));
     return fmaf(fy, bot - top, top);
 }
 
