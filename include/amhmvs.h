@@ -117,6 +117,11 @@ typedef struct {
     int n_fuse_kernels;         /* ... and their number (one per view) */
     uint64_t fallback_pixels;   /* initialisation from a proposal: pixels that kept the random plane (confidence
                                  * below conf_min, no normal, or the predicted plane out of range there) */
+    uint64_t evals_short;       /* of evals_propagation + evals_refine: evaluations whose cost 2 was decided
+                                 * before any sample was taken (plane depth outside [depth_min, depth_max] at the
+                                 * pixel, window centre behind the source camera or outside its image, a window
+                                 * corner not in front of it) */
+    uint64_t evals_init_short;  /* the same among evals_init */
 } amh_stats;
 
 /* Batched job (see amh_run_batch). */

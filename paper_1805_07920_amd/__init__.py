@@ -62,7 +62,7 @@ class amh_stats(C.Structure):
     _fields_ = [("evals_total", C.c_uint64), ("evals_init", C.c_uint64), ("evals_propagation", C.c_uint64),
                 ("evals_refine", C.c_uint64), ("n_passes", C.c_int), ("ms_per_pass", C.c_float * 64),
                 ("ms_init", C.c_float), ("ms_fuse_kernels", C.c_float), ("n_fuse_kernels", C.c_int),
-                ("fallback_pixels", C.c_uint64)]
+                ("fallback_pixels", C.c_uint64), ("evals_short", C.c_uint64), ("evals_init_short", C.c_uint64)]
 
 
 class amh_fusion_params(C.Structure):
@@ -361,7 +361,8 @@ class Context:
                     evals_refine=s.evals_refine, n_passes=s.n_passes,
                     ms_per_pass=list(s.ms_per_pass[:s.n_passes]), ms_init=s.ms_init,
                     ms_fuse_kernels=s.ms_fuse_kernels, n_fuse_kernels=s.n_fuse_kernels,
-                    fallback_pixels=s.fallback_pixels)
+                    fallback_pixels=s.fallback_pixels, evals_short=s.evals_short,
+                    evals_init_short=s.evals_init_short)
 
     # --- learned proposal ----------------------------------------------------------------
     @staticmethod

@@ -1075,17 +1075,21 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
         out->evals_propagation = c->batch_counts[1];
         out->evals_refine = c->batch_counts[2];
         out->fallback_pixels = c->batch_counts[3];
+        out->evals_short = c->batch_counts[4];
+        out->evals_init_short = c->batch_counts[5];
     } else if (!c->batch_stats && c->counters) {
         std::vector<unsigned long long> h(kCounterKinds * kCounterSlots);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->counters, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        unsigned long long s[kCounterKinds] = {0, 0, 0, 0};
+        unsigned long long s[kCounterKinds] = {};
         for (int k = 0; k < kCounterKinds; ++k)
             for (int i = 0; i < kCounterSlots; ++i) s[k] += h[k * kCounterSlots + i];
         out->evals_init = s[0];
         out->evals_propagation = s[1];
         out->evals_refine = s[2];
         out->fallback_pixels = s[3];
+        out->evals_short = s[4];
+        out->evals_init_short = s[5];
     }
     out->evals_total = out->evals_init + out->evals_propagation + out->evals_refine;
     out->n_passes = c->n_timed;

@@ -84,7 +84,7 @@ struct amh_ctx {
     int batch_jobs = 0;
     bool batch_ran = false;
     bool batch_stats = false;
-    unsigned long long batch_counts[kCounterKinds] = {0, 0, 0, 0};
+    unsigned long long batch_counts[kCounterKinds] = {};
     // proposal network (weights, optimiser state, activations), created by amh_nn_init
     amh::NetState *net = nullptr;
     void *prop_feats = nullptr;   // amh_run_proposal: network input and prediction of the reference

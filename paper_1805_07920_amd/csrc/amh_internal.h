@@ -8,7 +8,8 @@ namespace amh {
 
 constexpr int kMaxSrc = 32;
 constexpr int kCounterSlots = 256;    // eval counters are spread over slots to avoid one hot atomic
-constexpr int kCounterKinds = 4;      // init, propagation, refinement evaluations; proposal fallbacks
+constexpr int kCounterKinds = 6;      // init, propagation, refinement evaluations; proposal fallbacks;
+                                       // short evaluations (no samples taken) of the half-pass and of init
 constexpr int kGroups = 7;            // pixels per wave (7 groups x 9 lanes = 63 lanes)
 constexpr int kRows = 9;              // 8 propagated hypotheses + the pixel's own
 constexpr int kTilePix = kGroups;     // same-colour pixels per tile row
@@ -59,7 +60,7 @@ struct PassArgs {
     StateDev st;
     int t, colour;
     int tiles_x, n_tiles;        // tile grid of this colour
-    unsigned long long *counters;  // [kCounterKinds][kCounterSlots]: init, propagation, refinement evals, fallbacks
+    unsigned long long *counters;  // [kCounterKinds][kCounterSlots], kinds as listed at kCounterKinds
     int order;                   // tile order: 0 XCD bands, 1 hardware order
     int waves = kDefaultTileRows;  // tile rows = waves per workgroup (2 or 4)
     // initialisation from per-cell predictions (NULL: random initialisation)

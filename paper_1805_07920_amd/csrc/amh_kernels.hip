@@ -340,18 +340,32 @@ __device__ __forceinline__ void window_moments(const void *__restrict__ quads, c
     }
 }
 
+// An evaluation whose cost 2 is decided before any sample is taken (plane depth out of range at the pixel,
+// window centre behind the source camera or outside its image, a window corner not in front of it) returns
+// kShort from ncc_cost_raw; callers that count such evaluations map it to 2 with short_to_cost, which adds
+// it to an LDS counter (carrying the flag in the result keeps a register free in the sample loop).
+constexpr float kShort = -1.f;
+
+__device__ __forceinline__ float short_to_cost(float c, unsigned *nshort) {
+    if (c < 0.f) {
+        atomicAdd(nshort, 1u);
+        return 2.f;
+    }
+    return c;
+}
+
 template <int HALF>
-__device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__restrict__ rw_in, const WinStats &ws,
-                                          int x, int y, double q0, float qu, float qv) {
+__device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *__restrict__ rw_in,
+                                              const WinStats &ws, int x, int y, double q0, float qu, float qv) {
     const float2 *__restrict__ rw = rw_in;
     const double P0x = fma(vw.A[1], (double)y, fma(vw.A[0], (double)x, vw.A[2])) + vw.b[0] * q0;
     const double P0y = fma(vw.A[4], (double)y, fma(vw.A[3], (double)x, vw.A[5])) + vw.b[1] * q0;
     const double P0z = fma(vw.A[7], (double)y, fma(vw.A[6], (double)x, vw.A[8])) + vw.b[2] * q0;
-    if (!(P0z > 0.0)) return 2.f;
+    if (!(P0z > 0.0)) return kShort;
     const double rz = 1.0 / P0z;
     const double cu = P0x * rz, cv = P0y * rz;
     const int W = vw.W, H = vw.H;
-    if (!(cu >= 0.0 && cu <= (double)(W - 1) && cv >= 0.0 && cv <= (double)(H - 1))) return 2.f;
+    if (!(cu >= 0.0 && cu <= (double)(W - 1) && cv >= 0.0 && cv <= (double)(H - 1))) return kShort;
     const int ix = (int)floor(cu), iy = (int)floor(cv);
     const float N0x = (float)(P0x - (double)ix * P0z);
     const float N0y = (float)(P0y - (double)iy * P0z);
@@ -366,7 +380,7 @@ __device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__res
     // window offsets, so the four corners decide
     const float zc0 = Z0 - 5.f * puz - 5.f * pvz, zc1 = Z0 + 5.f * puz - 5.f * pvz;
     const float zc2 = Z0 - 5.f * puz + 5.f * pvz, zc3 = Z0 + 5.f * puz + 5.f * pvz;
-    if (!(fminf(fminf(zc0, zc1), fminf(zc2, zc3)) > 1e-20f)) return 2.f;
+    if (!(fminf(fminf(zc0, zc1), fminf(zc2, zc3)) > 1e-20f)) return kShort;
 
     const void *__restrict__ quads = vw.quads;
     // texel indices relative to (ix, iy), clamped to [-1, W-1] x [-1, H-1] in absolute terms;
@@ -398,6 +412,14 @@ __device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__res
     if (ws.var_a < 1e-5f || var_b < 1e-5f) return 2.f;
     const float mm = 1.f - cov * rsqrtf(ws.var_a * var_b);
     return fminf(fmaxf(mm, 0.f), 2.f);
+}
+
+// The cost with short evaluations not counted.
+template <int HALF>
+__device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__restrict__ rw, const WinStats &ws, int x,
+                                          int y, double q0, float qu, float qv) {
+    const float c = ncc_cost_raw<HALF>(vw, rw, ws, x, y, q0, qu, qv);
+    return c < 0.f ? 2.f : c;
 }
 
 // inverse-depth terms of a plane at reference pixel (x, y): q = -(n . K^-1 (x, y, 1)) / d
@@ -483,6 +505,7 @@ struct PassLds {
     unsigned char *act;  // [wave][group][32] active views for refinement
     float4 *cand;    // [wave][group][6] refinement candidates
     float *wgt;      // [wave][group][32] view weights of each pixel
+    unsigned *nshort;  // [wave] evaluations of the wave that took no samples (touched by that wave only)
 };
 
 constexpr int kTileW = 2 * kTilePix + 10;
@@ -490,7 +513,7 @@ constexpr int kTileW = 2 * kTilePix + 10;
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 // LDS of a workgroup of `waves` waves (one image row of the tile per wave)
-__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[10]) {
+__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[11]) {
     size_t o = 0;
     off[0] = o; o = align16(o + sizeof(float) * (waves + 10) * kTileW);
     off[1] = o; o = align16(o + sizeof(float2) * waves * kGroups * kWinStride);
@@ -502,16 +525,17 @@ __host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[10
     off[7] = o; o = align16(o + waves * kGroups * kMaxSrc);
     off[8] = o; o = align16(o + sizeof(float4) * waves * kGroups * 6);
     off[9] = o; o = align16(o + sizeof(float) * waves * kGroups * kMaxSrc);
+    off[10] = o; o = align16(o + sizeof(unsigned) * waves);
     return o;
 }
 
 size_t pass_lds_bytes(int n_src, int waves) {
-    size_t off[10];
+    size_t off[11];
     return lds_layout(n_src, waves, off);
 }
 
 __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int waves) {
-    size_t off[10];
+    size_t off[11];
     lds_layout(n_src, waves, off);
     PassLds L;
     L.tile = reinterpret_cast<float *>(smem + off[0]);
@@ -524,6 +548,7 @@ __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int wav
     L.act = smem + off[7];
     L.cand = reinterpret_cast<float4 *>(smem + off[8]);
     L.wgt = reinterpret_cast<float *>(smem + off[9]);
+    L.nshort = reinterpret_cast<unsigned *>(smem + off[10]);
     return L;
 }
 
@@ -624,6 +649,7 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
     const bool pix_ok = grp < kGroups && y < a.ref.H && x < a.ref.W;
 
     stage_tile<WAVES>(a.ref, S.tile, y0, x0);
+    if (lane == 0) S.nshort[wave] = 0u;
     __syncthreads();
     float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * kWinStride;
     WinStats ws = {1.f, 0.f};
@@ -650,7 +676,8 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
         }
         const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
         for (int j = row; j < N; j += kRows) {
-            const float c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+            const float c = short_to_cost(q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv)
+                                               : kShort, &S.nshort[wave]);
             mcol[j * 64 + grp * kRows] = c;
             ++n_eval;
         }
@@ -679,6 +706,7 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
         glob(a.st.v)[p] = -1;
     }
     count_evals(a.counters, 0, (unsigned long long)n_eval);
+    count_evals(a.counters, 5, lane == 0 ? (unsigned long long)S.nshort[wave] : 0ull);
     if (a.prop) count_evals(a.counters, 3, (fell_back && row == 0) ? 1ull : 0ull);
 }
 
@@ -697,6 +725,7 @@ template <int HALF>
 __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
     __shared__ __align__(16) float2 rwbuf[kInitMaxPix * kWinStride];
     __shared__ float cst[256];
+    __shared__ unsigned nshort;
     const int N = a.n_src;
     const int G = min(kInitMaxPix, 256 / N);
     const int t = threadIdx.x, g = t / N, j = t - g * N;
@@ -712,6 +741,7 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
         GlobalReader rd{&a.ref, x, y};
         ws = build_window(rd, a.m, rw, j, N);
     }
+    if (t == 0) nshort = 0u;
     __syncthreads();
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
     bool fell_back = false;
@@ -726,11 +756,13 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
             pl = plane_from(r, depth, nx, ny, nz);
         }
         const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
-        cst[t] = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+        cst[t] = short_to_cost(q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort,
+                               &nshort);
     }
     count_evals(a.counters, 0, pix_ok ? 1ull : 0ull);
     if (a.prop) count_evals(a.counters, 3, (fell_back && j == 0) ? 1ull : 0ull);
     __syncthreads();
+    count_evals(a.counters, 5, t == 0 ? (unsigned long long)nshort : 0ull);
     if (pix_ok && j == 0) {
         // mean of the k lowest costs, in ascending order
         const float *c = cst + g * N;
@@ -761,7 +793,11 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
 // ---------------------------------------------------------------------------
 // One checkerboard half-pass (Sec. 3.1 - 3.3).
 // ---------------------------------------------------------------------------
-// Mean of the kk lowest of n values at stride `stride` (heuristic view selection of the ablation).
+// A weighted refinement cost w * m as stored: a short evaluation is stored as w * kShort = -w, its cost is 2 w.
+__device__ __forceinline__ float weighted_cost(float r) { return r < 0.f ? -2.f * r : r; }
+
+// Mean of the kk lowest of n values at stride `stride` (heuristic view selection of the ablation); the
+// values are costs, or weighted costs as stored by refinement.
 __device__ __forceinline__ float mean_k_lowest(const float *c, int stride, int n, int kk) {
     uint32_t taken = 0;
     float sum = 0.f;
@@ -770,7 +806,7 @@ __device__ __forceinline__ float mean_k_lowest(const float *c, int stride, int n
         float bv = 0.f;
         for (int j = 0; j < n; ++j) {
             if ((taken >> j) & 1u) continue;
-            const float v = c[j * stride];
+            const float v = weighted_cost(c[j * stride]);
             if (bj < 0 || v < bv) { bj = j; bv = v; }
         }
         taken |= 1u << bj;
@@ -837,6 +873,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     }
     S.pl[tid] = pl;
     S.valid[tid] = valid ? 1 : 0;
+    if (lane == 0) S.nshort[wave] = 0u;
     __syncthreads();
 
     // (2) reference window, split over the 9 lanes of the pixel
@@ -855,10 +892,22 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     for (int j = 0; j < N; ++j) {
         float c = 2.f;
         if (valid) {
-            c = q.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : 2.f;
+            c = q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort;
             ++n_prop;
         }
         mcol[j * 64 + lane] = c;
+    }
+    // short evaluations were stored as kShort: counted and set to 2 from LDS after the loop, so that
+    // the loop itself carries no counter
+    if (valid) {
+        unsigned ns = 0;
+        for (int j = 0; j < N; ++j) {
+            if (mcol[j * 64 + lane] < 0.f) {
+                ++ns;
+                mcol[j * 64 + lane] = 2.f;
+            }
+        }
+        if (ns) atomicAdd(&S.nshort[wave], ns);
     }
     __syncthreads();
 
@@ -1021,20 +1070,26 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                 const int j = act[qi - c * nw];
                 const float4 cp = cand[c];
                 const PlaneQ cq = plane_q(a.ref, m, cp, x, y);
-                const float cost = cq.ok ? ncc_cost<HALF>(a.views[j], rw, ws, x, y, cq.q0, cq.qu, cq.qv) : 2.f;
+                // kShort stays in the stored product (wgt > 0 on active views): counted after the loop
+                const float cost = cq.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, cq.q0, cq.qu, cq.qv) : kShort;
                 res[qi] = wgt[j] * cost;
                 ++n_ref;
             }
         }
         __syncthreads();
         if (pix_ok) {
+            if (row == 0) {
+                unsigned ns = 0;
+                for (int i = 0; i < pairs; ++i) ns += res[i] < 0.f;
+                if (ns) atomicAdd(&S.nshort[wave], ns);
+            }
             for (int c = 0; c < ncand; ++c) {
                 float cc;
                 if (heur) {
                     cc = mean_k_lowest(res + c * nw, 1, nw, min(m.k, nw));
                 } else {
                     float acc = 0.f;
-                    for (int i = 0; i < nw; ++i) acc += res[c * nw + i];
+                    for (int i = 0; i < nw; ++i) acc += weighted_cost(res[c * nw + i]);
                     cc = acc / wsum;
                 }
                 if (cc < bcost) {
@@ -1054,6 +1109,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     }
     count_evals(a.counters, 1, (unsigned long long)n_prop);
     if (m.refine) count_evals(a.counters, 2, (unsigned long long)n_ref);
+    // the wave's own LDS atomics are complete before this read (LDS operations of a wave are in order)
+    count_evals(a.counters, 4, lane == 0 ? (unsigned long long)S.nshort[wave] : 0ull);
 }
 
 // ---------------------------------------------------------------------------

@@ -13,6 +13,7 @@ import sys
 
 import numpy as np
 import pytest
+from short_predicate import short_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -211,6 +212,57 @@ def test_single_pass_without_self_row(amh, oracle_mod, scene_c1):
     say("case pass include_self=0")
     _pass_parity(amh, oracle_mod, scene_c1, 0, 0, seed=2, refine=0, include_self=0)
 
+
+
+def test_short_evaluation_counters(amh, oracle_mod, scene_c1):
+    """evals_init_short / evals_short count the evaluations whose cost was decided before sampling:
+    compared with the same predicate evaluated on the planes the oracle's pass actually scores."""
+    say("case short-evaluation counters c1")
+    sc, O = scene_c1, oracle_mod
+    Wd, Hd, n = sc.width, sc.height, len(sc.srcs)
+    with make_ctx(amh, sc, refine=0, seed=5) as ctx:
+        ctx.begin(0, list(range(1, n + 1)))
+        ctx.init_hypotheses()
+        s_init = ctx.get_stats()
+        pl_init, _, _, _ = ctx.get_state()
+        ctx.pass_(0, 0)
+        ctx.pass_(0, 1)
+        s0 = ctx.get_stats()
+        pl0, c0, S0, v0 = ctx.get_state()
+        ctx.pass_(1, 0)
+        s1 = ctx.get_stats()
+    ys, xs = np.mgrid[0:Hd, 0:Wd]
+    xy = np.c_[xs.ravel(), ys.ravel()]
+    want_init = int(short_mask(sc, xy, pl_init.reshape(-1, 4), 2.0, 6.0).sum())
+    say(f"  init: gpu {s_init['evals_init_short']} of {s_init['evals_init']}, predicate {want_init}")
+    assert s_init["evals_init"] == Wd * Hd * n
+    assert abs(s_init["evals_init_short"] - want_init) <= 2 + 0.002 * want_init
+    # the pass at t = 1, colour 0: rows of every pixel as the oracle forms them from the same state
+    V = O.Views(sc.images, sc.cams)
+    P = O.Params(refine=0, seed=5)
+    st = O.State.from_arrays(pl0, c0, S0, v0)
+    order = np.array([i for i in range(Wd * Hd) if ((i % Wd) + (i // Wd)) % 2 == 0], np.int32)
+    dg = O.run_pass(V, P, st, 1, 0, order=order, diag=True)
+    odx, ody, _ = O.acp_offsets()
+    flat_pl = pl0.reshape(-1, 4)
+    rows_xy, rows_pl = [], []
+    for q, d in zip(order, dg):
+        x, y = q % Wd, q // Wd
+        for r in range(8):
+            if d.row_valid[r]:
+                ci = d.cand_index[r]
+                rows_xy.append((x, y))
+                rows_pl.append(flat_pl[(y + ody[ci]) * Wd + x + odx[ci]])
+        if d.row_valid[8]:
+            rows_xy.append((x, y))
+            rows_pl.append(flat_pl[q])
+    want = int(short_mask(sc, np.array(rows_xy), np.array(rows_pl), 2.0, 6.0).sum())
+    got = s1["evals_short"] - s0["evals_short"]
+    evals = s1["evals_propagation"] - s0["evals_propagation"]
+    say(f"  pass: gpu {got} short of {evals}, predicate {want} of {len(rows_xy) * n}")
+    assert evals == len(rows_xy) * n
+    assert abs(got - want) <= 2 + 0.002 * want
+    assert 0 < got < evals
 
 
 # ablation modes of Sec. 4 (symmetric propagation, heuristic best-k view selection), same bars

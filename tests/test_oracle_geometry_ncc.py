@@ -232,3 +232,26 @@ def test_squared_bilateral_weights_match_weighted_cov(oracle_mod):
     c = np.cov(np.stack([window(ref2, 8, 8), b]), aweights=w, bias=True)
     assert oracle_mod.matching_cost(V, P, 8, 8, pl, 0) == pytest.approx(1.0 - c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]),
                                                                        abs=1e-12)
+
+
+def test_short_predicate_matches_oracle_early_exits():
+    """The predicate used to check the library's short-evaluation counters marks exactly the evaluations that
+    the oracle ends with cost 2 on its range and visibility tests (R3); on random initial planes of the
+    128x96 scene every other evaluation reaches the NCC (none here has a flat window)."""
+    import oracle as O
+    import scenegen
+    from short_predicate import short_mask
+    sc = scenegen.config_scene("c1", seed=0)
+    V = O.Views(sc.images, sc.cams)
+    P = O.Params(seed=5, refine=0)
+    st = O.init(V, P)
+    ys, xs = np.mgrid[0:sc.height, 0:sc.width]
+    xy = np.c_[xs.ravel(), ys.ravel()]
+    pl = st.plane.reshape(-1, 4)
+    m = short_mask(sc, xy, pl, P.d_min, P.d_max)
+    assert 0.02 < m.mean() < 0.3
+    idx = np.random.default_rng(0).choice(len(xy), 400, replace=False)
+    for i in idx:
+        for j in range(len(sc.srcs)):
+            c = O.matching_cost(V, P, int(xy[i, 0]), int(xy[i, 1]), pl[i], j)
+            assert (c == 2.0) == bool(m[i, j]), (xy[i], j, c)
