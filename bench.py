@@ -44,7 +44,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2444876.9, "write_kib": 312666.8},
                                  4: {"fetch_kib": 1566426.7, "write_kib": 289149.4}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "89ee28dc9026304e62dd5a569ea226ab7a45305f0c39d3808e52959f01482992"}
+                "kernel_sha256": "00bf6e7328cec32eedf064f47c1f041a8964e9ab23fe8f2d79d4db8c9927243e"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

@@ -23,8 +23,9 @@
 // 512 / waves VGPRs).  The single-image half-pass fits 128 VGPRs (4 waves per
 // SIMD) with a 20-byte spill and runs 8 % faster there than at its natural 132
 // (3 waves): 4.60 vs 5.02 ms per half-pass on the 1920x1280 / 10-source
-// workload.  The batched kernel and the ablation build spill 56-120 bytes at
-// that budget and stay at 2 (~150 VGPRs, 3 waves).
+// workload.  The batched half-pass uses the same budget (28-byte spill); the
+// batched initialisation and the ablation build spill 56-120 bytes at that
+// budget and stay at 2 (~150 VGPRs, 3 waves).
 #ifndef AMH_PASS_WAVES_PER_EU
 #define AMH_PASS_WAVES_PER_EU 4
 #endif
