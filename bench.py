@@ -41,10 +41,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2444876.9, "write_kib": 312666.8},
-                                 4: {"fetch_kib": 1566426.7, "write_kib": 289149.4}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2447019.2, "write_kib": 312812.1},
+                                 4: {"fetch_kib": 1568668.5, "write_kib": 289050.3}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "00bf6e7328cec32eedf064f47c1f041a8964e9ab23fe8f2d79d4db8c9927243e"}
+                "kernel_sha256": "e85ca77813d63d110e1cd854d641c1fdaf2c0f36e47b59ac1830c9c8f0b7ef50"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

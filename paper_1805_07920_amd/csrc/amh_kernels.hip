@@ -712,24 +712,35 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation of one colour with one lane per (pixel, source): a
-// workgroup holds G = min(64, 256 / N) pixels of the colour in row-major order
-// x N lanes, so nearly every lane evaluates (the tiled body above leaves most
-// lanes of its second round idle when N is not a multiple of 9).  The N lanes
+// Initialisation of one colour with L = ceil(N / 2) lanes per pixel, each
+// scoring two sources (j and j + L): a workgroup holds G = min(64, 256 / L)
+// pixels of the colour in row-major order x L lanes, so nearly every lane
+// evaluates (the tiled body above leaves most lanes of its second round idle
+// when N is not a multiple of 9), and the per-pixel work every lane repeats
+// (window block, random plane) is spread over two evaluations.  The L lanes
 // of a pixel build its window block together, score the same plane on their
 // sources, and the pixel's first lane takes the mean of the k lowest costs.
 // Same arithmetic as init_body, so the two give identical states.
 // ---------------------------------------------------------------------------
 constexpr int kInitMaxPix = 64;
+constexpr int kInitViewsPerLane = 2;
+
+__host__ __device__ inline int init_lanes_per_pixel(int n_src) {
+    return (n_src + kInitViewsPerLane - 1) / kInitViewsPerLane;
+}
+__host__ __device__ inline int init_pixels_per_group(int n_src) {
+    const int g = 256 / init_lanes_per_pixel(n_src);
+    return g < kInitMaxPix ? g : kInitMaxPix;
+}
 
 template <int HALF>
 __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
     __shared__ __align__(16) float2 rwbuf[kInitMaxPix * kWinStride];
-    __shared__ float cst[256];
+    __shared__ float cst[256 * kInitViewsPerLane];  // G * N <= 256 * N / ceil(N / 2) <= 512
     __shared__ unsigned nshort;
     const int N = a.n_src;
-    const int G = min(kInitMaxPix, 256 / N);
-    const int t = threadIdx.x, g = t / N, j = t - g * N;
+    const int Lp = init_lanes_per_pixel(N), G = init_pixels_per_group(N);
+    const int t = threadIdx.x, g = t / Lp, j = t - g * Lp;
     const bool lane_ok = g < G;
     const int per_row = (a.ref.W + 1) / 2;  // slots per row; x beyond the image is skipped
     const long long pc = (long long)blockIdx.x * G + g;
@@ -740,7 +751,7 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
     WinStats ws = {1.f, 0.f};
     if (pix_ok) {
         GlobalReader rd{&a.ref, x, y};
-        ws = build_window(rd, a.m, rw, j, N);
+        ws = build_window(rd, a.m, rw, j, Lp);
     }
     if (t == 0) nshort = 0u;
     __syncthreads();
@@ -757,10 +768,11 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
             pl = plane_from(r, depth, nx, ny, nz);
         }
         const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
-        cst[t] = short_to_cost(q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort,
-                               &nshort);
+        for (int v = j; v < N; v += Lp)
+            cst[g * N + v] = short_to_cost(
+                q.ok ? ncc_cost_raw<HALF>(a.views[v], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort, &nshort);
     }
-    count_evals(a.counters, 0, pix_ok ? 1ull : 0ull);
+    count_evals(a.counters, 0, pix_ok ? (unsigned long long)((N - j + Lp - 1) / Lp) : 0ull);
     if (a.prop) count_evals(a.counters, 3, (fell_back && j == 0) ? 1ull : 0ull);
     __syncthreads();
     count_evals(a.counters, 5, t == 0 ? (unsigned long long)nshort : 0ull);
@@ -1435,7 +1447,7 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
-    const int G = std::min(kInitMaxPix, 256 / a.n_src);
+    const int G = init_pixels_per_group(a.n_src);
     const long long slots = (long long)a.ref.H * ((a.ref.W + 1) / 2);
     const dim3 grid((unsigned)((slots + G - 1) / G));
     if (half) AMH_LAUNCH(init_pix_kernel<1>, grid, dim3(256), 0, s, a);
