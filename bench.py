@@ -44,7 +44,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2447019.2, "write_kib": 312812.1},
                                  4: {"fetch_kib": 1568668.5, "write_kib": 289050.3}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "e85ca77813d63d110e1cd854d641c1fdaf2c0f36e47b59ac1830c9c8f0b7ef50"}
+                "kernel_sha256": "c235d0368e74ba914e4146e20917892637316dc028804024f2d1da223d929fb8"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

@@ -712,12 +712,14 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation of one colour with L = ceil(N / 2) lanes per pixel, each
-// scoring two sources (j and j + L): a workgroup holds G = min(64, 256 / L)
-// pixels of the colour in row-major order x L lanes, so nearly every lane
-// evaluates (the tiled body above leaves most lanes of its second round idle
-// when N is not a multiple of 9), and the per-pixel work every lane repeats
-// (window block, random plane) is spread over two evaluations.  The L lanes
+// Initialisation of one colour with L lanes per pixel, lane j scoring sources
+// j, j + L, ...: L = ceil(N / 2) (two sources per lane), but at least
+// min(N, 4) so that 64 pixels still fill the 256 lanes.  A workgroup holds
+// G = min(64, 256 / L) pixels of the colour in row-major order x L lanes, so
+// nearly every lane evaluates (the tiled body above leaves most lanes of its
+// second round idle when N is not a multiple of 9), and the per-pixel work
+// every lane repeats (window block, random plane) is spread over up to two
+// evaluations.  The L lanes
 // of a pixel build its window block together, score the same plane on their
 // sources, and the pixel's first lane takes the mean of the k lowest costs.
 // Same arithmetic as init_body, so the two give identical states.
@@ -726,7 +728,8 @@ constexpr int kInitMaxPix = 64;
 constexpr int kInitViewsPerLane = 2;
 
 __host__ __device__ inline int init_lanes_per_pixel(int n_src) {
-    return (n_src + kInitViewsPerLane - 1) / kInitViewsPerLane;
+    const int l = (n_src + kInitViewsPerLane - 1) / kInitViewsPerLane, fill = 256 / kInitMaxPix;
+    return l >= fill ? l : (n_src < fill ? n_src : fill);
 }
 __host__ __device__ inline int init_pixels_per_group(int n_src) {
     const int g = 256 / init_lanes_per_pixel(n_src);
@@ -736,7 +739,7 @@ __host__ __device__ inline int init_pixels_per_group(int n_src) {
 template <int HALF>
 __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
     __shared__ __align__(16) float2 rwbuf[kInitMaxPix * kWinStride];
-    __shared__ float cst[256 * kInitViewsPerLane];  // G * N <= 256 * N / ceil(N / 2) <= 512
+    __shared__ float cst[256 * kInitViewsPerLane];  // G * N <= 512 for every N (G <= 64, G * L <= 256)
     __shared__ unsigned nshort;
     const int N = a.n_src;
     const int Lp = init_lanes_per_pixel(N), G = init_pixels_per_group(N);
