@@ -132,6 +132,31 @@ def test_init_matches_oracle(amh, oracle_mod, scene_c1):
     assert st["evals_init"] == sc.width * sc.height * 4
 
 
+@pytest.mark.parametrize("n", [1, 5, 8, 9, 17, 32])
+def test_init_matches_oracle_source_counts(amh, oracle_mod, n):
+    """Initialisation with 1, 5, 8, 9, 17 and 32 sources: every mapping of sources to the lanes of a pixel
+    (one per lane, two per lane for some or all lanes, 16 lanes per pixel), on a ragged 61x37 image."""
+    say("case init n", n)
+    import scenegen
+
+    O = oracle_mod
+    sc = scenegen.make_scene(61, 37, n, 40.0, 2, seed=20 + n, supersample=1)
+    with make_ctx(amh, sc, seed=13) as ctx:
+        ctx.begin(0, list(range(1, n + 1)))
+        ctx.init_hypotheses()
+        pl, cost, S, v = ctx.get_state()
+        st = ctx.get_stats()
+    ost = O.init(O.Views.from_scene(sc), O.Params(seed=13))
+    assert np.all(S == 0) and np.all(v == -1)
+    np.testing.assert_allclose(pl, ost.plane, atol=2e-5, rtol=2e-5)
+    d = np.abs(cost - ost.cost)
+    assert (d <= 1e-4).mean() >= 0.999
+    assert st["evals_init"] == sc.width * sc.height * n
+    ys, xs = np.mgrid[0:sc.height, 0:sc.width]
+    want = int(short_mask(sc, np.c_[xs.ravel(), ys.ravel()], pl.reshape(-1, 4), 2.0, 6.0).sum())
+    assert abs(st["evals_init_short"] - want) <= 2 + 0.002 * want
+
+
 def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1, sym_prop=0, heuristic=0,
                  bil_sq=0, delta=1e-5, ctol=1e-4, min_plane=0.99):
     n = len(sc.srcs) if n_src is None else n_src
