@@ -41,10 +41,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2447019.2, "write_kib": 312812.1},
-                                 4: {"fetch_kib": 1568668.5, "write_kib": 289050.3}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2422867.4, "write_kib": 298150.7},
+                                 4: {"fetch_kib": 1547035.3, "write_kib": 276597.1}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "c235d0368e74ba914e4146e20917892637316dc028804024f2d1da223d929fb8"}
+                "kernel_sha256": "7a108abf206868c00de9e56b9767ab861de9ffc88ae3a62163a281fb1f316066"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

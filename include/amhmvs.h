@@ -32,7 +32,8 @@
  *     stream-ordered and return without waiting.
  *   - A context is used by one host thread at a time.
  *   - Limits: 1..32 sources per reference (the view-selection set is a 32-bit
- *     mask); images up to 16383 x 16383 (the gather layout of one image stays below 4 GiB).
+ *     mask); images up to 16351 x 16351 (the gather layout of one image, with its
+ *     border of 16 texels, stays within 4 GiB).
  */
 #ifndef AMHMVS_H
 #define AMHMVS_H

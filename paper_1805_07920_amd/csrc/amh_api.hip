@@ -566,8 +566,9 @@ amh_status amh_init_views(amh_ctx *c, int n_views, const amh_image *views, const
     for (int i = 0; i < n_views; ++i) {
         const amh_image &im = views[i];
         if (!im.data) return fail(c, AMH_E_INVALID_ARG, "view %d: data is NULL", i);
-        if (im.width < 1 || im.height < 1 || im.width > 16383 || im.height > 16383)
-            return fail(c, AMH_E_INVALID_ARG, "view %d: size %dx%d outside 1..16383", i, im.width, im.height);
+        if (im.width < 1 || im.height < 1 || im.width > kMaxImageSide || im.height > kMaxImageSide)
+            return fail(c, AMH_E_INVALID_ARG, "view %d: size %dx%d outside 1..%d", i, im.width, im.height,
+                        kMaxImageSide);
         if (im.pitch_elems < im.width) return fail(c, AMH_E_INVALID_ARG, "view %d: pitch < width", i);
         if (im.dtype != AMH_F32 && im.dtype != AMH_F16) return fail(c, AMH_E_INVALID_ARG, "view %d: bad dtype", i);
         if (im.on_device != 0 && im.on_device != 1) return fail(c, AMH_E_INVALID_ARG, "view %d: on_device is 0/1", i);
@@ -599,7 +600,7 @@ amh_status amh_init_views(amh_ctx *c, int n_views, const amh_image *views, const
         memcpy(v.R, cams[i].R, sizeof v.R);
         memcpy(v.t, cams[i].t, sizeof v.t);
         const size_t px = (size_t)v.W * v.H;
-        const size_t qbytes = (size_t)(v.W + 1) * (v.H + 1) * (c->half ? 8 : 16);
+        const size_t qbytes = (size_t)(v.W + 1 + 2 * kQuadPad) * (v.H + 1 + 2 * kQuadPad) * (c->half ? 8 : 16);
         if (i < (int)old.size() && old[i].W == v.W && old[i].H == v.H && old[i].half == v.half && old[i].img) {
             v.img = old[i].img;
             v.quads = old[i].quads;

@@ -7,6 +7,11 @@
 namespace amh {
 
 constexpr int kMaxSrc = 32;
+// Border of the sources' gather layout: kQuadPad extra texel quads on every side, holding the clamped footprint
+// (a window that crosses the image edge by up to kQuadPad texels reads the values clamping would give, without
+// clamping).  Images are limited to kMaxImageSide so that the layout's byte offsets stay below 2^32.
+constexpr int kQuadPad = 16;
+constexpr int kMaxImageSide = 16383 - 2 * kQuadPad;
 constexpr int kCounterSlots = 256;    // eval counters are spread over slots to avoid one hot atomic
 constexpr int kCounterKinds = 6;      // init, propagation, refinement evaluations; proposal fallbacks;
                                        // short evaluations (no samples taken) of the half-pass and of init

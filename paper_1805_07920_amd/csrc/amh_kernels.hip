@@ -90,9 +90,11 @@ __device__ __forceinline__ void region_offset(int r, int e, int &dx, int &dy) {
 }
 
 // ---------------------------------------------------------------------------
-// Texel quads: entry (y0 + 1, x0 + 1) of a (H+1) x (W+1) array describes the
-// bilinear footprint with top-left texel (x0, y0), indices clamped to the
-// image, so one 16-byte (or 8-byte) load serves a sample.
+// Texel quads: entry (y0 + 1 + P, x0 + 1 + P) of a (H+1+2P) x (W+1+2P) array
+// (P = kQuadPad) describes the bilinear footprint with top-left texel (x0, y0),
+// x0 in [-1-P, W-1+P], indices clamped to the image, so one 16-byte (or
+// 8-byte) load serves a sample, and a sample up to P texels outside the image
+// reads what clamping its indices would read.
 //   float32: the bilinear coefficients (a, b - a, c - a, a - b - c + d) of the
 //            texels a = (x0,y0), b = (x0+1,y0), c = (x0,y0+1), d = (x0+1,y0+1),
 //            so a sample is a + fx (b - a) + fy ((c - a) + fx (a - b - c + d)):
@@ -199,7 +201,7 @@ __device__ __forceinline__ void issue_row(const void *quads, float vf, float N0x
         const int yr = CLAMP ? med3i(cvt_floor(dy), ylo, yhi) : cvt_floor(dy);
         fxs[su] = __builtin_amdgcn_fractf(dx);
         fys[su] = __builtin_amdgcn_fractf(dy);
-        // modulo-2^32 arithmetic; the true offset is in [0, (W+1)(H+1) * entry) < 2^32
+        // modulo-2^32 arithmetic; the true offset is in [0, (W+1+2P)(H+1+2P) * entry) <= 2^32
         const uint32_t off = (uint32_t)__mul24(yr, row_bytes) + (uint32_t)base + (uint32_t)xr * kEntry;
         qd[su] = load_quad<HALF>(quads, off);
     }
@@ -387,20 +389,22 @@ __device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *_
     // texel indices relative to (ix, iy), clamped to [-1, W-1] x [-1, H-1] in absolute terms;
     // byte offset = base + yrel * row_bytes + xrel * entry_bytes (non-negative after clamping)
     constexpr int kEntry = HALF ? 8 : 16;
-    const int row_bytes = (W + 1) * kEntry;
+    const int row_bytes = (W + 1 + 2 * kQuadPad) * kEntry;
     const int xlo = -1 - ix, xhi = W - 1 - ix, ylo = -1 - iy, yhi = H - 1 - iy;
-    const int base = ((iy + 1) * (W + 1) + (ix + 1)) * kEntry;
+    const int base = ((iy + 1 + kQuadPad) * (W + 1 + 2 * kQuadPad) + (ix + 1 + kQuadPad)) * kEntry;
     // Clamp-free fast path: the samples lie in the convex image of the window square (the depth is
     // positive at its corners, so the warp has no pole inside), hence |dx| <= (|N0x| + 5 |pux| + 5 |pvx|)
     // / min corner depth, likewise dy.  When that bound (widened by 1 % + 0.01 px, far above the float
     // rounding of the samples once the min depth exceeds 1e-3 of the centre's) keeps every texel index
-    // inside the clamp range, the clamps are no-ops and are skipped: the same offsets, the same result.
+    // inside the layout (the clamp range widened by its border), the clamps are skipped: inside the clamp
+    // range they change nothing, and the border holds the clamped footprint: the same values, the same result.
     const float zmin = fminf(fminf(zc0, zc1), fminf(zc2, zc3));
     const float rzm = __builtin_amdgcn_rcpf(zmin);
     const float bx = fmaf(fmaf(5.f, fabsf(pux) + fabsf(pvx), fabsf(N0x)) * rzm, 1.01f, 0.01f);
     const float by = fmaf(fmaf(5.f, fabsf(puy) + fabsf(pvy), fabsf(N0y)) * rzm, 1.01f, 0.01f);
-    const bool interior = zmin > 1e-3f * Z0 && bx <= (float)(ix + 1) && bx < (float)(W - ix) &&
-                          by <= (float)(iy + 1) && by < (float)(H - iy);
+    // (the border of the layout extends the clamp-free range by kQuadPad texels on every side)
+    const bool interior = zmin > 1e-3f * Z0 && bx <= (float)(ix + 1 + kQuadPad) && bx < (float)(W - ix + kQuadPad) &&
+                          by <= (float)(iy + 1 + kQuadPad) && by < (float)(H - iy + kQuadPad);
     float m2, cab;
     if (interior)
         window_moments<HALF, false>(quads, rw, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
@@ -1377,13 +1381,13 @@ __global__ void convert_kernel(const void *src, int dtype, int64_t pitch, int W,
 }
 
 __global__ void pack_quads_kernel(const float *img, int W, int H, void *quads, int half) {
-    const int xx = blockIdx.x * blockDim.x + threadIdx.x, yy = blockIdx.y;  // 0..W, 0..H
-    if (xx > W || yy > H) return;
-    const int x0 = min(max(xx - 1, 0), W - 1), x1 = min(max(xx, 0), W - 1);
-    const int y0 = min(max(yy - 1, 0), H - 1), y1 = min(max(yy, 0), H - 1);
+    const int xx = blockIdx.x * blockDim.x + threadIdx.x, yy = blockIdx.y;  // 0..W+2P, 0..H+2P
+    if (xx > W + 2 * kQuadPad || yy > H + 2 * kQuadPad) return;
+    const int x0 = min(max(xx - 1 - kQuadPad, 0), W - 1), x1 = min(max(xx - kQuadPad, 0), W - 1);
+    const int y0 = min(max(yy - 1 - kQuadPad, 0), H - 1), y1 = min(max(yy - kQuadPad, 0), H - 1);
     const float a = img[(size_t)y0 * W + x0], b = img[(size_t)y0 * W + x1];
     const float c = img[(size_t)y1 * W + x0], d = img[(size_t)y1 * W + x1];
-    const size_t i = (size_t)yy * (W + 1) + xx;
+    const size_t i = (size_t)yy * (W + 1 + 2 * kQuadPad) + xx;
     if (!half) {
         // bilinear coefficients, each rounded once from its exact double value
         const double da = a, db = b, dc = c, dd = d;
@@ -1437,7 +1441,7 @@ hipError_t launch_convert_to_f32(const void *src, int src_dtype, int64_t pitch, 
 }
 
 hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int half, hipStream_t s) {
-    dim3 grid((W + 1 + 255) / 256, H + 1);
+    dim3 grid((W + 1 + 2 * kQuadPad + 255) / 256, H + 1 + 2 * kQuadPad);
     AMH_LAUNCH(pack_quads_kernel, grid, dim3(256), 0, s, img, W, H, quads, half);
     return hipGetLastError();
 }

@@ -461,4 +461,14 @@ def test_errors_on_device(amh, scene_c1):
     bad = [np.zeros((4, 4), np.float32)]
     with pytest.raises(amh.AmhError):
         ctx.init_views(bad, sc.cams[:1])  # camera size differs from the image
+    # the widest image the 32-bit gather offsets allow (16351 with the layout's 16-texel border), and one more
+    import dataclasses
+    for w, ok in ((16352, False), (16351, True)):
+        cam = dataclasses.replace(sc.cams[0], width=w, height=2)
+        if ok:
+            ctx.init_views([np.zeros((2, w), np.float32)], [cam])
+        else:
+            with pytest.raises(amh.AmhError) as e:
+                ctx.init_views([np.zeros((2, w), np.float32)], [cam])
+            assert e.value.status == amh.AMH_E_INVALID_ARG
     ctx.close()
