@@ -44,7 +44,7 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2422867.4, "write_kib": 298150.7},
                                  4: {"fetch_kib": 1547035.3, "write_kib": 276597.1}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "7a108abf206868c00de9e56b9767ab861de9ffc88ae3a62163a281fb1f316066"}
+                "kernel_sha256": "479537f6b6100ad617189a973be1fd805e3903653240dde084592c3c0a589fbb"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

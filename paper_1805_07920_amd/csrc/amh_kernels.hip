@@ -723,10 +723,10 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
 // nearly every lane evaluates (the tiled body above leaves most lanes of its
 // second round idle when N is not a multiple of 9), and the per-pixel work
 // every lane repeats (window block, random plane) is spread over up to two
-// evaluations.  The L lanes
-// of a pixel build its window block together, score the same plane on their
-// sources, and the pixel's first lane takes the mean of the k lowest costs.
-// Same arithmetic as init_body, so the two give identical states.
+// evaluations.  The L lanes of a pixel build its window block together, score
+// the same plane on their sources, and the pixel's first lane takes the mean
+// of the k lowest costs.  Same arithmetic as init_body, so the two give
+// identical states.
 // ---------------------------------------------------------------------------
 constexpr int kInitMaxPix = 64;
 constexpr int kInitViewsPerLane = 2;
