@@ -115,6 +115,54 @@ def test_score_fixed_matches_oracle(amh, oracle_mod, key):
     assert np.all(np.isfinite(got))
 
 
+def _centre_in_source(sc, xy, planes):
+    """[M, N, 2] position of each window centre in each source (camera conventions of the scenes)."""
+    ref = sc.cams[0]
+    pl = planes.astype(np.float64)
+    r = np.linalg.solve(ref.K, np.c_[xy.astype(np.float64), np.ones(len(xy))].T).T
+    q = -np.einsum("ij,ij->i", pl[:, :3], r) / pl[:, 3]
+    out = []
+    for cam in sc.cams[1:]:
+        R_rel = cam.R @ ref.R.T
+        h = r @ (cam.K @ R_rel).T + q[:, None] * (cam.K @ (cam.t - R_rel @ ref.t))
+        out.append(h[:, :2] / h[:, 2:3])
+    return np.stack(out, axis=1)
+
+
+def test_score_fixed_windows_crossing_source_edges(amh, oracle_mod, scene_c1):
+    """Windows whose centre lies within 6 px inside a source's edge read texels beyond it: through the
+    gather layout's clamped border (up to 16 texels) or the clamped path.  Their costs must equal the
+    oracle's, which clamps every texel index."""
+    say("case score_fixed near source edges")
+    sc, O = scene_c1, oracle_mod
+    rng = np.random.default_rng(4)
+    W, H, n = sc.width, sc.height, len(sc.srcs)
+    pix = [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(4000)]
+    planes = np.concatenate([gt_planes(sc, pix, 0.01, rng), random_planes(sc, pix, rng)])
+    xy = np.array(pix * 2, np.int32)
+    c = _centre_in_source(sc, xy, planes)
+    Ws = np.array([cam.width for cam in sc.cams[1:]]) - 1
+    Hs = np.array([cam.height for cam in sc.cams[1:]]) - 1
+    inside = (c[..., 0] >= 0) & (c[..., 0] <= Ws) & (c[..., 1] >= 0) & (c[..., 1] <= Hs)
+    edge = np.minimum(np.minimum(c[..., 0], Ws - c[..., 0]), np.minimum(c[..., 1], Hs - c[..., 1]))
+    near = inside & (edge < 6.0)
+    sel = np.nonzero(near.any(axis=1))[0][:400]
+    assert len(sel) >= 100
+    with make_ctx(amh, sc) as ctx:
+        ctx.begin(0, list(range(1, n + 1)))
+        got = ctx.score_fixed(planes[sel], xy[sel])
+    V = O.Views.from_scene(sc)
+    P = O.Params()
+    want = np.array([[O.matching_cost(V, P, int(x), int(y), pl.astype(np.float64), j) for j in range(n)]
+                     for (x, y), pl in zip(xy[sel], planes[sel])])
+    m = near[sel] & (want < 2)
+    err = np.abs(got - want)
+    say(f"  {int(m.sum())} scored evaluations near an edge, max err {err[m].max():.2e}")
+    assert m.sum() >= 100
+    assert err[m].max() <= 1e-4
+    assert ((want < 2) != (got < 2)).mean() < 1e-3
+
+
 def test_init_matches_oracle(amh, oracle_mod, scene_c1):
     say("case init c1")
     O = oracle_mod
