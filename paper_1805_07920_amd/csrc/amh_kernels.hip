@@ -1453,7 +1453,33 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 
 static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
+// Single-image initialisation with the tiled body of the batched launch (9 lanes per pixel, windows from the
+// LDS tile, the pass's tile order): with many sources its rounds of 9 sources fill the lanes well, and it is
+// faster than init_pix_kernel (6.6 vs 7.2 ms per launch at 3200x2130 with 20 sources); with few it is slower.
+template <int HALF, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_BATCH_WAVES_PER_EU)))
+void init_tile_kernel(PassArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = tile_of_block(a.n_tiles, a.order);
+    if (L < 0) return;
+    init_body<HALF, WAVES>(a, L, smem);
+}
+
+constexpr int kInitTiledFrom = 14;  // sources from which the tiled initialisation is used
+
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
+    if (a.n_src >= kInitTiledFrom && (a.waves == 2 || a.waves == 4)) {
+        const size_t lds = pass_lds_bytes(a.n_src, a.waves);
+        const dim3 grid(grid_for(a.n_tiles)), block(64 * a.waves);
+        if (a.waves == 2) {
+            if (half) AMH_LAUNCH((init_tile_kernel<1, 2>), grid, block, lds, s, a);
+            else AMH_LAUNCH((init_tile_kernel<0, 2>), grid, block, lds, s, a);
+        } else {
+            if (half) AMH_LAUNCH((init_tile_kernel<1, 4>), grid, block, lds, s, a);
+            else AMH_LAUNCH((init_tile_kernel<0, 4>), grid, block, lds, s, a);
+        }
+        return hipGetLastError();
+    }
     const int G = init_pixels_per_group(a.n_src);
     const long long slots = (long long)a.ref.H * ((a.ref.W + 1) / 2);
     const dim3 grid((unsigned)((slots + G - 1) / G));
