@@ -100,6 +100,8 @@ MethodDev method_dev(const amh_params &p, int t) {
     m.sym_prop = p.sym_prop;
     m.heuristic = p.heuristic_views;
     m.bil_sq = p.bilateral_squared;
+    m.q_lo = 1.0 / ((double)p.depth_max * (1.0 + 1e-5));
+    m.q_hi = 1.0 / ((double)p.depth_min * (1.0 - 1e-5));
     return m;
 }
 

@@ -48,6 +48,7 @@ struct MethodDev {
     uint64_t seed;
     int sym_prop, heuristic;     // ablation switches (symmetric propagation, heuristic views)
     int bil_sq;                  // squared colour difference and distance in the bilateral weight
+    double q_lo, q_hi;           // inverse depths of d_max (1 + 1e-5) and d_min (1 - 1e-5): the range test
 };
 
 struct StateDev {

@@ -440,12 +440,13 @@ __device__ __forceinline__ PlaneQ plane_q(const RefDev &ref, const MethodDev &m,
     const double nr = (double)pl.x * rx + (double)pl.y * ry + (double)pl.z;
     const double d = (double)pl.w;
     PlaneQ q;
-    const double depth = -d / nr;
-    // range test with a relative tolerance of 1e-5: refinement clamps depths to the ends of the
-    // range, and the plane rebuilt from a clamped depth must not fail on its last bit
-    q.ok = depth > 0.0 && depth >= (double)m.d_min * (1.0 - 1e-5) && depth <= (double)m.d_max * (1.0 + 1e-5);
-    q.q0 = -nr / d;
-    const float invd = (float)(-1.0 / d);
+    const double inv_d = -1.0 / d;  // the one division: q0 = -nr / d is the inverse depth at the pixel
+    q.q0 = nr * inv_d;
+    // range test on the inverse depth, with a relative tolerance of 1e-5 on the depth (refinement clamps
+    // depths to the ends of the range, and the plane rebuilt from a clamped depth must not fail on its last
+    // bit); q_lo > 0, so a depth behind the camera fails too
+    q.ok = q.q0 >= m.q_lo && q.q0 <= m.q_hi;
+    const float invd = (float)inv_d;
     q.qu = (float)(pl.x * ref.kinv_a) * invd;
     q.qv = (float)(pl.x * ref.kinv_b + pl.y * ref.kinv_e) * invd;
     // every window sample's ray must meet the plane in front of the camera: the inverse depth is
