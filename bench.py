@@ -41,10 +41,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2317905.1, "write_kib": 90206.0},
-                                 4: {"fetch_kib": 1390455.8, "write_kib": 88625.4}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2301421.3, "write_kib": 90234.0},
+                                 4: {"fetch_kib": 1395229.4, "write_kib": 88653.0}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "850a8737577ec079526be49a8a97480e57ab23469e8025e11d5b71ff204a33b2"}
+                "kernel_sha256": "6b3f05592743751ffd0c335540de336f51e2f028921a7efbef1639e61b7a3ea1"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the

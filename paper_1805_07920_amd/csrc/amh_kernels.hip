@@ -365,11 +365,15 @@ __device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *_
     const double P0y = fma(vw.A[4], (double)y, fma(vw.A[3], (double)x, vw.A[5])) + vw.b[1] * q0;
     const double P0z = fma(vw.A[7], (double)y, fma(vw.A[6], (double)x, vw.A[8])) + vw.b[2] * q0;
     if (!(P0z > 0.0)) return kShort;
-    const double rz = 1.0 / P0z;
-    const double cu = P0x * rz, cv = P0y * rz;
     const int W = vw.W, H = vw.H;
-    if (!(cu >= 0.0 && cu <= (double)(W - 1) && cv >= 0.0 && cv <= (double)(H - 1))) return kShort;
-    const int ix = (int)floor(cu), iy = (int)floor(cv);
+    // centre inside the source: 0 <= P0x / P0z <= W - 1 with P0z > 0, tested without a division
+    if (!(P0x >= 0.0 && P0x <= (double)(W - 1) * P0z && P0y >= 0.0 && P0y <= (double)(H - 1) * P0z))
+        return kShort;
+    // the texel the window is re-centred on need not be the exact floor of the centre: everything below is
+    // relative to it (N0 = P0 - (ix, iy) P0z in double, the bound on the sample offsets includes |N0|), so a
+    // float estimate serves; it lies in [-1, W - 1] x [-1, H - 1] (the estimate is a few 1e-3 px off at most)
+    const float rzf = __builtin_amdgcn_rcpf((float)P0z);
+    const int ix = (int)floorf((float)P0x * rzf), iy = (int)floorf((float)P0y * rzf);
     const float N0x = (float)(P0x - (double)ix * P0z);
     const float N0y = (float)(P0y - (double)iy * P0z);
     const float Z0 = (float)P0z;
