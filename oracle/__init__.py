@@ -6,8 +6,7 @@ the smoke check and the benchmark's CPU-baseline leg may import it; the GPU
 library neither imports nor links it, and this module imports nothing from
 the library.
 
-The C file's header lists which functions are pinned by the tests and which
-are "parity unpinned" (refinement, initial cost, empty-selection fallback).
+The C header lists which functions are pinned by the tests and by what.
 """
 from __future__ import annotations
 
@@ -19,19 +18,53 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_build", "liborc.so")
 MAX_SRC = 32
 N_OFFSETS = 72
+# gcc flags: optimised for the host it runs on, every floating-point operation rounded as written
+CFLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-std=gnu11", "-fopenmp"]
+
+
+def _host_tag() -> str:
+    """Short tag of this host's CPU (model and feature flags): a library built with -march=native
+    on one machine is never loaded on another."""
+    import hashlib
+
+    model = flags = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and not model:
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("flags") and not flags:
+                    flags = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return hashlib.sha1((model + "|" + flags).encode()).hexdigest()[:12]
+
+
+LIB_PATH = os.path.join(HERE, "_build", f"liborc-{_host_tag()}.so")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP over same-colour pixels)."""
+    """Compile the oracle with gcc for this host (OpenMP over same-colour pixels)."""
     os.makedirs(os.path.dirname(LIB_PATH), exist_ok=True)
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-o", LIB_PATH,
-           os.path.join(HERE, "amh_oracle.c"), "-lm"]
+    tmp = LIB_PATH + f".{os.getpid()}.tmp"
+    cmd = ["gcc", *CFLAGS, "-shared", "-fPIC", "-o", tmp, os.path.join(HERE, "amh_oracle.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
 
@@ -100,6 +133,7 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(_Views), C.POINTER(_Params), C.POINTER(_State), C.c_int]
         L.orc_depth_normal.argtypes = [C.POINTER(_Views), C.POINTER(_State), dp, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -302,3 +336,8 @@ def depth_normal(views: Views, state: State):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls (the CPU baseline's one-core figure)."""
+    lib().orc_set_num_threads(int(n))

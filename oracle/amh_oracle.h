@@ -19,10 +19,19 @@
  *   orc_scp_offsets        pinned (symmetry, colour and subset invariants)
  *   heuristic view mode    pinned (mean of the k lowest against numpy sorts; k >= N
  *                          equals the plain mean, k = 1 the minimum)
+ *   orc_random_plane       pinned (uniform depth on the range; direction uniform on
+ *                          the hemisphere facing the ray: Kolmogorov-Smirnov tests)
+ *   orc_init               pinned (mean of the min(k, N) lowest costs against a numpy
+ *                          sort; empty selection memory)
  *   orc_pass / orc_run     pinned by recovery of rendered ground truth, brute-force
- *                          plane sweep and order independence; the refinement step,
- *                          the initial cost and the empty-selection fallback are
- *                          readings the paper does not fix: parity unpinned.
+ *                          plane sweep and order independence; the empty-selection
+ *                          fallback by a hand-built matrix; refinement by the
+ *                          invariants of its candidates (counts, perturbation
+ *                          ranges reached and never exceeded, shared and fresh
+ *                          draws, clamping), Eq. 7 scoring on the weighted views
+ *                          and strict in-order acceptance (an exact-tie case).
+ *                          The refinement schedule itself is a reading (R13) of a
+ *                          step the paper defers to an earlier system.
  */
 #ifndef AMH_ORACLE_H
 #define AMH_ORACLE_H
@@ -100,5 +109,6 @@ void orc_pass(const orc_views *V, const orc_params *p, orc_state *s, int t, int 
 void orc_run(const orc_views *V, const orc_params *p, orc_state *s, int iters);
 void orc_depth_normal(const orc_views *V, const orc_state *s, double *depth, double *normal);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #endif
