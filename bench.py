@@ -28,11 +28,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "hypothesis·view NCC evals/s; sec per depth map at equal accuracy vs plain"
-# algorithmic VALU lane-operations per hypothesis x view evaluation (36 warped samples; the
-# breakdown is in the design notes): projective coordinates 3.5, reciprocal 4 (quarter rate),
-# perspective divide 2, floor/fraction 4, texel index 6, bilinear 6, two-pass moments 5 -> 30.5 per
-# sample, x 36 = 1098, + per-evaluation set-up and epilogue ~62
-OPS_PER_EVAL = 1160
+# Algorithmic VALU lane-operations per hypothesis x view evaluation (36 warped samples): per sample
+# 3 adds for the incremental projective coordinates, a reciprocal and 2 multiplies for the perspective
+# divide, 2 floors + 2 fractions + 2 conversions + ~3 address operations, 3 lerps (6), and the
+# shift-subtract, w*b and 3 moment accumulations (5) = 26; x 36, + ~20 for the epilogue (variances,
+# rsqrt, clamp) + ~15 for the warp from the plane -> ~950.  The roofline fraction is taken on this count.
+OPS_PER_EVAL = 950
+# What this implementation issues per evaluation, counted on its instruction stream: the reciprocal at
+# quarter rate (4 slots), 6 texel-index operations, the two-pass row moments and ~62 set-up and
+# epilogue slots -> 1160.  Reported beside the fraction as the issue-slot figure.
+ISSUE_SLOTS_PER_EVAL = 1160
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one VALU lane-operation per lane per clock
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # Bytes the half-pass kernel moves between L2 and memory per launch, from two rocprofv3 --pmc runs
@@ -84,40 +89,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sc, params_kw, gpu_state, budget_s=15.0):
-    """The oracle (as it stands) on a bounded sample: one red half-pass over a band of rows."""
+def cpu_baseline(sc, params_kw, state, budget_s=15.0):
+    """The oracle (as it stands) on a bounded sample: one red half-pass over a band of rows, from the
+    oracle's own initial state, on all host threads and on one."""
     import oracle as O
 
     O.build()
     V = O.Views.from_scene(sc)
     P = O.Params(**params_kw)
-    pl, cost, S, v = gpu_state
+    pl, cost, S, v = state
     W, H = sc.width, sc.height
     st = O.State.from_arrays(pl, cost, S, v)
 
     def band(y0, rows):
         return np.array([y * W + x for y in range(y0, y0 + rows) for x in range(W) if (x + y) % 2 == 0], np.int32)
 
-    # calibrate on a small band, then size the sample to the time budget
+    def timed_band(y0, rows):
+        order = band(y0, rows)
+        t0 = time.time()
+        dg = O.run_pass(V, P, st.copy(), 0, 0, order=order, diag=True)
+        el = time.time() - t0
+        n = V.n_src
+        evals = 0
+        for d in dg:
+            evals += sum(d.row_valid[r] for r in range(9)) * n
+            evals += d.n_cand * sum(1 for j in range(n) if d.w[j] > 0)
+        return len(order), evals, el
+
+    # calibrate on a small band, then size the sample to the time budget (all host threads)
+    threads = O.num_threads()
     y0 = H // 3
-    t0 = time.time()
-    probe = band(y0, 2)
-    dg = O.run_pass(V, P, st.copy(), 0, 0, order=probe, diag=True)
-    t_probe = time.time() - t0
+    _, _, t_probe = timed_band(y0, 2)
     rows = int(max(2, min(H - y0, 2 * budget_s / max(t_probe, 1e-3))))
-    order = band(y0, rows)
-    s2 = st.copy()
-    t0 = time.time()
-    dg = O.run_pass(V, P, s2, 0, 0, order=order, diag=True)
-    el = time.time() - t0
-    n = V.n_src
-    evals = 0
-    for d in dg:
-        evals += sum(d.row_valid[r] for r in range(9)) * n
-        evals += d.n_cand * sum(1 for j in range(n) if d.w[j] > 0)
-    return {"value": evals / el, "unit": "evals/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"one red half-pass (t=0, refinement on) over {len(order)} pixels in rows {y0}..{y0 + rows - 1}"
-                      f" of the {W}x{H} reference, {evals} evaluations in {el:.1f} s"}
+    npix, evals, el = timed_band(y0, rows)
+    # the same oracle on one thread, over a band sized to a third of the budget
+    O.set_num_threads(1)
+    try:
+        rows1 = int(max(2, min(H - y0, 2 * (budget_s / 3) / max(t_probe * threads, 1e-3))))
+        npix1, evals1, el1 = timed_band(y0, rows1)
+    finally:
+        O.set_num_threads(threads)
+    return {"value": evals / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": O.cpu_model(), "host_cpus": os.cpu_count(),
+            "build": "gcc " + " ".join(O.CFLAGS),
+            "value_1core": evals1 / el1,
+            "sample": f"one red half-pass (t=0, refinement on) over {npix} pixels in rows {y0}..{y0 + rows - 1}"
+                      f" of the {W}x{H} reference, {evals} evaluations in {el:.1f} s on {threads} threads; "
+                      f"one thread: {npix1} pixels (rows {y0}..{y0 + rows1 - 1}), {evals1} evaluations in {el1:.1f} s"}
 
 
 def bench_batch(args):
@@ -214,9 +232,10 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
-def bench_learned(args):
-    """Seconds per depth map at equal accuracy: learned proposal + 1 iteration against the plain method
-    (random initialisation + 3 iterations), 1920x1280 with 10 sources, held-out scene seeds."""
+def learned_comparison(seeds, steps: int, warmup: int, seed: int = 0, weights=None):
+    """Learned proposal + 1 iteration against random initialisation + 1 and + 3 iterations (the plain
+    method) on held-out 1920x1280 scenes with 10 sources: device-synchronised time per depth map and the
+    fraction of visible pixels within 1 %, 2 cm and 10 cm of the rendered depth, per path and scene."""
     import torch
 
     import paper_1805_07920_amd as amh
@@ -224,20 +243,20 @@ def bench_learned(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    weights = args.weights or os.path.join(ROOT, "paper_1805_07920_amd", "weights", "proposal.bin")
-    seeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_scenes))
-    ctx = amh.Context(refine=1, seed=args.seed)
+    weights = weights or os.path.join(ROOT, "paper_1805_07920_amd", "weights", "proposal.bin")
+    ctx = amh.Context(refine=1, seed=seed)
     ctx.nn_load(weights)
     runs = {"proposal+1": [], "random+1": [], "random+3": []}
     H = W = 0
-    for seed in seeds:
-        sc = scenegen.config_scene("c2", seed, device="cuda")
+    tuned = (None, None)
+    for sd in seeds:
+        sc = scenegen.config_scene("c2", sd, device="cuda")
         H, W = sc.height, sc.width
         ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
         srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]  # nearest sources first
         imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images]
         ctx.init_views(imgs, sc.cams)
-        if seed == seeds[0]:
+        if sd == seeds[0]:
             tuned = ctx.tune([dict(ref=0, srcs=srcs, iters=3)])
             ctx.init_views(imgs, sc.cams)
         vis = sc.vis_count >= 2
@@ -245,40 +264,50 @@ def bench_learned(args):
         for name, fn in (("proposal+1", lambda: ctx.run_proposal(0, srcs, 1)),
                          ("random+1", lambda: ctx.run_checkerboard(0, srcs, 1)),
                          ("random+3", lambda: ctx.run_checkerboard(0, srcs, 3))):
-            for _ in range(max(1, args.warmup)):
+            for _ in range(max(1, warmup)):
                 fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(steps):
                 fn()
                 ctx.get_depth_normal_cost(depth=depth)
             torch.cuda.synchronize()
-            ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+            ms = 1000.0 * (time.perf_counter() - t0) / steps
             stats = ctx.get_stats()
-            evals = stats["evals_total"]
             d = depth.cpu().numpy()
             e = np.abs(d - sc.depth_gt)[vis]
             gt = sc.depth_gt[vis]
-            runs[name].append(dict(ms=ms, evals=evals, rel1=float((e < 0.01 * gt).mean()),
+            runs[name].append(dict(ms=ms, evals=stats["evals_total"], rel1=float((e < 0.01 * gt).mean()),
                                    cm2=float((e < 0.02).mean()), cm10=float((e < 0.10).mean()),
                                    fallback_frac=stats["fallback_pixels"] / float(H * W)))
-            log(f"seed {seed} {name}: {runs[name][-1]}")
+            log(f"seed {sd} {name}: {runs[name][-1]}")
     ctx.close()
     mean = {k: {f: float(np.mean([r[f] for r in v])) for f in ("ms", "evals", "rel1", "cm2", "cm10")}
             for k, v in runs.items()}
     p, plain = mean["proposal+1"], mean["random+3"]
     equal = p["cm10"] >= plain["cm10"] and p["cm2"] >= plain["cm2"] - 0.005
+    return {"sec_per_depth_map": p["ms"] / 1000.0, "plain_sec_per_depth_map": plain["ms"] / 1000.0,
+            "speedup_vs_plain": plain["ms"] / p["ms"], "equal_accuracy": bool(equal),
+            "equal_accuracy_rule": "proposal >= plain within 10 cm and no more than 0.5 points below it within 2 cm",
+            "workload": f"learned proposal + 1 iteration vs plain 3 iterations, {W}x{H}, 10 sources, held-out "
+                        f"scene seeds {seeds[0]}-{seeds[-1]}",
+            "accuracy": mean, "per_scene": runs, "autotune": {"best_config": tuned[0], "ms_per_config": tuned[1]}}
+
+
+def bench_learned(args):
+    """Seconds per depth map at equal accuracy: learned proposal + 1 iteration against the plain method
+    (random initialisation + 3 iterations), 1920x1280 with 10 sources, held-out scene seeds."""
+    seeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_scenes))
+    r = learned_comparison(seeds, args.steps, args.warmup, seed=args.seed, weights=args.weights)
     out = {
-        "metric": METRIC, "value": p["ms"] / 1000.0, "unit": "s per depth map", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": p["ms"], "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 (network bf16 on MFMA, fp32 accumulation)", "data": "synthetic",
-        "config": {"workload": f"learned proposal + 1 iteration vs plain 3 iterations, {W}x{H}, 10 sources, "
-                               f"held-out scene seeds {seeds[0]}-{seeds[-1]}", "parallelism": "single GPU"},
-        "plain_s_per_depth_map": plain["ms"] / 1000.0, "speedup_vs_plain": plain["ms"] / p["ms"],
-        "equal_accuracy": bool(equal),
-        "equal_accuracy_rule": "proposal >= plain within 10 cm and no more than 0.5 points below it within 2 cm",
-        "accuracy": mean, "per_scene": runs,
-        "autotune": {"best_config": tuned[0], "ms_per_config": tuned[1]},
+        "metric": METRIC, "value": r["sec_per_depth_map"], "unit": "s per depth map", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * r["sec_per_depth_map"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (network bf16 on MFMA, fp32 accumulation)", "data": "synthetic",
+        "config": {"workload": r["workload"], "parallelism": "single GPU"},
+        "plain_s_per_depth_map": r["plain_sec_per_depth_map"], "speedup_vs_plain": r["speedup_vs_plain"],
+        "equal_accuracy": r["equal_accuracy"], "equal_accuracy_rule": r["equal_accuracy_rule"],
+        "accuracy": r["accuracy"], "per_scene": r["per_scene"], "autotune": r["autotune"],
     }
     print(json.dumps(out))
 
@@ -568,6 +597,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal leg (seconds per depth map at equal accuracy vs plain)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--batch", action="store_true",
                     help="the batched workload instead: 32 reference images of uneven sizes (640x480..3200x2130) "
@@ -687,15 +718,20 @@ def main():
     vis = sc.vis_count >= 2
     acc = float((rel[vis] < 0.01).mean())
 
+    # the metric's second half: seconds per depth map of the learned proposal + 1 iteration against the
+    # plain method (random init + 3 iterations) at equal accuracy, on a held-out scene of the same recipe
+    learned = None
+    if args.config == "c2" and not args.no_learned:
+        learned = learned_comparison([1], steps=max(3, args.steps), warmup=1, seed=args.seed)
+        learned = {k: learned[k] for k in ("sec_per_depth_map", "plain_sec_per_depth_map", "speedup_vs_plain",
+                                            "equal_accuracy", "equal_accuracy_rule", "workload", "accuracy")}
+
     cpu = None
     if not args.no_cpu:
-        ctx2 = amh.Context(refine=cfg["refine"], seed=args.seed)
-        ctx2.init_views([np.ascontiguousarray(im) for im in sc.images], sc.cams)
-        ctx2.begin(0, srcs)
-        ctx2.init_hypotheses()
-        state = ctx2.get_state()
-        ctx2.close()
-        cpu = cpu_baseline(sc, params_kw, state)
+        import oracle as O
+
+        state = O.init(O.Views.from_scene(sc), O.Params(**params_kw))
+        cpu = cpu_baseline(sc, params_kw, (state.plane, state.cost, state.S, state.v))
 
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
@@ -727,7 +763,14 @@ def main():
                                f"(fused checkerboard half-pass, {2 if best_cfg & 4 else 4}-row tiles)",
                      "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals_per_pass,
                      "sampled_evals_per_launch": sampled_per_pass,
-                     "achieved_basis": "evaluations that took their 36 samples x ops_per_eval / mean launch time"},
+                     "achieved_basis": "evaluations that took their 36 samples x ops_per_eval (algorithmic) / "
+                                       "mean launch time",
+                     "issue_slots_per_eval": ISSUE_SLOTS_PER_EVAL,
+                     "issue_slot_frac": sampled_per_pass * ISSUE_SLOTS_PER_EVAL / (avg_pass_ms / 1000.0)
+                                        / VALU_PEAK_OPS},
+        "speedup_vs_plain": learned["speedup_vs_plain"] if learned else None,
+        "equal_accuracy": learned["equal_accuracy"] if learned else None,
+        "learned_vs_plain": learned,
         "cpu_baseline": cpu,
         "autotune": {"best_config": best_cfg, "ms_per_config": tune_ms,
                      "configs": "tile order (XCD bands / hardware) + 2 x job order + 4 x (2-row tiles)"},

@@ -255,6 +255,7 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             orc_project(V, x + dx, y + dy, plane, j, h);
             if (!(h[2] > 0.0)) return 2.0;
             b[n] = bilinear(V->src[j], V->srcW[j], V->srcH[j], h[0] / h[2], h[1] / h[2]);
+            if (p->sample_f32) b[n] = (double)(float)b[n]; /* conditioning probe only */
             ++n;
         }
     }

@@ -68,6 +68,9 @@ typedef struct {
     int prop_mode;   /* 0: asymmetric checkerboard propagation (the method);
                         1: symmetric fast checkerboard propagation (ablation) */
     int bilateral_sq; /* 1: squared colour difference and distance in the bilateral weight */
+    int sample_f32;   /* conditioning probe, not the method: 1 rounds every interpolated source sample to
+                         float32, to measure how far the method's result moves when only the samples
+                         carry single precision; 0 (the method): every step in double */
 } orc_params;
 
 typedef struct {

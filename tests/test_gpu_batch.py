@@ -216,3 +216,85 @@ def test_batched_proposal_equals_single_proposal_runs(amh, batch_setup):
     for a, b, c in zip(got, again, singles):
         for x, y, z in zip(a, b, c):
             assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def _job_views(O, images, cams, jb):
+    idx = [jb["ref"]] + list(jb["srcs"])
+    return O.Views([images[i] for i in idx], [cams[i] for i in idx])
+
+
+def test_batch_jobs_match_oracle(amh, oracle_mod, batch_setup):
+    """Every job of one batch (both LDS classes, 0 to 3 iterations) against the oracle's whole run of that
+    job: >= 99.5 % of the pixels within 0.1 % relative depth (Sec. 3 with refinement)."""
+    say("case batch jobs vs oracle")
+    O = oracle_mod
+    images, cams, jobs = batch_setup
+    with amh.Context(refine=1, seed=13) as ctx:
+        ctx.init_views(images, cams)
+        ctx.run_batch(jobs)
+        res = [ctx.get_job_result(i) for i in range(len(jobs))]
+    for i, jb in enumerate(jobs):
+        V = _job_views(O, images, cams, jb)
+        st = O.run(V, O.Params(refine=1, seed=13), jb["iters"])
+        od, on = O.depth_normal(V, st)
+        d, nrm, c = res[i]
+        agree = float((np.abs(d - od) / od <= 1e-3).mean())
+        say(f"  job {i}: {V.W}x{V.H}, {V.n_src} sources, {jb['iters']} iterations: depth agreement {agree:.5f}")
+        assert agree >= 0.995, f"job {i}"
+        if jb["iters"] == 0:  # initialisation only: the planes are the same random draws
+            np.testing.assert_allclose(nrm, on, atol=2e-5)
+            assert (np.abs(c - st.cost) <= 1e-4).mean() >= 0.999
+
+
+def _head_bias_network(nn):
+    """Every weight and bias 0 except the head's bias: each hidden layer outputs ReLU(0) = 0 and the head
+    outputs its bias, exactly (the values are bfloat16 numbers), so the proposal is known in closed form:
+    the sweep winner's depth (tanh 0 = 0), one normal, confidence sigmoid(2)."""
+    theta = np.zeros(nn.param_count())
+    theta[-5:] = [0.0, 0.25, -0.5, -1.0, 2.0]
+    return theta
+
+
+def test_batched_proposal_initial_state_matches_oracle(amh, oracle_mod, batch_setup):
+    """The learned-proposal batch with no iteration: every job's initial planes and costs against the
+    oracle's sweep (winning plane of each cell), decoding and proposal initialisation, for a network whose
+    output is fixed by its head bias.  Compared on the pixels of cells whose sweep winner leads the
+    runner-up by more than 2e-4 (elsewhere the winner is a near-tie of the sweep's float32 costs)."""
+    say("case batched proposal initial state vs oracle")
+    import torch  # noqa: F401
+    from oracle import nn_oracle as nn
+    from oracle import proposal
+
+    O = oracle_mod
+    images, cams, jobs = batch_setup
+    theta = _head_bias_network(nn)
+    pjobs = [dict(jb, iters=0) for jb in jobs]
+    with amh.Context(refine=1, seed=7, conf_min=0.5) as ctx:
+        ctx.init_views(images, cams)
+        ctx.nn_set_params(theta)
+        ctx.run_batch_proposal(pjobs)
+        res = [ctx.get_job_result(i) for i in range(len(jobs))]
+    z = nn.unflatten(theta)["head"][1]
+    for i, jb in enumerate(jobs):
+        V = _job_views(O, images, cams, jb)
+        P = O.Params(seed=7)
+        h4, w4 = proposal.grid(V.H, V.W)
+        q = proposal.sweep_reference_q(V, P)
+        robust = np.zeros((h4, w4), bool)
+        for a in range(h4):
+            for b in range(w4):
+                s = np.sort(proposal.sweep_costs(V, P, *proposal.sample_pixel(V.H, V.W, a, b)))
+                robust[a, b] = s[1] - s[0] > 2e-4
+        depth, normal, conf = nn.decode(np.broadcast_to(z, (h4, w4, 5)), q, P.d_min, P.d_max)
+        ost, used = proposal.proposal_state(V, P, depth, normal, conf, conf_min=0.5)
+        od, on = O.depth_normal(V, ost)
+        ys, xs = np.mgrid[0:V.H, 0:V.W]
+        ok = robust[ys // 4, xs // 4]
+        near_end = np.minimum(np.abs(od - P.d_min), np.abs(od - P.d_max)) < 6e-4
+        ok &= ~near_end
+        d, nrm, c = res[i]
+        say(f"  job {i}: {V.W}x{V.H}: proposal used on {used.mean():.3f}, compared on {ok.mean():.3f} of the pixels")
+        assert ok.mean() >= 0.6 and used[ok].mean() >= 0.99
+        np.testing.assert_allclose(d[ok], od[ok], rtol=2e-5)
+        np.testing.assert_allclose(nrm[ok], on[ok], atol=2e-5)
+        assert (np.abs(c - ost.cost)[ok] <= 1e-4).mean() >= 0.999

@@ -255,3 +255,35 @@ def test_short_predicate_matches_oracle_early_exits():
         for j in range(len(sc.srcs)):
             c = O.matching_cost(V, P, int(xy[i, 0]), int(xy[i, 1]), pl[i], j)
             assert (c == 2.0) == bool(m[i, j]), (xy[i], j, c)
+
+
+def test_sample_f32_probe_only_rounds_the_samples(oracle_mod, scene_c1):
+    """The conditioning probe (sample_f32 = 1) changes nothing but the precision of the interpolated source
+    samples: where every sample lands on a texel (integer disparity) the samples are float32 values already
+    and the cost is unchanged; elsewhere it moves by no more than float32 rounding of the
+    samples can move a correlation (~1e-5 on the rendered scene), and it does move."""
+    rng = np.random.default_rng(11)
+    W, H, f, Z, B = 64, 40, 100.0, 4.0, 0.12
+    K = np.array([[f, 0, (W - 1) / 2], [0, f, (H - 1) / 2], [0, 0, 1]])
+    ref = rng.uniform(0, 255, (H, W)).astype(np.float32)
+    src = np.zeros_like(ref)
+    src[:, :W - 3] = ref[:, 3:] * 1.07 + 5.0
+    V = oracle_mod.Views([ref, src], [cam(K, np.eye(3), np.zeros(3), W, H), cam(K, np.eye(3), [-B, 0, 0], W, H)])
+    pl = np.array([0.0, 0.0, -1.0, Z * 1.3])  # disparity 3 / 1.3: samples between texels
+    exact = np.array([0.0, 0.0, -1.0, Z / 2.0])  # disparity 6: samples on texels
+    P0, P1 = oracle_mod.Params(), oracle_mod.Params(sample_f32=1)
+    for x, y in [(20, 10), (30, 20), (40, 30)]:
+        # (the warped positions are texel centres up to double rounding)
+        assert oracle_mod.matching_cost(V, P1, x, y, exact, 0) == pytest.approx(
+            oracle_mod.matching_cost(V, P0, x, y, exact, 0), abs=1e-12)
+    V = oracle_mod.Views.from_scene(scene_c1)
+    diffs = []
+    for _ in range(300):
+        x, y = int(rng.integers(0, V.W)), int(rng.integers(0, V.H))
+        plane = oracle_mod.random_plane(V, P0, x, y, 5, 0)
+        for j in range(V.n_src):
+            a, b = oracle_mod.matching_cost(V, P0, x, y, plane, j), oracle_mod.matching_cost(V, P1, x, y, plane, j)
+            if a < 2.0:
+                diffs.append(abs(a - b))
+    diffs = np.array(diffs)
+    assert diffs.max() <= 1e-4 and diffs.max() > 0.0
