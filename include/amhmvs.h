@@ -177,6 +177,29 @@ amh_status amh_run_checkerboard(amh_ctx *ctx, int ref, const int *srcs, int n_sr
  * of the three may be NULL.  dst_on_device: destinations are device pointers. */
 amh_status amh_get_depth_normal_cost(amh_ctx *ctx, float *depth, float *normal, float *cost, int dst_on_device);
 
+/* Largest reference (pixels) of amh_run_checkerboard_static, e.g. 2048 x 1280. */
+#define AMH_STATIC_MAX_PIXELS 2621440
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): amh_run_checkerboard
+ * followed by amh_get_depth_normal_cost into device buffers, allocating
+ * nothing.  The per-pixel state and the sources' warp constants live in one
+ * library-wide static device array (about 70 MiB per GPU the library runs on,
+ * held until the process ends) instead of context buffers.
+ *   ref, srcs, n_src, iters: as amh_run_checkerboard (views registered with
+ *     amh_init_views); the reference may have at most AMH_STATIC_MAX_PIXELS
+ *     pixels, larger ones give AMH_E_INVALID_ARG before any work.
+ *   depth (H*W), normal (H*W*3), cost (H*W): device pointers owned by the
+ *     caller, any may be NULL; written in stream order on the context's stream.
+ * Results equal amh_run_checkerboard's bit for bit.  The context's current
+ * reference is released (amh_get_state / amh_score_fixed need a new amh_begin);
+ * amh_get_stats counts this run's evaluations, without per-pass times.
+ * Every call on a GPU shares that GPU's array and leaves its state there: calls
+ * that overlap on one GPU (other streams or contexts, not yet complete) race.
+ * Synchronises the context's stream once, before writing the constants. */
+amh_status amh_run_checkerboard_static(amh_ctx *ctx, int ref, const int *srcs, int n_src, int iters, float *depth,
+                                       float *normal, float *cost);
+
 /* Per-pixel state of the current reference: planes (H*W*4: n_x, n_y, n_z, d
  * with n.X + d = 0 in the reference camera frame), cost (H*W), S (H*W view
  * masks, bit j = j-th source of amh_begin), v (H*W, most important view or -1).

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libamhmvs.so")
 
 AMH_OK, AMH_E_INVALID_ARG, AMH_E_OOM, AMH_E_HIP, AMH_E_STATE, AMH_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 AMH_F32, AMH_F16 = 0, 1
+AMH_STATIC_MAX_PIXELS = 2621440  # largest reference of amh_run_checkerboard_static (include/amhmvs.h)
 
 # every function the header declares (checked against include/amhmvs.h by the tests)
 EXPORTS = [
@@ -27,7 +28,7 @@ EXPORTS = [
     "amh_nn_param_count", "amh_nn_init", "amh_nn_get_params", "amh_nn_set_params", "amh_nn_get_grads",
     "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
     "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config", "amh_run_batch_proposal",
-    "amh_fusion_params_default", "amh_median_filter4", "amh_fuse",
+    "amh_fusion_params_default", "amh_median_filter4", "amh_fuse", "amh_run_checkerboard_static",
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
@@ -92,6 +93,7 @@ def lib():
         L.amh_init_hypotheses.argtypes = [vp]
         L.amh_pass.argtypes = [vp, ip, ip]
         L.amh_run_checkerboard.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
+        L.amh_run_checkerboard_static.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip, vp, vp, vp]
         L.amh_get_depth_normal_cost.argtypes = [vp, vp, vp, vp, ip]
         L.amh_get_state.argtypes = [vp, vp, vp, vp, vp, ip]
         L.amh_set_state.argtypes = [vp, vp, vp, vp, vp, ip]
@@ -262,6 +264,21 @@ class Context:
         self._check(self.L.amh_run_checkerboard(self.h, ref, s, len(srcs), iters), "amh_run_checkerboard")
         self.H, self.W = self._views_shape[ref]
         self.n_src = len(srcs)
+
+    def run_checkerboard_static(self, ref: int, srcs, iters: int, depth=None, normal=None, cost=None):
+        """amh_run_checkerboard_static: the allocation-free run; outputs are device tensors (or None)."""
+        H, W = self._views_shape[ref]
+        for x, per_px, name in ((depth, 1, "depth"), (normal, 3, "normal"), (cost, 1, "cost")):
+            if x is not None and (x.numel() != H * W * per_px or str(x.dtype) != "torch.float32"):
+                raise ValueError(f"{name} must be a float32 tensor of {H * W * per_px} elements")
+        ptrs = [_ptr(x) for x in (depth, normal, cost)]
+        if any(p is not None and d != 1 for p, d in ptrs):
+            raise ValueError("the allocation-free run writes device buffers only")
+        s = (C.c_int * len(srcs))(*[int(v) for v in srcs])
+        self._check(self.L.amh_run_checkerboard_static(self.h, ref, s, len(srcs), iters, *[p for p, _ in ptrs]),
+                    "amh_run_checkerboard_static")
+        self.n_src = len(srcs)
+        return depth, normal, cost
 
     def get_depth_normal_cost(self, depth=None, normal=None, cost=None):
         """Host numpy outputs by default; pass device tensors to fill them in place."""

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +17,53 @@
 #include "amh_ctx.h"
 
 using namespace amh;
+
+// ---------------------------------------------------------------------------
+// Storage of the allocation-free run (amh_run_checkerboard_static): the warp
+// constants of the reference's sources and the per-pixel state (planes, cost,
+// view masks, best views) live in this file-scope device array, one copy per
+// GPU, held until the process ends.  On the host the array's name only stands
+// for the symbol: kernels receive its device address, looked up once per
+// device with hipGetSymbolAddress when a context is first created there.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kStaticAlign = 256;
+constexpr size_t static_align(size_t b) { return (b + kStaticAlign - 1) & ~(kStaticAlign - 1); }
+constexpr size_t kStaticMaxPixels = AMH_STATIC_MAX_PIXELS;
+constexpr size_t kStaticViewcOff = 0;
+constexpr size_t kStaticPlanesOff = kStaticViewcOff + static_align(sizeof(ViewDev) * kMaxSrc);
+constexpr size_t kStaticCostOff = kStaticPlanesOff + static_align(kStaticMaxPixels * sizeof(float4));
+constexpr size_t kStaticSOff = kStaticCostOff + static_align(kStaticMaxPixels * sizeof(float));
+constexpr size_t kStaticVOff = kStaticSOff + static_align(kStaticMaxPixels * sizeof(uint32_t));
+constexpr size_t kStaticBytes = kStaticVOff + static_align(kStaticMaxPixels * sizeof(int32_t));
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+unsigned char *g_static_ptr[kStaticMaxDevices] = {};
+hipError_t g_static_err[kStaticMaxDevices] = {};
+bool g_static_done[kStaticMaxDevices] = {};
+
+// Called with `device` current: looks up that device's copy of the array once, and returns the result of
+// that lookup (the address, or the error that left it unknown).
+hipError_t static_scratch(int device, unsigned char **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kStaticMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_done[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_static_err[device] = e;
+        g_static_ptr[device] = e == hipSuccess ? static_cast<unsigned char *>(p) : nullptr;
+        g_static_done[device] = true;
+    }
+    *ptr = g_static_ptr[device];
+    return g_static_err[device];
+}
+
+}  // namespace
 
 namespace amh {
 
@@ -545,6 +593,10 @@ amh_status amh_create(amh_ctx **out, const amh_params *p, void *hip_stream) {
         delete c;
         return st;
     }
+    // device address of this GPU's copy of the allocation-free run's array (once per device); a failed
+    // lookup is kept and reported by amh_run_checkerboard_static, the rest of the library does not need it
+    unsigned char *sp = nullptr;
+    (void)static_scratch(c->device, &sp);
     *out = c;
     return AMH_OK;
 }
@@ -670,8 +722,8 @@ amh_status amh_init_views(amh_ctx *c, int n_views, const amh_image *views, const
     return result;
 }
 
-amh_status amh_begin(amh_ctx *c, int ref, const int *srcs, int n_src) {
-    if (!c) return AMH_E_INVALID_ARG;
+// reference and source list of a depth map: registered views, no repeats, the reference not a source
+static amh_status check_sources(amh_ctx *c, int ref, const int *srcs, int n_src) {
     if (c->views.empty()) return fail(c, AMH_E_STATE, "no views registered (amh_init_views)");
     const int nv = (int)c->views.size();
     if (ref < 0 || ref >= nv) return fail(c, AMH_E_INVALID_ARG, "ref %d outside 0..%d", ref, nv - 1);
@@ -682,6 +734,13 @@ amh_status amh_begin(amh_ctx *c, int ref, const int *srcs, int n_src) {
         for (int k = 0; k < i; ++k)
             if (srcs[k] == srcs[i]) return fail(c, AMH_E_INVALID_ARG, "source view %d listed twice", srcs[i]);
     }
+    return AMH_OK;
+}
+
+amh_status amh_begin(amh_ctx *c, int ref, const int *srcs, int n_src) {
+    if (!c) return AMH_E_INVALID_ARG;
+    amh_status chk = check_sources(c, ref, srcs, n_src);
+    if (chk != AMH_OK) return chk;
     HIPCHK(c, hipStreamSynchronize(c->stream));  // the previous constants may still be in flight
     const View &r = c->views[ref];
     c->ref = ref;
@@ -762,6 +821,59 @@ amh_status amh_run_checkerboard(amh_ctx *c, int ref, const int *srcs, int n_src,
     for (int t = 0; t < iters; ++t)
         for (int colour = 0; colour < 2; ++colour)
             if ((st = amh_pass(c, t, colour)) != AMH_OK) return st;
+    return AMH_OK;
+}
+
+amh_status amh_run_checkerboard_static(amh_ctx *c, int ref, const int *srcs, int n_src, int iters, float *depth,
+                                       float *normal, float *cost) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (iters < 0 || iters > 1000) return fail(c, AMH_E_INVALID_ARG, "iters must be in 0..1000");
+    amh_status st = check_sources(c, ref, srcs, n_src);
+    if (st != AMH_OK) return st;
+    const View &r = c->views[ref];
+    const size_t P = (size_t)r.W * r.H;
+    if (P > kStaticMaxPixels)
+        return fail(c, AMH_E_INVALID_ARG, "reference of %dx%d = %zu pixels: the allocation-free run holds at most %zu",
+                    r.W, r.H, P, kStaticMaxPixels);
+    unsigned char *base = nullptr;
+    const hipError_t se = static_scratch(c->device, &base);
+    if (se != hipSuccess || !base)
+        return fail(c, AMH_E_HIP, "no device address for the allocation-free run's array: %s", hipGetErrorString(se));
+    ViewDev *viewc = reinterpret_cast<ViewDev *>(base + kStaticViewcOff);
+    const StateDev sd{reinterpret_cast<float4 *>(base + kStaticPlanesOff), reinterpret_cast<float *>(base + kStaticCostOff),
+                      reinterpret_cast<uint32_t *>(base + kStaticSOff), reinterpret_cast<int32_t *>(base + kStaticVOff)};
+    // the context's current reference is released: its own state is not this run's, and its warp-constant
+    // table no longer matches the source list (the host copy below is reused for this run)
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // an earlier copy from the host table may still be in flight
+    c->ref = -1;
+    c->have_state = false;
+    c->srcs.assign(srcs, srcs + n_src);
+    c->h_viewc.resize(n_src);
+    for (int i = 0; i < n_src; ++i) c->h_viewc[i] = view_dev(r, c->views[srcs[i]]);
+    HIPCHK(c, hipMemcpyAsync(viewc, c->h_viewc.data(), sizeof(ViewDev) * n_src, hipMemcpyHostToDevice, c->stream));
+    c->refdev.img = r.img;
+    c->refdev.W = r.W;
+    c->refdev.H = r.H;
+    kinv_upper(r.K, c->refdev.kinv_a, c->refdev.kinv_b, c->refdev.kinv_c, c->refdev.kinv_e, c->refdev.kinv_f);
+    // statistics count this run's evaluations (no per-pass times)
+    c->n_timed = 0;
+    c->init_timed = false;
+    c->batch_stats = false;
+    HIPCHK(c, launch_zero_u64(c->counters, kCounterKinds * kCounterSlots, c->stream));
+    for (int colour = 0; colour < 2; ++colour) {  // random initialisation writes every pixel of the state
+        PassArgs a = pass_args(c, 0, colour);
+        a.views = viewc;
+        a.st = sd;
+        HIPCHK(c, launch_init(a, c->half, c->stream));
+    }
+    for (int t = 0; t < iters; ++t)
+        for (int colour = 0; colour < 2; ++colour) {
+            PassArgs a = pass_args(c, t, colour);
+            a.views = viewc;
+            a.st = sd;
+            HIPCHK(c, launch_pass(a, c->half, c->stream));
+        }
+    if (depth || normal || cost) HIPCHK(c, launch_outputs(c->refdev, sd, depth, normal, cost, c->stream));
     return AMH_OK;
 }
 
