@@ -85,7 +85,7 @@ class _Params(C.Structure):
                 ("beta", C.c_double), ("tau_up", C.c_double),
                 ("n1", C.c_int), ("n2", C.c_int), ("k", C.c_int), ("seed", C.c_uint64),
                 ("view_mode", C.c_int), ("prop_mode", C.c_int), ("bilateral_sq", C.c_int),
-                ("sample_f32", C.c_int)]
+                ("sample_f32", C.c_int), ("cost_noise", C.c_double)]
 
 
 class _State(C.Structure):
@@ -170,13 +170,14 @@ class Params:
     view_mode: int = 0  # 1: plain mean over all views (static objective for the sweep pin); 2: heuristic best-k
     prop_mode: int = 0  # 1: symmetric fast checkerboard propagation (ablation)
     bilateral_sq: int = 0  # 1: squared colour difference and distance in the bilateral weight
-    sample_f32: int = 0  # conditioning probe (not the method): interpolated source samples rounded to float32
+    sample_f32: int = 0  # conditioning probe (not the method): sample positions and values rounded to float32
+    cost_noise: float = 0.0  # conditioning probe (not the method): deterministic cost offsets of this width
 
     def c(self) -> _Params:
         return _Params(self.refine, self.include_self, self.d_min, self.d_max, self.sigma_color,
                        self.sigma_spatial, self.tau_mc_init, self.alpha, self.beta, self.tau_up,
                        self.n1, self.n2, self.k, self.seed & 0xFFFFFFFFFFFFFFFF, self.view_mode,
-                       self.prop_mode, self.bilateral_sq, self.sample_f32)
+                       self.prop_mode, self.bilateral_sq, self.sample_f32, self.cost_noise)
 
 
 class Views:

@@ -220,6 +220,24 @@ static double bilinear(const float *img, int W, int H, double px, double py)
     return (1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11);
 }
 
+/* Conditioning probe (not the method): a deterministic offset uniform in     */
+/* [-1/2, 1/2) for a (pixel, view, plane), from a 64-bit mix of their bits.   */
+static double probe_noise(int x, int y, int j, const double plane[4])
+{
+    uint64_t h = (uint64_t)(uint32_t)x * 0x9E3779B97F4A7C15ULL ^ (uint64_t)(uint32_t)y * 0xC2B2AE3D27D4EB4FULL ^
+                 (uint64_t)(uint32_t)j * 0x165667B19E3779F9ULL;
+    for (int i = 0; i < 4; ++i) {
+        uint64_t bits;
+        memcpy(&bits, &plane[i], sizeof bits);
+        h = (h ^ bits) * 0xD6E8FEB86659FD93ULL;
+        h ^= h >> 32;
+    }
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ULL;
+    h ^= h >> 32;
+    return (double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Matching cost m(p, h(p)): bilaterally weighted NCC over the window,        */
 /* every other row and column (Sec. 3.3, Eq. 8; R3-R6).                       */
@@ -254,7 +272,12 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             double h[3];
             orc_project(V, x + dx, y + dy, plane, j, h);
             if (!(h[2] > 0.0)) return 2.0;
-            b[n] = bilinear(V->src[j], V->srcW[j], V->srcH[j], h[0] / h[2], h[1] / h[2]);
+            double px = h[0] / h[2], py = h[1] / h[2];
+            if (p->sample_f32) { /* conditioning probe only: positions relative to the centre's texel */
+                px = floor(cu) + (double)(float)(px - floor(cu));
+                py = floor(cv) + (double)(float)(py - floor(cv));
+            }
+            b[n] = bilinear(V->src[j], V->srcW[j], V->srcH[j], px, py);
             if (p->sample_f32) b[n] = (double)(float)b[n]; /* conditioning probe only */
             ++n;
         }
@@ -277,6 +300,7 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
     caa /= sw; cbb /= sw; cab /= sw;
     if (caa < 1e-5 || cbb < 1e-5) return 2.0;
     double m = 1.0 - cab / sqrt(caa * cbb);
+    if (p->cost_noise > 0.0) m += probe_noise(x, y, j, plane) * p->cost_noise; /* conditioning probe only */
     if (m < 0.0) m = 0.0;
     if (m > 2.0) m = 2.0;
     return m;

@@ -68,9 +68,13 @@ typedef struct {
     int prop_mode;   /* 0: asymmetric checkerboard propagation (the method);
                         1: symmetric fast checkerboard propagation (ablation) */
     int bilateral_sq; /* 1: squared colour difference and distance in the bilateral weight */
-    int sample_f32;   /* conditioning probe, not the method: 1 rounds every interpolated source sample to
-                         float32, to measure how far the method's result moves when only the samples
-                         carry single precision; 0 (the method): every step in double */
+    int sample_f32;   /* conditioning probe, not the method: 1 rounds every sample's source position
+                         (relative to the texel under the window centre) and its interpolated value to
+                         float32, to measure how far the method's result moves when those carry single
+                         precision; 0 (the method): every step in double */
+    double cost_noise; /* conditioning probe, not the method: > 0 adds to every scored cost a deterministic
+                          offset uniform in [-cost_noise/2, cost_noise/2) (a hash of pixel, view and
+                          plane), to measure what cost errors of that size do to the result; 0: none */
 } orc_params;
 
 typedef struct {

@@ -516,6 +516,8 @@ struct PassLds {
     float4 *cand;    // [wave][group][6] refinement candidates
     float *wgt;      // [wave][group][32] view weights of each pixel
     unsigned *nshort;  // [wave] evaluations of the wave that took no samples (touched by that wave only)
+    int *gnw;          // [wave][8] refinement: active views of each pixel of the wave (0: no pixel)
+    float2 *gws;       // [wave][8] ... and its window statistics (1 / sum w, weighted reference variance)
 };
 
 constexpr int kTileW = 2 * kTilePix + 10;
@@ -523,7 +525,7 @@ constexpr int kTileW = 2 * kTilePix + 10;
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 // LDS of a workgroup of `waves` waves (one image row of the tile per wave)
-__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[11]) {
+__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[13]) {
     size_t o = 0;
     off[0] = o; o = align16(o + sizeof(float) * (waves + 10) * kTileW);
     off[1] = o; o = align16(o + sizeof(float2) * waves * kGroups * kWinStride);
@@ -536,16 +538,18 @@ __host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[11
     off[8] = o; o = align16(o + sizeof(float4) * waves * kGroups * 6);
     off[9] = o; o = align16(o + sizeof(float) * waves * kGroups * kMaxSrc);
     off[10] = o; o = align16(o + sizeof(unsigned) * waves);
+    off[11] = o; o = align16(o + sizeof(int) * waves * 8);
+    off[12] = o; o = align16(o + sizeof(float2) * waves * 8);
     return o;
 }
 
 size_t pass_lds_bytes(int n_src, int waves) {
-    size_t off[11];
+    size_t off[13];
     return lds_layout(n_src, waves, off);
 }
 
 __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int waves) {
-    size_t off[11];
+    size_t off[13];
     lds_layout(n_src, waves, off);
     PassLds L;
     L.tile = reinterpret_cast<float *>(smem + off[0]);
@@ -559,6 +563,8 @@ __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int wav
     L.cand = reinterpret_cast<float4 *>(smem + off[8]);
     L.wgt = reinterpret_cast<float *>(smem + off[9]);
     L.nshort = reinterpret_cast<unsigned *>(smem + off[10]);
+    L.gnw = reinterpret_cast<int *>(smem + off[11]);
+    L.gws = reinterpret_cast<float2 *>(smem + off[12]);
     return L;
 }
 
@@ -1046,13 +1052,11 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     int n_ref = 0;
     if (m.refine) {
         const int ncand = a.t >= 3 ? 6 : 3;
-        unsigned char *act = S.act + (wave * kGroups + g) * kMaxSrc;
-        float4 *cand = S.cand + (wave * kGroups + g) * 6;
-        int nw = 0;
-        if (pix_ok) {
-            for (int j = 0; j < N; ++j) nw += wgt[j] > 0.f;
-            if (row == 0) {
-                int c = 0;
+        if (row == 0 && grp < kGroups) {
+            unsigned char *act = S.act + (wave * kGroups + g) * kMaxSrc;
+            float4 *cand = S.cand + (wave * kGroups + g) * 6;
+            int c = 0;
+            if (pix_ok) {
                 for (int j = 0; j < N; ++j)
                     if (wgt[j] > 0.f) act[c++] = (unsigned char)j;
                 // candidates: (dprt, n), (d, nprt), (dprt, nprt) [, (drnd, n), (d, nrnd), (drnd, nrnd)]
@@ -1081,28 +1085,50 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                     cand[5] = plane_from(rr, drnd, qx, qy, qz);
                 }
             }
+            S.gnw[wave * 8 + g] = c;
+            S.gws[wave * 8 + g] = make_float2(ws.invW, ws.var_a);
         }
         __syncthreads();
-        // (candidate, active view) pairs spread over the 9 lanes of the pixel
-        float *res = S.ms + wave * N * 64 + g * (6 * N);  // reuse the cost-matrix area (7 * 6N <= 64N)
-        const int pairs = pix_ok ? ncand * nw : 0;
-        for (int it = 0;; ++it) {
-            const int qi = row + kRows * it;
-            const bool act_lane = qi < pairs;
-            if (!__any(act_lane)) break;
-            if (act_lane) {
-                const int c = qi / nw;
-                const int j = act[qi - c * nw];
-                const float4 cp = cand[c];
-                const PlaneQ cq = plane_q(a.ref, m, cp, x, y);
-                // kShort stays in the stored product (wgt > 0 on active views): counted after the loop
-                const float cost = cq.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, cq.q0, cq.qu, cq.qv) : kShort;
-                res[qi] = wgt[j] * cost;
-                ++n_ref;
-            }
+        // The (candidate, active view) pairs of the wave's 7 pixels, numbered pixel by pixel, spread over
+        // all 64 lanes (pixels with more active views no longer hold the wave for extra rounds); results go
+        // to the pixel's area of the cost-matrix LDS (7 * 6N <= 64N).
+        float *resw = S.ms + wave * N * 64;
+        int start[kGroups + 1];
+        start[0] = 0;
+#pragma unroll
+        for (int h = 0; h < kGroups; ++h)
+            start[h + 1] = start[h] + ncand * __builtin_amdgcn_readfirstlane(S.gnw[wave * 8 + h]);
+        const int yrow = __builtin_amdgcn_readfirstlane(y);
+        for (int qi = lane; qi < start[kGroups]; qi += 64) {
+            int h = 0;
+#pragma unroll
+            for (int k = 1; k < kGroups; ++k) h += qi >= start[k];
+            const int base = wave * kGroups + h;
+            const int nwh = S.gnw[wave * 8 + h];
+            const int loc = qi - start[h];
+            const int c = loc / nwh;
+            const int j = S.act[base * kMaxSrc + (loc - c * nwh)];
+            const float4 cp = S.cand[base * 6 + c];
+            const float2 wsh = S.gws[wave * 8 + h];
+            const WinStats wsv = {wsh.x, wsh.y};
+            const int xh = 2 * (tx * kTilePix + h) + ((yrow + a.colour) & 1);
+            // only the weight and the destination stay live across the evaluation
+            const float wj = S.wgt[base * kMaxSrc + j];
+            float *dst = resw + (h * (6 * N) + loc);
+            const PlaneQ cq = plane_q(a.ref, m, cp, xh, yrow);
+            // kShort stays in the stored product (wgt > 0 on active views): counted after the loop
+            const float cost = cq.ok ? ncc_cost_raw<HALF>(a.views[j], S.rw + base * kWinStride, wsv, xh, yrow, cq.q0,
+                                                          cq.qu, cq.qv)
+                                     : kShort;
+            *dst = wj * cost;
+            ++n_ref;
         }
         __syncthreads();
         if (pix_ok) {
+            const int nw = S.gnw[wave * 8 + g];
+            const int pairs = ncand * nw;
+            const float4 *cand = S.cand + (wave * kGroups + g) * 6;
+            const float *res = resw + g * (6 * N);
             if (row == 0) {
                 unsigned ns = 0;
                 for (int i = 0; i < pairs; ++i) ns += res[i] < 0.f;

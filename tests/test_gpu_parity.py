@@ -265,7 +265,7 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
     assert frac_robust >= 0.5
     assert ok[robust].mean() >= 0.999
     assert ok_plane.mean() >= min_plane
-    return ok, robust
+    return ok, robust, float(ok_plane.mean())
 
 
 @pytest.mark.parametrize("t,colour,refine", [(0, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (3, 0, 1)])
@@ -370,39 +370,116 @@ def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_c1, sym, heur):
         assert np.all(S == 0) and np.all(v == -1)
 
 
+# Squared bilateral weights (reading R5's alternative, Sec. 3.3): exp(-dI^2 / 18) leaves weight only on the few
+# samples closest in intensity to the centre, and the NCC of so few effective samples is far worse conditioned
+# than with the printed weights.  Two conditioning probes of the oracle measure that, and the bars below are
+# derived from them, not from the kernel's errors:
+#  * sample_f32 (sample positions and values in float32, nothing else): costs move by up to ~4e-5 with squared
+#    weights against ~2e-7 with the printed ones, and whole runs keep only 70-80 % of their depths (100 %);
+#  * cost_noise = 2e-4 (every cost moved by a fixed offset within +-1e-4, the per-hypothesis cost bar): what a
+#    kernel whose costs all meet the bar may produce.  With squared weights it keeps fewer planes per pass and
+#    ends 1-3 points less accurate than the exact oracle (cost errors within the bar pick worse near-ties in
+#    this flat objective); with the printed weights it changes nothing measurable.
+NOISE_AT_BAR = 2e-4
+
+
+@pytest.mark.parametrize("key", list(SCENES))
+def test_score_fixed_squared_weights(amh, oracle_mod, key):
+    """Fixed hypotheses with squared weights.  Where float32 positions and samples move the oracle's cost by
+    less than 1e-6 the 1e-4 bar holds as for the printed weights; the ill-conditioned rest (the probe moves
+    them by more) must stay within 1e-3, and the cost-2 decisions (weighted variance at the 1e-5 threshold)
+    may differ only as often as the probe's do, plus 0.5 %."""
+    say("case score_fixed squared weights", key)
+    sc = build_scene(SCENES[key])
+    O = oracle_mod
+    rng = np.random.default_rng(2)
+    W, H = sc.width, sc.height
+    pix = [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(200)]
+    planes = np.concatenate([gt_planes(sc, pix), gt_planes(sc, pix, 0.02, rng), random_planes(sc, pix, rng)])
+    pix3 = np.array(pix * 3, np.int32)
+    n = len(sc.srcs)
+    with make_ctx(amh, sc, bilateral_squared=1) as ctx:
+        ctx.begin(0, list(range(1, n + 1)))
+        got = ctx.score_fixed(planes, pix3)
+    V = O.Views.from_scene(sc)
+    P, Pp = O.Params(bilateral_sq=1), O.Params(bilateral_sq=1, sample_f32=1)
+    want = np.array([[O.matching_cost(V, P, int(x), int(y), pl.astype(np.float64), j) for j in range(n)]
+                     for (x, y), pl in zip(pix3, planes)])
+    probe = np.array([[O.matching_cost(V, Pp, int(x), int(y), pl.astype(np.float64), j) for j in range(n)]
+                      for (x, y), pl in zip(pix3, planes)])
+    both = (want < 2) & (got < 2) & (probe < 2)
+    err, cond = np.abs(got - want), np.abs(probe - want)
+    well = both & (cond < 1e-6)
+    flips, probe_flips = ((want < 2) != (got < 2)).mean(), ((want < 2) != (probe < 2)).mean()
+    say(f"  well-conditioned {well.sum()} of {both.sum()}: max err {err[well].max():.2e}; ill-conditioned: max err "
+        f"{err[both & ~well].max() if (both & ~well).any() else 0:.2e} (probe {cond[both].max():.2e}); "
+        f"cost-2 decisions differing: gpu {flips:.4f}, probe {probe_flips:.4f}")
+    assert well.sum() >= 0.8 * both.sum()
+    assert err[well].max() <= 1e-4
+    assert err[both].max() <= 1e-3
+    assert flips <= probe_flips + 5e-3
+
+
 @pytest.mark.parametrize("t,colour,include_self", [(0, 0, 1), (1, 1, 0)])
 def test_squared_bilateral_pass_matches_oracle(amh, oracle_mod, scene_c1, t, colour, include_self):
-    # squared colour differences concentrate the weight on the few samples closest in intensity to the
-    # centre, and the float32 moments of so few effective samples carry cost errors up to ~1e-4 (measured
-    # 8.9e-5, against ~1e-6 with the printed weights): margin and cost bar 2e-4, and >= 98 % of all pixels
-    # keep the oracle's plane
+    """One half-pass with squared weights: a decision must clear the cost bar itself (1e-4) to count as robust;
+    on robust pixels exact agreement and the 1e-4 cost bar hold.  Over all pixels the GPU keeps the oracle's
+    plane at least as often as the oracle with costs moved within the bar does (cost_noise), less 0.5 %."""
     say("case pass squared bilateral", t, colour, include_self)
-    _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=9, refine=1, include_self=include_self, bil_sq=1,
-                 delta=2e-4, ctol=2e-4, min_plane=0.98)
+    _, _, gpu_keeps = _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=9, refine=1,
+                                   include_self=include_self, bil_sq=1, delta=1e-4, ctol=1e-4, min_plane=0.0)
+    O, sc = oracle_mod, scene_c1
+    V = O.Views.from_scene(sc)
+    P = O.Params(refine=1, seed=9, include_self=include_self, bilateral_sq=1)
+    Pn = O.Params(refine=1, seed=9, include_self=include_self, bilateral_sq=1, cost_noise=NOISE_AT_BAR)
+    st = O.init(V, P)
+    for tt in range(t):
+        O.run_pass(V, P, st, tt, 0)
+        O.run_pass(V, P, st, tt, 1)
+    if colour == 1:
+        O.run_pass(V, P, st, t, 0)
+    a, b = st.copy(), st.copy()
+    O.run_pass(V, P, a, t, colour)
+    O.run_pass(V, Pn, b, t, colour)
+    sel = (np.add.outer(np.arange(sc.height), np.arange(sc.width)) % 2) == colour
+    pa, pb = a.plane[sel], b.plane[sel]
+    noisy = float(np.all(np.abs(pa - pb) <= 1e-5 * (1 + np.abs(pa)), axis=-1).mean())
+    say(f"  oracle with costs within the bar keeps the plane on {noisy:.4f} of the pixels")
+    assert gpu_keeps >= noisy - 0.005
 
 
 @pytest.mark.parametrize("include_self", [1, 0])
-def test_squared_bilateral_full_run_accuracy(amh, oracle_mod, scene_c1, include_self):
-    """Full runs with squared weights: the near-ties of a single pass (1.3 % of the pixels keep a different
-    plane, against 0.1 % with the printed weights) spread over the iterations, so depth maps are compared
-    by their accuracy against the rendered depth: within 1 % and within 5 %, GPU and oracle within 2 points."""
+def test_squared_bilateral_full_run_accuracy(amh, oracle_mod, include_self):
+    """Full runs with squared weights, scene seeds 0-2: the probes show the method's result is not fixed at
+    float32 precision there (sample_f32 keeps < 99.5 % of the oracle's depths), so runs are compared by
+    accuracy against the rendered depth, within 1 % and within 5 %: on each seed the GPU's accuracy differs from
+    the exact oracle's by no more than the oracle's own with costs moved within the bar (cost_noise) does, plus
+    half a point."""
     say("case full run squared bilateral, include_self", include_self)
+    import scenegen
+
     O = oracle_mod
-    sc = scene_c1
-    with make_ctx(amh, sc, refine=1, seed=4, bilateral_squared=1, include_self=include_self) as ctx:
-        ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
-        depth, _, _ = ctx.get_depth_normal_cost()
-    V = O.Views.from_scene(sc)
-    st = O.run(V, O.Params(refine=1, seed=4, bilateral_sq=1, include_self=include_self), 3)
-    od, _ = O.depth_normal(V, st)
-    vis = sc.vis_count >= 2
-    g = np.abs(depth - sc.depth_gt)[vis] / sc.depth_gt[vis]
-    o = np.abs(od - sc.depth_gt)[vis] / sc.depth_gt[vis]
-    for tol in (0.01, 0.05):
-        say(f"  within {tol:.0%}: gpu {(g < tol).mean():.4f} oracle {(o < tol).mean():.4f}")
-        assert abs((g < tol).mean() - (o < tol).mean()) <= 0.02
-    if include_self:  # without the own plane a pixel can be left with a neighbour's plane out of range here
-        assert np.all((depth >= 2.0 - 1e-5) & (depth <= 6.0 + 1e-5))
+    probe_agree = []
+    for seed in (0, 1, 2):
+        sc = scenegen.config_scene("c1", seed)
+        with make_ctx(amh, sc, refine=1, seed=4, bilateral_squared=1, include_self=include_self) as ctx:
+            ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
+            depth, _, _ = ctx.get_depth_normal_cost()
+        V = O.Views.from_scene(sc)
+        run = lambda **kw: O.depth_normal(V, O.run(V, O.Params(refine=1, seed=4, bilateral_sq=1,
+                                                                   include_self=include_self, **kw), 3))[0]
+        od, pd, nd = run(), run(sample_f32=1), run(cost_noise=NOISE_AT_BAR)
+        vis = sc.vis_count >= 2
+        acc = lambda d, tol: float((np.abs(d - sc.depth_gt)[vis] < tol * sc.depth_gt[vis]).mean())
+        probe_agree.append(float((np.abs(pd - od) / od <= 1e-3).mean()))
+        for tol in (0.01, 0.05):
+            g, o, nz = acc(depth, tol), acc(od, tol), acc(nd, tol)
+            say(f"  seed {seed}, within {tol:.0%}: gpu {g:.4f}, oracle {o:.4f}, oracle with costs within the bar "
+                f"{nz:.4f}; float32 probe keeps {probe_agree[-1]:.4f} of the depths")
+            assert abs(g - o) <= abs(nz - o) + 0.005
+        if include_self:  # without the own plane a pixel can be left with a neighbour's plane out of range here
+            assert np.all((depth >= 2.0 - 1e-5) & (depth <= 6.0 + 1e-5))
+    assert min(probe_agree) < 0.995  # the premise
 
 
 def test_ablation_rejected_by_the_batched_path(amh, scene_c1):

@@ -257,11 +257,11 @@ def test_short_predicate_matches_oracle_early_exits():
             assert (c == 2.0) == bool(m[i, j]), (xy[i], j, c)
 
 
-def test_sample_f32_probe_only_rounds_the_samples(oracle_mod, scene_c1):
-    """The conditioning probe (sample_f32 = 1) changes nothing but the precision of the interpolated source
-    samples: where every sample lands on a texel (integer disparity) the samples are float32 values already
-    and the cost is unchanged; elsewhere it moves by no more than float32 rounding of the
-    samples can move a correlation (~1e-5 on the rendered scene), and it does move."""
+def test_sample_f32_probe_only_rounds_positions_and_samples(oracle_mod, scene_c1):
+    """The conditioning probe (sample_f32 = 1) changes nothing but the precision of the samples' source
+    positions (relative to the centre's texel) and interpolated values: where every sample lands on a texel
+    (integer disparity) both are float32 numbers already and the cost is unchanged; elsewhere it moves by no
+    more than float32 rounding of them can move a correlation (~1e-5 on the rendered scene), and it does move."""
     rng = np.random.default_rng(11)
     W, H, f, Z, B = 64, 40, 100.0, 4.0, 0.12
     K = np.array([[f, 0, (W - 1) / 2], [0, f, (H - 1) / 2], [0, 0, 1]])
@@ -287,3 +287,27 @@ def test_sample_f32_probe_only_rounds_the_samples(oracle_mod, scene_c1):
                 diffs.append(abs(a - b))
     diffs = np.array(diffs)
     assert diffs.max() <= 1e-4 and diffs.max() > 0.0
+
+
+def test_cost_noise_probe_is_bounded_deterministic_and_centred(oracle_mod, scene_c1):
+    """The second conditioning probe (cost_noise = e) moves every scored cost by a fixed offset in
+    [-e/2, e/2) that depends only on (pixel, view, plane); cost 2 and the clamp are untouched."""
+    O = oracle_mod
+    V = O.Views.from_scene(scene_c1)
+    P0, P1 = O.Params(), O.Params(cost_noise=2e-4)
+    rng = np.random.default_rng(3)
+    d = []
+    for _ in range(300):
+        x, y = int(rng.integers(5, V.W - 5)), int(rng.integers(5, V.H - 5))
+        plane = O.random_plane(V, P0, x, y, 7, 0)
+        for j in range(V.n_src):
+            a = O.matching_cost(V, P0, x, y, plane, j)
+            b = O.matching_cost(V, P1, x, y, plane, j)
+            assert b == O.matching_cost(V, P1, x, y, plane, j)
+            if a == 2.0:
+                assert b == 2.0
+            elif 1e-4 < a < 2.0 - 1e-4:
+                d.append(b - a)
+    d = np.array(d)
+    assert len(d) > 200 and np.all(np.abs(d) <= 1e-4)
+    assert abs(d.mean()) < 1e-5 and d.std() > 4e-5  # uniform on +-1e-4: std 5.8e-5
