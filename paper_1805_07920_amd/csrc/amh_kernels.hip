@@ -966,19 +966,18 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     }
     __syncthreads();
 
-    // (5) view inference, part 2 (every lane of the pixel, identical result):
-    //     S_t, v_t = argmax psi, modified importance (x2 for v_{t-1}), top-k,
-    //     0.2 for views that left the selection, uniform fallback (Eq. 4-6)
-    uint32_t Sm = 0, keep = 0;
+    // (5) view inference, part 2 (Eq. 4-6): S_t and v_t = argmax psi (every lane of the pixel, identical
+    //     result); then lane r sets the weights of views r, r+9, ...: a view of S_t keeps its modified
+    //     importance (x2 for v_{t-1}) when fewer than k views of S_t rank above it (larger modified
+    //     importance, or equal and a lower index: the k largest, ties to the lower index), a view of
+    //     S_{t-1} that left the selection weighs 0.2, every other view 0
+    uint32_t Sm = 0;
     int vt = -1;
     int vprev = -1;
-    uint32_t Sprev = 0;
-    float wsum = 0.f;
-    bool uniform = heur;
-    if (heur) wsum = (float)N;
+    float *wgt = S.wgt + (wave * kGroups + g) * kMaxSrc;
     if (pix_ok && !heur) {
         vprev = glob(a.st.v)[p];
-        Sprev = glob(a.st.S)[p];
+        const uint32_t Sprev = glob(a.st.S)[p];
         float best = 0.f;
         for (int j = 0; j < N; ++j) {
             const float ps = psi[j];
@@ -987,36 +986,35 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                 if (vt < 0 || ps > best) { vt = j; best = ps; }
             }
         }
-        for (int r = 0; r < m.k; ++r) {
-            int bj = -1;
-            float bm = 0.f;
-            for (int j = 0; j < N; ++j) {
-                if (!((Sm >> j) & 1u) || ((keep >> j) & 1u)) continue;
-                const float md = (j == vprev ? 2.f : 1.f) * psi[j];
-                if (bj < 0 || md > bm) { bj = j; bm = md; }
-            }
-            if (bj < 0) break;
-            keep |= 1u << bj;
-        }
-        for (int j = 0; j < N; ++j) {
-            if ((keep >> j) & 1u) wsum += (j == vprev ? 2.f : 1.f) * psi[j];
-            else if (!((Sm >> j) & 1u) && ((Sprev >> j) & 1u)) wsum += 0.2f;
-        }
-        uniform = !(wsum > 0.f);
-        if (uniform) wsum = (float)N;
-    }
-    // the weights of the pixel, shared through LDS (lane r writes views r, r+9, ...)
-    float *wgt = S.wgt + (wave * kGroups + g) * kMaxSrc;
-    if (pix_ok) {
         for (int j = row; j < N; j += kRows) {
             float wj = 0.f;
-            if (uniform) wj = 1.f;
-            else if ((keep >> j) & 1u) wj = (j == vprev ? 2.f : 1.f) * psi[j];
-            else if (!((Sm >> j) & 1u) && ((Sprev >> j) & 1u)) wj = 0.2f;
+            if ((Sm >> j) & 1u) {
+                const float mj = (j == vprev ? 2.f : 1.f) * psi[j];
+                int rank = 0;
+                for (int i = 0; i < N; ++i) {
+                    if (!((Sm >> i) & 1u)) continue;
+                    const float mi = (i == vprev ? 2.f : 1.f) * psi[i];
+                    rank += (mi > mj || (mi == mj && i < j)) ? 1 : 0;
+                }
+                if (rank < m.k) wj = mj;
+            } else if ((Sprev >> j) & 1u) {
+                wj = 0.2f;
+            }
             wgt[j] = wj;
         }
+    } else if (pix_ok) {  // heuristic selection (ablation): every view weighs 1
+        for (int j = row; j < N; j += kRows) wgt[j] = 1.f;
     }
     __syncthreads();
+    // the pixel's weight sum in view order; all weights 0: the plain mean over all views (uniform weights)
+    float wsum = 0.f;
+    if (pix_ok)
+        for (int j = 0; j < N; ++j) wsum += wgt[j];
+    const bool uniform = !(wsum > 0.f);
+    if (uniform) wsum = (float)N;
+    // made explicit for the refinement; meanwhile the pixel's lanes read 1 for every view when uniform
+    if (pix_ok && uniform)
+        for (int j = row; j < N; j += kRows) wgt[j] = 1.f;
 
     // (6) unified cost of the lane's hypothesis (Eq. 7)
     float mfin = __builtin_inff();
@@ -1025,68 +1023,74 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             mfin = mean_k_lowest(mcol + lane, 64, N, min(m.k, N));
         } else {
             float acc = 0.f;
-            for (int j = 0; j < N; ++j) acc = fmaf(wgt[j], mcol[j * 64 + lane], acc);
+            for (int j = 0; j < N; ++j) acc = fmaf(uniform ? 1.f : wgt[j], mcol[j * 64 + lane], acc);
             mfin = acc / wsum;
         }
     }
     S.mf[tid] = mfin;
     __syncthreads();
 
-    // (7) best hypothesis: own plane first, then region order; strictly lower wins
-    int brow = -1;
-    float bcost = 0.f;
+    // (7) best hypothesis: own plane first, then region order; strictly lower wins.  Only its row is kept
+    //     (its plane and cost stay in LDS): fewer registers live across the refinement's evaluations
+    int brow = 8;
     if (pix_ok) {
         const int base = wave * 64 + g * kRows;
-        if (S.valid[base + 8]) { brow = 8; bcost = S.mf[base + 8]; }
+        int br = -1;
+        float bc = 0.f;
+        if (S.valid[base + 8]) { br = 8; bc = S.mf[base + 8]; }
         for (int r = 0; r < 8; ++r) {
             if (!S.valid[base + r]) continue;
             const float c = S.mf[base + r];
-            if (brow < 0 || c < bcost) { brow = r; bcost = c; }
+            if (br < 0 || c < bc) { br = r; bc = c; }
         }
-        if (brow < 0) { brow = 8; bcost = S.mf[base + 8]; }  // no valid row at all (1-pixel image, no self)
+        brow = br < 0 ? 8 : br;  // no valid row at all (1-pixel image, no self): the own plane
     }
-    float4 best = pix_ok ? S.pl[wave * 64 + g * kRows + brow] : make_float4(0.f, 0.f, -1.f, 1.f);
+    const int bslot = wave * 64 + g * kRows + brow;
 
     // (8) refinement (Sec. 3.3): perturbed (and, from t = 3, random) depth/normal candidates,
     //     scored with the same weights on the views that carry weight; strictly lower wins
     int n_ref = 0;
+    float bcost = 0.f;  // cost of the kept hypothesis: the best row, or the candidate bcand that beat it
+    int bcand = -1;
     if (m.refine) {
         const int ncand = a.t >= 3 ? 6 : 3;
-        if (row == 0 && grp < kGroups) {
+        // the pixel's lanes share the set-up: lane 8 lists the active views, lane r < ncand builds candidate r
+        // (candidates: (dprt, n), (d, nprt), (dprt, nprt) [, (drnd, n), (d, nrnd), (drnd, nrnd)]; the
+        // perturbation draws come from stream 1, the random ones from stream 2, one draw per lane)
+        if (grp < kGroups && row == 8) {
             unsigned char *act = S.act + (wave * kGroups + g) * kMaxSrc;
-            float4 *cand = S.cand + (wave * kGroups + g) * 6;
             int c = 0;
-            if (pix_ok) {
+            if (pix_ok)
                 for (int j = 0; j < N; ++j)
                     if (wgt[j] > 0.f) act[c++] = (unsigned char)j;
-                // candidates: (dprt, n), (d, nprt), (dprt, nprt) [, (drnd, n), (d, nrnd), (drnd, nrnd)]
-                const float2 rr = ref_ray(a.ref, x, y);
-                const float dcur = plane_depth(rr, best);
-                const float rho = ldexpf(1.f, -(a.t + 2));
-                float ua[4];
-                philox(p, (uint64_t)a.t, 1, m.seed, ua);
-                float dprt = dcur + (2.f * ua[0] - 1.f) * rho * (m.d_max - m.d_min);
-                dprt = fminf(fmaxf(dprt, m.d_min), m.d_max);
-                float npx = best.x + 2.f * rho * (2.f * ua[1] - 1.f);
-                float npy = best.y + 2.f * rho * (2.f * ua[2] - 1.f);
-                float npz = best.z + 2.f * rho * (2.f * ua[3] - 1.f);
-                const float inv = 1.f / sqrtf(npx * npx + npy * npy + npz * npz);
-                npx *= inv; npy *= inv; npz *= inv;
-                cand[0] = plane_from(rr, dprt, best.x, best.y, best.z);
-                cand[1] = plane_from(rr, dcur, npx, npy, npz);
-                cand[2] = plane_from(rr, dprt, npx, npy, npz);
-                if (ncand == 6) {
-                    float ub[4], qx, qy, qz;
-                    philox(p, (uint64_t)a.t, 2, m.seed, ub);
-                    const float drnd = m.d_min + ub[0] * (m.d_max - m.d_min);
-                    normal_from_uniforms(ub[1], ub[2], qx, qy, qz);
-                    cand[3] = plane_from(rr, drnd, best.x, best.y, best.z);
-                    cand[4] = plane_from(rr, dcur, qx, qy, qz);
-                    cand[5] = plane_from(rr, drnd, qx, qy, qz);
-                }
-            }
             S.gnw[wave * 8 + g] = c;
             S.gws[wave * 8 + g] = make_float2(ws.invW, ws.var_a);
+        }
+        if (pix_ok && row < ncand) {
+            const float4 best = S.pl[bslot];
+            const bool rnd = row >= 3;
+            const int kind = rnd ? row - 3 : row;  // 0: (new depth, n), 1: (d, new normal), 2: both new
+            const float2 rr = ref_ray(a.ref, x, y);
+            const float dcur = plane_depth(rr, best);
+            float u[4];
+            philox(p, (uint64_t)a.t, rnd ? 2 : 1, m.seed, u);
+            float dnew, qx, qy, qz;
+            if (!rnd) {
+                const float rho = ldexpf(1.f, -(a.t + 2));
+                dnew = dcur + (2.f * u[0] - 1.f) * rho * (m.d_max - m.d_min);
+                dnew = fminf(fmaxf(dnew, m.d_min), m.d_max);
+                qx = best.x + 2.f * rho * (2.f * u[1] - 1.f);
+                qy = best.y + 2.f * rho * (2.f * u[2] - 1.f);
+                qz = best.z + 2.f * rho * (2.f * u[3] - 1.f);
+                const float inv = 1.f / sqrtf(qx * qx + qy * qy + qz * qz);
+                qx *= inv; qy *= inv; qz *= inv;
+            } else {
+                dnew = m.d_min + u[0] * (m.d_max - m.d_min);
+                normal_from_uniforms(u[1], u[2], qx, qy, qz);
+            }
+            S.cand[(wave * kGroups + g) * 6 + row] =
+                kind == 0 ? plane_from(rr, dnew, best.x, best.y, best.z)
+                          : plane_from(rr, kind == 1 ? dcur : dnew, qx, qy, qz);
         }
         __syncthreads();
         // The (candidate, active view) pairs of the wave's 7 pixels, numbered pixel by pixel, spread over
@@ -1125,9 +1129,9 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
         }
         __syncthreads();
         if (pix_ok) {
+            bcost = S.mf[bslot];
             const int nw = S.gnw[wave * 8 + g];
             const int pairs = ncand * nw;
-            const float4 *cand = S.cand + (wave * kGroups + g) * 6;
             const float *res = resw + g * (6 * N);
             if (row == 0) {
                 unsigned ns = 0;
@@ -1145,14 +1149,17 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                 }
                 if (cc < bcost) {
                     bcost = cc;
-                    best = cand[c];
+                    bcand = c;
                 }
             }
         }
+    } else if (pix_ok) {
+        bcost = S.mf[bslot];
     }
 
     // (9) write the pixel
     if (pix_ok && row == 0) {
+        const float4 best = bcand < 0 ? S.pl[bslot] : S.cand[(wave * kGroups + g) * 6 + bcand];
         store_plane(a.st.planes, p, best);
         glob(a.st.cost)[p] = bcost;
         glob(a.st.S)[p] = Sm;
