@@ -308,6 +308,16 @@ amh_status amh_nn_forward(amh_ctx *ctx, const void *feats, const float *q_ref, i
  * which synchronises the stream.  STATE without a forward pass. */
 amh_status amh_nn_backward(amh_ctx *ctx, const float *target, float *loss);
 
+/* Training targets of the proposal network from a depth map of the plain method:
+ * depth (H*W), normal (H*W*3) and cost (H*W, the final aggregated matching
+ * cost) of a width x height reference, device pointers -> target (device,
+ * [h][w][6], h = 8 ceil(H / 32), w = 8 ceil(W / 32)), for cell (i, j) the
+ * values at pixel (min(4j + 2, W - 1), min(4i + 2, H - 1)): depth, normal (3),
+ * and the confidence C(m) = exp(-m^2 / (2 beta^2)) of Eq. 3 twice (the
+ * confidence target and the weight of the depth and normal terms).  Stream-ordered. */
+amh_status amh_nn_targets(amh_ctx *ctx, const float *depth, const float *normal, const float *cost, int width,
+                          int height, float *target);
+
 /* One Adam step (Kingma & Ba, bias-corrected) with the last gradient. */
 amh_status amh_nn_adam_step(amh_ctx *ctx, float lr, float beta1, float beta2, float eps);
 
@@ -342,6 +352,22 @@ amh_status amh_sweep_features(amh_ctx *ctx, void *feats, float *q_ref);
  * amh_init_hypotheses.  Initial cost, S and v as there.  Replaces
  * amh_init_hypotheses after amh_begin. */
 amh_status amh_init_from_proposal(amh_ctx *ctx, const float *pred, int h, int w);
+
+/* Initial hypotheses from per-pixel estimates (for instance an earlier depth
+ * map, another reference's result warped here, or a learned predictor at full
+ * resolution), in place of the random initialisation (Sec. 3, the PatchMatch
+ * random start):  depth (H*W, camera z), normal (H*W*3, camera frame, any
+ * length and orientation) and conf (H*W, or NULL for all 1) of the current
+ * reference, in host (on_device = 0) or device memory (1).  Pixel (x, y) takes
+ * the plane through the point at its depth on its ray with its normal turned
+ * to face the camera when conf >= conf_min, the normal is non-zero and finite
+ * and the depth is finite and within [depth_min, depth_max]; otherwise the
+ * random plane of amh_init_hypotheses.  Initial cost (mean of the k lowest
+ * per-view costs), S and v as there.  Replaces amh_init_hypotheses after
+ * amh_begin; amh_pass continues from it.  Host inputs may be reused on return;
+ * device inputs must stay unchanged until the stream reaches this work. */
+amh_status amh_set_initial_hypotheses(amh_ctx *ctx, const float *depth, const float *normal, const float *conf,
+                                      int on_device);
 
 /* amh_begin + amh_sweep_features + amh_nn_forward + amh_init_from_proposal +
  * iters x (red pass, black pass).  The sweep reads the first min(4, n_src)

@@ -114,16 +114,19 @@ def sweep_reference_q(views: Views, params: Params) -> np.ndarray:
     return out
 
 
-def proposal_plane(views: Views, params: Params, x: int, y: int, depth, normal, conf, conf_min: float = 0.5):
-    """(plane, used) for pixel (x, y) from per-cell maps (h4, w4) and (h4, w4, 3)."""
+def proposal_plane(views: Views, params: Params, x: int, y: int, depth, normal, conf, conf_min: float = 0.5,
+                   cell: int = CELL):
+    """(plane, used) for pixel (x, y) from per-cell maps (h, w) and (h, w, 3) of cell x cell pixels (cell 1:
+    per-pixel hypotheses)."""
     H, W = views.H, views.W
-    i, j = y // CELL, x // CELL
+    i, j = y // cell, x // cell
     nv = np.asarray(normal[i, j], np.float64)
     nn = float(np.linalg.norm(nv))
     if conf[i, j] >= conf_min and np.isfinite(nn) and nn > 0.0 and np.isfinite(depth[i, j]):
         Ki = _kinv(views)
         n = nv / nn
-        Xc = float(depth[i, j]) * (Ki @ np.array([*sample_pixel(H, W, i, j), 1.0]))
+        sx, sy = min(cell * j + cell // 2, W - 1), min(cell * i + cell // 2, H - 1)
+        Xc = float(depth[i, j]) * (Ki @ np.array([sx, sy, 1.0]))
         dp = -float(n @ Xc)
         r = Ki @ np.array([x, y, 1.0])
         nr = float(n @ r)
@@ -136,15 +139,15 @@ def proposal_plane(views: Views, params: Params, x: int, y: int, depth, normal, 
     return random_plane(views, params, x, y, 0, 0), False
 
 
-def proposal_state(views: Views, params: Params, depth, normal, conf, conf_min: float = 0.5):
-    """(State, used mask) of proposal initialisation."""
+def proposal_state(views: Views, params: Params, depth, normal, conf, conf_min: float = 0.5, cell: int = CELL):
+    """(State, used mask) of proposal initialisation (cell 1: from per-pixel hypotheses)."""
     H, W, N = views.H, views.W, views.n_src
     kk = min(params.k, N)
     st = State.empty(H, W)
     used = np.zeros((H, W), bool)
     for y in range(H):
         for x in range(W):
-            pl, u = proposal_plane(views, params, x, y, depth, normal, conf, conf_min)
+            pl, u = proposal_plane(views, params, x, y, depth, normal, conf, conf_min, cell)
             st.plane[y, x] = pl
             used[y, x] = u
             c = sorted(matching_cost(views, params, x, y, pl, jv) for jv in range(N))

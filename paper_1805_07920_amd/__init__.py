@@ -29,6 +29,7 @@ EXPORTS = [
     "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
     "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config", "amh_run_batch_proposal",
     "amh_fusion_params_default", "amh_median_filter4", "amh_fuse", "amh_run_checkerboard_static",
+    "amh_set_initial_hypotheses", "amh_nn_targets",
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
@@ -121,6 +122,8 @@ def lib():
         L.amh_nn_load.argtypes = [vp, C.c_char_p]
         L.amh_sweep_features.argtypes = [vp, vp, vp]
         L.amh_init_from_proposal.argtypes = [vp, vp, ip, ip]
+        L.amh_set_initial_hypotheses.argtypes = [vp, vp, vp, vp, ip]
+        L.amh_nn_targets.argtypes = [vp, vp, vp, vp, ip, ip, vp]
         L.amh_run_proposal.argtypes = [vp, ip, C.POINTER(C.c_int), ip, ip]
         L.amh_set_launch_config.argtypes = [vp, ip]
         L.amh_run_batch_proposal.argtypes = [vp, ip, C.POINTER(amh_job)]
@@ -430,6 +433,21 @@ class Context:
                     "amh_nn_backward")
         return float(loss.value) if want_loss else None
 
+    def nn_targets(self, depth, normal, cost, out=None):
+        """amh_nn_targets: device maps (H, W), (H, W, 3), (H, W) -> device targets (h, w, 6)."""
+        import torch
+
+        H, W = depth.shape
+        h4, w4 = 8 * -(-H // 32), 8 * -(-W // 32)
+        if out is None:
+            out = torch.empty((h4, w4, 6), dtype=torch.float32, device=depth.device)
+        for t, n in ((depth, H * W), (normal, 3 * H * W), (cost, H * W), (out, h4 * w4 * 6)):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+                raise ValueError("nn_targets takes contiguous float32 device tensors of the documented sizes")
+        self._check(self.L.amh_nn_targets(self.h, depth.data_ptr(), normal.data_ptr(), cost.data_ptr(), W, H,
+                                          out.data_ptr()), "amh_nn_targets")
+        return out
+
     def nn_adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
         self._check(self.L.amh_nn_adam_step(self.h, lr, beta1, beta2, eps), "amh_nn_adam_step")
 
@@ -456,6 +474,22 @@ class Context:
         """pred: device float32 (h, w, 5) per-cell depth, normal, confidence."""
         h, w = int(pred.shape[0]), int(pred.shape[1])
         self._check(self.L.amh_init_from_proposal(self.h, _ptr(pred)[0], h, w), "amh_init_from_proposal")
+
+    def set_initial_hypotheses(self, depth, normal, conf=None):
+        """amh_set_initial_hypotheses: per-pixel depth (H, W), normal (H, W, 3) and optional confidence
+        (H, W), all numpy (host) or all device tensors."""
+        arrs = [depth, normal, conf]
+        if isinstance(depth, np.ndarray):
+            arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in arrs]
+        ptrs = [_ptr(a) for a in arrs]
+        devs = {d for p, d in ptrs if p is not None}
+        if len(devs) != 1:
+            raise ValueError("inputs must all be host or all device")
+        for a, per, name in ((arrs[0], 1, "depth"), (arrs[1], 3, "normal"), (arrs[2], 1, "conf")):
+            if a is not None and (a.size if isinstance(a, np.ndarray) else a.numel()) != self.H * self.W * per:
+                raise ValueError(f"{name} must hold {self.H * self.W * per} values")
+        self._check(self.L.amh_set_initial_hypotheses(self.h, ptrs[0][0], ptrs[1][0], ptrs[2][0], devs.pop()),
+                    "amh_set_initial_hypotheses")
 
     def run_proposal(self, ref: int, srcs, iters: int):
         s = (C.c_int * len(srcs))(*[int(v) for v in srcs])

@@ -1144,6 +1144,42 @@ amh_status amh_init_from_proposal(amh_ctx *c, const float *pred, int h, int w) {
     return init_state(c, pred, w, kCell);
 }
 
+amh_status amh_set_initial_hypotheses(amh_ctx *c, const float *depth, const float *normal, const float *conf,
+                                      int on_device) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (on_device != 0 && on_device != 1) return fail(c, AMH_E_INVALID_ARG, "on_device is 0 or 1");
+    if (!depth || !normal) return fail(c, AMH_E_INVALID_ARG, "depth and normal are required (conf may be NULL)");
+    if (c->ref < 0) return fail(c, AMH_E_STATE, "no reference selected (amh_begin)");
+    const size_t P = (size_t)c->refdev.W * c->refdev.H;
+    // packed [H][W][5] (depth, normal, confidence), followed by a staging copy of host inputs
+    const size_t need = P * (on_device ? 5 : 10);
+    if (need > c->hyp_cap) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->hyp) (void)hipFree(c->hyp);
+        c->hyp = nullptr;
+        c->hyp_cap = 0;
+        amh_status st = dalloc(c, (void **)&c->hyp, need * sizeof(float));
+        if (st != AMH_OK) return st;
+        c->hyp_cap = need;
+    }
+    float *packed = c->hyp;
+    const float *d = depth, *n = normal, *w = conf;
+    if (!on_device) {
+        float *stage = c->hyp + 5 * P;
+        HIPCHK(c, hipMemcpyAsync(stage, depth, P * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(stage + P, normal, P * 12, hipMemcpyHostToDevice, c->stream));
+        if (conf) HIPCHK(c, hipMemcpyAsync(stage + 4 * P, conf, P * 4, hipMemcpyHostToDevice, c->stream));
+        d = stage;
+        n = stage + P;
+        w = conf ? stage + 4 * P : nullptr;
+    }
+    HIPCHK(c, launch_pack_hypotheses(d, n, w, (int64_t)P, packed, c->stream));
+    amh_status st = init_state(c, packed, c->refdev.W, 1);
+    // host inputs: the caller may reuse its buffers once this returns
+    if (st == AMH_OK && !on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return st;
+}
+
 amh_status amh_run_proposal(amh_ctx *c, int ref, const int *srcs, int n_src, int iters) {
     if (!c) return AMH_E_INVALID_ARG;
     if (iters < 0 || iters > 1000) return fail(c, AMH_E_INVALID_ARG, "iters must be in 0..1000");
@@ -1241,6 +1277,7 @@ void amh_destroy(amh_ctx *c) {
     if (c->prop_feats) (void)hipFree(c->prop_feats);
     if (c->prop_pred) (void)hipFree(c->prop_pred);
     if (c->prop_qref) (void)hipFree(c->prop_qref);
+    if (c->hyp) (void)hipFree(c->hyp);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     for (auto e : c->ev_init)
         if (e) (void)hipEventDestroy(e);

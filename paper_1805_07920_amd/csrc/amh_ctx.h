@@ -90,6 +90,8 @@ struct amh_ctx {
     void *prop_feats = nullptr;   // amh_run_proposal: network input and prediction of the reference
     float *prop_pred = nullptr;
     float *prop_qref = nullptr;
+    float *hyp = nullptr;         // amh_set_initial_hypotheses: packed per-pixel hypotheses (+ host staging)
+    size_t hyp_cap = 0;           // floats
     size_t prop_cap = 0;          // cells
     // fusion workspace (amh_fuse): used marks, one view's dense outputs, tables
     void *fuse_ws = nullptr;

@@ -144,6 +144,8 @@ hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int ha
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s);
 hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s);
+hipError_t launch_pack_hypotheses(const float *depth, const float *normal, const float *conf, int64_t n, float *out,
+                                  hipStream_t s);
 hipError_t launch_score(const ScoreArgs &a, int half, hipStream_t s);
 hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, float *normal, float *cost,
                           hipStream_t s);

@@ -611,9 +611,10 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 }
 
 // ---------------------------------------------------------------------------
-// Plane of pixel (x, y) from the per-cell prediction of its 4 x 4 cell: through
-// the point at the predicted depth on the ray of the cell's sample pixel
-// (4j + 2, 4i + 2, clamped to the image), with the predicted normal turned to
+// Plane of pixel (x, y) from the prediction of its s x s cell (s = a.prop_s: 4
+// for the learned proposal, 1 for per-pixel hypotheses): through the point at
+// the predicted depth on the ray of the cell's sample pixel (s j + s / 2,
+// s i + s / 2, clamped to the image), with the predicted normal turned to
 // face the pixel's ray.  False (keep the random
 // plane) when the confidence is below conf_min, the normal is zero or not
 // finite, or the plane's depth along the pixel's ray leaves [d_min, d_max].
@@ -621,7 +622,8 @@ __device__ __forceinline__ void count_evals(unsigned long long *counters, int ki
 __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int x, int y, float4 &pl) {
     // explicit fused multiply-adds: the two initialisation kernels inline this function, and the
     // result must not depend on how the compiler contracts it at each call site
-    const int i = y / kCell, j = x / kCell;
+    const int cs = a.prop_s;
+    const int i = y / cs, j = x / cs;
     const float *pp = a.prop + ((size_t)i * a.prop_w + j) * 5;
     const float depth = pp[0], conf = pp[4];
     float nx = pp[1], ny = pp[2], nz = pp[3];
@@ -630,7 +632,7 @@ __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int 
     nx /= nn;
     ny /= nn;
     nz /= nn;
-    const float2 rc = ref_ray(a.ref, min(kCell * j + kCell / 2, a.ref.W - 1), min(kCell * i + kCell / 2, a.ref.H - 1));
+    const float2 rc = ref_ray(a.ref, min(cs * j + cs / 2, a.ref.W - 1), min(cs * i + cs / 2, a.ref.H - 1));
     float dp = __fmul_rn(-depth, fmaf(nx, rc.x, fmaf(ny, rc.y, nz)));
     float nr = fmaf(nx, r.x, fmaf(ny, r.y, nz));
     if (nr > 0.f) {
@@ -1442,6 +1444,19 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n) {
     if (i < n) p[i] = 0ull;
 }
 
+// per-pixel hypotheses (depth, normal, confidence) interleaved as the initialisation reads predictions
+__global__ void pack_hypotheses_kernel(const float *depth, const float *normal, const float *conf, int64_t n,
+                                       float *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float *o = out + i * 5;
+        o[0] = depth[i];
+        o[1] = normal[3 * i];
+        o[2] = normal[3 * i + 1];
+        o[3] = normal[3 * i + 2];
+        o[4] = conf ? conf[i] : 1.f;
+    }
+}
+
 __global__ void outputs_kernel(RefDev ref, StateDev st, float *depth, float *normal, float *cost) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= ref.W || y >= ref.H) return;
@@ -1470,6 +1485,14 @@ __global__ void outputs_kernel(RefDev ref, StateDev st, float *depth, float *nor
         (void)hipGetLastError();         \
         hipLaunchKernelGGL(__VA_ARGS__); \
     } while (0)
+
+hipError_t launch_pack_hypotheses(const float *depth, const float *normal, const float *conf, int64_t n, float *out,
+                                  hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    AMH_LAUNCH(pack_hypotheses_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, depth, normal,
+               conf, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_convert_to_f32(const void *src, int src_dtype, int64_t pitch, int W, int H, float *dst,
                                  hipStream_t s) {

@@ -56,6 +56,8 @@ hipError_t launch_loss(const float *z, const float *q_ref, const float *target, 
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, bf16_t *pb, int n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);
 hipError_t launch_to_bf16(const float *src, int n, bf16_t *dst, hipStream_t s);
+hipError_t launch_targets(const float *depth, const float *normal, const float *cost, int W, int H, int cell,
+                          int h4, int w4, float beta, float *target, hipStream_t s);
 
 }  // namespace nn
 }  // namespace amh

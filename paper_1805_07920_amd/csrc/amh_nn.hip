@@ -402,6 +402,36 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, bf16_t
     pb[e] = f2bf(pe);
 }
 
+// Training targets at the cell pixels (min(s j + s/2, W - 1), min(s i + s/2, H - 1)) of the network's grid of
+// s x s cells: depth,
+// normal, and the confidence C(m) = exp(-m^2 / (2 beta^2)) of Eq. 3 on the final matching cost m, twice (the
+// confidence target and the weight of the depth and normal terms).
+__global__ void targets_kernel(const float *depth, const float *normal, const float *cost, int W, int H, int cell,
+                               int h4, int w4, float inv_2b2, float *target) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= h4 * w4) return;
+    const int i = c / w4, j = c - i * w4;
+    const int x = min(cell * j + cell / 2, W - 1), y = min(cell * i + cell / 2, H - 1);
+    const size_t p = (size_t)y * W + x;
+    const float m = cost[p];
+    const float conf = expf(-m * m * inv_2b2);
+    float *t = target + (size_t)c * 6;
+    t[0] = depth[p];
+    t[1] = normal[3 * p];
+    t[2] = normal[3 * p + 1];
+    t[3] = normal[3 * p + 2];
+    t[4] = conf;
+    t[5] = conf;
+}
+
+hipError_t launch_targets(const float *depth, const float *normal, const float *cost, int W, int H, int cell,
+                          int h4, int w4, float beta, float *target, hipStream_t s) {
+    const int n = h4 * w4;
+    hipLaunchKernelGGL(targets_kernel, dim3((n + 255) / 256), dim3(256), 0, s, depth, normal, cost, W, H, cell, h4,
+                       w4, 1.f / (2.f * beta * beta), target);
+    return hipGetLastError();
+}
+
 __global__ void to_bf16_kernel(const float *src, int n, bf16_t *dst) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) dst[e] = f2bf(src[e]);

@@ -531,6 +531,17 @@ amh_status amh_nn_backward(amh_ctx *c, const float *target, float *loss) {
     return AMH_OK;
 }
 
+amh_status amh_nn_targets(amh_ctx *c, const float *depth, const float *normal, const float *cost, int width, int height,
+                          float *target) {
+    if (!c) return AMH_E_INVALID_ARG;
+    if (!depth || !normal || !cost || !target) return fail(c, AMH_E_INVALID_ARG, "depth, normal, cost and target are required");
+    if (width < 1 || height < 1 || width > kMaxImageSide || height > kMaxImageSide)
+        return fail(c, AMH_E_INVALID_ARG, "need 1 <= width, height <= %d", kMaxImageSide);
+    const int h4 = 8 * ((height + 31) / 32), w4 = 8 * ((width + 31) / 32);
+    HIPCHK(c, launch_targets(depth, normal, cost, width, height, kCell, h4, w4, c->p.beta, target, c->stream));
+    return AMH_OK;
+}
+
 amh_status amh_nn_adam_step(amh_ctx *c, float lr, float beta1, float beta2, float eps) {
     if (!c) return AMH_E_INVALID_ARG;
     if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) ||

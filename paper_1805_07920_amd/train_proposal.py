@@ -47,16 +47,6 @@ def scene_views(ctx, sc):
     ctx.init_views([torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in sc.images], sc.cams)
 
 
-def labels_of(depth, normal, cost, beta: float):
-    """(h, w, 6) targets at the cell pixels (4j + 2, 4i + 2) of device maps."""
-    c = amh.NET_CELL
-    d = depth[c // 2::c, c // 2::c]
-    n = normal[c // 2::c, c // 2::c]
-    m = cost[c // 2::c, c // 2::c]
-    conf = torch.exp(-m * m / (2.0 * beta * beta))
-    return torch.cat([d[..., None], n, conf[..., None], conf[..., None]], -1).contiguous()
-
-
 def nearest_first(sc):
     """Source indices by angular distance from the reference camera: the sweep reads the first few."""
     ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
@@ -78,7 +68,7 @@ def make_dataset(ctx, seeds, iters: int = 3, n_src=(8, 8)):
         normal = torch.empty((H, W, 3), device="cuda")
         cost = torch.empty((H, W), device="cuda")
         ctx.get_depth_normal_cost(depth, normal, cost)
-        targets.append(labels_of(depth, normal, cost, ctx.p.beta))
+        targets.append(ctx.nn_targets(depth, normal, cost))  # Eq. 3 on the device
         f, q = ctx.sweep_features()
         feats.append(f)
         qrefs.append(q)

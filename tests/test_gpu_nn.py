@@ -513,3 +513,33 @@ def test_allocation_failure_leaves_no_half_network(amh, monkeypatch):
         assert e.value.status == amh.AMH_E_STATE
         ctx.nn_init(1)  # later allocations succeed: a complete network
         assert ctx.nn_get_params().size == 196341
+
+
+def test_training_targets_match_oracle(amh):
+    """amh_nn_targets: depth, normal and Eq. 3's confidence C(m) of the final cost at every cell pixel,
+    on a ragged 70 x 45 map (cells past the image take its edge pixels)."""
+    say("case training targets")
+    import torch
+    from oracle import nn_oracle as nn
+
+    rng = np.random.default_rng(8)
+    H, W = 45, 70
+    depth = rng.uniform(2, 6, (H, W)).astype(np.float32)
+    normal = rng.standard_normal((H, W, 3)).astype(np.float32)
+    cost = rng.uniform(0, 2, (H, W)).astype(np.float32)
+    cost[0, 2] = 0.0
+    cost[2, 2] = 2.0
+    with amh.Context(beta=0.3) as ctx:
+        d = lambda a: torch.from_numpy(a).cuda()
+        t = ctx.nn_targets(d(depth), d(normal), d(cost)).cpu().numpy()
+        with pytest.raises(ValueError):
+            ctx.nn_targets(d(depth), d(normal[:-1]), d(cost))
+    h4, w4 = 8 * -(-H // 32), 8 * -(-W // 32)
+    assert t.shape == (h4, w4, 6)
+    ys = np.minimum(4 * np.arange(h4) + 2, H - 1)
+    xs = np.minimum(4 * np.arange(w4) + 2, W - 1)
+    np.testing.assert_array_equal(t[..., 0], depth[np.ix_(ys, xs)])
+    np.testing.assert_array_equal(t[..., 1:4], normal[np.ix_(ys, xs)])
+    want = nn.confidence_target(cost[np.ix_(ys, xs)].astype(np.float64), 0.3)
+    np.testing.assert_allclose(t[..., 4], want, rtol=2e-6, atol=1e-7)
+    np.testing.assert_array_equal(t[..., 4], t[..., 5])

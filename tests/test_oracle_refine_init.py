@@ -229,3 +229,41 @@ def test_refinement_keeps_the_plane_on_exact_ties(oracle_mod, scene_c1):
             assert d.chosen == 8 and d.S == 0 and d.v == -1
         assert np.array_equal(st.plane, pre.plane)
         assert np.all(st.cost == 2.0)
+
+
+def test_per_pixel_hypotheses_pass_through_their_point(oracle_mod, scene_c1):
+    """Initial hypotheses from per-pixel estimates (cells of one pixel): a confident, in-range pixel's plane
+    passes through the point at its depth on its own ray with its normal (unit, facing the camera); the
+    others keep the random plane; the cost is the initial cost of that plane."""
+    from oracle import proposal
+
+    O, sc = oracle_mod, scene_c1
+    V = O.Views.from_scene(sc)
+    P = O.Params(seed=4)
+    H, W = sc.height, sc.width
+    rng = np.random.default_rng(5)
+    depth = sc.depth_gt.astype(np.float64) * (1 + rng.uniform(-0.01, 0.01, (H, W)))
+    depth[3, 4] = 7.0  # out of range
+    depth[5, 6] = np.nan
+    normal = sc.normal_gt.astype(np.float64) * rng.choice([-2.0, 0.5], (H, W, 1))  # any length, either sign
+    normal[7, 8] = 0.0
+    conf = rng.uniform(0, 1, (H, W))
+    st, used = proposal.proposal_state(V, P, depth, normal, conf, conf_min=0.5, cell=1)
+    Kinv = np.linalg.inv(sc.cams[0].K)
+    for y, x in [(3, 4), (5, 6), (7, 8)]:
+        assert not used[y, x]
+    assert np.array_equal(used, (conf >= 0.5) & used)
+    assert 0.4 < used.mean() < 0.6
+    for y in range(0, H, 5):
+        for x in range(0, W, 3):
+            pl = st.plane[y, x]
+            if used[y, x]:
+                d, r = depth_of(Kinv, x, y, pl)
+                assert d == pytest.approx(depth[y, x], rel=1e-12)
+                n = normal[y, x] / np.linalg.norm(normal[y, x])
+                np.testing.assert_allclose(np.abs(pl[:3] @ n), 1.0, atol=1e-12)
+                assert pl[:3] @ r < 0
+            else:
+                assert np.array_equal(pl, O.random_plane(V, P, x, y, 0, 0))
+            c = np.sort([O.matching_cost(V, P, x, y, pl, j) for j in range(V.n_src)])[:4].mean()
+            assert st.cost[y, x] == pytest.approx(c, rel=1e-12, abs=1e-15)
