@@ -163,7 +163,9 @@ def bench_batch(args):
     log(f"32 scenes rendered in {time.time() - t0:.1f} s")
     ctx = amh.Context(refine=1, seed=args.seed)
     ctx.init_views(images, cams)
+    log("autotuning the batch's launch configurations")
     best, tune_ms = ctx.tune(jobs)
+    log(f"autotune: config {best}, ms per configuration {np.round(tune_ms, 1).tolist()}")
     for _ in range(max(1, args.warmup)):
         ctx.run_batch(jobs)
     torch.cuda.synchronize()

@@ -241,18 +241,26 @@ amh_status amh_get_job_times(amh_ctx *ctx, int n, float *job_ms);
 
 /* Autotuner: times the batch under each launch configuration -- tile order (XCD
  * bands or hardware order) x job order (as given or largest first) x tile shape
- * of the half-pass (4 or 2 image rows per workgroup); configuration =
- * tile_order + 2 * job_order + 4 * (two-row tiles) -- keeps the fastest for the
- * following launches of this context (single images included) and returns it in
- * *best_config (may be NULL) with the measured ms in ms_per_config[8] (may be
- * NULL; -1 where not measured).  If the environment variable AMH_TUNE_CACHE
+ * of the half-pass (4 or 2 image rows per workgroup) x the batch's half-passes
+ * launched one per phase or all in one persistent launch; configuration =
+ * tile_order + 2 * job_order + 4 * (two-row tiles) + 8 * persistent -- keeps the
+ * fastest for the following launches of this context (single images included)
+ * and returns it in *best_config (may be NULL) with the measured ms in
+ * ms_per_config[16] (may be NULL; -1 where not measured).  The persistent
+ * launch runs every half-pass of every job in one kernel: each XCD's workgroups
+ * take tiles from that XCD's bands of every job through a device-scope
+ * counter, and the half-passes are separated by a grid barrier (device-scope
+ * release, arrival count, acquire), so its grid is sized to the workgroups
+ * that are resident at once; every wait is bounded, and a barrier that runs out
+ * (workgroups not all resident, e.g. other work on the GPU) is reported as
+ * AMH_E_HIP by amh_get_job_result, amh_get_job_times and amh_get_stats.  If the environment variable AMH_TUNE_CACHE
  * names a file, the choice is looked up there by shape bucket (job count,
  * largest view count, pixel count) and appended after tuning. */
 amh_status amh_tune(amh_ctx *ctx, int n_jobs, const amh_job *jobs, int *best_config, float *ms_per_config);
 
-/* Sets the launch configuration (0..7, numbered as for amh_tune) for the
+/* Sets the launch configuration (0..15, numbered as for amh_tune) for the
  * following launches of this context; results do not depend on it.
- * INVALID_ARG outside 0..7. */
+ * INVALID_ARG outside 0..15. */
 amh_status amh_set_launch_config(amh_ctx *ctx, int config);
 
 /* Work counters and timings of the current reference (or of the last batch). */

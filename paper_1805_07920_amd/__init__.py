@@ -33,7 +33,9 @@ EXPORTS = [
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
-N_TUNE_CONFIGS = 8  # tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2}
+# tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2} x batch half-passes
+# {one launch each, one persistent launch}
+N_TUNE_CONFIGS = 16
 
 
 class AmhError(RuntimeError):

@@ -285,12 +285,13 @@ amh_status ensure_events(amh_ctx *c, int n) {
 
 // launch configurations: tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2};
 // configuration = tile_order + 2 job_order + 4 (tile rows == 2)
-constexpr int kTuneConfigs = 8;
+constexpr int kTuneConfigs = 16;
 
 void apply_config(amh_ctx *c, int cfg) {
     c->cfg_order = cfg & 1;
     c->cfg_job_order = (cfg >> 1) & 1;
     c->cfg_waves = (cfg & 4) ? 2 : kDefaultTileRows;
+    c->cfg_persist = (cfg >> 3) & 1;
 }
 
 amh_status check_jobs(amh_ctx *c, int n_jobs, const amh_job *jobs) {
@@ -323,10 +324,24 @@ void free_batch(amh_ctx *c) {
     if (c->d_bviews) (void)hipFree(c->d_bviews);
     if (c->d_tables) (void)hipFree(c->d_tables);
     if (c->d_bcount) (void)hipFree(c->d_bcount);
+    if (c->d_persist) (void)hipFree(c->d_persist);
     c->d_jobs = nullptr;
     c->d_bviews = nullptr;
     c->d_tables = nullptr;
     c->d_bcount = nullptr;
+    c->d_persist = nullptr;
+    c->d_pfault = nullptr;
+}
+
+// A persistent batch whose grid barrier ran out of time (its workgroups were not all resident) leaves a
+// flag; the calls that read a batch's results report it.
+amh_status check_persist_fault(amh_ctx *c) {
+    if (!c->d_pfault) return AMH_OK;
+    unsigned f = 0;
+    HIPCHK(c, hipMemcpyAsync(&f, c->d_pfault, sizeof f, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f) return fail(c, AMH_E_HIP, "persistent batch: a grid barrier timed out (workgroups not all resident)");
+    return AMH_OK;
 }
 
 // Builds the device tables of a batch and captures its phases into a graph:
@@ -463,10 +478,25 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
     };
     add_phase(0, 0, 0);
     add_phase(0, 1, 0);
-    for (int t = 0; t < max_iters; ++t) {
-        add_phase(1, 0, t);
-        add_phase(1, 1, t);
-    }
+    // persistent launch: the half-passes of all jobs as phases of one kernel, all jobs in one LDS class
+    // (the largest view count), tiles in per-XCD bands
+    std::vector<Phase> pphases;
+    for (int t = 0; t < max_iters; ++t)
+        for (int colour = 0; colour < 2; ++colour) {
+            if (!c->cfg_persist) {
+                add_phase(1, colour, t);
+                continue;
+            }
+            std::vector<int> act;
+            for (int j : order)
+                if (jobs[j].iters > t) act.push_back(j);
+            const size_t before = phases.size();
+            add_group(1, colour, t, act);
+            if (phases.size() > before) {
+                pphases.push_back(phases.back());
+                phases.pop_back();
+            }
+        }
     if ((st = dalloc(c, (void **)&c->d_tables, sizeof(int) * tab.size())) != AMH_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->d_bviews, hv.data(), sizeof(ViewDev) * total_src, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_jobs, hj.data(), sizeof(BatchJobDev) * n_jobs, hipMemcpyHostToDevice, c->stream));
@@ -476,13 +506,94 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         for (int j = 0; j < n_jobs; ++j) most = std::max(most, c->jobs[j].cells);
         if ((st = nn_reserve(c, most)) != AMH_OK) return st;  // before capture: may allocate
     }
+    unsigned long long *tiles_done = c->d_bcount + kCounterKinds * kCounterSlots;
+    unsigned long long *clocks = tiles_done + n_jobs;  // [n_jobs] completion, [n_jobs] start
+    // persistent launch: its arguments and phase table in device memory, then the counters it clears
+    // (next tile of each XCD's queue per phase, barrier arrivals, fault flag) as 64-bit words
+    const int n_pp = (int)pphases.size();
+    int p_grid = 0;
+    PersistArgs *d_pargs = nullptr;
+    unsigned long long *d_psync = nullptr;
+    size_t n_psync = 0;
+    if (n_pp > 0) {
+        int cus = 0, khz = 0;
+        HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        HIPCHK(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+        const int per_cu = persist_blocks_per_cu(c->half, c->cfg_waves, max_src);
+        if (per_cu < 1 || cus < 1 || khz <= 0)
+            return fail(c, AMH_E_UNSUPPORTED, "persistent batch: no resident workgroup fits (%d per CU)", per_cu);
+        int most_tiles = 0;
+        for (const Phase &ph : pphases) most_tiles = std::max(most_tiles, ph.total);
+        // every workgroup must be resident at once (grid barrier): at most one per free slot, a multiple of 8
+        p_grid = std::max(8, (std::min(per_cu * cus, most_tiles + 7) / 8) * 8);
+        const size_t o_args = 0, o_ph = 256, o_sync = o_ph + ((sizeof(PersistPhase) * n_pp + 255) & ~(size_t)255);
+        n_psync = ((size_t)n_pp * 8 + 2 + 1) / 2;
+        if ((st = dalloc(c, &c->d_persist, o_sync + n_psync * 8)) != AMH_OK) return st;
+        unsigned char *base = static_cast<unsigned char *>(c->d_persist);
+        d_pargs = reinterpret_cast<PersistArgs *>(base + o_args);
+        PersistPhase *d_ph = reinterpret_cast<PersistPhase *>(base + o_ph);
+        d_psync = reinterpret_cast<unsigned long long *>(base + o_sync);
+        unsigned *sync32 = reinterpret_cast<unsigned *>(d_psync);
+        std::vector<PersistPhase> hp(n_pp);
+        for (int i = 0; i < n_pp; ++i) {
+            const Phase &ph = pphases[i];
+            PersistPhase &q = hp[i];
+            q.tile_start = c->d_tables + ph.off;
+            q.job_of = c->d_tables + ph.off + ph.n_active + 1;
+            q.is_last = c->d_tables + ph.off + 2 * ph.n_active + 1;
+            q.xcd_pre = c->d_tables + ph.off + 3 * ph.n_active + 1;
+            q.n_active = ph.n_active;
+            q.total_tiles = ph.total;
+            q.t = ph.t;
+            q.colour = ph.colour;
+            q.m = method_dev(c->p, ph.t);
+        }
+        PersistArgs pa;
+        pa.jobs = c->d_jobs;
+        pa.views = c->d_bviews;
+        pa.phases = d_ph;
+        pa.n_phases = n_pp;
+        pa.conf_min = c->p.conf_min;
+        pa.counters = c->d_bcount;
+        pa.tiles_done = tiles_done;
+        pa.job_end = clocks;
+        pa.next = sync32;
+        pa.arrived = sync32 + (size_t)n_pp * 8;
+        pa.fault = sync32 + (size_t)n_pp * 8 + 1;
+        pa.spin_limit = (unsigned long long)khz * 1000ull * 4ull;  // 4 s of device clock per wait
+        pa.probe = 0;
+        pa.probe_ticks = (unsigned long long)khz * 20ull;  // 20 ms
+        c->d_pfault = pa.fault;
+        HIPCHK(c, hipMemcpyAsync(d_ph, hp.data(), sizeof(PersistPhase) * n_pp, hipMemcpyHostToDevice, c->stream));
+        // the grid barrier needs every workgroup resident at once: the occupancy figure is checked once per
+        // shape by a probe launch of the same kernel (residency can also be limited by scratch or reserved CUs)
+        int resident = -1;
+        for (const auto &r : c->persist_resident)
+            if (r[0] == c->half && r[1] == c->cfg_waves && r[2] == max_src && r[3] == p_grid) resident = r[4];
+        if (resident < 0) {
+            PersistArgs probe = pa;
+            probe.probe = 1;
+            HIPCHK(c, launch_zero_u64(d_psync, (int)n_psync, c->stream));
+            HIPCHK(c, hipMemcpyAsync(d_pargs, &probe, sizeof probe, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, launch_persist(d_pargs, c->half, c->cfg_waves, max_src, p_grid, c->stream));
+            unsigned peak = 0;
+            HIPCHK(c, hipMemcpyAsync(&peak, reinterpret_cast<unsigned *>(d_psync) + 2, sizeof peak,
+                                     hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            resident = (int)peak;
+            c->persist_resident.push_back({c->half, c->cfg_waves, max_src, p_grid, resident});
+        }
+        if (resident < p_grid) p_grid = (resident / 8) * 8;
+        if (p_grid < 8)
+            return fail(c, AMH_E_UNSUPPORTED, "persistent batch: only %d workgroups resident at once", resident);
+        HIPCHK(c, hipMemcpyAsync(d_pargs, &pa, sizeof pa, hipMemcpyHostToDevice, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     // capture (kernels only: counters are cleared by a kernel, not a memset)
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    unsigned long long *tiles_done = c->d_bcount + kCounterKinds * kCounterSlots;
-    unsigned long long *clocks = tiles_done + n_jobs;  // [n_jobs] completion, [n_jobs] start
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_zero_u64(c->d_bcount, kCounterKinds * kCounterSlots + n_jobs, c->cap_stream);
+    if (e == hipSuccess && n_psync) e = launch_zero_u64(d_psync, (int)n_psync, c->cap_stream);
     if (e == hipSuccess) e = launch_stamp(clocks + n_jobs, c->cap_stream);
     // learned proposal: sweep and network forward of every job before its initialisation
     for (int j = 0; proposal && j < n_jobs && e == hipSuccess; ++j) {
@@ -517,6 +628,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         b.job_end = clocks;
         e = launch_batch(b, c->half, ph.max_src, c->cap_stream);
     }
+    if (e == hipSuccess && n_pp > 0) e = launch_persist(d_pargs, c->half, c->cfg_waves, max_src, p_grid, c->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -980,7 +1092,7 @@ static amh_status run_batch_impl(amh_ctx *c, int n_jobs, const amh_job *jobs, bo
     if (proposal && !c->net) return fail(c, AMH_E_STATE, "no proposal network (amh_nn_init or amh_nn_load)");
     if (c->p.sym_prop || c->p.heuristic_views)
         return fail(c, AMH_E_UNSUPPORTED, "the ablation modes run on the single-image path only");
-    std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order, c->cfg_waves, proposal ? 1 : 0};
+    std::vector<int> key = {n_jobs, c->cfg_order, c->cfg_job_order, c->cfg_waves, c->cfg_persist, proposal ? 1 : 0};
     for (int j = 0; j < n_jobs; ++j) {
         key.push_back(jobs[j].ref);
         key.push_back(jobs[j].n_src);
@@ -1032,7 +1144,7 @@ amh_status amh_get_job_result(amh_ctx *c, int job, float *depth, float *normal, 
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(c, AMH_E_HIP, "get_job_result: %s", hipGetErrorString(e));
-    return AMH_OK;
+    return check_persist_fault(c);
 }
 
 amh_status amh_get_job_times(amh_ctx *c, int n, float *job_ms) {
@@ -1040,6 +1152,8 @@ amh_status amh_get_job_times(amh_ctx *c, int n, float *job_ms) {
     if (!c->batch_ran) return fail(c, AMH_E_STATE, "no batch has run");
     if (!job_ms || n != c->batch_jobs) return fail(c, AMH_E_INVALID_ARG, "need n == the batch's job count");
     if (!c->d_bcount) return fail(c, AMH_E_STATE, "the batch's clocks were released (parameters changed)");
+    amh_status fs = check_persist_fault(c);
+    if (fs != AMH_OK) return fs;
     // clocks: [n] job completions then the batch start, after the evaluation counters and tiles-done
     std::vector<unsigned long long> h((size_t)n + 1);
     const size_t off = kCounterKinds * (size_t)kCounterSlots + (size_t)n;
@@ -1073,7 +1187,7 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
         px += (double)c->views[jobs[j].ref].W * c->views[jobs[j].ref].H;
     }
     char bucket[128];
-    snprintf(bucket, sizeof bucket, "gfx950/cfg8/jobs%d/src%d/px2^%d/half%d", n_jobs, max_src,
+    snprintf(bucket, sizeof bucket, "gfx950/cfg16/jobs%d/src%d/px2^%d/half%d", n_jobs, max_src,
              (int)std::ceil(std::log2(px + 1)), c->half);
     const char *path = getenv("AMH_TUNE_CACHE");
     int cached = -1;
@@ -1097,7 +1211,9 @@ amh_status amh_tune(amh_ctx *c, int n_jobs, const amh_job *jobs, int *best_confi
         float best_ms = 0.f;
         for (int cfg = 0; cfg < kTuneConfigs; ++cfg) {
             apply_config(c, cfg);
-            if ((st = amh_run_batch(c, n_jobs, jobs)) != AMH_OK) return st;  // build + warm
+            st = amh_run_batch(c, n_jobs, jobs);  // build + warm
+            if (st == AMH_E_UNSUPPORTED && c->cfg_persist) continue;  // the persistent grid does not fit
+            if (st != AMH_OK) return st;
             HIPCHK(c, hipEventRecord(e0, c->stream));
             if ((st = amh_run_batch(c, n_jobs, jobs)) != AMH_OK) return st;  // replay, timed
             HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -1218,6 +1334,8 @@ amh_status amh_get_stats(const amh_ctx *cc, amh_stats *out) {
         std::vector<unsigned long long> h(kCounterKinds * kCounterSlots);
         HIPCHK(c, hipMemcpyAsync(h.data(), c->d_bcount, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        amh_status fs = check_persist_fault(c);
+        if (fs != AMH_OK) return fs;
         for (int k = 0; k < kCounterKinds; ++k) {
             c->batch_counts[k] = 0;
             for (int i = 0; i < kCounterSlots; ++i) c->batch_counts[k] += h[k * kCounterSlots + i];

@@ -71,6 +71,7 @@ struct amh_ctx {
     int cfg_order = 0;
     int cfg_job_order = 1;
     int cfg_waves = kDefaultTileRows;  // tile rows of the half-pass (2 or 4)
+    int cfg_persist = 0;               // batches: every half-pass in one persistent launch (1) or one launch each
     // batch: per-job state, device tables and the captured graph of the last job list
     std::vector<JobResult> jobs;
     std::vector<int> batch_key;       // serialized job list of the captured graph
@@ -81,6 +82,10 @@ struct amh_ctx {
     ViewDev *d_bviews = nullptr;
     int *d_tables = nullptr;
     unsigned long long *d_bcount = nullptr;  // [kCounterKinds * kCounterSlots] counts, [n_jobs] tiles done, [n_jobs + 1] clocks
+    void *d_persist = nullptr;  // persistent launch: PersistArgs, PersistPhase table, work / barrier / fault counters
+    unsigned *d_pfault = nullptr;  // ... its fault flag (inside d_persist)
+    // workgroups of the persistent kernel measured resident at once, per (half, tile rows, largest view count)
+    std::vector<std::vector<int>> persist_resident;
     int batch_jobs = 0;
     bool batch_ran = false;
     bool batch_stats = false;

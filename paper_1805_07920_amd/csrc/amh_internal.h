@@ -107,6 +107,37 @@ struct BatchPhaseArgs {
     unsigned long long *job_end; // [n_jobs] device clock at the job's completion
 };
 
+// One phase of the persistent batched launch: the tables of BatchPhaseArgs, with every job of the phase
+// in one LDS class (the launch's).
+struct PersistPhase {
+    const int *tile_start, *job_of, *is_last, *xcd_pre;
+    int n_active, total_tiles;
+    int t, colour;
+    MethodDev m;
+};
+
+// The persistent batched launch: every half-pass of every job in one kernel.  Workgroup b serves the queue of
+// XCD b mod 8 (that XCD's bands of every job, as tile order 0 of the per-phase launches), taking tiles with
+// a device-scope counter; the phases are separated by a grid barrier (device-scope release, arrival count,
+// acquire).  Every wait is bounded by spin_limit device-clock ticks; a wait that runs out sets *fault and
+// every workgroup leaves (reported by the host as an error).
+struct PersistArgs {
+    const BatchJobDev *jobs;
+    const ViewDev *views;
+    const PersistPhase *phases;  // [n_phases]
+    int n_phases;
+    float conf_min;
+    unsigned long long *counters, *tiles_done, *job_end;
+    unsigned *next;              // [n_phases][8] tiles taken from each XCD's queue
+    unsigned *arrived;           // grid-barrier arrivals (monotonic over the phases)
+    unsigned *fault;
+    unsigned long long spin_limit;
+    // residency probe (probe = 1): every workgroup counts in (next[0]), waits up to probe_ticks for the
+    // whole grid to be in at once, records the most it saw resident together (next[2]), counts out (next[1])
+    int probe;
+    unsigned long long probe_ticks;
+};
+
 constexpr int kSweepCoarse = 12;  // coarse inverse-depth bins of the proposal's input sweep
 constexpr int kNetSrc = 4;        // sources the sweep reads
 constexpr int kSweepK = 2;        // aggregate: mean of the kSweepK lowest costs
@@ -144,6 +175,8 @@ hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int ha
 hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s);
 hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s);
+hipError_t launch_persist(const PersistArgs *a, int half, int waves, int max_src, int grid, hipStream_t s);
+int persist_blocks_per_cu(int half, int waves, int max_src);
 hipError_t launch_pack_hypotheses(const float *depth, const float *normal, const float *conf, int64_t n, float *out,
                                   hipStream_t s);
 hipError_t launch_score(const ScoreArgs &a, int half, hipStream_t s);

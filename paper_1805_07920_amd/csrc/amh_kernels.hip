@@ -570,8 +570,8 @@ __device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int wav
 
 // reference tile of a workgroup: rows y0-5 .. y0+WAVES+4, cols x0-5 .. x0+2*kTilePix+4, clamped
 template <int WAVES>
-__device__ __forceinline__ void stage_tile(const RefDev &ref, float *tile, int y0, int x0) {
-    for (int i = threadIdx.x; i < (WAVES + 10) * kTileW; i += blockDim.x) {
+__device__ __forceinline__ void stage_tile(const RefDev &ref, float *tile, int y0, int x0, int tid) {
+    for (int i = tid; i < (WAVES + 10) * kTileW; i += 64 * WAVES) {
         const int ty = i / kTileW, tx = i - ty * kTileW;
         const int gy = min(max(y0 - 5 + ty, 0), ref.H - 1);
         const int gx = min(max(x0 - 5 + tx, 0), ref.W - 1);
@@ -666,7 +666,7 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
     const int x = 2 * (tx * kTilePix + grp) + ((y + a.colour) & 1);
     const bool pix_ok = grp < kGroups && y < a.ref.H && x < a.ref.W;
 
-    stage_tile<WAVES>(a.ref, S.tile, y0, x0);
+    stage_tile<WAVES>(a.ref, S.tile, y0, x0, tid);
     if (lane == 0) S.nshort[wave] = 0u;
     __syncthreads();
     float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * kWinStride;
@@ -853,10 +853,12 @@ __device__ __forceinline__ float mean_k_lowest(const float *c, int stride, int n
 // neighbour at distance 1 (r < 4) or 5 (r >= 4) up/down/left/right, the fast
 // pattern of Fig. 2(c)) and m.heuristic (each hypothesis, and each refinement
 // candidate, costs the mean of its own k lowest per-view costs; no selection memory).
+// tid: threadIdx.x (the persistent launch passes it through an opaque copy, so that nothing derived from
+// it is kept live across its tiles)
 template <int HALF, int WAVES, bool ABL = false>
-__device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned char *smem) {
+__device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned char *smem, int tid) {
     PassLds S = carve(smem, a.n_src, WAVES);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wave = tid >> 6, lane = tid & 63;
     const int grp = lane / kRows, row = lane - grp * kRows;
     const int g = grp < kGroups ? grp : 0;
     const int ty = L / a.tiles_x, tx = L - ty * a.tiles_x;
@@ -869,7 +871,7 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     const int N = a.n_src;
     const MethodDev &m = a.m;
 
-    stage_tile<WAVES>(a.ref, S.tile, y0, x0);
+    stage_tile<WAVES>(a.ref, S.tile, y0, x0, tid);
 
     // (1) asymmetric propagation: lane r < 8 takes the lowest-cost candidate of region r
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
@@ -1182,7 +1184,7 @@ void pass_kernel(PassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = tile_of_block(a.n_tiles, a.order);
     if (L < 0) return;
-    pass_body<HALF, WAVES, ABL>(a, L, smem);
+    pass_body<HALF, WAVES, ABL>(a, L, smem, (int)threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1268,7 +1270,7 @@ void batch_kernel(BatchPhaseArgs b) {
     // read like the single-image kernels read theirs (scalar loads from a kernel-argument buffer)
     a.views = b.views + __builtin_amdgcn_readfirstlane(J.view_off);
     if (KIND == 0) init_body<HALF, WAVES>(a, L, smem);
-    else pass_body<HALF, WAVES>(a, L, smem);
+    else pass_body<HALF, WAVES>(a, L, smem, (int)threadIdx.x);
     if (b.is_last[lo]) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1276,6 +1278,126 @@ void batch_kernel(BatchPhaseArgs b) {
             if (atomicAdd(&b.tiles_done[j], 1ull) == (unsigned long long)(J.n_tiles - 1))
                 b.job_end[j] = wall_clock64();
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launch (see PersistArgs): one kernel runs every
+// half-pass of every job (the two initialisation phases before it are
+// ordinary batched launches).
+// ---------------------------------------------------------------------------
+// Grid barrier between phases: every thread releases its writes at device scope, the workgroup counts its
+// arrival, waits (bounded) until `target` workgroups arrived, and acquires.  False when a wait ran out.
+__device__ __forceinline__ bool grid_barrier(const PersistArgs *P, unsigned target, int *s_ok) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(P->arrived, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t0 = wall_clock64();
+        int ok = 1;
+        while (__hip_atomic_load(P->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(P->fault, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                wall_clock64() - t0 > P->spin_limit) {
+                __hip_atomic_fetch_or(P->fault, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *s_ok != 0;
+}
+
+// The launch's arguments live in device memory and are re-read around every tile through a pointer the
+// compiler cannot treat as loop-invariant, so that none of them occupies registers during the tile's body.
+__device__ __forceinline__ const PersistArgs *opaque(const PersistArgs *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+template <int HALF, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void persist_kernel(const PersistArgs *__restrict__ Pg) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item, s_ok;
+    const int x = blockIdx.x & 7;
+    if (Pg->probe) {  // how many workgroups of this kernel are resident at once
+        if (threadIdx.x == 0) {
+            unsigned *in = Pg->next, *out = Pg->next + 1, *peak = Pg->next + 2;
+            __hip_atomic_fetch_add(in, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long t0 = wall_clock64();
+            unsigned most = 0;
+            for (;;) {
+                const unsigned a = __hip_atomic_load(in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned b = __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                most = max(most, a - b);
+                if (most >= gridDim.x || wall_clock64() - t0 > Pg->probe_ticks) break;
+                __builtin_amdgcn_s_sleep(4);
+            }
+            __hip_atomic_fetch_max(peak, most, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    const int n_phases = __builtin_amdgcn_readfirstlane(Pg->n_phases);
+    for (int ph = 0; ph < n_phases; ++ph) {
+        for (;;) {
+            const PersistArgs *P = opaque(Pg);
+            if (threadIdx.x == 0) s_item = (int)atomicAdd(&P->next[ph * 8 + x], 1u);
+            __syncthreads();
+            const int g = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            const PersistPhase Q = make_uniform(P->phases[ph]);
+            const int *pre = Q.xcd_pre + x * (Q.n_active + 1);
+            if (g >= __builtin_amdgcn_readfirstlane(pre[Q.n_active])) break;
+            // the g-th tile of this XCD's queue: band (x + slot) mod 8 of the job at active slot `slot`
+            int a0 = 0, a1 = Q.n_active;  // pre[a0] <= g < pre[a1]
+            while (a1 - a0 > 1) {
+                const int mid = (a0 + a1) >> 1;
+                if (pre[mid] <= g) a0 = mid;
+                else a1 = mid;
+            }
+            const int lo = __builtin_amdgcn_readfirstlane(a0);
+            const int n = Q.tile_start[lo + 1] - Q.tile_start[lo];
+            const int L = __builtin_amdgcn_readfirstlane((int)(((long long)n * ((x + lo) & 7)) >> 3) + (g - pre[lo]));
+            const int j = __builtin_amdgcn_readfirstlane(Q.job_of[lo]);
+            const BatchJobDev &J = P->jobs[j];
+            PassArgs a;
+            a.ref = J.ref;
+            a.n_src = J.n_src;
+            a.m = Q.m;
+            a.st = J.st;
+            a.t = Q.t;
+            a.colour = Q.colour;
+            a.tiles_x = J.tiles_x;
+            a.n_tiles = J.n_tiles;
+            a.counters = P->counters;
+            a.order = 0;
+            a.waves = WAVES;
+            a.prop = J.prop;
+            a.prop_w = J.prop_w;
+            a.prop_s = kCell;
+            a.conf_min = P->conf_min;
+            a = make_uniform(a);
+            a.views = P->views + __builtin_amdgcn_readfirstlane(J.view_off);
+            int tid = (int)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            pass_body<HALF, WAVES>(a, L, smem, tid);
+            // per-job completion stamp of the job's last half-pass
+            const PersistArgs *P2 = opaque(Pg);
+            if (P2->phases[ph].is_last[lo]) {
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    __threadfence();
+                    if (atomicAdd(&P2->tiles_done[j], 1ull) == (unsigned long long)(P2->jobs[j].n_tiles - 1))
+                        P2->job_end[j] = wall_clock64();
+                }
+            }
+        }
+        if (ph + 1 < n_phases && !grid_barrier(opaque(Pg), (unsigned)(ph + 1) * gridDim.x, &s_ok)) return;
     }
 }
 
@@ -1594,6 +1716,34 @@ hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStrea
         return hipErrorInvalidValue;
     }
 #undef AMH_BATCH_LAUNCH
+    return hipGetLastError();
+}
+
+size_t persist_lds_bytes(int max_src, int waves) { return pass_lds_bytes(max_src, waves); }
+
+int persist_blocks_per_cu(int half, int waves, int max_src) {
+    const size_t lds = persist_lds_bytes(max_src, waves);
+    int nb = 0;
+    hipError_t e;
+    if (waves == 2) e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel<1, 2>, 128, lds)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel<0, 2>, 128, lds);
+    else e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel<1, 4>, 256, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel<0, 4>, 256, lds);
+    return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_persist(const PersistArgs *a, int half, int waves, int max_src, int grid, hipStream_t s) {
+    const size_t lds = persist_lds_bytes(max_src, waves);
+    const dim3 g(grid), block(64 * waves);
+    if (waves == 2) {
+        if (half) AMH_LAUNCH((persist_kernel<1, 2>), g, block, lds, s, a);
+        else AMH_LAUNCH((persist_kernel<0, 2>), g, block, lds, s, a);
+    } else if (waves == 4) {
+        if (half) AMH_LAUNCH((persist_kernel<1, 4>), g, block, lds, s, a);
+        else AMH_LAUNCH((persist_kernel<0, 4>), g, block, lds, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

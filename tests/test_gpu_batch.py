@@ -181,7 +181,7 @@ def test_single_image_launch_configurations_agree(amh, batch_setup, config):
         ctx.run_checkerboard(jb["ref"], jb["srcs"], 2)
         out = ctx.get_state()
         with pytest.raises(amh.AmhError) as e:
-            ctx.set_launch_config(8)
+            ctx.set_launch_config(amh.N_TUNE_CONFIGS)
         assert e.value.status == amh.AMH_E_INVALID_ARG
     for x, y in zip(ref, out):
         assert np.array_equal(x, y)
@@ -298,3 +298,41 @@ def test_batched_proposal_initial_state_matches_oracle(amh, oracle_mod, batch_se
         np.testing.assert_allclose(d[ok], od[ok], rtol=2e-5)
         np.testing.assert_allclose(nrm[ok], on[ok], atol=2e-5)
         assert (np.abs(c - ost.cost)[ok] <= 1e-4).mean() >= 0.999
+
+
+@pytest.mark.parametrize("config", [8, 13])
+def test_persistent_launch_equals_per_phase_launches(amh, batch_setup, config):
+    """Every half-pass of every job in one persistent kernel (configurations 8-15) gives the per-phase
+    launches' results bit for bit, on a first run and on a graph replay, and with the learned proposal."""
+    say(f"case persistent batch, configuration {config}")
+    import os
+
+    weights = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1805_07920_amd",
+                           "weights", "proposal.bin")
+    images, cams, jobs = batch_setup
+    with amh.Context(refine=1, seed=13) as ctx:
+        ctx.init_views(images, cams)
+        ctx.nn_load(weights)
+        ctx.set_launch_config(config & 7)
+        ctx.run_batch(jobs)
+        ref = [ctx.get_job_result(i) for i in range(len(jobs))]
+        ref_st = ctx.get_stats()
+        ctx.run_batch_proposal(jobs)
+        ref_p = [ctx.get_job_result(i) for i in range(len(jobs))]
+        ctx.set_launch_config(config)
+        for rep in range(2):  # build + first run, then a replay
+            ctx.run_batch(jobs)
+            out = [ctx.get_job_result(i) for i in range(len(jobs))]
+            for i, (a, b) in enumerate(zip(ref, out)):
+                for x, y in zip(a, b):
+                    assert np.array_equal(x, y), f"job {i}, run {rep}"
+        st = ctx.get_stats()
+        times = ctx.get_job_times()
+        ctx.run_batch_proposal(jobs)
+        out_p = [ctx.get_job_result(i) for i in range(len(jobs))]
+    for k in ("evals_init", "evals_propagation", "evals_refine", "evals_short"):
+        assert st[k] == ref_st[k], k
+    assert np.all(np.isfinite(times)) and np.all(times >= 0)
+    for a, b in zip(ref_p, out_p):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
