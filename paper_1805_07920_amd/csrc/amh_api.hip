@@ -283,8 +283,9 @@ amh_status ensure_events(amh_ctx *c, int n) {
 }
 
 
-// launch configurations: tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2};
-// configuration = tile_order + 2 job_order + 4 (tile rows == 2)
+// launch configurations: tile order {XCD bands, hardware} x job order {given, largest first} x tile rows {4, 2}
+// x batch launch {one per phase, persistent}; configuration = tile_order + 2 job_order + 4 (tile rows == 2)
+// + 8 persistent
 constexpr int kTuneConfigs = 16;
 
 void apply_config(amh_ctx *c, int cfg) {
@@ -766,7 +767,7 @@ amh_status amh_init_views(amh_ctx *c, int n_views, const amh_image *views, const
         memcpy(v.R, cams[i].R, sizeof v.R);
         memcpy(v.t, cams[i].t, sizeof v.t);
         const size_t px = (size_t)v.W * v.H;
-        const size_t qbytes = (size_t)(v.W + 1 + 2 * kQuadPad) * (v.H + 1 + 2 * kQuadPad) * (c->half ? 8 : 16);
+        const size_t qbytes = (size_t)(v.W + 2 + 2 * kQuadPad) * (v.H + 1 + 2 * kQuadPad) * (c->half ? 4 : 8);
         if (i < (int)old.size() && old[i].W == v.W && old[i].H == v.H && old[i].half == v.half && old[i].img) {
             v.img = old[i].img;
             v.quads = old[i].quads;

@@ -7,7 +7,7 @@
 namespace amh {
 
 constexpr int kMaxSrc = 32;
-// Border of the sources' gather layout: kQuadPad extra texel quads on every side, holding the clamped footprint
+// Border of the sources' gather layout: kQuadPad extra texel columns on every side, holding the clamped footprint
 // (a window that crosses the image edge by up to kQuadPad texels reads the values clamping would give, without
 // clamping).  Images are limited to kMaxImageSide so that the layout's byte offsets stay below 2^32.
 constexpr int kQuadPad = 16;
@@ -28,7 +28,7 @@ constexpr int kDefaultTileRows = 4;
 struct ViewDev {
     double A[9];            // K_j R_rel K_ref^-1 (row-major)
     double b[3];            // K_j t_rel
-    const void *quads;      // (H+1) x (W+1) texel quads, float4 or 4 x half
+    const void *quads;      // (H+1+2P) x (W+2+2P) texel columns, 2 x float or 2 x half
     int W, H;
 };
 

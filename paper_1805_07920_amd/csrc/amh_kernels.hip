@@ -20,12 +20,10 @@
 #include "amh_internal.h"
 
 // Minimum waves per SIMD the kernels are compiled for (a register budget of
-// 512 / waves VGPRs).  The single-image half-pass fits 128 VGPRs (4 waves per
-// SIMD) with a 20-byte spill and runs 8 % faster there than at its natural 132
-// (3 waves): 4.60 vs 5.02 ms per half-pass on the 1920x1280 / 10-source
-// workload.  The batched half-pass uses the same budget (28-byte spill); the
-// batched initialisation and the ablation build spill 56-120 bytes at that
-// budget and stay at 2 (~150 VGPRs, 3 waves).
+// 512 / waves VGPRs).  The single-image and batched half-passes are held to 4
+// waves per SIMD (128 VGPRs), which they fit without spilling; the batched
+// initialisation and the ablation build get the budget of 2 waves and settle
+// near 125 VGPRs by themselves.
 #ifndef AMH_PASS_WAVES_PER_EU
 #define AMH_PASS_WAVES_PER_EU 4
 #endif
@@ -90,17 +88,20 @@ __device__ __forceinline__ void region_offset(int r, int e, int &dx, int &dy) {
 }
 
 // ---------------------------------------------------------------------------
-// Texel quads: entry (y0 + 1 + P, x0 + 1 + P) of a (H+1+2P) x (W+1+2P) array
-// (P = kQuadPad) describes the bilinear footprint with top-left texel (x0, y0),
-// x0 in [-1-P, W-1+P], indices clamped to the image, so one 16-byte (or
-// 8-byte) load serves a sample, and a sample up to P texels outside the image
-// reads what clamping its indices would read.
-//   float32: the bilinear coefficients (a, b - a, c - a, a - b - c + d) of the
-//            texels a = (x0,y0), b = (x0+1,y0), c = (x0,y0+1), d = (x0+1,y0+1),
-//            so a sample is a + fx (b - a) + fy ((c - a) + fx (a - b - c + d)):
-//            3 FMAs;
-//   float16: the texels themselves (a, b, c, d) (differences would not be exact
-//            in half precision).
+// Texel columns: entry (y0 + 1 + P, x0 + 1 + P) of a (H+1+2P) x (W+2+2P)
+// array (P = kQuadPad) holds the vertical texel pair a = (x0, y0),
+// c = (x0, y0 + 1), x0 in [-1-P, W+P], y0 in [-1-P, H-1+P], indices clamped to
+// the image.  Two neighbouring entries are the bilinear footprint with top-left
+// texel (x0, y0) -- a, c and b = (x0+1, y0), d = (x0+1, y0+1) -- so one 16-byte
+// (8-byte) load at an 8-byte (4-byte) aligned address serves a sample, and a
+// sample up to P texels outside the image reads what clamping its indices would
+// read.  At 8 (4) bytes per texel the layout is half the size of one holding
+// the four texels per texel, which halves the lines a window row touches and
+// the footprint the caches must hold where the hypotheses are random.
+//   float32: (a, c - a), the difference rounded once from its exact value; a
+//            sample is L + fx (R - L) with L = a + fy (c - a), R = b + fy (d - b);
+//   float16: the texels (a, c) themselves (differences would not be exact in
+//            half precision).
 // Offsets are 32-bit byte offsets from a wave-uniform base (global loads with
 // a scalar base address).
 // ---------------------------------------------------------------------------
@@ -139,20 +140,35 @@ struct QuadT<1> {
     typedef gh4 type;
 };
 
+// the footprint (two neighbouring entries) at half its natural alignment
+typedef float gf4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef _Float16 gh4a4 __attribute__((ext_vector_type(4), aligned(4)));
+template <int HALF>
+struct QuadLd {
+    typedef gf4a8 type;
+};
+template <>
+struct QuadLd<1> {
+    typedef gh4a4 type;
+};
+
 template <int HALF>
 __device__ __forceinline__ typename QuadT<HALF>::type load_quad(const void *base, uint32_t off) {
-    return *reinterpret_cast<const __attribute__((address_space(1))) typename QuadT<HALF>::type *>((gbyte *)base +
-                                                                                                   off);
+    return *reinterpret_cast<const __attribute__((address_space(1))) typename QuadLd<HALF>::type *>(
+        (gbyte *)base + off);
 }
 
+// q = (a, c - a, b, d - b)
 __device__ __forceinline__ float eval_quad_f32(gf4 q, float fx, float fy) {
-    return fmaf(fy, fmaf(fx, q.w, q.z), fmaf(fx, q.y, q.x));
+    const float l = fmaf(fy, q.y, q.x), r = fmaf(fy, q.w, q.z);
+    return fmaf(fx, r - l, l);
 }
 
+// q = (a, c, b, d)
 __device__ __forceinline__ float eval_quad_f16(gh4 q, float fx, float fy) {
     // a + fx (b - a) as fma(b, fx, fma(-a, fx, a)): the halves enter mixed-precision FMAs directly
     // (exact conversion inside the instruction), which saves the separate conversions and differences
-    const float a = (float)q.x, b = (float)q.y, c = (float)q.z, d = (float)q.w;
+    const float a = (float)q.x, c = (float)q.y, b = (float)q.z, d = (float)q.w;
     const float top = fmaf(b, fx, fmaf(-a, fx, a));
     const float bot = fmaf(d, fx, fmaf(-c, fx, c));
     return fmaf(fy, bot - top, top);
@@ -189,7 +205,7 @@ __device__ __forceinline__ void issue_row(const void *quads, float vf, float N0x
                                           float puy, float puz, float pvx, float pvy, float pvz, int xlo, int xhi,
                                           int ylo, int yhi, int row_bytes, int base,
                                           typename QuadT<HALF>::type (&qd)[6], float (&fxs)[6], float (&fys)[6]) {
-    constexpr int kEntry = HALF ? 8 : 16;
+    constexpr int kEntry = HALF ? 4 : 8;
     const float rx = fmaf(vf, pvx, N0x), ry = fmaf(vf, pvy, N0y), rzz = fmaf(vf, pvz, Z0);
 #pragma unroll
     for (int su = 0; su < 6; ++su) {
@@ -201,7 +217,7 @@ __device__ __forceinline__ void issue_row(const void *quads, float vf, float N0x
         const int yr = CLAMP ? med3i(cvt_floor(dy), ylo, yhi) : cvt_floor(dy);
         fxs[su] = __builtin_amdgcn_fractf(dx);
         fys[su] = __builtin_amdgcn_fractf(dy);
-        // modulo-2^32 arithmetic; the true offset is in [0, (W+1+2P)(H+1+2P) * entry) <= 2^32
+        // modulo-2^32 arithmetic; the true offset is in [0, (W+2+2P)(H+1+2P) * entry) <= 2^32
         const uint32_t off = (uint32_t)__mul24(yr, row_bytes) + (uint32_t)base + (uint32_t)xr * kEntry;
         qd[su] = load_quad<HALF>(quads, off);
     }
@@ -224,9 +240,10 @@ struct WinStats {
 // formed row by row and merged exactly (see ncc_cost).
 constexpr int kWinStride = 48;  // float2 units: 36 + 6 float4
 
-template <typename Reader>
-__device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodDev &m, float2 *rw, int write_phase,
-                                                 int write_stride) {
+// Computes a pixel's window block and hands each entry to the sink: sink.sample(s, (w, w (a - mean))) for the
+// 36 samples, sink.row(r, constants) for the 6 rows.
+template <typename Reader, typename Sink>
+__device__ __forceinline__ WinStats build_window_to(const Reader &rd, const MethodDev &m, Sink &sink) {
     float a[36];
     const float ac = rd(0, 0);
     float sw = 0.f, swa = 0.f;
@@ -254,7 +271,6 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
     const float invW = 1.f / sw;
     const float mean = swa * invW;
     float saa = 0.f;
-    float4 *rowc = reinterpret_cast<float4 *>(rw + 36);
     float wcum = 0.f;
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
@@ -267,19 +283,45 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
             saa = fmaf(wap, ap, saa);
             wr += w[s];
             ar += wap;
-            if ((s % write_stride) == write_phase) rw[s] = make_float2(w[s], wap);
+            sink.sample(s, make_float2(w[s], wap));
         }
         const float wprev = wcum;
         wcum += wr;
         // a row whose weights all underflow adds nothing (its constants are 0)
-        if ((r % write_stride) == write_phase)
-            rowc[r] = wr > 0.f ? make_float4(1.f / wr, wr / wcum, wprev * wr / wcum, ar) : make_float4(0.f, 0.f, 0.f, 0.f);
+        sink.row(r, wr > 0.f ? make_float4(1.f / wr, wr / wcum, wprev * wr / wcum, ar) : make_float4(0.f, 0.f, 0.f, 0.f));
     }
     WinStats ws;
     ws.invW = invW;
     ws.var_a = saa * invW;
     return ws;
 }
+
+// LDS block of kWinStride float2: the entries s with s mod stride == phase (the lanes of a pixel split the writes)
+struct LdsWinSink {
+    float2 *rw;
+    int phase, stride;
+    __device__ __forceinline__ void sample(int s, float2 v) const {
+        if ((s % stride) == phase) rw[s] = v;
+    }
+    __device__ __forceinline__ void row(int r, float4 v) const {
+        if ((r % stride) == phase) reinterpret_cast<float4 *>(rw + 36)[r] = v;
+    }
+};
+
+template <typename Reader>
+__device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodDev &m, float2 *rw, int write_phase,
+                                                 int write_stride) {
+    LdsWinSink sink{rw, write_phase, write_stride};
+    return build_window_to(rd, m, sink);
+}
+
+// Reader of a window block in LDS for the source loop.
+struct LdsWin {
+    const float2 *__restrict__ rw;
+    __device__ __forceinline__ float2 sample(int s) const { return rw[s]; }
+    __device__ __forceinline__ float4 row(int r) const { return reinterpret_cast<const float4 *>(rw + 36)[r]; }
+};
+
 
 // ---------------------------------------------------------------------------
 // Bilaterally weighted NCC of one hypothesis on one source (Sec. 3.3, Eq. 8).
@@ -291,8 +333,8 @@ __device__ __forceinline__ WinStats build_window(const Reader &rd, const MethodD
 //   change per reference pixel in x and y.
 // ---------------------------------------------------------------------------
 // Source moments of the 36 samples, row by row (see ncc_cost); CLAMP as in issue_row.
-template <int HALF, bool CLAMP>
-__device__ __forceinline__ void window_moments(const void *__restrict__ quads, const float2 *__restrict__ rw,
+template <int HALF, bool CLAMP, typename Win>
+__device__ __forceinline__ void window_moments(const void *__restrict__ quads, const Win &win,
                                                float N0x, float N0y, float Z0, float pux, float puy, float puz,
                                                float pvx, float pvy, float pvz, int xlo, int xhi, int ylo, int yhi,
                                                int row_bytes, int base, float &m2, float &cab) {
@@ -303,7 +345,6 @@ __device__ __forceinline__ void window_moments(const void *__restrict__ quads, c
     //   M2'   = M2 + M2_r + (mu_r - mean)^2 W_<r W_r / W_<=r,
     //   C'    = C + C_r + (mu_r - mean') A_r + (mean - mean') A_<r.
     // No cancellation at any size of the offsets, and only 6 samples live at a time.
-    const float4 *__restrict__ rowc = reinterpret_cast<const float4 *>(rw + 36);
     float mu = 0.f, acum = 0.f;
     m2 = 0.f;
     cab = 0.f;
@@ -319,17 +360,17 @@ __device__ __forceinline__ void window_moments(const void *__restrict__ quads, c
 #pragma unroll
         for (int su = 0; su < 6; ++su) {
             v6[su] = eval_quad<HALF>(qd[su], fxs[su], fys[su]);
-            srow = fmaf(rw[sv * 6 + su].x, v6[su], srow);
+            srow = fmaf(win.sample(sv * 6 + su).x, v6[su], srow);
         }
         if (sv < 5)
             issue_row<HALF, CLAMP>(quads, -3.f + 2.f * sv, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo,
                                    yhi, row_bytes, base, qd, fxs, fys);
-        const float4 rc = rowc[sv];
+        const float4 rc = win.row(sv);
         const float mur = srow * rc.x;
         float m2r = 0.f, cr = 0.f;
 #pragma unroll
         for (int su = 0; su < 6; ++su) {
-            const float2 wa = rw[sv * 6 + su];
+            const float2 wa = win.sample(sv * 6 + su);
             const float d = v6[su] - mur;
             m2r = fmaf(wa.x * d, d, m2r);
             cr = fmaf(wa.y, d, cr);
@@ -357,10 +398,9 @@ __device__ __forceinline__ float short_to_cost(float c, unsigned *nshort) {
     return c;
 }
 
-template <int HALF>
-__device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *__restrict__ rw_in,
-                                              const WinStats &ws, int x, int y, double q0, float qu, float qv) {
-    const float2 *__restrict__ rw = rw_in;
+template <int HALF, bool SPLIT, typename Win>
+__device__ __forceinline__ float ncc_cost_win(const ViewDev &vw, const Win &rw, const WinStats &ws, int x, int y,
+                                              double q0, float qu, float qv) {
     const double P0x = fma(vw.A[1], (double)y, fma(vw.A[0], (double)x, vw.A[2])) + vw.b[0] * q0;
     const double P0y = fma(vw.A[4], (double)y, fma(vw.A[3], (double)x, vw.A[5])) + vw.b[1] * q0;
     const double P0z = fma(vw.A[7], (double)y, fma(vw.A[6], (double)x, vw.A[8])) + vw.b[2] * q0;
@@ -392,10 +432,10 @@ __device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *_
     const void *__restrict__ quads = vw.quads;
     // texel indices relative to (ix, iy), clamped to [-1, W-1] x [-1, H-1] in absolute terms;
     // byte offset = base + yrel * row_bytes + xrel * entry_bytes (non-negative after clamping)
-    constexpr int kEntry = HALF ? 8 : 16;
-    const int row_bytes = (W + 1 + 2 * kQuadPad) * kEntry;
+    constexpr int kEntry = HALF ? 4 : 8;
+    const int row_bytes = (W + 2 + 2 * kQuadPad) * kEntry;
     const int xlo = -1 - ix, xhi = W - 1 - ix, ylo = -1 - iy, yhi = H - 1 - iy;
-    const int base = ((iy + 1 + kQuadPad) * (W + 1 + 2 * kQuadPad) + (ix + 1 + kQuadPad)) * kEntry;
+    const int base = ((iy + 1 + kQuadPad) * (W + 2 + 2 * kQuadPad) + (ix + 1 + kQuadPad)) * kEntry;
     // Clamp-free fast path: the samples lie in the convex image of the window square (the depth is
     // positive at its corners, so the warp has no pole inside), hence |dx| <= (|N0x| + 5 |pux| + 5 |pvx|)
     // / min corner depth, likewise dy.  When that bound (widened by 1 % + 0.01 px, far above the float
@@ -409,8 +449,11 @@ __device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *_
     // (the border of the layout extends the clamp-free range by kQuadPad texels on every side)
     const bool interior = zmin > 1e-3f * Z0 && bx <= (float)(ix + 1 + kQuadPad) && bx < (float)(W - ix + kQuadPad) &&
                           by <= (float)(iy + 1 + kQuadPad) && by < (float)(H - iy + kQuadPad);
+    // SPLIT = false: every lane takes the clamped path, which gives interior lanes the same result.  A wave
+    // whose lanes disagree runs both paths in turn, so where the hypotheses are random (steep planes, windows
+    // at the image edges: the two mix in nearly every wave) the clamped path alone is the cheaper one.
     float m2, cab;
-    if (interior)
+    if (SPLIT && interior)
         window_moments<HALF, false>(quads, rw, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
                                     row_bytes, base, m2, cab);
     else
@@ -421,6 +464,12 @@ __device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *_
     if (ws.var_a < 1e-5f || var_b < 1e-5f) return 2.f;
     const float mm = 1.f - cov * rsqrtf(ws.var_a * var_b);
     return fminf(fmaxf(mm, 0.f), 2.f);
+}
+
+template <int HALF, bool SPLIT = true>
+__device__ __forceinline__ float ncc_cost_raw(const ViewDev &vw, const float2 *__restrict__ rw, const WinStats &ws,
+                                              int x, int y, double q0, float qu, float qv) {
+    return ncc_cost_win<HALF, SPLIT>(vw, LdsWin{rw}, ws, x, y, q0, qu, qv);
 }
 
 // The cost with short evaluations not counted.
@@ -694,7 +743,7 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
         }
         const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
         for (int j = row; j < N; j += kRows) {
-            const float c = short_to_cost(q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv)
+            const float c = short_to_cost(q.ok ? ncc_cost_raw<HALF, false>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv)
                                                : kShort, &S.nshort[wave]);
             mcol[j * 64 + grp * kRows] = c;
             ++n_eval;
@@ -763,7 +812,13 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
     const int t = threadIdx.x, g = t / Lp, j = t - g * Lp;
     const bool lane_ok = g < G;
     const int per_row = (a.ref.W + 1) / 2;  // slots per row; x beyond the image is skipped
-    const long long pc = (long long)blockIdx.x * G + g;
+    // XCD bands: block b runs on XCD b mod 8 and takes the (b / 8)-th group of that XCD's contiguous band of
+    // groups, so that each XCD's L2 holds the sources' footprint of its own rows only
+    const long long n_groups = ((long long)a.ref.H * per_row + G - 1) / G;
+    const long long per_xcd = (n_groups + 7) >> 3;
+    const long long grp_id = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (grp_id >= n_groups) return;  // the whole workgroup leaves before any barrier
+    const long long pc = grp_id * G + g;
     const int y = (int)(pc / per_row);
     const int x = 2 * (int)(pc - (long long)y * per_row) + ((y + a.colour) & 1);
     const bool pix_ok = lane_ok && y < a.ref.H && x < a.ref.W;
@@ -790,7 +845,7 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
         const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
         for (int v = j; v < N; v += Lp)
             cst[g * N + v] = short_to_cost(
-                q.ok ? ncc_cost_raw<HALF>(a.views[v], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort, &nshort);
+                q.ok ? ncc_cost_raw<HALF, false>(a.views[v], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort, &nshort);
     }
     count_evals(a.counters, 0, pix_ok ? (unsigned long long)((N - j + Lp - 1) / Lp) : 0ull);
     if (a.prop) count_evals(a.counters, 3, (fell_back && j == 0) ? 1ull : 0ull);
@@ -1543,21 +1598,17 @@ __global__ void convert_kernel(const void *src, int dtype, int64_t pitch, int W,
 }
 
 __global__ void pack_quads_kernel(const float *img, int W, int H, void *quads, int half) {
-    const int xx = blockIdx.x * blockDim.x + threadIdx.x, yy = blockIdx.y;  // 0..W+2P, 0..H+2P
-    if (xx > W + 2 * kQuadPad || yy > H + 2 * kQuadPad) return;
-    const int x0 = min(max(xx - 1 - kQuadPad, 0), W - 1), x1 = min(max(xx - kQuadPad, 0), W - 1);
+    const int xx = blockIdx.x * blockDim.x + threadIdx.x, yy = blockIdx.y;  // 0..W+1+2P, 0..H+2P
+    if (xx > W + 1 + 2 * kQuadPad || yy > H + 2 * kQuadPad) return;
+    const int x = min(max(xx - 1 - kQuadPad, 0), W - 1);
     const int y0 = min(max(yy - 1 - kQuadPad, 0), H - 1), y1 = min(max(yy - kQuadPad, 0), H - 1);
-    const float a = img[(size_t)y0 * W + x0], b = img[(size_t)y0 * W + x1];
-    const float c = img[(size_t)y1 * W + x0], d = img[(size_t)y1 * W + x1];
-    const size_t i = (size_t)yy * (W + 1 + 2 * kQuadPad) + xx;
+    const float a = img[(size_t)y0 * W + x], c = img[(size_t)y1 * W + x];
+    const size_t i = (size_t)yy * (W + 2 + 2 * kQuadPad) + xx;
     if (!half) {
-        // bilinear coefficients, each rounded once from its exact double value
-        const double da = a, db = b, dc = c, dd = d;
-        reinterpret_cast<float4 *>(quads)[i] =
-            make_float4(a, (float)(db - da), (float)(dc - da), (float)((da - db) - (dc - dd)));
+        // the difference rounded once from its exact double value
+        reinterpret_cast<float2 *>(quads)[i] = make_float2(a, (float)((double)c - (double)a));
     } else {
-        __half2 lo = __floats2half2_rn(a, b), hi = __floats2half2_rn(c, d);
-        reinterpret_cast<uint2 *>(quads)[i] = make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
+        reinterpret_cast<__half2 *>(quads)[i] = __floats2half2_rn(a, c);
     }
 }
 
@@ -1624,7 +1675,7 @@ hipError_t launch_convert_to_f32(const void *src, int src_dtype, int64_t pitch, 
 }
 
 hipError_t launch_pack_quads(const float *img, int W, int H, void *quads, int half, hipStream_t s) {
-    dim3 grid((W + 1 + 2 * kQuadPad + 255) / 256, H + 1 + 2 * kQuadPad);
+    dim3 grid((W + 2 + 2 * kQuadPad + 255) / 256, H + 1 + 2 * kQuadPad);
     AMH_LAUNCH(pack_quads_kernel, grid, dim3(256), 0, s, img, W, H, quads, half);
     return hipGetLastError();
 }
@@ -1663,9 +1714,9 @@ hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
         }
         return hipGetLastError();
     }
-    const int G = init_pixels_per_group(a.n_src);
     const long long slots = (long long)a.ref.H * ((a.ref.W + 1) / 2);
-    const dim3 grid((unsigned)((slots + G - 1) / G));
+    const int G = init_pixels_per_group(a.n_src);
+    const dim3 grid((unsigned)(8 * (((slots + G - 1) / G + 7) / 8)));
     if (half) AMH_LAUNCH(init_pix_kernel<1>, grid, dim3(256), 0, s, a);
     else AMH_LAUNCH(init_pix_kernel<0>, grid, dim3(256), 0, s, a);
     return hipGetLastError();

@@ -361,7 +361,7 @@ def test_sweep_features_two_sub_planes_ten_sources(amh, oracle_mod):
 
 
 def test_sweep_features_fp16_sources(amh, oracle_mod):
-    """Sources stored as float16: the sweep reads the texel quads of the half-precision layout; the
+    """Sources stored as float16: the sweep reads the texel columns of the half-precision layout; the
     oracle reads the same fp16-rounded values."""
     say("case sweep features 96x64, fp16 sources")
     import scenegen
