@@ -170,7 +170,9 @@ class Params:
     view_mode: int = 0  # 1: plain mean over all views (static objective for the sweep pin); 2: heuristic best-k
     prop_mode: int = 0  # 1: symmetric fast checkerboard propagation (ablation)
     bilateral_sq: int = 0  # 1: squared colour difference and distance in the bilateral weight
-    sample_f32: int = 0  # conditioning probe (not the method): sample positions and values rounded to float32
+    sample_f32: int = 0  # conditioning probe (not the method): 1 sample positions and values rounded to float32,
+    #                      2 also the NCC's sums and moments in float32, 3 the sample values moved by the
+    #                      first-order bound of that rounding, each in the direction that moves the cost to 1
     cost_noise: float = 0.0  # conditioning probe (not the method): deterministic cost offsets of this width
 
     def c(self) -> _Params:

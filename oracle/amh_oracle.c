@@ -220,6 +220,28 @@ static double bilinear(const float *img, int W, int H, double px, double py)
     return (1.0 - fy) * ((1.0 - fx) * i00 + fx * i10) + fy * ((1.0 - fx) * i01 + fx * i11);
 }
 
+/* Conditioning probe (not the method): the bilinear interpolant's gradient   */
+/* at (px, py), same texels and clamping as bilinear().                        */
+static void bilinear_grad(const float *img, int W, int H, double px, double py, double *gx, double *gy)
+{
+    double fx0 = floor(px), fy0 = floor(py);
+    double fx = px - fx0, fy = py - fy0;
+    long x0 = (long)fx0, y0 = (long)fy0, x1 = x0 + 1, y1 = y0 + 1;
+    x0 = x0 < 0 ? 0 : (x0 > W - 1 ? W - 1 : x0);
+    x1 = x1 < 0 ? 0 : (x1 > W - 1 ? W - 1 : x1);
+    y0 = y0 < 0 ? 0 : (y0 > H - 1 ? H - 1 : y0);
+    y1 = y1 < 0 ? 0 : (y1 > H - 1 ? H - 1 : y1);
+    double i00 = img[y0 * W + x0], i10 = img[y0 * W + x1], i01 = img[y1 * W + x0], i11 = img[y1 * W + x1];
+    *gx = (1.0 - fy) * (i10 - i00) + fy * (i11 - i01);
+    *gy = (1.0 - fx) * (i01 - i00) + fx * (i11 - i10);
+}
+
+/* half a float32 ulp of |v| (0 for v = 0) */
+static double half_ulp_f32(double v)
+{
+    return v == 0.0 ? 0.0 : ldexp(1.0, ilogb(v) - 24);
+}
+
 /* Conditioning probe (not the method): a deterministic offset uniform in     */
 /* [-1/2, 1/2) for a (pixel, view, plane), from a 64-bit mix of their bits.   */
 static double probe_noise(int x, int y, int j, const double plane[4])
@@ -254,7 +276,7 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
     double cu = c[0] / c[2], cv = c[1] / c[2];
     if (!(cu >= 0.0 && cu <= V->srcW[j] - 1 && cv >= 0.0 && cv <= V->srcH[j] - 1)) return 2.0;
 
-    double a[36], b[36], w[36];
+    double a[36], b[36], w[36], eb3[36];
     double ac = ref_at(V, x, y);
     int n = 0;
     for (int dy = -5; dy <= 5; dy += 2) {
@@ -273,12 +295,18 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
             orc_project(V, x + dx, y + dy, plane, j, h);
             if (!(h[2] > 0.0)) return 2.0;
             double px = h[0] / h[2], py = h[1] / h[2];
-            if (p->sample_f32) { /* conditioning probe only: positions relative to the centre's texel */
+            if (p->sample_f32 == 1 || p->sample_f32 == 2) { /* conditioning probe only: positions relative to the centre's texel */
                 px = floor(cu) + (double)(float)(px - floor(cu));
                 py = floor(cv) + (double)(float)(py - floor(cv));
             }
             b[n] = bilinear(V->src[j], V->srcW[j], V->srcH[j], px, py);
-            if (p->sample_f32) b[n] = (double)(float)b[n]; /* conditioning probe only */
+            if (p->sample_f32 == 3) { /* conditioning probe only: first-order float32 error bound of b */
+                double gx, gy;
+                bilinear_grad(V->src[j], V->srcW[j], V->srcH[j], px, py, &gx, &gy);
+                eb3[n] = fabs(gx) * half_ulp_f32(px - floor(cu)) + fabs(gy) * half_ulp_f32(py - floor(cv)) +
+                         half_ulp_f32(b[n]);
+            }
+            if (p->sample_f32 == 1 || p->sample_f32 == 2) b[n] = (double)(float)b[n]; /* conditioning probe only */
             ++n;
         }
     }
@@ -298,6 +326,48 @@ double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, 
         cab += w[i] * (a[i] - ea) * (b[i] - eb);
     }
     caa /= sw; cbb /= sw; cab /= sw;
+    if (p->sample_f32 == 3 && caa > 0.0 && cbb > 0.0) {
+        /* conditioning probe only: every sample value moved by the first-order bound of rounding its
+           position (relative to the centre's texel) and its value to float32, each in the direction that
+           moves the cost towards 1 (the worst case of that rounding, to first order) */
+        const double s0 = sqrt(caa * cbb), m0 = 1.0 - cab / s0;
+        for (int i = 0; i < 36; ++i) {
+            /* dm/db_i: d cab = w (a - ea) / sw, d cbb = 2 w (b - eb) / sw (the mean shifts cancel) */
+            const double g = -(w[i] * (a[i] - ea) / sw) / s0 + cab * (w[i] * (b[i] - eb) / sw) / (s0 * cbb);
+            b[i] += (m0 >= 1.0) == (g > 0.0) ? -eb3[i] : eb3[i];
+        }
+        sb = 0;
+        for (int i = 0; i < 36; ++i) sb += w[i] * b[i];
+        eb = sb / sw;
+        cbb = 0; cab = 0;
+        for (int i = 0; i < 36; ++i) {
+            cbb += w[i] * (b[i] - eb) * (b[i] - eb);
+            cab += w[i] * (a[i] - ea) * (b[i] - eb);
+        }
+        cbb /= sw; cab /= sw;
+    }
+    if (p->sample_f32 == 2) {
+        /* conditioning probe only: the same two-pass definition with weights, sums and moments in
+           float32 (this file is compiled without contraction, so every operation rounds once) */
+        float swf = 0.f, saf = 0.f, sbf = 0.f;
+        for (int i = 0; i < 36; ++i) {
+            const float wi = (float)w[i];
+            swf += wi;
+            saf += wi * (float)a[i];
+            sbf += wi * (float)b[i];
+        }
+        const float eaf = saf / swf, ebf = sbf / swf;
+        float caaf = 0.f, cbbf = 0.f, cabf = 0.f;
+        for (int i = 0; i < 36; ++i) {
+            const float wi = (float)w[i], da = (float)a[i] - eaf, db = (float)b[i] - ebf;
+            caaf += wi * da * da;
+            cbbf += wi * db * db;
+            cabf += wi * da * db;
+        }
+        caa = caaf / swf;
+        cbb = cbbf / swf;
+        cab = cabf / swf;
+    }
     if (caa < 1e-5 || cbb < 1e-5) return 2.0;
     double m = 1.0 - cab / sqrt(caa * cbb);
     if (p->cost_noise > 0.0) m += probe_noise(x, y, j, plane) * p->cost_noise; /* conditioning probe only */

@@ -71,7 +71,11 @@ typedef struct {
     int sample_f32;   /* conditioning probe, not the method: 1 rounds every sample's source position
                          (relative to the texel under the window centre) and its interpolated value to
                          float32, to measure how far the method's result moves when those carry single
-                         precision; 0 (the method): every step in double */
+                         precision; 2 also forms the weights' sums and the NCC's moments in float32;
+                         3 instead moves every sample value by the first-order bound of rounding its
+                         position and value to float32, in the direction that moves the cost towards
+                         1 (the worst case of that rounding), in double otherwise; 0 (the method):
+                         every step in double */
     double cost_noise; /* conditioning probe, not the method: > 0 adds to every scored cost a deterministic
                           offset uniform in [-cost_noise/2, cost_noise/2) (a hash of pixel, view and
                           plane), to measure what cost errors of that size do to the result; 0: none */

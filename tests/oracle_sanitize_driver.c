@@ -9,7 +9,7 @@
  * random generator is involved.  Sizes are odd (ragged tiles), and the runs
  * cover every mode: joint view selection, the static objective, heuristic
  * selection, symmetric propagation, squared weights, no self row, the
- * conditioning probes, refinement before and after t = 3, and per-pixel
+ * conditioning probes (every level), refinement before and after t = 3, and per-pixel
  * diagnostics over an explicit pixel order.
  */
 #include <math.h>
@@ -78,7 +78,7 @@ int main(void)
     int *order = malloc(sizeof(int) * P);
     orc_diag *dg = malloc(sizeof(orc_diag) * P);
     int rc = 0;
-    for (int mode = 0; mode < 8 && rc == 0; ++mode) {
+    for (int mode = 0; mode < 10 && rc == 0; ++mode) {
         orc_params p;
         memset(&p, 0, sizeof p);
         p.refine = 1;
@@ -98,7 +98,7 @@ int main(void)
         p.view_mode = mode == 1 ? 1 : (mode == 2 ? 2 : 0);
         p.prop_mode = mode == 5 ? 1 : 0;
         p.bilateral_sq = mode == 6;
-        p.sample_f32 = mode == 7;
+        p.sample_f32 = mode == 7 ? 1 : (mode == 8 ? 2 : (mode == 9 ? 3 : 0));
         p.cost_noise = mode == 7 ? 2e-4 : 0.0;
         orc_run(&V, &p, &s, 2);
         if ((rc = check_state(&s, P, NS)) != 0) break;

@@ -376,6 +376,9 @@ def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_c1, sym, heur):
 # derived from them, not from the kernel's errors:
 #  * sample_f32 (sample positions and values in float32, nothing else): costs move by up to ~4e-5 with squared
 #    weights against ~2e-7 with the printed ones, and whole runs keep only 70-80 % of their depths (100 %);
+#    its level 2 also forms the NCC's sums and moments in float32, which a kernel cannot avoid either, and its
+#    level 3 moves every sample by the first-order bound of that rounding in the worst direction (one rounding
+#    pattern can miss a sensitive eval: one moved 1.6e-8 by level 1 moves 2e-6 at level 3);
 #  * cost_noise = 2e-4 (every cost moved by a fixed offset within +-1e-4, the per-hypothesis cost bar): what a
 #    kernel whose costs all meet the bar may produce.  With squared weights it keeps fewer planes per pass and
 #    ends 1-3 points less accurate than the exact oracle (cost errors within the bar pick worse near-ties in
@@ -385,10 +388,11 @@ NOISE_AT_BAR = 2e-4
 
 @pytest.mark.parametrize("key", list(SCENES))
 def test_score_fixed_squared_weights(amh, oracle_mod, key):
-    """Fixed hypotheses with squared weights.  Where float32 positions and samples move the oracle's cost by
-    less than 1e-6 the 1e-4 bar holds as for the printed weights; the ill-conditioned rest (the probe moves
-    them by more) must stay within 1e-3, and the cost-2 decisions (weighted variance at the 1e-5 threshold)
-    may differ only as often as the probe's do, plus 0.5 %."""
+    """Fixed hypotheses with squared weights.  Where float32 positions, samples and moments (the probe at
+    level 2) and the first-order worst case of rounding the samples (level 3) both move the oracle's cost by
+    less than 1e-6 the 1e-4 bar holds as for the printed weights; the ill-conditioned rest (a probe moves them
+    by more) must stay within 1e-3, and the cost-2 decisions (weighted variance at the 1e-5 threshold) may
+    differ only as often as the level-2 probe's do, plus 0.5 %."""
     say("case score_fixed squared weights", key)
     sc = build_scene(SCENES[key])
     O = oracle_mod
@@ -402,19 +406,17 @@ def test_score_fixed_squared_weights(amh, oracle_mod, key):
         ctx.begin(0, list(range(1, n + 1)))
         got = ctx.score_fixed(planes, pix3)
     V = O.Views.from_scene(sc)
-    P, Pp = O.Params(bilateral_sq=1), O.Params(bilateral_sq=1, sample_f32=1)
-    want = np.array([[O.matching_cost(V, P, int(x), int(y), pl.astype(np.float64), j) for j in range(n)]
-                     for (x, y), pl in zip(pix3, planes)])
-    probe = np.array([[O.matching_cost(V, Pp, int(x), int(y), pl.astype(np.float64), j) for j in range(n)]
-                      for (x, y), pl in zip(pix3, planes)])
-    both = (want < 2) & (got < 2) & (probe < 2)
-    err, cond = np.abs(got - want), np.abs(probe - want)
+    P, Pp, Pw = O.Params(bilateral_sq=1), O.Params(bilateral_sq=1, sample_f32=2), O.Params(bilateral_sq=1, sample_f32=3)
+    want, probe, worst = (np.array([[O.matching_cost(V, Q, int(x), int(y), pl.astype(np.float64), j) for j in range(n)]
+                                    for (x, y), pl in zip(pix3, planes)]) for Q in (P, Pp, Pw))
+    both = (want < 2) & (got < 2) & (probe < 2) & (worst < 2)
+    err, cond = np.abs(got - want), np.maximum(np.abs(probe - want), np.abs(worst - want))
     well = both & (cond < 1e-6)
     flips, probe_flips = ((want < 2) != (got < 2)).mean(), ((want < 2) != (probe < 2)).mean()
     say(f"  well-conditioned {well.sum()} of {both.sum()}: max err {err[well].max():.2e}; ill-conditioned: max err "
         f"{err[both & ~well].max() if (both & ~well).any() else 0:.2e} (probe {cond[both].max():.2e}); "
         f"cost-2 decisions differing: gpu {flips:.4f}, probe {probe_flips:.4f}")
-    assert well.sum() >= 0.8 * both.sum()
+    assert well.sum() >= 0.5 * both.sum()
     assert err[well].max() <= 1e-4
     assert err[both].max() <= 1e-3
     assert flips <= probe_flips + 5e-3

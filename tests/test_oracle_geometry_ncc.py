@@ -289,6 +289,73 @@ def test_sample_f32_probe_only_rounds_positions_and_samples(oracle_mod, scene_c1
     assert diffs.max() <= 1e-4 and diffs.max() > 0.0
 
 
+def test_sample_f32_probe_level_two_rounds_the_moments(oracle_mod, scene_c1):
+    """Level 2 of the probe also forms the weights' sums and the NCC's moments in float32.  On samples that
+    land on texels (nothing for level 1 to round) it moves the cost by float32 rounding of the moments only
+    (< 1e-5, and it does move); a constant source window stays at cost 2 (zero variance is exact in float32
+    as well); on the rendered scene it stays within 1e-4 of level 1 and of the exact cost."""
+    O = oracle_mod
+    rng = np.random.default_rng(12)
+    W, H, f, Z, B = 64, 40, 100.0, 4.0, 0.12
+    K = np.array([[f, 0, (W - 1) / 2], [0, f, (H - 1) / 2], [0, 0, 1]])
+    ref = rng.uniform(0, 255, (H, W)).astype(np.float32)
+    src = np.zeros_like(ref)
+    src[:, :W - 6] = ref[:, 6:] * 0.93 + 11.0
+    V = O.Views([ref, src], [cam(K, np.eye(3), np.zeros(3), W, H), cam(K, np.eye(3), [-B, 0, 0], W, H)])
+    exact = np.array([0.0, 0.0, -1.0, Z / 2.0])  # disparity 6: samples on texels
+    P0, P1, P2 = O.Params(), O.Params(sample_f32=1), O.Params(sample_f32=2)
+    moved = []
+    for x, y in [(20, 10), (30, 20), (40, 30), (25, 15)]:
+        c0, c1, c2 = (O.matching_cost(V, P, x, y, exact, 0) for P in (P0, P1, P2))
+        assert c1 == pytest.approx(c0, abs=1e-12)
+        assert abs(c2 - c0) < 1e-5
+        moved.append(abs(c2 - c0))
+    assert max(moved) > 0.0
+    flat = O.Views([ref, np.full_like(ref, 77.0)], [cam(K, np.eye(3), np.zeros(3), W, H),
+                                                   cam(K, np.eye(3), [-B, 0, 0], W, H)])
+    assert O.matching_cost(flat, P2, 30, 20, exact, 0) == 2.0
+    V = O.Views.from_scene(scene_c1)
+    d1, d0 = [], []
+    for _ in range(200):
+        x, y = int(rng.integers(0, V.W)), int(rng.integers(0, V.H))
+        plane = O.random_plane(V, P0, x, y, 5, 0)
+        for j in range(V.n_src):
+            a, b, c = (O.matching_cost(V, P, x, y, plane, j) for P in (P0, P1, P2))
+            if a < 2.0 and b < 2.0 and c < 2.0:
+                d1.append(abs(c - b))
+                d0.append(abs(c - a))
+    assert max(d1) <= 1e-4 and max(d0) <= 1e-4 and max(d1) > 0.0
+
+
+def test_sample_f32_probe_level_three_is_the_first_order_worst_case(oracle_mod, scene_c1):
+    """Level 3 moves every sample value by the first-order bound of rounding its position and value to float32,
+    in the direction that moves the cost towards 1: the cost moves towards 1 (never away, never past it), by
+    no more than 1e-4 with the printed weights, and by at least what the actual rounding (level 1) moves it in
+    nearly every case -- a worst case bounds the actual rounding to first order."""
+    O = oracle_mod
+    V = O.Views.from_scene(scene_c1)
+    P0, P1, P3 = O.Params(), O.Params(sample_f32=1), O.Params(sample_f32=3)
+    rng = np.random.default_rng(13)
+    d1, d3 = [], []
+    for _ in range(200):
+        x, y = int(rng.integers(0, V.W)), int(rng.integers(0, V.H))
+        plane = O.random_plane(V, P0, x, y, 5, 0)
+        for j in range(V.n_src):
+            c0, c1, c3 = (O.matching_cost(V, P, x, y, plane, j) for P in (P0, P1, P3))
+            if not (c0 < 2.0 and c1 < 2.0 and c3 < 2.0):
+                continue
+            if c0 >= 1.0:
+                assert c3 <= c0 + 1e-15
+            else:
+                assert c3 >= c0 - 1e-15
+            assert abs(c3 - c0) <= 1e-4
+            d1.append(abs(c1 - c0))
+            d3.append(abs(c3 - c0))
+    d1, d3 = np.array(d1), np.array(d3)
+    assert len(d3) > 500 and d3.max() > 0.0
+    assert np.mean(d3 >= d1) >= 0.9
+
+
 def test_cost_noise_probe_is_bounded_deterministic_and_centred(oracle_mod, scene_c1):
     """The second conditioning probe (cost_noise = e) moves every scored cost by a fixed offset in
     [-e/2, e/2) that depends only on (pixel, view, plane); cost 2 and the clamp are untouched."""
