@@ -244,6 +244,9 @@ constexpr int kWinStride = 48;  // float2 units: 36 + 6 float4
 // 36 samples, sink.row(r, constants) for the 6 rows.
 template <typename Reader, typename Sink>
 __device__ __forceinline__ WinStats build_window_to(const Reader &rd, const MethodDev &m, Sink &sink) {
+    // every operation rounded as written: the kernels that build a pixel's block must agree bit for bit, and
+    // a contraction the compiler may or may not make in each of them would break that
+#pragma clang fp contract(off)
     float a[36];
     const float ac = rd(0, 0);
     float sw = 0.f, swa = 0.f;
@@ -296,6 +299,22 @@ __device__ __forceinline__ WinStats build_window_to(const Reader &rd, const Meth
     return ws;
 }
 
+// The window block of one pixel in its lane's registers: the 36 sample entries and 6 row constants.
+struct RegWin {
+    float2 smp[36];
+    float4 rc[6];
+};
+struct RegWinSink {
+    RegWin *win;
+    __device__ __forceinline__ void sample(int s, float2 v) const { win->smp[s] = v; }
+    __device__ __forceinline__ void row(int r, float4 v) const { win->rc[r] = v; }
+};
+struct RegWinRef {
+    const RegWin &win;
+    __device__ __forceinline__ float2 sample(int s) const { return win.smp[s]; }
+    __device__ __forceinline__ float4 row(int r) const { return win.rc[r]; }
+};
+
 // LDS block of kWinStride float2: the entries s with s mod stride == phase (the lanes of a pixel split the writes)
 struct LdsWinSink {
     float2 *rw;
@@ -338,6 +357,9 @@ __device__ __forceinline__ void window_moments(const void *__restrict__ quads, c
                                                float N0x, float N0y, float Z0, float pux, float puy, float puz,
                                                float pvx, float pvy, float pvz, int xlo, int xhi, int ylo, int yhi,
                                                int row_bytes, int base, float &m2, float &cab) {
+    // every operation rounded as written (see build_window_to); the products with the unrounded row mean
+    // are explicit fused multiply-adds
+#pragma clang fp contract(off)
     // Source moments row by row: the 6 samples of a window row are held, their weighted mean,
     // centred square sum and cross sum with the reference formed exactly (two passes over the
     // row), and the rows merged with the parallel-variance update (Chan, Golub, LeVeque):
@@ -366,19 +388,19 @@ __device__ __forceinline__ void window_moments(const void *__restrict__ quads, c
             issue_row<HALF, CLAMP>(quads, -3.f + 2.f * sv, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo,
                                    yhi, row_bytes, base, qd, fxs, fys);
         const float4 rc = win.row(sv);
-        const float mur = srow * rc.x;
+        // mu_r = srow / W_r enters unrounded: d = v - mu_r, delta = mu_r - mean and mu_r - mean' in one rounding
         float m2r = 0.f, cr = 0.f;
 #pragma unroll
         for (int su = 0; su < 6; ++su) {
             const float2 wa = win.sample(sv * 6 + su);
-            const float d = v6[su] - mur;
+            const float d = fmaf(-srow, rc.x, v6[su]);
             m2r = fmaf(wa.x * d, d, m2r);
             cr = fmaf(wa.y, d, cr);
         }
-        const float delta = mur - mu;
+        const float delta = fmaf(srow, rc.x, -mu);
         const float mun = fmaf(delta, rc.y, mu);
         m2 += fmaf(rc.z * delta, delta, m2r);
-        cab += fmaf(mur - mun, rc.w, fmaf(mu - mun, acum, cr));
+        cab += fmaf(fmaf(srow, rc.x, -mun), rc.w, fmaf(mu - mun, acum, cr));
         acum += rc.w;
         mu = mun;
     }
@@ -778,61 +800,43 @@ __device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned cha
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation of one colour with L lanes per pixel, lane j scoring sources
-// j, j + L, ...: L = ceil(N / 2) (two sources per lane), but at least
-// min(N, 4) so that 64 pixels still fill the 256 lanes.  A workgroup holds
-// G = min(64, 256 / L) pixels of the colour in row-major order x L lanes, so
-// nearly every lane evaluates (the tiled body above leaves most lanes of its
-// second round idle when N is not a multiple of 9), and the per-pixel work
-// every lane repeats (window block, random plane) is spread over up to two
-// evaluations.  The L lanes of a pixel build its window block together, score
-// the same plane on their sources, and the pixel's first lane takes the mean
-// of the k lowest costs.  Same arithmetic as init_body, so the two give
-// identical states.
+// Initialisation of one colour with one pixel per lane: the pixel's window
+// block is built once, in its lane's registers, and the wave walks the sources
+// together (the view's warp constants in scalar registers, as in the pass), so
+// that the per-pixel work (window block, random plane) is done once per pixel
+// and no lane loads warp constants of its own.  256 pixels of the colour per
+// workgroup in row-major order, workgroups in XCD bands; the costs go to LDS,
+// one row per source, and each lane takes the mean of its k lowest.  Same
+// arithmetic as the batched initialisation (init_body), so the two give
+// identical states.  The block takes 96 registers of the lane; the kernel is
+// compiled for 2 waves per SIMD (at 3 it spills inside the source loop).
 // ---------------------------------------------------------------------------
-constexpr int kInitMaxPix = 64;
-constexpr int kInitViewsPerLane = 2;
-
-__host__ __device__ inline int init_lanes_per_pixel(int n_src) {
-    const int l = (n_src + kInitViewsPerLane - 1) / kInitViewsPerLane, fill = 256 / kInitMaxPix;
-    return l >= fill ? l : (n_src < fill ? n_src : fill);
-}
-__host__ __device__ inline int init_pixels_per_group(int n_src) {
-    const int g = 256 / init_lanes_per_pixel(n_src);
-    return g < kInitMaxPix ? g : kInitMaxPix;
-}
-
 template <int HALF>
-__global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
-    __shared__ __align__(16) float2 rwbuf[kInitMaxPix * kWinStride];
-    __shared__ float cst[256 * kInitViewsPerLane];  // G * N <= 512 for every N (G <= 64, G * L <= 256)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void init_reg_kernel(PassArgs a) {
+    extern __shared__ __align__(16) float cst[];  // [n_src][256]
     __shared__ unsigned nshort;
     const int N = a.n_src;
-    const int Lp = init_lanes_per_pixel(N), G = init_pixels_per_group(N);
-    const int t = threadIdx.x, g = t / Lp, j = t - g * Lp;
-    const bool lane_ok = g < G;
+    const int t = threadIdx.x;
     const int per_row = (a.ref.W + 1) / 2;  // slots per row; x beyond the image is skipped
-    // XCD bands: block b runs on XCD b mod 8 and takes the (b / 8)-th group of that XCD's contiguous band of
-    // groups, so that each XCD's L2 holds the sources' footprint of its own rows only
-    const long long n_groups = ((long long)a.ref.H * per_row + G - 1) / G;
-    const long long per_xcd = (n_groups + 7) >> 3;
-    const long long grp_id = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (grp_id >= n_groups) return;  // the whole workgroup leaves before any barrier
-    const long long pc = grp_id * G + g;
+    const long long n_blocks = ((long long)a.ref.H * per_row + 255) / 256;
+    const long long per_xcd = (n_blocks + 7) >> 3;
+    const long long blk = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (blk >= n_blocks) return;  // the whole workgroup leaves before any barrier
+    const long long pc = blk * 256 + t;
     const int y = (int)(pc / per_row);
     const int x = 2 * (int)(pc - (long long)y * per_row) + ((y + a.colour) & 1);
-    const bool pix_ok = lane_ok && y < a.ref.H && x < a.ref.W;
-    float2 *rw = rwbuf + (lane_ok ? g : 0) * kWinStride;
-    WinStats ws = {1.f, 0.f};
-    if (pix_ok) {
-        GlobalReader rd{&a.ref, x, y};
-        ws = build_window(rd, a.m, rw, j, Lp);
-    }
+    const bool pix_ok = y < a.ref.H && x < a.ref.W;
     if (t == 0) nshort = 0u;
-    __syncthreads();
+    RegWin win;
+    WinStats ws = {1.f, 0.f};
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
     bool fell_back = false;
+    PlaneQ q;
+    q.ok = false;
     if (pix_ok) {
+        GlobalReader rd{&a.ref, x, y};
+        RegWinSink sink{&win};
+        ws = build_window_to(rd, a.m, sink);
         const float2 r = ref_ray(a.ref, x, y);
         if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
             fell_back = a.prop != nullptr;
@@ -842,18 +846,21 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
             normal_from_uniforms(u[1], u[2], nx, ny, nz);
             pl = plane_from(r, depth, nx, ny, nz);
         }
-        const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
-        for (int v = j; v < N; v += Lp)
-            cst[g * N + v] = short_to_cost(
-                q.ok ? ncc_cost_raw<HALF, false>(a.views[v], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort, &nshort);
+        q = plane_q(a.ref, a.m, pl, x, y);
+        // the plane is final: store it now, so that it is not held through the source loop
+        store_plane(a.st.planes, (size_t)y * a.ref.W + x, pl);
     }
-    count_evals(a.counters, 0, pix_ok ? (unsigned long long)((N - j + Lp - 1) / Lp) : 0ull);
-    if (a.prop) count_evals(a.counters, 3, (fell_back && j == 0) ? 1ull : 0ull);
     __syncthreads();
-    count_evals(a.counters, 5, t == 0 ? (unsigned long long)nshort : 0ull);
-    if (pix_ok && j == 0) {
-        // mean of the k lowest costs, in ascending order
-        const float *c = cst + g * N;
+    for (int j = 0; j < N; ++j) {
+        if (pix_ok)
+            cst[j * 256 + t] = short_to_cost(
+                q.ok ? ncc_cost_win<HALF, false>(a.views[j], RegWinRef{win}, ws, x, y, q.q0, q.qu, q.qv) : kShort,
+                &nshort);
+    }
+    count_evals(a.counters, 0, pix_ok ? (unsigned long long)N : 0ull);
+    if (a.prop) count_evals(a.counters, 3, fell_back ? 1ull : 0ull);
+    if (pix_ok) {
+        // mean of the k lowest costs, in ascending order (each lane reads only the costs it wrote)
         const int kk = a.m.k < N ? a.m.k : N;
         uint32_t taken = 0;
         float sum = 0.f;
@@ -862,20 +869,22 @@ __global__ __launch_bounds__(256) void init_pix_kernel(PassArgs a) {
             float bc = 0.f;
             for (int v = 0; v < N; ++v) {
                 if ((taken >> v) & 1u) continue;
-                if (best < 0 || c[v] < bc) {
+                const float c = cst[v * 256 + t];
+                if (best < 0 || c < bc) {
                     best = v;
-                    bc = c[v];
+                    bc = c;
                 }
             }
             taken |= 1u << best;
             sum += bc;
         }
         const size_t p = (size_t)y * a.ref.W + x;
-        store_plane(a.st.planes, p, pl);
         glob(a.st.cost)[p] = sum / (float)kk;
         glob(a.st.S)[p] = 0u;
         glob(a.st.v)[p] = -1;
     }
+    __syncthreads();
+    count_evals(a.counters, 5, t == 0 ? (unsigned long long)nshort : 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -1687,38 +1696,12 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 
 static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
-// Single-image initialisation with the tiled body of the batched launch (9 lanes per pixel, windows from the
-// LDS tile, the pass's tile order): with many sources its rounds of 9 sources fill the lanes well, and it is
-// faster than init_pix_kernel (6.6 vs 7.2 ms per launch at 3200x2130 with 20 sources); with few it is slower.
-template <int HALF, int WAVES>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_BATCH_WAVES_PER_EU)))
-void init_tile_kernel(PassArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int L = tile_of_block(a.n_tiles, a.order);
-    if (L < 0) return;
-    init_body<HALF, WAVES>(a, L, smem);
-}
-
-constexpr int kInitTiledFrom = 14;  // sources from which the tiled initialisation is used
-
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
-    if (a.n_src >= kInitTiledFrom && (a.waves == 2 || a.waves == 4)) {
-        const size_t lds = pass_lds_bytes(a.n_src, a.waves);
-        const dim3 grid(grid_for(a.n_tiles)), block(64 * a.waves);
-        if (a.waves == 2) {
-            if (half) AMH_LAUNCH((init_tile_kernel<1, 2>), grid, block, lds, s, a);
-            else AMH_LAUNCH((init_tile_kernel<0, 2>), grid, block, lds, s, a);
-        } else {
-            if (half) AMH_LAUNCH((init_tile_kernel<1, 4>), grid, block, lds, s, a);
-            else AMH_LAUNCH((init_tile_kernel<0, 4>), grid, block, lds, s, a);
-        }
-        return hipGetLastError();
-    }
     const long long slots = (long long)a.ref.H * ((a.ref.W + 1) / 2);
-    const int G = init_pixels_per_group(a.n_src);
-    const dim3 grid((unsigned)(8 * (((slots + G - 1) / G + 7) / 8)));
-    if (half) AMH_LAUNCH(init_pix_kernel<1>, grid, dim3(256), 0, s, a);
-    else AMH_LAUNCH(init_pix_kernel<0>, grid, dim3(256), 0, s, a);
+    const dim3 grid((unsigned)(8 * (((slots + 255) / 256 + 7) / 8)));
+    const size_t lds = sizeof(float) * 256 * a.n_src;
+    if (half) AMH_LAUNCH(init_reg_kernel<1>, grid, dim3(256), lds, s, a);
+    else AMH_LAUNCH(init_reg_kernel<0>, grid, dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
