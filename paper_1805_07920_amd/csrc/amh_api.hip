@@ -412,6 +412,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         b.st = StateDev{c->jobs[j].planes, c->jobs[j].cost, c->jobs[j].S, c->jobs[j].v};
         b.tiles_x = ((r.W + 1) / 2 + kTilePix - 1) / kTilePix;
         b.n_tiles = b.tiles_x * ((r.H + c->cfg_waves - 1) / c->cfg_waves);
+        b.n_iblocks = (int)init_blocks(r.W, r.H);
         b.prop = proposal ? c->jobs[j].pred : nullptr;
         b.prop_w = proposal ? cell_rows(r.W) : 0;
         so += jobs[j].n_src;
@@ -427,7 +428,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
     };
     std::vector<Phase> phases;
     std::vector<int> tab;
-    // A phase is launched once per LDS class: workgroups whose sources need less LDS fit more of them on
+    // A half-pass is launched once per LDS class: workgroups whose sources need less LDS fit more of them on
     // a CU (160 KB), so the jobs of a phase are grouped by how many workgroups per CU their view count
     // allows (capped at 4 waves per SIMD); one launch per group, largest occupancy first.
     const int wg_cap = 16 / c->cfg_waves;
@@ -437,10 +438,12 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         ph.n_active = (int)act.size();
         if (ph.n_active == 0) return;
         for (int j : act) ph.max_src = std::max(ph.max_src, jobs[j].n_src);
+        // work items per job: initialisation blocks or pass tiles
+        auto items = [&](int j) { return kind == 0 ? hj[j].n_iblocks : hj[j].n_tiles; };
         int acc = 0;
         for (int j : act) {
             tab.push_back(acc);
-            acc += hj[j].n_tiles;
+            acc += items(j);
         }
         tab.push_back(acc);
         ph.total = acc;
@@ -456,7 +459,7 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
             int acc_x = 0;
             tab.push_back(0);
             for (int k = 0; k < (int)act.size(); ++k) {
-                const long long n = hj[act[k]].n_tiles;
+                const long long n = items(act[k]);
                 const int bi = (x + k) & 7;
                 acc_x += (int)((n * (bi + 1)) >> 3) - (int)((n * bi) >> 3);
                 tab.push_back(acc_x);
@@ -470,6 +473,10 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         std::vector<int> act;
         for (int j : order)
             if (kind == 0 || jobs[j].iters > t) act.push_back(j);
+        if (kind == 0) {  // the initialisation's LDS (costs of 256 pixels) is small for every view count
+            add_group(kind, colour, t, act);
+            return;
+        }
         for (int w = wg_cap; w >= 1; --w) {
             std::vector<int> grp;
             for (int j : act)

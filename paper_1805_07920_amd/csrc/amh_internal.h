@@ -75,6 +75,12 @@ struct PassArgs {
     float conf_min = 0.f;
 };
 
+// Pixels of one colour per initialisation workgroup (one per lane), and the workgroups of one colour.
+constexpr int kInitBlock = 256;
+__host__ __device__ inline long long init_blocks(int W, int H) {
+    return ((long long)H * ((W + 1) / 2) + kInitBlock - 1) / kInitBlock;
+}
+
 // one reference image of a batch
 struct BatchJobDev {
     RefDev ref;
@@ -83,6 +89,7 @@ struct BatchJobDev {
     int n_src;
     StateDev st;
     int tiles_x, n_tiles;        // tile grid of one colour
+    int n_iblocks;               // initialisation blocks of one colour (init_blocks)
     const float *prop;           // per-cell predictions for the initialisation, or NULL (random)
     int prop_w;                  // cell grid width
 };

@@ -721,108 +721,25 @@ __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int 
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation: a random plane per pixel (PatchMatch random init), or the
-// proposal's plane where one is given and usable; initial cost = mean of the k
-// lowest per-view costs.  Same tile mapping as the pass, one launch per
-// colour.  Lane r of a pixel scores views r, r+9, r+18, r+27.
-// ---------------------------------------------------------------------------
-template <int HALF, int WAVES>
-__device__ __forceinline__ void init_body(const PassArgs &a, int L, unsigned char *smem) {
-    PassLds S = carve(smem, a.n_src, WAVES);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int grp = lane / kRows, row = lane - grp * kRows;
-    const int ty = L / a.tiles_x, tx = L - ty * a.tiles_x;
-    const int y0 = ty * WAVES, x0 = tx * 2 * kTilePix;
-    const int y = y0 + wave;
-    const int x = 2 * (tx * kTilePix + grp) + ((y + a.colour) & 1);
-    const bool pix_ok = grp < kGroups && y < a.ref.H && x < a.ref.W;
-
-    stage_tile<WAVES>(a.ref, S.tile, y0, x0, tid);
-    if (lane == 0) S.nshort[wave] = 0u;
-    __syncthreads();
-    float2 *rw = S.rw + (wave * kGroups + (grp < kGroups ? grp : 0)) * kWinStride;
-    WinStats ws = {1.f, 0.f};
-    if (pix_ok) {
-        TileReader rd{S.tile, 5 + wave, 5 + (x - x0), &a.ref, x, y};
-        ws = build_window(rd, a.m, rw, row, kRows);
-    }
-    __syncthreads();
-
-    const int N = a.n_src;
-    float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
-    float *mcol = S.ms + wave * N * 64;  // m of view j for group g at mcol[j * 64 + g * 9]
-    int n_eval = 0;
-    bool fell_back = false;  // a proposal was given but this pixel keeps the random plane
-    if (pix_ok) {
-        const float2 r = ref_ray(a.ref, x, y);
-        if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
-            fell_back = a.prop != nullptr;
-            float u[4], nx, ny, nz;
-            philox((uint64_t)y * a.ref.W + x, 0, 0, a.m.seed, u);
-            const float depth = a.m.d_min + u[0] * (a.m.d_max - a.m.d_min);
-            normal_from_uniforms(u[1], u[2], nx, ny, nz);
-            pl = plane_from(r, depth, nx, ny, nz);
-        }
-        const PlaneQ q = plane_q(a.ref, a.m, pl, x, y);
-        for (int j = row; j < N; j += kRows) {
-            const float c = short_to_cost(q.ok ? ncc_cost_raw<HALF, false>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv)
-                                               : kShort, &S.nshort[wave]);
-            mcol[j * 64 + grp * kRows] = c;
-            ++n_eval;
-        }
-    }
-    __syncthreads();
-    if (pix_ok && row == 0) {
-        // mean of the k lowest costs, in ascending order
-        const int kk = a.m.k < N ? a.m.k : N;
-        uint32_t taken = 0;
-        float sum = 0.f;
-        for (int r = 0; r < kk; ++r) {
-            int best = -1;
-            float bc = 0.f;
-            for (int j = 0; j < N; ++j) {
-                if ((taken >> j) & 1u) continue;
-                const float c = mcol[j * 64 + grp * kRows];
-                if (best < 0 || c < bc) { best = j; bc = c; }
-            }
-            taken |= 1u << best;
-            sum += bc;
-        }
-        const size_t p = (size_t)y * a.ref.W + x;
-        store_plane(a.st.planes, p, pl);
-        glob(a.st.cost)[p] = sum / (float)kk;
-        glob(a.st.S)[p] = 0u;
-        glob(a.st.v)[p] = -1;
-    }
-    count_evals(a.counters, 0, (unsigned long long)n_eval);
-    count_evals(a.counters, 5, lane == 0 ? (unsigned long long)S.nshort[wave] : 0ull);
-    if (a.prop) count_evals(a.counters, 3, (fell_back && row == 0) ? 1ull : 0ull);
-}
-
-// ---------------------------------------------------------------------------
 // Initialisation of one colour with one pixel per lane: the pixel's window
 // block is built once, in its lane's registers, and the wave walks the sources
 // together (the view's warp constants in scalar registers, as in the pass), so
 // that the per-pixel work (window block, random plane) is done once per pixel
 // and no lane loads warp constants of its own.  256 pixels of the colour per
 // workgroup in row-major order, workgroups in XCD bands; the costs go to LDS,
-// one row per source, and each lane takes the mean of its k lowest.  Same
-// arithmetic as the batched initialisation (init_body), so the two give
-// identical states.  The block takes 96 registers of the lane; the kernel is
-// compiled for 2 waves per SIMD (at 3 it spills inside the source loop).
+// one row per source, and each lane takes the mean of its k lowest.  The
+// batched initialisation runs the same body, so a job's initial state is the
+// same bits either way.  The block takes 96 registers of the lane; the kernel
+// is compiled for 2 waves per SIMD (at 3 it spills inside the source loop).
 // ---------------------------------------------------------------------------
+// Block blk (of init_blocks) of the colour: cst is [n_src][256] floats of LDS, nshort an LDS counter.
 template <int HALF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void init_reg_kernel(PassArgs a) {
-    extern __shared__ __align__(16) float cst[];  // [n_src][256]
-    __shared__ unsigned nshort;
+__device__ __forceinline__ void init_reg_body(const PassArgs &a, long long blk, float *cst, unsigned *nshort_p) {
+    unsigned &nshort = *nshort_p;
     const int N = a.n_src;
     const int t = threadIdx.x;
     const int per_row = (a.ref.W + 1) / 2;  // slots per row; x beyond the image is skipped
-    const long long n_blocks = ((long long)a.ref.H * per_row + 255) / 256;
-    const long long per_xcd = (n_blocks + 7) >> 3;
-    const long long blk = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (blk >= n_blocks) return;  // the whole workgroup leaves before any barrier
-    const long long pc = blk * 256 + t;
+    const long long pc = blk * kInitBlock + t;
     const int y = (int)(pc / per_row);
     const int x = 2 * (int)(pc - (long long)y * per_row) + ((y + a.colour) & 1);
     const bool pix_ok = y < a.ref.H && x < a.ref.W;
@@ -885,6 +802,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void i
     }
     __syncthreads();
     count_evals(a.counters, 5, t == 0 ? (unsigned long long)nshort : 0ull);
+}
+
+template <int HALF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void init_reg_kernel(PassArgs a) {
+    extern __shared__ __align__(16) float cst[];  // [n_src][256]
+    __shared__ unsigned nshort;
+    // XCD bands: block b runs on XCD b mod 8 and takes the (b / 8)-th block of that XCD's band
+    const long long n_blocks = init_blocks(a.ref.W, a.ref.H);
+    const long long per_xcd = (n_blocks + 7) >> 3;
+    const long long blk = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (blk >= n_blocks) return;  // the whole workgroup leaves before any barrier
+    init_reg_body<HALF>(a, blk, cst, &nshort);
 }
 
 // ---------------------------------------------------------------------------
@@ -1271,22 +1200,17 @@ __device__ __forceinline__ T make_uniform(const T &v) {
     return r;
 }
 
-// KIND: 0 initialisation, 1 half-pass (separate kernels, so that each gets its own register budget)
-template <int HALF, int WAVES, int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND ? AMH_PASS_WAVES_PER_EU : AMH_BATCH_WAVES_PER_EU)))
-void batch_kernel(BatchPhaseArgs b) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    // order 0: every job's tiles are cut into 8 contiguous bands; XCD x (workgroups round-robin over
-    // the XCDs) walks one band of each job in job order -- band (x + slot) mod 8 of the job at active
-    // slot `slot`, so that the larger bands of uneven cuts rotate over the XCDs -- and all XCDs move
-    // through the jobs together (one job's sources in the shared cache, neighbouring tiles in each
-    // XCD's L2).  xcd_pre[x][slot] is the prefix sum of XCD x's band sizes.
-    // order 1: hardware order over the concatenated tiles.
-    int lo, L;
+// Work item g of a batched phase: the active slot lo and the job-local tile (or initialisation block) L.
+// Order 0: every job's items are cut into 8 contiguous bands; XCD x (workgroups round-robin over the
+// XCDs) walks one band of each job in job order -- band (x + slot) mod 8 of the job at active slot `slot`,
+// so that the larger bands of uneven cuts rotate over the XCDs -- and all XCDs move through the jobs
+// together (one job's sources in the shared cache, neighbouring items in each XCD's L2).  xcd_pre[x][slot]
+// is the prefix sum of XCD x's band sizes.  Order 1: hardware order over the concatenated items.
+__device__ __forceinline__ bool batch_locate(const BatchPhaseArgs &b, int &lo, int &L) {
     if (b.order == 0) {
         const int x = blockIdx.x & 7, g = (int)(blockIdx.x >> 3);
         const int *pre = b.xcd_pre + x * (b.n_active + 1);
-        if (g >= pre[b.n_active]) return;
+        if (g >= pre[b.n_active]) return false;
         int a0 = 0, a1 = b.n_active;  // pre[a0] <= g < pre[a1]
         while (a1 - a0 > 1) {
             const int mid = (a0 + a1) >> 1;
@@ -1298,7 +1222,7 @@ void batch_kernel(BatchPhaseArgs b) {
         L = (int)(((long long)n * ((x + lo) & 7)) >> 3) + (g - pre[lo]);
     } else {
         const int g = blockIdx.x;
-        if (g >= b.total_tiles) return;
+        if (g >= b.total_tiles) return false;
         int a0 = 0, a1 = b.n_active;  // tile_start[a0] <= g < tile_start[a1]
         while (a1 - a0 > 1) {
             const int mid = (a0 + a1) >> 1;
@@ -1308,8 +1232,13 @@ void batch_kernel(BatchPhaseArgs b) {
         lo = a0;
         L = g - b.tile_start[lo];
     }
-    const int j = b.job_of[lo];
-    const BatchJobDev &J = b.jobs[j];
+    return true;
+}
+
+// The single-image arguments of job J in a batched phase, in scalar registers (the job's arguments are the
+// same for the whole workgroup; the source table as an offset from the argument's pointer, so that the
+// per-view constants are read like the single-image kernels read theirs: scalar loads)
+__device__ __forceinline__ PassArgs batch_pass_args(const BatchPhaseArgs &b, const BatchJobDev &J, int waves) {
     PassArgs a;
     a.ref = J.ref;
     a.n_src = J.n_src;
@@ -1321,28 +1250,54 @@ void batch_kernel(BatchPhaseArgs b) {
     a.n_tiles = J.n_tiles;
     a.counters = b.counters;
     a.order = b.order;
-    a.waves = WAVES;
+    a.waves = waves;
     a.prop = J.prop;
     a.prop_w = J.prop_w;
     a.prop_s = kCell;
     a.conf_min = b.conf_min;
-    // the job's arguments are the same for the whole workgroup: keep them (and the gathers' base
-    // addresses) in scalar registers, as for the single-image kernels' by-value arguments
     a = make_uniform(a);
-    L = __builtin_amdgcn_readfirstlane(L);
-    // the source table as an offset from the argument's pointer, so that the per-view constants are
-    // read like the single-image kernels read theirs (scalar loads from a kernel-argument buffer)
     a.views = b.views + __builtin_amdgcn_readfirstlane(J.view_off);
-    if (KIND == 0) init_body<HALF, WAVES>(a, L, smem);
-    else pass_body<HALF, WAVES>(a, L, smem, (int)threadIdx.x);
+    return a;
+}
+
+// the job's completion time: stamped by the last work item of its last phase
+__device__ __forceinline__ void batch_stamp(const BatchPhaseArgs &b, int lo, int j, long long items) {
     if (b.is_last[lo]) {
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();
-            if (atomicAdd(&b.tiles_done[j], 1ull) == (unsigned long long)(J.n_tiles - 1))
-                b.job_end[j] = wall_clock64();
+            if (atomicAdd(&b.tiles_done[j], 1ull) == (unsigned long long)(items - 1)) b.job_end[j] = wall_clock64();
         }
     }
+}
+
+// Batched half-pass: one tile per workgroup.
+template <int HALF, int WAVES>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AMH_PASS_WAVES_PER_EU)))
+void batch_kernel(BatchPhaseArgs b) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int lo, L;
+    if (!batch_locate(b, lo, L)) return;
+    const int j = b.job_of[lo];
+    const BatchJobDev &J = b.jobs[j];
+    const PassArgs a = batch_pass_args(b, J, WAVES);
+    pass_body<HALF, WAVES>(a, __builtin_amdgcn_readfirstlane(L), smem, (int)threadIdx.x);
+    batch_stamp(b, lo, j, J.n_tiles);
+}
+
+// Batched initialisation: one initialisation block (256 pixels of the colour) per workgroup, the body of
+// the single-image kernel, so that a job's initial state is the same bits either way.
+template <int HALF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_init_kernel(BatchPhaseArgs b) {
+    extern __shared__ __align__(16) float cst[];  // [max n_src][256]
+    __shared__ unsigned nshort;
+    int lo, L;
+    if (!batch_locate(b, lo, L)) return;
+    const int j = b.job_of[lo];
+    const BatchJobDev &J = b.jobs[j];
+    const PassArgs a = batch_pass_args(b, J, 4);
+    init_reg_body<HALF>(a, __builtin_amdgcn_readfirstlane(L), cst, &nshort);
+    batch_stamp(b, lo, j, J.n_iblocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -1697,9 +1652,8 @@ hipError_t launch_zero_u64(unsigned long long *p, int n, hipStream_t s) {
 static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
-    const long long slots = (long long)a.ref.H * ((a.ref.W + 1) / 2);
-    const dim3 grid((unsigned)(8 * (((slots + 255) / 256 + 7) / 8)));
-    const size_t lds = sizeof(float) * 256 * a.n_src;
+    const dim3 grid((unsigned)(8 * ((init_blocks(a.ref.W, a.ref.H) + 7) / 8)));
+    const size_t lds = sizeof(float) * kInitBlock * a.n_src;
     if (half) AMH_LAUNCH(init_reg_kernel<1>, grid, dim3(256), lds, s, a);
     else AMH_LAUNCH(init_reg_kernel<0>, grid, dim3(256), lds, s, a);
     return hipGetLastError();
@@ -1733,23 +1687,24 @@ hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
 
 hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s) {
     if (b.total_tiles == 0) return hipSuccess;
+    const dim3 grid(b.grid);
+    if (b.kind == 0) {
+        const size_t lds = sizeof(float) * kInitBlock * max_src;
+        if (half) AMH_LAUNCH(batch_init_kernel<1>, grid, dim3(kInitBlock), lds, s, b);
+        else AMH_LAUNCH(batch_init_kernel<0>, grid, dim3(kInitBlock), lds, s, b);
+        return hipGetLastError();
+    }
     const size_t lds = pass_lds_bytes(max_src, b.waves);
-    const dim3 grid(b.grid), block(64 * b.waves);
-#define AMH_BATCH_LAUNCH(H, WV)                                                  \
-    do {                                                                         \
-        if (b.kind == 0) AMH_LAUNCH((batch_kernel<H, WV, 0>), grid, block, lds, s, b); \
-        else AMH_LAUNCH((batch_kernel<H, WV, 1>), grid, block, lds, s, b);            \
-    } while (0)
+    const dim3 block(64 * b.waves);
     if (b.waves == 2) {
-        if (half) AMH_BATCH_LAUNCH(1, 2);
-        else AMH_BATCH_LAUNCH(0, 2);
+        if (half) AMH_LAUNCH((batch_kernel<1, 2>), grid, block, lds, s, b);
+        else AMH_LAUNCH((batch_kernel<0, 2>), grid, block, lds, s, b);
     } else if (b.waves == 4) {
-        if (half) AMH_BATCH_LAUNCH(1, 4);
-        else AMH_BATCH_LAUNCH(0, 4);
+        if (half) AMH_LAUNCH((batch_kernel<1, 4>), grid, block, lds, s, b);
+        else AMH_LAUNCH((batch_kernel<0, 4>), grid, block, lds, s, b);
     } else {
         return hipErrorInvalidValue;
     }
-#undef AMH_BATCH_LAUNCH
     return hipGetLastError();
 }
 
