@@ -47,10 +47,10 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
 # profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
 # autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 2301421.3, "write_kib": 90234.0},
-                                 4: {"fetch_kib": 1395229.4, "write_kib": 88653.0}},
+PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 448802.7, "write_kib": 85945.6},
+                                 4: {"fetch_kib": 360426.3, "write_kib": 83603.5}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
-                "kernel_sha256": "6b3f05592743751ffd0c335540de336f51e2f028921a7efbef1639e61b7a3ea1"}
+                "kernel_sha256": "9c076b5c0652b8547547f5a8f6b403e6648049577438827b721d5fa5c74460cf"}
 
 
 # The same two counters for the fusion kernel of one reference view (11 views of 1920x1280, mean over the
