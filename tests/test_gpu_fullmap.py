@@ -12,8 +12,9 @@ Cases (the oracle runs whole, on all host cores):
     one the benchmark times);
   * 800x532 reference + 20 sources stored in float16, 30 % of the area
     low-texture planes, 4 iterations + refinement -- the 3200x2130 recipe at a
-    quarter of its side: the tiled initialisation (>= 14 sources), the float16
-    gather layout and the random refinement candidates of t >= 3 all run.
+    quarter of its side: the initialisation and the source loop at 20 sources,
+    the float16 gather layout and the random refinement candidates of t >= 3
+    all run.
 
 Both sides' accuracy against the rendered depth is printed and compared, which
 separates what the method reaches from what the kernels do.
