@@ -235,10 +235,12 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
-def learned_comparison(seeds, steps: int, warmup: int, seed: int = 0, weights=None):
+def learned_comparison(seeds, steps: int, warmup: int, seed: int = 0, weights=None, sweep_sources: int = 0):
     """Learned proposal + 1 iteration against random initialisation + 1 and + 3 iterations (the plain
     method) on held-out 1920x1280 scenes with 10 sources: device-synchronised time per depth map and the
-    fraction of visible pixels within 1 %, 2 cm and 10 cm of the rendered depth, per path and scene."""
+    fraction of visible pixels within 1 %, 2 cm and 10 cm of the rendered depth, per path and scene.
+    sweep_sources: sources the proposal's plane sweep reads (0: the library's 4); the weights must have
+    been trained with the same count."""
     import torch
 
     import paper_1805_07920_amd as amh
@@ -247,7 +249,7 @@ def learned_comparison(seeds, steps: int, warmup: int, seed: int = 0, weights=No
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     weights = weights or os.path.join(ROOT, "paper_1805_07920_amd", "weights", "proposal.bin")
-    ctx = amh.Context(refine=1, seed=seed)
+    ctx = amh.Context(refine=1, seed=seed, sweep_sources=sweep_sources)
     ctx.nn_load(weights)
     runs = {"proposal+1": [], "random+1": [], "random+3": []}
     H = W = 0
@@ -293,7 +295,7 @@ def learned_comparison(seeds, steps: int, warmup: int, seed: int = 0, weights=No
             "speedup_vs_plain": plain["ms"] / p["ms"], "equal_accuracy": bool(equal),
             "equal_accuracy_rule": "proposal >= plain within 10 cm and no more than 0.5 points below it within 2 cm",
             "workload": f"learned proposal + 1 iteration vs plain 3 iterations, {W}x{H}, 10 sources, held-out "
-                        f"scene seeds {seeds[0]}-{seeds[-1]}",
+                        f"scene seeds {seeds[0]}-{seeds[-1]}, sweep over {sweep_sources or 4} sources",
             "accuracy": mean, "per_scene": runs, "autotune": {"best_config": tuned[0], "ms_per_config": tuned[1]}}
 
 
@@ -302,6 +304,11 @@ def bench_learned(args):
     (random initialisation + 3 iterations), 1920x1280 with 10 sources, held-out scene seeds."""
     seeds = list(range(args.eval_seed0, args.eval_seed0 + args.eval_scenes))
     r = learned_comparison(seeds, args.steps, args.warmup, seed=args.seed, weights=args.weights)
+    # the configuration's 8-source plane sweep, with the network trained on it, beside the 4-source one
+    w8 = os.path.join(ROOT, "paper_1805_07920_amd", "weights", "proposal8.bin")
+    r8 = None
+    if args.weights is None and os.path.exists(w8):
+        r8 = learned_comparison(seeds, args.steps, args.warmup, seed=args.seed, weights=w8, sweep_sources=8)
     out = {
         "metric": METRIC, "value": r["sec_per_depth_map"], "unit": "s per depth map", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * r["sec_per_depth_map"],
@@ -312,6 +319,9 @@ def bench_learned(args):
         "equal_accuracy": r["equal_accuracy"], "equal_accuracy_rule": r["equal_accuracy_rule"],
         "accuracy": r["accuracy"], "per_scene": r["per_scene"], "autotune": r["autotune"],
     }
+    if r8 is not None:
+        out["sweep_8_sources"] = {k: r8[k] for k in ("sec_per_depth_map", "plain_sec_per_depth_map",
+                                                     "speedup_vs_plain", "equal_accuracy", "accuracy", "workload")}
     print(json.dumps(out))
 
 

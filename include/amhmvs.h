@@ -103,6 +103,8 @@ typedef struct {
     int bilateral_squared; /* 1: the bilateral weight of Eq. 8 with squared colour difference and squared
                             * distance, exp(-dI^2 / (2 sigma_color^2) - |dx|^2 / (2 sigma_spatial^2));
                             * default 0: unsquared, as the equation is printed */
+    int sweep_sources;   /* learned proposal: the plane sweep reads the first min(sweep_sources, n_src)
+                          * sources (list the nearest first); 0 (default) = 4; at most 32 */
 } amh_params;
 
 /* Counters of the work performed since the last amh_begin / amh_run_checkerboard. */
@@ -225,7 +227,7 @@ amh_status amh_run_batch(amh_ctx *ctx, int n_jobs, const amh_job *jobs);
 
 /* amh_run_batch with every job initialised from the learned proposal instead of
  * random planes: the plane sweep and the network's forward pass of each job
- * (amh_sweep_features, amh_nn_forward; sweep on the job's first min(4, n_src)
+ * (amh_sweep_features, amh_nn_forward; sweep on the job's first min(s, n_src), s = sweep_sources or 4,
  * sources) and the proposal initialisation (amh_init_from_proposal) are
  * captured in the same graph ahead of the iterations.  STATE if the network
  * does not exist. */
@@ -341,7 +343,7 @@ amh_status amh_nn_load(amh_ctx *ctx, const char *path);
  * D = 12 m fronto-parallel planes, m = max(1, (W + 80) / 160) (integer
  * division), at inverse depths 1/depth_max + (i + 1/2) (1/depth_min -
  * 1/depth_max) / D; a plane's aggregate is the mean of the min(2, n) lowest
- * matching costs (Eq. 8) over the first n = min(4, n_src) sources.  Channels:
+ * matching costs (Eq. 8) over the first n = min(s, n_src) sources, s = amh_params.sweep_sources (4 when 0).  Channels:
  * (mean of the cell's 16 reference intensities - 127.5) / 64, their standard
  * deviation / 32, 2 (i* + 1/2) / D - 1 for the lowest aggregate i* (first on
  * ties), 1 - that aggregate, and 1 - the lowest aggregate of each of the 12
@@ -378,7 +380,7 @@ amh_status amh_set_initial_hypotheses(amh_ctx *ctx, const float *depth, const fl
                                       int on_device);
 
 /* amh_begin + amh_sweep_features + amh_nn_forward + amh_init_from_proposal +
- * iters x (red pass, black pass).  The sweep reads the first min(4, n_src)
+ * iters x (red pass, black pass).  The sweep reads the first min(s, n_src), s = sweep_sources or 4,
  * sources (list the nearest first); the iterations use all of them.  STATE if
  * the network does not exist. */
 amh_status amh_run_proposal(amh_ctx *ctx, int ref, const int *srcs, int n_src, int iters);

@@ -12,7 +12,7 @@ TEST INFRASTRUCTURE ONLY (same rules as the rest of ``oracle``).
    moves a near source's warp by ~2 px at any image width), at inverse depths
    q_i = 1/d_max + (i + 0.5) (1/d_min - 1/d_max) / D; the aggregated cost of
    plane i is the mean of the min(2, n) lowest matching costs (Eq. 8) over the
-   first n = min(4, N) sources.  Channels:
+   first n = min(n_sweep, N) sources (n_sweep = 4 unless given).  Channels:
      0: (mean of the cell's 16 reference intensities - 127.5) / 64;
      1: population standard deviation of those 16 intensities / 32;
      2: position of the lowest aggregated cost, 2 (i* + 0.5) / D - 1 (ties: lowest i);
@@ -65,9 +65,9 @@ def sweep_planes(params: Params, width: int) -> list:
     return [np.array([0.0, 0.0, -1.0, 1.0 / (qf + (i + 0.5) * (qn - qf) / D)]) for i in range(D)]
 
 
-def sweep_costs(views: Views, params: Params, x: int, y: int) -> np.ndarray:
-    """Aggregated cost of every sweep plane at reference pixel (x, y)."""
-    n = min(N_NET_SRC, views.n_src)
+def sweep_costs(views: Views, params: Params, x: int, y: int, n_sweep: int = N_NET_SRC) -> np.ndarray:
+    """Aggregated cost of every sweep plane at reference pixel (x, y) over the first n_sweep sources."""
+    n = min(n_sweep, views.n_src)
     kk = min(K_SWEEP, n)
     out = []
     for pl in sweep_planes(params, views.W):
@@ -76,8 +76,8 @@ def sweep_costs(views: Views, params: Params, x: int, y: int) -> np.ndarray:
     return np.array(out)
 
 
-def sweep_features(views: Views, params: Params) -> np.ndarray:
-    """(h4, w4, 16) float64 network input of the reference of ``views``."""
+def sweep_features(views: Views, params: Params, n_sweep: int = N_NET_SRC) -> np.ndarray:
+    """(h4, w4, 16) float64 network input of the reference of ``views`` (sweep over the first n_sweep sources)."""
     H, W = views.H, views.W
     h4, w4 = grid(H, W)
     m = sub_bins(W)
@@ -91,7 +91,7 @@ def sweep_features(views: Views, params: Params) -> np.ndarray:
             blk = ref[np.ix_(ys, xs)]
             F[i, j, 0] = (blk.mean() - 127.5) / 64.0
             F[i, j, 1] = blk.std() / 32.0
-            a = sweep_costs(views, params, *sample_pixel(H, W, i, j))
+            a = sweep_costs(views, params, *sample_pixel(H, W, i, j), n_sweep=n_sweep)
             best = int(np.argmin(a))
             F[i, j, 2] = 2.0 * (best + 0.5) / D - 1.0
             F[i, j, 3] = 1.0 - a[best]
@@ -99,7 +99,7 @@ def sweep_features(views: Views, params: Params) -> np.ndarray:
     return F
 
 
-def sweep_reference_q(views: Views, params: Params) -> np.ndarray:
+def sweep_reference_q(views: Views, params: Params, n_sweep: int = N_NET_SRC) -> np.ndarray:
     """(h4, w4) inverse depth of each cell's winning sweep plane (the network's depth base)."""
     H, W = views.H, views.W
     h4, w4 = grid(H, W)
@@ -109,7 +109,7 @@ def sweep_reference_q(views: Views, params: Params) -> np.ndarray:
     for i in range(h4):
         for j in range(w4):
             x, y = sample_pixel(H, W, i, j)
-            best = int(np.argmin(sweep_costs(views, params, x, y)))
+            best = int(np.argmin(sweep_costs(views, params, x, y, n_sweep=n_sweep)))
             out[i, j] = qf + (best + 0.5) * (qn - qf) / D
     return out
 

@@ -59,7 +59,8 @@ class amh_params(C.Structure):
                 ("sigma_color", C.c_float), ("sigma_spatial", C.c_float), ("tau_mc_init", C.c_float),
                 ("alpha", C.c_float), ("beta", C.c_float), ("tau_up", C.c_float), ("n1", C.c_int), ("n2", C.c_int),
                 ("k", C.c_int), ("seed", C.c_uint64), ("timing", C.c_int), ("conf_min", C.c_float),
-                ("sym_prop", C.c_int), ("heuristic_views", C.c_int), ("bilateral_squared", C.c_int)]
+                ("sym_prop", C.c_int), ("heuristic_views", C.c_int), ("bilateral_squared", C.c_int),
+                ("sweep_sources", C.c_int)]
 
 
 class amh_stats(C.Structure):

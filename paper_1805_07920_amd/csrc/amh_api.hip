@@ -116,6 +116,8 @@ amh_status check_params(amh_ctx *c, const amh_params *p) {
     if ((p->sym_prop != 0 && p->sym_prop != 1) || (p->heuristic_views != 0 && p->heuristic_views != 1) ||
         (p->bilateral_squared != 0 && p->bilateral_squared != 1))
         return fail(c, AMH_E_INVALID_ARG, "sym_prop, heuristic_views and bilateral_squared are 0 or 1");
+    if (p->sweep_sources < 0 || p->sweep_sources > kMaxSrc)
+        return fail(c, AMH_E_INVALID_ARG, "sweep_sources %d outside [0, %d]", p->sweep_sources, kMaxSrc);
     if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(c, AMH_E_INVALID_ARG, "conf_min must be in [0, 1]");
     return AMH_OK;
 }
@@ -235,7 +237,7 @@ SweepArgs sweep_args(amh_ctx *c, const RefDev &ref, const ViewDev *views, int n_
     SweepArgs a;
     a.ref = ref;
     a.views = views;
-    a.n_net = std::min(kNetSrc, n_src);
+    a.n_net = std::min(c->p.sweep_sources > 0 ? c->p.sweep_sources : kNetSrc, n_src);
     a.m = method_dev(c->p, 0);
     a.h4 = cell_rows(ref.H);
     a.w4 = cell_rows(ref.W);
@@ -688,6 +690,7 @@ amh_status amh_params_default(amh_params *out) {
     out->sym_prop = 0;
     out->heuristic_views = 0;
     out->bilateral_squared = 0;
+    out->sweep_sources = 0;
     return AMH_OK;
 }
 

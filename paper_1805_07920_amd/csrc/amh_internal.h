@@ -146,7 +146,7 @@ struct PersistArgs {
 };
 
 constexpr int kSweepCoarse = 12;  // coarse inverse-depth bins of the proposal's input sweep
-constexpr int kNetSrc = 4;        // sources the sweep reads
+constexpr int kNetSrc = 4;        // sources the sweep reads unless amh_params::sweep_sources says otherwise
 constexpr int kSweepK = 2;        // aggregate: mean of the kSweepK lowest costs
 constexpr int kCell = 4;          // reference pixels per feature cell side
 
@@ -154,7 +154,7 @@ constexpr int kCell = 4;          // reference pixels per feature cell side
 struct SweepArgs {
     RefDev ref;
     const ViewDev *views;
-    int n_net;                   // sources used (first min(4, n_src))
+    int n_net;                   // sources used (the first min(sweep_sources or 4, n_src))
     MethodDev m;
     int h4, w4;                  // cell grid
     int sub;                     // sweep planes per coarse bin (12 * sub planes)

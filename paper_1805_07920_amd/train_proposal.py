@@ -118,13 +118,15 @@ def main(argv=None):
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--n-src", type=int, nargs=2, default=(4, 16), metavar=("LO", "HI"),
                     help="source count per training scene, drawn uniformly from LO..HI")
+    ap.add_argument("--sweep-sources", type=int, default=0,
+                    help="sources the plane sweep reads (amh_params.sweep_sources; 0: the library's 4)")
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--report", default=None, help="JSON file for the loss history")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("training runs on the GPU")
     torch.cuda.init()
-    ctx = amh.Context(seed=args.init_seed)
+    ctx = amh.Context(seed=args.init_seed, sweep_sources=args.sweep_sources)
     t0 = time.time()
     feats, qrefs, targets = make_dataset(ctx, range(args.seed0, args.seed0 + args.scenes), n_src=tuple(args.n_src))
     t_data = time.time() - t0
@@ -134,7 +136,8 @@ def main(argv=None):
     t_train = time.time() - t1
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     ctx.nn_save(args.out)
-    rep = dict(scenes=args.scenes, seed0=args.seed0, n_src=list(args.n_src), epochs=args.epochs, batch=args.batch,
+    rep = dict(scenes=args.scenes, seed0=args.seed0, n_src=list(args.n_src), sweep_sources=args.sweep_sources or 4,
+               epochs=args.epochs, batch=args.batch,
                lr=args.lr,
                loss_per_epoch=hist, data_seconds=t_data, train_seconds=t_train, out=os.path.relpath(args.out, ROOT))
     log(json.dumps(rep))

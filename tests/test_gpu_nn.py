@@ -305,14 +305,14 @@ def make_ctx(amh, sc, **kw):
     return ctx
 
 
-def check_features(f, q, V, P, min_robust=0.9):
+def check_features(f, q, V, P, min_robust=0.9, n_sweep=4):
     """Every channel within a bf16 rounding plus 2e-4 (twice the cost bar); the winning plane
     (channel 2, and its fp32 inverse depth q) exactly, on cells whose winner leads the runner-up
     by more than 2e-4."""
     from oracle import proposal
 
-    qo = proposal.sweep_reference_q(V, P)
-    fo = proposal.sweep_features(V, P)
+    qo = proposal.sweep_reference_q(V, P, n_sweep=n_sweep)
+    fo = proposal.sweep_features(V, P, n_sweep=n_sweep)
     assert f.shape == fo.shape
     err = np.abs(f - fo)
     bound = 2.0 ** -8 * np.abs(fo) + 2e-4
@@ -323,7 +323,7 @@ def check_features(f, q, V, P, min_robust=0.9):
     robust = 0
     for i in range(fo.shape[0]):
         for j in range(fo.shape[1]):
-            a = np.sort(proposal.sweep_costs(V, P, 4 * j + 2, 4 * i + 2))
+            a = np.sort(proposal.sweep_costs(V, P, 4 * j + 2, 4 * i + 2, n_sweep=n_sweep))
             if a[1] - a[0] > 2e-4:
                 robust += 1
                 assert abs(f[i, j, 2] - fo[i, j, 2]) <= 2.0 ** -8 * abs(fo[i, j, 2]) + 1e-6, (i, j)
@@ -358,6 +358,25 @@ def test_sweep_features_two_sub_planes_ten_sources(amh, oracle_mod):
         st = ctx.get_stats()
     check_features(f, q, oracle_mod.Views(sc.images[:5], sc.cams[:5]), oracle_mod.Params())
     assert st["evals_init"] == 16 * 80 * 24 * 4
+
+
+def test_sweep_features_eight_sources(amh, oracle_mod):
+    """sweep_sources = 8: the sweep reads the first eight of ten sources (the aggregate is still the mean of
+    the two lowest costs), and the work counter counts them."""
+    say("case sweep features 320x64, 8 of 10 sources")
+    import scenegen
+
+    sc = scenegen.make_scene(320, 64, 10, 40.0, 4, 5, supersample=1)
+    with make_ctx(amh, sc, sweep_sources=8) as ctx:
+        ctx.begin(0, list(range(1, 11)))
+        fd, qd = ctx.sweep_features()
+        f, q = fd.float().cpu().numpy().astype(np.float64), qd.cpu().numpy().astype(np.float64)
+        st = ctx.get_stats()
+    check_features(f, q, oracle_mod.Views(sc.images, sc.cams), oracle_mod.Params(), n_sweep=8)
+    assert st["evals_init"] == 16 * 80 * 24 * 8
+    with pytest.raises(amh.AmhError) as e:
+        amh.Context(sweep_sources=33)
+    assert e.value.status == amh.AMH_E_INVALID_ARG
 
 
 def test_sweep_features_fp16_sources(amh, oracle_mod):
