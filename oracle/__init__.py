@@ -93,11 +93,16 @@ class _State(C.Structure):
                 ("S", C.POINTER(C.c_uint32)), ("v", C.POINTER(C.c_int32))]
 
 
+MAX_ROWS = 21  # propagated rows (8, or 20 in the standard symmetric pattern) + the pixel's own
+
+
 class Diag(C.Structure):
-    _fields_ = [("mfinal", C.c_double * 9), ("M", (C.c_double * MAX_SRC) * 9), ("row_valid", C.c_int * 9),
-                ("cand_index", C.c_int * 8), ("w", C.c_double * MAX_SRC), ("S", C.c_uint32), ("v", C.c_int),
+    """Rows 0..n_prop-1 are the propagated hypotheses, row n_prop the pixel's own plane."""
+    _fields_ = [("mfinal", C.c_double * MAX_ROWS), ("M", (C.c_double * MAX_SRC) * MAX_ROWS),
+                ("row_valid", C.c_int * MAX_ROWS), ("cand_index", C.c_int * (MAX_ROWS - 1)),
+                ("w", C.c_double * MAX_SRC), ("S", C.c_uint32), ("v", C.c_int),
                 ("chosen", C.c_int), ("cand_cost", C.c_double * 6), ("cand_plane", (C.c_double * 4) * 6),
-                ("n_cand", C.c_int), ("robust", C.c_int)]
+                ("n_cand", C.c_int), ("robust", C.c_int), ("n_prop", C.c_int)]
 
 
 _lib = None
@@ -119,6 +124,8 @@ def lib():
         L.orc_acp_offsets.restype = C.c_int
         L.orc_scp_offsets.argtypes = [ip, ip, ip]
         L.orc_scp_offsets.restype = C.c_int
+        L.orc_sscp_offsets.argtypes = [ip, ip, ip]
+        L.orc_sscp_offsets.restype = C.c_int
         L.orc_project.argtypes = [C.POINTER(_Views), C.c_double, C.c_double, dp, C.c_int, dp]
         L.orc_matching_cost.argtypes = [C.POINTER(_Views), C.POINTER(_Params), C.c_int, C.c_int, dp, C.c_int]
         L.orc_matching_cost.restype = C.c_double
@@ -126,6 +133,8 @@ def lib():
         L.orc_tau.restype = C.c_double
         L.orc_view_selection.argtypes = [C.POINTER(_Params), C.c_int, dp, ip, C.c_int, C.c_uint32, C.c_int,
                                          C.POINTER(C.c_uint32), ip, dp]
+        L.orc_view_selection_rows.argtypes = [C.POINTER(_Params), C.c_int, dp, ip, C.c_int, C.c_int, C.c_uint32,
+                                              C.c_int, C.POINTER(C.c_uint32), ip, dp]
         L.orc_random_plane.argtypes = [C.POINTER(_Views), C.POINTER(_Params), C.c_int, C.c_int, C.c_uint64,
                                        C.c_uint64, dp]
         L.orc_init.argtypes = [C.POINTER(_Views), C.POINTER(_Params), C.POINTER(_State)]
@@ -168,7 +177,7 @@ class Params:
     k: int = 4
     seed: int = 0
     view_mode: int = 0  # 1: plain mean over all views (static objective for the sweep pin); 2: heuristic best-k
-    prop_mode: int = 0  # 1: symmetric fast checkerboard propagation (ablation)
+    prop_mode: int = 0  # 1: symmetric checkerboard propagation, fast (ablation); 2: standard (20 rows)
     bilateral_sq: int = 0  # 1: squared colour difference and distance in the bilateral weight
     sample_f32: int = 0  # conditioning probe (not the method): 1 sample positions and values rounded to float32,
     #                      2 also the NCC's sums and moments in float32, 3 the sample values moved by the
@@ -269,6 +278,14 @@ def scp_offsets():
     return dx[:n], dy[:n], reg[:n]
 
 
+def sscp_offsets():
+    dx = np.zeros(N_OFFSETS, np.int32)
+    dy = np.zeros(N_OFFSETS, np.int32)
+    reg = np.zeros(N_OFFSETS, np.int32)
+    n = lib().orc_sscp_offsets(_iptr(dx), _iptr(dy), _iptr(reg))
+    return dx[:n], dy[:n], reg[:n]
+
+
 def project(views: Views, sx: float, sy: float, plane, j: int) -> np.ndarray:
     pl = np.ascontiguousarray(plane, np.float64)
     out = np.zeros(3)
@@ -286,15 +303,21 @@ def tau(params: Params, t: int) -> float:
 
 
 def view_selection(params: Params, t: int, M, row_valid, S_prev: int = 0, v_prev: int = -1):
+    """M: (R, N) costs of R propagated rows; R = 8 calls orc_view_selection, any other R
+    orc_view_selection_rows (counts n1, n2 compared as fractions n R / 8 of the rows)."""
     M = np.ascontiguousarray(M, np.float64)
-    assert M.shape[0] == 8
-    N = M.shape[1]
+    R, N = M.shape
+    assert 1 <= R <= MAX_ROWS - 1
     rv = np.ascontiguousarray(row_valid, np.int32)
     S = C.c_uint32(0)
     v = C.c_int(0)
     w = np.zeros(N)
-    lib().orc_view_selection(C.byref(params.c()), t, _dptr(M), _iptr(rv), N, S_prev, v_prev, C.byref(S),
-                             C.byref(v), _dptr(w))
+    if R == 8:
+        lib().orc_view_selection(C.byref(params.c()), t, _dptr(M), _iptr(rv), N, S_prev, v_prev, C.byref(S),
+                                 C.byref(v), _dptr(w))
+    else:
+        lib().orc_view_selection_rows(C.byref(params.c()), t, _dptr(M), _iptr(rv), R, N, S_prev, v_prev,
+                                      C.byref(S), C.byref(v), _dptr(w))
     return int(S.value), int(v.value), w
 
 

@@ -138,6 +138,24 @@ int orc_scp_offsets(int *dx, int *dy, int *region)
     return 8;
 }
 
+/* Symmetric checkerboard propagation, standard version (Sec. 3.1, Fig. 2(b),  */
+/* Sec. 4; R15): every other-colour pixel within L1 distance 3 and the four    */
+/* axial pixels at distance 5, each its own region (20 rows).                  */
+int orc_sscp_offsets(int *dx, int *dy, int *region)
+{
+    int n = 0;
+    for (int oy = -5; oy <= 5; ++oy)
+        for (int ox = -5; ox <= 5; ++ox) {
+            int l1 = abs(ox) + abs(oy);
+            if (!(l1 & 1)) continue; /* the other colour */
+            if (l1 <= 3 || (l1 == 5 && (ox == 0 || oy == 0))) {
+                dx[n] = ox; dy[n] = oy; region[n] = n;
+                ++n;
+            }
+        }
+    return n;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry (R0).                                                             */
 /* ------------------------------------------------------------------------ */
@@ -384,18 +402,21 @@ double orc_tau(const orc_params *p, int t) { return p->tau_mc_init * exp(-(doubl
 
 static double confidence(const orc_params *p, double m) { return exp(-m * m / (2.0 * p->beta * p->beta)); }
 
-void orc_view_selection(const orc_params *p, int t, const double *M, const int *row_valid, int N,
-                        uint32_t S_prev, int v_prev, uint32_t *S_out, int *v_out, double *w_out)
+/* The good-view counts n1, n2 are stated for the 8 rows of the method's matrix; with R rows they are
+   compared as the same fractions of the rows, n R / 8 (R15). */
+void orc_view_selection_rows(const orc_params *p, int t, const double *M, const int *row_valid, int R, int N,
+                             uint32_t S_prev, int v_prev, uint32_t *S_out, int *v_out, double *w_out)
 {
     double tau = orc_tau(p, t);
+    const double n1 = p->n1 * (double)R / 8.0, n2 = p->n2 * (double)R / 8.0;
     int nv = 0;
-    for (int i = 0; i < 8; ++i) nv += row_valid[i] ? 1 : 0;
+    for (int i = 0; i < R; ++i) nv += row_valid[i] ? 1 : 0;
     uint32_t S = 0;
     double psi[ORC_MAX_SRC];
     for (int j = 0; j < N; ++j) {
         int lt = 0, gt = 0;
         double sc = 0;
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < R; ++i) {
             if (!row_valid[i]) continue;
             double m = M[i * N + j];
             if (m < tau) ++lt;
@@ -403,7 +424,7 @@ void orc_view_selection(const orc_params *p, int t, const double *M, const int *
             sc += confidence(p, m);
         }
         psi[j] = 0.0;
-        if (nv > 0 && lt > p->n1 && gt < p->n2) {
+        if (nv > 0 && lt > n1 && gt < n2) {
             S |= 1u << j;
             psi[j] = sc / nv;
         }
@@ -439,22 +460,29 @@ void orc_view_selection(const orc_params *p, int t, const double *M, const int *
     *v_out = v;
 }
 
+void orc_view_selection(const orc_params *p, int t, const double *M, const int *row_valid, int N,
+                        uint32_t S_prev, int v_prev, uint32_t *S_out, int *v_out, double *w_out)
+{
+    orc_view_selection_rows(p, t, M, row_valid, 8, N, S_prev, v_prev, S_out, v_out, w_out);
+}
+
 /* Robustness of the view-selection decisions to perturbations of size delta
  * in M, as bits: ORC_ROBUST_S (the good-view tests), ORC_ROBUST_V (the argmax
  * v_t), ORC_ROBUST_TOPK (the top-k cut).  A good-view test that can flip
  * changes the weights, so it clears every bit. */
-static int view_selection_robust(const orc_params *p, int t, const double *M, const int *row_valid, int N,
+static int view_selection_robust(const orc_params *p, int t, const double *M, const int *row_valid, int R, int N,
                                  uint32_t S, int v_prev, double delta)
 {
     double tau = orc_tau(p, t);
     double dpsi = 2.1 * delta;  /* |dC/dm| <= 1/(beta sqrt(e)) ~ 2.02 */
+    const double n1 = p->n1 * (double)R / 8.0, n2 = p->n2 * (double)R / 8.0;
     int nv = 0;
-    for (int i = 0; i < 8; ++i) nv += row_valid[i] ? 1 : 0;
+    for (int i = 0; i < R; ++i) nv += row_valid[i] ? 1 : 0;
     double psi[ORC_MAX_SRC];
     for (int j = 0; j < N; ++j) {
         int lt_lo = 0, lt_hi = 0, gt_lo = 0, gt_hi = 0;
         double sc = 0;
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < R; ++i) {
             if (!row_valid[i]) continue;
             double m = M[i * N + j];
             lt_lo += m < tau - delta;
@@ -463,8 +491,8 @@ static int view_selection_robust(const orc_params *p, int t, const double *M, co
             gt_hi += m > p->tau_up - delta;
             sc += confidence(p, m);
         }
-        int can_true = lt_hi > p->n1 && gt_lo < p->n2;
-        int can_false = !(lt_lo > p->n1 && gt_hi < p->n2);
+        int can_true = lt_hi > n1 && gt_lo < n2;
+        int can_false = !(lt_lo > n1 && gt_hi < n2);
         if (nv > 0 && can_true && can_false) return 0;
         psi[j] = nv > 0 ? sc / nv : 0.0;
     }
@@ -572,13 +600,14 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
                          const int *odx, const int *ody, const int *oreg, int n_off, double delta, orc_diag *dg)
 {
     const int N = V->n_src;
+    const int R = p->prop_mode == 2 ? 20 : 8; /* propagated rows; row R is the pixel's own plane */
     int x = (int)(idx % V->W), y = (int)(idx / V->W);
-    double planes[9][4];
-    int valid[9];
-    int cidx[8];
+    double planes[ORC_MAX_ROWS][4];
+    int valid[ORC_MAX_ROWS];
+    int cidx[ORC_MAX_ROWS - 1];
     /* checkerboard propagation: per region, the neighbour with the lowest current cost
-       (one neighbour per region in the symmetric pattern) */
-    for (int r = 0; r < 8; ++r) {
+       (one neighbour per region in the symmetric patterns) */
+    for (int r = 0; r < R; ++r) {
         int best = -1;
         double bc = 0;
         for (int e = 0; e < n_off; ++e) {
@@ -592,22 +621,22 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
         valid[r] = best >= 0;
         if (valid[r]) memcpy(planes[r], &s->plane[((long)(y + ody[best]) * V->W + (x + odx[best])) * 4], 4 * sizeof(double));
     }
-    memcpy(planes[8], &s->plane[idx * 4], 4 * sizeof(double));
-    valid[8] = p->include_self ? 1 : 0;
+    memcpy(planes[R], &s->plane[idx * 4], 4 * sizeof(double));
+    valid[R] = p->include_self ? 1 : 0;
 
     /* cost matrix (Eq. 1) plus the self row */
-    double M[9][ORC_MAX_SRC];
-    for (int r = 0; r < 9; ++r)
+    double M[ORC_MAX_ROWS][ORC_MAX_SRC];
+    for (int r = 0; r <= R; ++r)
         for (int j = 0; j < N; ++j)
             M[r][j] = valid[r] ? orc_matching_cost(V, p, x, y, planes[r], j) : 2.0;
 
-    double Mflat[8 * ORC_MAX_SRC];
-    for (int r = 0; r < 8; ++r)
+    double Mflat[(ORC_MAX_ROWS - 1) * ORC_MAX_SRC];
+    for (int r = 0; r < R; ++r)
         for (int j = 0; j < N; ++j) Mflat[r * N + j] = M[r][j];
     uint32_t S;
     int v;
     double w[ORC_MAX_SRC];
-    orc_view_selection(p, t, Mflat, valid, N, s->S[idx], s->v[idx], &S, &v, w);
+    orc_view_selection_rows(p, t, Mflat, valid, R, N, s->S[idx], s->v[idx], &S, &v, w);
     if (p->view_mode != 0) {
         S = 0;
         v = -1;
@@ -619,8 +648,8 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
        ties keep self, then region order */
     double sw = 0;
     for (int j = 0; j < N; ++j) sw += w[j];
-    double mf[9];
-    for (int r = 0; r < 9; ++r) {
+    double mf[ORC_MAX_ROWS];
+    for (int r = 0; r <= R; ++r) {
         mf[r] = INFINITY;
         if (!valid[r]) continue;
         if (heuristic) { mf[r] = mean_k_lowest(M[r], N, p->k); continue; }
@@ -628,10 +657,9 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
         for (int j = 0; j < N; ++j) acc += w[j] * M[r][j];
         mf[r] = acc / sw;
     }
-    int order_rows[9] = {8, 0, 1, 2, 3, 4, 5, 6, 7};
     int best = -1;
-    for (int q = 0; q < 9; ++q) {
-        int r = order_rows[q];
+    for (int q = 0; q <= R; ++q) {
+        int r = q == 0 ? R : q - 1; /* self first, then the regions in order */
         if (!valid[r]) continue;
         if (best < 0 || mf[r] < mf[best]) best = r;
     }
@@ -640,10 +668,10 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
     double cur_cost = mf[best];
     int chosen = best;
     int robust = (p->view_mode != 0 ? ORC_ROBUST_S | ORC_ROBUST_V | ORC_ROBUST_TOPK
-                                     : view_selection_robust(p, t, Mflat, valid, N, S, s->v[idx], delta)) |
+                                     : view_selection_robust(p, t, Mflat, valid, R, N, S, s->v[idx], delta)) |
                  ORC_ROBUST_ARGMIN | ORC_ROBUST_REFINE;
     if (!(robust & ORC_ROBUST_S)) robust = 0;
-    for (int r = 0; r < 9; ++r)
+    for (int r = 0; r <= R; ++r)
         if (valid[r] && r != best && fabs(mf[r] - mf[best]) < 4 * delta &&
             memcmp(planes[r], planes[best], sizeof(planes[r])) != 0)
             robust &= ~ORC_ROBUST_ARGMIN; /* identical planes tie exactly on any implementation */
@@ -693,7 +721,7 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
             if (cand_cost[c] < cur_cost) {
                 cur_cost = cand_cost[c];
                 memcpy(cur, cand[c], sizeof(cur));
-                chosen = 9 + c;
+                chosen = R + 1 + c;
             }
         }
     }
@@ -704,12 +732,13 @@ static void update_pixel(const orc_views *V, const orc_params *p, orc_state *s, 
     s->v[idx] = v;
 
     if (dg) {
-        for (int r = 0; r < 9; ++r) {
+        for (int r = 0; r <= R; ++r) {
             dg->mfinal[r] = mf[r];
             dg->row_valid[r] = valid[r];
             for (int j = 0; j < N; ++j) dg->M[r][j] = M[r][j];
         }
-        for (int r = 0; r < 8; ++r) dg->cand_index[r] = cidx[r];
+        for (int r = 0; r < R; ++r) dg->cand_index[r] = cidx[r];
+        dg->n_prop = R;
         for (int j = 0; j < N; ++j) dg->w[j] = w[j];
         dg->S = S;
         dg->v = v;
@@ -727,7 +756,8 @@ void orc_pass(const orc_views *V, const orc_params *p, orc_state *s, int t, int 
               const int *order, int n_order, double delta, orc_diag *diag)
 {
     int odx[ORC_N_OFFSETS], ody[ORC_N_OFFSETS], oreg[ORC_N_OFFSETS];
-    int n_off = p->prop_mode == 1 ? orc_scp_offsets(odx, ody, oreg) : orc_acp_offsets(odx, ody, oreg);
+    int n_off = p->prop_mode == 1 ? orc_scp_offsets(odx, ody, oreg)
+                : p->prop_mode == 2 ? orc_sscp_offsets(odx, ody, oreg) : orc_acp_offsets(odx, ody, oreg);
     long P = (long)V->W * V->H;
     if (order) {
 #pragma omp parallel for schedule(dynamic, 16)

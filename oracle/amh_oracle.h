@@ -17,6 +17,10 @@
  *   orc_view_selection     pinned (hand-computed matrices, closed forms of Eq. 2-4)
  *   orc_acp_offsets        pinned (invariants of the region table)
  *   orc_scp_offsets        pinned (symmetry, colour and subset invariants)
+ *   orc_sscp_offsets       pinned (the same invariants; one half-pass reaches exactly
+ *                          its 20 neighbours)
+ *   orc_view_selection_rows  pinned (20-row matrices against a brute-force count
+ *                          with the thresholds scaled; 8 rows equal orc_view_selection)
  *   heuristic view mode    pinned (mean of the k lowest against numpy sorts; k >= N
  *                          equals the plain mean, k = 1 the minimum)
  *   orc_random_plane       pinned (uniform depth on the range; direction uniform on
@@ -39,6 +43,7 @@
 
 #define ORC_MAX_SRC 32
 #define ORC_N_OFFSETS 72
+#define ORC_MAX_ROWS 21   /* propagated rows (8, or 20 in the standard symmetric pattern) + the pixel's own */
 
 /* decisions of a pixel update that clear a given margin (orc_diag.robust) */
 #define ORC_ROBUST_S 1       /* good-view tests (S_t) */
@@ -66,7 +71,9 @@ typedef struct {
                         (a static objective, used only by the brute-force sweep pin);
                         2: heuristic selection, mean of each hypothesis' k lowest costs */
     int prop_mode;   /* 0: asymmetric checkerboard propagation (the method);
-                        1: symmetric fast checkerboard propagation (ablation) */
+                        1: symmetric checkerboard propagation, fast version (ablation, Fig. 2(c));
+                        2: symmetric checkerboard propagation, standard version (ablation, Fig. 2(b)):
+                           20 rows, the view selection's counts n1, n2 scaled by 20/8 */
     int bilateral_sq; /* 1: squared colour difference and distance in the bilateral weight */
     int sample_f32;   /* conditioning probe, not the method: 1 rounds every sample's source position
                          (relative to the texel under the window centre) and its interpolated value to
@@ -89,29 +96,35 @@ typedef struct {
 } orc_state;
 
 typedef struct {
-    double mfinal[9];   /* aggregated cost of rows 0..7 (regions) and 8 (self); +inf if absent */
-    double M[9][ORC_MAX_SRC];
-    int row_valid[9];
-    int cand_index[8];  /* index into the offset table of the picked neighbour, -1 if none */
+    /* rows 0..n_prop-1 are the propagated hypotheses (regions), row n_prop the pixel's own plane;
+       n_prop = 8, or 20 in the standard symmetric pattern */
+    double mfinal[ORC_MAX_ROWS];   /* aggregated cost of every row; +inf if absent */
+    double M[ORC_MAX_ROWS][ORC_MAX_SRC];
+    int row_valid[ORC_MAX_ROWS];
+    int cand_index[ORC_MAX_ROWS - 1];  /* index into the offset table of the picked neighbour, -1 if none */
     double w[ORC_MAX_SRC];
     uint32_t S;
     int v;
-    int chosen;         /* 0..7 region row, 8 self, 9+c refinement candidate c */
+    int chosen;         /* 0..n_prop-1 region row, n_prop self, n_prop+1+c refinement candidate c */
     double cand_cost[6];
     double cand_plane[6][4];
     int n_cand;
     int robust;         /* ORC_ROBUST_* bits of the decisions that clear the margin delta */
+    int n_prop;
 } orc_diag;
 
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 double orc_u24(uint64_t w);
 int orc_acp_offsets(int *dx, int *dy, int *region);
 int orc_scp_offsets(int *dx, int *dy, int *region);
+int orc_sscp_offsets(int *dx, int *dy, int *region);
 void orc_project(const orc_views *V, double sx, double sy, const double plane[4], int j, double out[3]);
 double orc_matching_cost(const orc_views *V, const orc_params *p, int x, int y, const double plane[4], int j);
 double orc_tau(const orc_params *p, int t);
 void orc_view_selection(const orc_params *p, int t, const double *M, const int *row_valid, int N,
                         uint32_t S_prev, int v_prev, uint32_t *S_out, int *v_out, double *w_out);
+void orc_view_selection_rows(const orc_params *p, int t, const double *M, const int *row_valid, int R, int N,
+                             uint32_t S_prev, int v_prev, uint32_t *S_out, int *v_out, double *w_out);
 void orc_random_plane(const orc_views *V, const orc_params *p, int x, int y, uint64_t t, uint64_t purpose,
                       double plane[4]);
 void orc_init(const orc_views *V, const orc_params *p, orc_state *s);

@@ -8,7 +8,7 @@
  * translated along x and y; textures are a fixed integer hash, so no library
  * random generator is involved.  Sizes are odd (ragged tiles), and the runs
  * cover every mode: joint view selection, the static objective, heuristic
- * selection, symmetric propagation, squared weights, no self row, the
+ * selection, symmetric propagation (fast and standard), squared weights, no self row, the
  * conditioning probes (every level), refinement before and after t = 3, and per-pixel
  * diagnostics over an explicit pixel order.
  */
@@ -78,7 +78,7 @@ int main(void)
     int *order = malloc(sizeof(int) * P);
     orc_diag *dg = malloc(sizeof(orc_diag) * P);
     int rc = 0;
-    for (int mode = 0; mode < 10 && rc == 0; ++mode) {
+    for (int mode = 0; mode < 11 && rc == 0; ++mode) {
         orc_params p;
         memset(&p, 0, sizeof p);
         p.refine = 1;
@@ -96,7 +96,7 @@ int main(void)
         p.k = mode == 4 ? 1 : 4;
         p.seed = 11u + (uint64_t)mode;
         p.view_mode = mode == 1 ? 1 : (mode == 2 ? 2 : 0);
-        p.prop_mode = mode == 5 ? 1 : 0;
+        p.prop_mode = mode == 5 ? 1 : (mode == 10 ? 2 : 0);
         p.bilateral_sq = mode == 6;
         p.sample_f32 = mode == 7 ? 1 : (mode == 8 ? 2 : (mode == 9 ? 3 : 0));
         p.cost_noise = mode == 7 ? 2e-4 : 0.0;
@@ -121,7 +121,9 @@ int main(void)
     }
     /* the remaining public functions */
     int dx[ORC_N_OFFSETS], dy[ORC_N_OFFSETS], reg[ORC_N_OFFSETS];
-    if (orc_acp_offsets(dx, dy, reg) != ORC_N_OFFSETS || orc_scp_offsets(dx, dy, reg) != 8) rc = 20;
+    if (orc_acp_offsets(dx, dy, reg) != ORC_N_OFFSETS || orc_scp_offsets(dx, dy, reg) != 8 ||
+        orc_sscp_offsets(dx, dy, reg) != 20)
+        rc = 20;
     double M[8 * NS], w[NS];
     int rv[8] = {1, 1, 1, 1, 1, 1, 0, 1};
     for (int i = 0; i < 8 * NS; ++i) M[i] = (i % 5) * 0.3;
