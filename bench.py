@@ -325,8 +325,8 @@ def bench_learned(args):
     print(json.dumps(out))
 
 
-ABLATION_VARIANTS = (("full", dict()), ("no_acp", dict(sym_prop=1)), ("no_mhj", dict(heuristic_views=1)),
-                     ("neither", dict(sym_prop=1, heuristic_views=1)))
+ABLATION_VARIANTS = (("full", dict()), ("no_acp", dict(sym_prop=1)), ("no_acp_standard", dict(sym_prop=2)),
+                     ("no_mhj", dict(heuristic_views=1)), ("neither", dict(sym_prop=1, heuristic_views=1)))
 # readings of the paper that the printed text leaves open, against its literal form: the pixel's own plane
 # competing in the final argmin (R7), the unsquared bilateral weight (R5) and the iteration count (R14: the
 # curves run to the paper's 6)

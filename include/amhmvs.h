@@ -92,9 +92,12 @@ typedef struct {
                                          * (default 0: on held-out 1920x1280 scenes every in-range predicted
                                          * plane beat a random one after one iteration) */
     int sym_prop;        /* ablation of Sec. 4 (default 0): 1 replaces the asymmetric propagation by the
-                          * symmetric checkerboard of Gipuma's fast version (Fig. 2(c)): row r of the cost
+                          * symmetric checkerboard of the fast version (Fig. 2(c)): row r of the cost
                           * matrix takes the one neighbour at distance 1 (r < 4) or 5 (r >= 4) up, down,
-                          * left, right */
+                          * left, right; 2 by the standard version (Fig. 2(b)): 20 rows, one per
+                          * other-colour neighbour within L1 distance 3 and the four axial ones at
+                          * distance 5 (row-major order), the view selection's counts n1, n2 compared as
+                          * the same fractions of the 20 rows (n 20 / 8) */
     int heuristic_views; /* ablation of Sec. 4 (default 0): 1 replaces the joint view selection by the
                           * heuristic one (Sec. 3.2): each hypothesis and each refinement candidate costs
                           * the mean of its own k lowest per-view costs; S = 0 and v = -1 are kept.

@@ -113,9 +113,9 @@ amh_status check_params(amh_ctx *c, const amh_params *p) {
     if ((p->refine != 0 && p->refine != 1) || (p->include_self != 0 && p->include_self != 1) ||
         (p->timing != 0 && p->timing != 1))
         return fail(c, AMH_E_INVALID_ARG, "refine, include_self and timing are 0 or 1");
-    if ((p->sym_prop != 0 && p->sym_prop != 1) || (p->heuristic_views != 0 && p->heuristic_views != 1) ||
+    if ((p->sym_prop < 0 || p->sym_prop > 2) || (p->heuristic_views != 0 && p->heuristic_views != 1) ||
         (p->bilateral_squared != 0 && p->bilateral_squared != 1))
-        return fail(c, AMH_E_INVALID_ARG, "sym_prop, heuristic_views and bilateral_squared are 0 or 1");
+        return fail(c, AMH_E_INVALID_ARG, "sym_prop is 0, 1 or 2; heuristic_views and bilateral_squared 0 or 1");
     if (p->sweep_sources < 0 || p->sweep_sources > kMaxSrc)
         return fail(c, AMH_E_INVALID_ARG, "sweep_sources %d outside [0, %d]", p->sweep_sources, kMaxSrc);
     if (!(p->conf_min >= 0.f && p->conf_min <= 1.f)) return fail(c, AMH_E_INVALID_ARG, "conf_min must be in [0, 1]");

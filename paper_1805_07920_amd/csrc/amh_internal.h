@@ -192,6 +192,6 @@ hipError_t launch_outputs(const RefDev &ref, const StateDev &st, float *depth, f
 hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStream_t s);
 hipError_t launch_stamp(unsigned long long *p, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs &a, int half, hipStream_t s);
-size_t pass_lds_bytes(int n_src, int waves);
+size_t pass_lds_bytes(int n_src, int waves, int rb = 1);
 
 }  // namespace amh

@@ -595,16 +595,18 @@ constexpr int kTileW = 2 * kTilePix + 10;
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// LDS of a workgroup of `waves` waves (one image row of the tile per wave)
-__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[13]) {
+// LDS of a workgroup of `waves` waves (one image row of the tile per wave); rb row blocks of the 9 lanes of
+// a pixel (1; 3 for the 21 rows of the standard symmetric pattern) for the hypotheses, their validity, the
+// cost matrix and the aggregated costs, block b at offset b * waves * 64 entries
+__host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[13], int rb = 1) {
     size_t o = 0;
     off[0] = o; o = align16(o + sizeof(float) * (waves + 10) * kTileW);
     off[1] = o; o = align16(o + sizeof(float2) * waves * kGroups * kWinStride);
-    off[2] = o; o = align16(o + sizeof(float4) * waves * 64);
-    off[3] = o; o = align16(o + sizeof(float) * waves * (n_src > 7 ? n_src : 7) * 64);
-    off[4] = o; o = align16(o + sizeof(float) * waves * 64);
+    off[2] = o; o = align16(o + sizeof(float4) * rb * waves * 64);
+    off[3] = o; o = align16(o + sizeof(float) * rb * waves * (n_src > 7 ? n_src : 7) * 64);
+    off[4] = o; o = align16(o + sizeof(float) * rb * waves * 64);
     off[5] = o; o = align16(o + sizeof(float) * waves * kGroups * kMaxSrc);
-    off[6] = o; o = align16(o + sizeof(int) * waves * 64);
+    off[6] = o; o = align16(o + sizeof(int) * rb * waves * 64);
     off[7] = o; o = align16(o + waves * kGroups * kMaxSrc);
     off[8] = o; o = align16(o + sizeof(float4) * waves * kGroups * 6);
     off[9] = o; o = align16(o + sizeof(float) * waves * kGroups * kMaxSrc);
@@ -614,14 +616,14 @@ __host__ __device__ inline size_t lds_layout(int n_src, int waves, size_t off[13
     return o;
 }
 
-size_t pass_lds_bytes(int n_src, int waves) {
+size_t pass_lds_bytes(int n_src, int waves, int rb) {
     size_t off[13];
-    return lds_layout(n_src, waves, off);
+    return lds_layout(n_src, waves, off, rb);
 }
 
-__device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int waves) {
+__device__ __forceinline__ PassLds carve(unsigned char *smem, int n_src, int waves, int rb = 1) {
     size_t off[13];
-    lds_layout(n_src, waves, off);
+    lds_layout(n_src, waves, off, rb);
     PassLds L;
     L.tile = reinterpret_cast<float *>(smem + off[0]);
     L.rw = reinterpret_cast<float2 *>(smem + off[1]);
@@ -841,16 +843,43 @@ __device__ __forceinline__ float mean_k_lowest(const float *c, int stride, int n
     return sum / (float)kk;
 }
 
+// Standard symmetric checkerboard pattern (Fig. 2(b), ablation): neighbour R (0..19) in the order of a
+// row-major scan of the 11 x 11 square around the pixel over the other-colour pixels within L1 distance 3 and
+// the four axial ones at distance 5.
+__device__ __forceinline__ void std_offset(int R, int &dx, int &dy) {
+    int n = 0;
+    dx = 0;
+    dy = 0;
+    for (int oy = -5; oy <= 5; ++oy)
+        for (int ox = -5; ox <= 5; ++ox) {
+            const int l1 = abs(ox) + abs(oy);
+            if (!(l1 & 1) || !(l1 <= 3 || (l1 == 5 && (ox == 0 || oy == 0)))) continue;
+            if (n == R) {
+                dx = ox;
+                dy = oy;
+            }
+            ++n;
+        }
+}
+constexpr int kStdRows = 20;  // propagated rows of the standard symmetric pattern; row 20 is the own plane
+
 // ABL: the ablation build of the pass, with the two switches of Sec. 4 read at run
-// time: m.sym_prop (symmetric checkerboard propagation: region r holds the one
+// time: m.sym_prop (symmetric checkerboard propagation: 1, region r holds the one
 // neighbour at distance 1 (r < 4) or 5 (r >= 4) up/down/left/right, the fast
-// pattern of Fig. 2(c)) and m.heuristic (each hypothesis, and each refinement
+// pattern of Fig. 2(c); 2, the 20 neighbours of the standard pattern of
+// Fig. 2(b), in three blocks of 9 rows per pixel: row R = 9 b + lane row, the
+// own plane at R = 20, and the view selection's counts n1, n2 compared as the
+// same fractions of 20 rows as of 8) and m.heuristic (each hypothesis, and each refinement
 // candidate, costs the mean of its own k lowest per-view costs; no selection memory).
 // tid: threadIdx.x (the persistent launch passes it through an opaque copy, so that nothing derived from
 // it is kept live across its tiles)
 template <int HALF, int WAVES, bool ABL = false>
 __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned char *smem, int tid) {
-    PassLds S = carve(smem, a.n_src, WAVES);
+    // row blocks: 3 in the standard symmetric pattern (ablation build only), else 1
+    const bool stdp = ABL && a.m.sym_prop == 2;
+    const int RB = stdp ? 3 : 1;
+    PassLds S = carve(smem, a.n_src, WAVES, RB);
+    constexpr int WL = 64 * WAVES;  // entries per row block of pl, valid, mf
     const int wave = tid >> 6, lane = tid & 63;
     const int grp = lane / kRows, row = lane - grp * kRows;
     const int g = grp < kGroups ? grp : 0;
@@ -869,7 +898,27 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     // (1) asymmetric propagation: lane r < 8 takes the lowest-cost candidate of region r
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
     bool valid = false;
-    if (pix_ok) {
+    if (stdp) {
+        for (int b = 0; b < 3; ++b) {
+            const int R = 9 * b + row;
+            float4 plb = make_float4(0.f, 0.f, -1.f, 1.f);
+            bool vb = false;
+            if (pix_ok && R < kStdRows) {
+                int dx, dy;
+                std_offset(R, dx, dy);
+                const int nx = x + dx, ny = y + dy;
+                if (nx >= 0 && nx < W && ny >= 0 && ny < H) {
+                    vb = true;
+                    plb = load_plane(a.st.planes, (size_t)ny * W + nx);
+                }
+            } else if (pix_ok && R == kStdRows) {
+                vb = m.include_self != 0;
+                plb = load_plane(a.st.planes, p);
+            }
+            S.pl[b * WL + tid] = plb;
+            S.valid[b * WL + tid] = vb ? 1 : 0;
+        }
+    } else if (pix_ok) {
         if (ABL && m.sym_prop && row < 8) {
             const int u = row < 4 ? 1 : 5, dir = row & 3;
             const int nx = x + (dir == 2 ? -u : (dir == 3 ? u : 0));
@@ -899,8 +948,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             pl = load_plane(a.st.planes, p);
         }
     }
-    S.pl[tid] = pl;
-    S.valid[tid] = valid ? 1 : 0;
+    if (!stdp) {
+        S.pl[tid] = pl;
+        S.valid[tid] = valid ? 1 : 0;
+    }
     if (lane == 0) S.nshort[wave] = 0u;
     __syncthreads();
 
@@ -913,29 +964,34 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     }
     __syncthreads();
 
-    // (3) cost matrix (Eq. 1) plus the own row: one column per view
+    // (3) cost matrix (Eq. 1) plus the own row: one column per view (row block b at mcol + b * WAVES * N * 64)
     float *mcol = S.ms + wave * N * 64;
-    const PlaneQ q = plane_q(a.ref, m, pl, x, y);
     int n_prop = 0;
-    for (int j = 0; j < N; ++j) {
-        float c = 2.f;
-        if (valid) {
-            c = q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort;
-            ++n_prop;
-        }
-        mcol[j * 64 + lane] = c;
-    }
-    // short evaluations were stored as kShort: counted and set to 2 from LDS after the loop, so that
-    // the loop itself carries no counter
-    if (valid) {
-        unsigned ns = 0;
+    for (int b = 0; b < RB; ++b) {
+        float *mc = mcol + b * WAVES * N * 64;
+        const float4 plb = stdp ? S.pl[b * WL + tid] : pl;
+        const bool vb = stdp ? S.valid[b * WL + tid] != 0 : valid;
+        const PlaneQ q = plane_q(a.ref, m, plb, x, y);
         for (int j = 0; j < N; ++j) {
-            if (mcol[j * 64 + lane] < 0.f) {
-                ++ns;
-                mcol[j * 64 + lane] = 2.f;
+            float c = 2.f;
+            if (vb) {
+                c = q.ok ? ncc_cost_raw<HALF>(a.views[j], rw, ws, x, y, q.q0, q.qu, q.qv) : kShort;
+                ++n_prop;
             }
+            mc[j * 64 + lane] = c;
         }
-        if (ns) atomicAdd(&S.nshort[wave], ns);
+        // short evaluations were stored as kShort: counted and set to 2 from LDS after the loop, so that
+        // the loop itself carries no counter
+        if (vb) {
+            unsigned ns = 0;
+            for (int j = 0; j < N; ++j) {
+                if (mc[j * 64 + lane] < 0.f) {
+                    ++ns;
+                    mc[j * 64 + lane] = 2.f;
+                }
+            }
+            if (ns) atomicAdd(&S.nshort[wave], ns);
+        }
     }
     __syncthreads();
 
@@ -945,20 +1001,41 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     float *psi = S.psi + (wave * kGroups + g) * kMaxSrc;
     const bool heur = ABL && m.heuristic;  // uniform over the launch
     int nv = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) nv += S.valid[wave * 64 + g * kRows + i];
-    if (pix_ok && !heur) {
-        for (int j = row; j < N; j += kRows) {
-            int lt = 0, gt = 0;
-            float sc = 0.f;
-            for (int i = 0; i < 8; ++i) {
-                if (!S.valid[wave * 64 + g * kRows + i]) continue;
-                const float c = mcol[j * 64 + g * kRows + i];
-                lt += c < m.tau;
-                gt += c > m.tau_up;
-                sc += __expf(-c * c * m.inv_2b2);
+    if (stdp) {
+        // 20 propagated rows: row i in block i / 9, lane row i % 9; counts against n R / 8
+        for (int i = 0; i < kStdRows; ++i) nv += S.valid[(i / 9) * WL + wave * 64 + g * kRows + i % 9];
+        const float n1s = (float)m.n1 * (kStdRows / 8.f), n2s = (float)m.n2 * (kStdRows / 8.f);
+        if (pix_ok && !heur) {
+            for (int j = row; j < N; j += kRows) {
+                int lt = 0, gt = 0;
+                float sc = 0.f;
+                for (int i = 0; i < kStdRows; ++i) {
+                    const int b = i / 9, r = i % 9;
+                    if (!S.valid[b * WL + wave * 64 + g * kRows + r]) continue;
+                    const float c = mcol[b * WAVES * N * 64 + j * 64 + g * kRows + r];
+                    lt += c < m.tau;
+                    gt += c > m.tau_up;
+                    sc += __expf(-c * c * m.inv_2b2);
+                }
+                psi[j] = (nv > 0 && (float)lt > n1s && (float)gt < n2s) ? sc / (float)nv : -1.f;
             }
-            psi[j] = (nv > 0 && lt > m.n1 && gt < m.n2) ? sc / (float)nv : -1.f;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) nv += S.valid[wave * 64 + g * kRows + i];
+        if (pix_ok && !heur) {
+            for (int j = row; j < N; j += kRows) {
+                int lt = 0, gt = 0;
+                float sc = 0.f;
+                for (int i = 0; i < 8; ++i) {
+                    if (!S.valid[wave * 64 + g * kRows + i]) continue;
+                    const float c = mcol[j * 64 + g * kRows + i];
+                    lt += c < m.tau;
+                    gt += c > m.tau_up;
+                    sc += __expf(-c * c * m.inv_2b2);
+                }
+                psi[j] = (nv > 0 && lt > m.n1 && gt < m.n2) ? sc / (float)nv : -1.f;
+            }
         }
     }
     __syncthreads();
@@ -1013,24 +1090,28 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     if (pix_ok && uniform)
         for (int j = row; j < N; j += kRows) wgt[j] = 1.f;
 
-    // (6) unified cost of the lane's hypothesis (Eq. 7)
-    float mfin = __builtin_inff();
-    if (valid) {
-        if (heur) {
-            mfin = mean_k_lowest(mcol + lane, 64, N, min(m.k, N));
-        } else {
-            float acc = 0.f;
-            for (int j = 0; j < N; ++j) acc = fmaf(uniform ? 1.f : wgt[j], mcol[j * 64 + lane], acc);
-            mfin = acc / wsum;
+    // (6) unified cost of the lane's hypothesis (Eq. 7), per row block
+    for (int b = 0; b < RB; ++b) {
+        const float *mc = mcol + b * WAVES * N * 64;
+        const bool vb = stdp ? S.valid[b * WL + tid] != 0 : valid;
+        float mfin = __builtin_inff();
+        if (vb) {
+            if (heur) {
+                mfin = mean_k_lowest(mc + lane, 64, N, min(m.k, N));
+            } else {
+                float acc = 0.f;
+                for (int j = 0; j < N; ++j) acc = fmaf(uniform ? 1.f : wgt[j], mc[j * 64 + lane], acc);
+                mfin = acc / wsum;
+            }
         }
+        S.mf[b * WL + tid] = mfin;
     }
-    S.mf[tid] = mfin;
     __syncthreads();
 
     // (7) best hypothesis: own plane first, then region order; strictly lower wins.  Only its row is kept
     //     (its plane and cost stay in LDS): fewer registers live across the refinement's evaluations
     int brow = 8;
-    if (pix_ok) {
+    if (pix_ok && !stdp) {
         const int base = wave * 64 + g * kRows;
         int br = -1;
         float bc = 0.f;
@@ -1042,7 +1123,22 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
         }
         brow = br < 0 ? 8 : br;  // no valid row at all (1-pixel image, no self): the own plane
     }
-    const int bslot = wave * 64 + g * kRows + brow;
+    int bslot = wave * 64 + g * kRows + brow;
+    if (stdp && pix_ok) {
+        // the own plane (row 20: block 2, lane row 2) first, then rows 0..19 in order; strictly lower wins
+        const int base = wave * 64 + g * kRows;
+        const int self = 2 * WL + base + 2;
+        int br = -1;
+        float bc = 0.f;
+        if (S.valid[self]) { br = self; bc = S.mf[self]; }
+        for (int i = 0; i < kStdRows; ++i) {
+            const int sl = (i / 9) * WL + base + i % 9;
+            if (!S.valid[sl]) continue;
+            const float c = S.mf[sl];
+            if (br < 0 || c < bc) { br = sl; bc = c; }
+        }
+        bslot = br < 0 ? self : br;
+    }
 
     // (8) refinement (Sec. 3.3): perturbed (and, from t = 3, random) depth/normal candidates,
     //     scored with the same weights on the views that carry weight; strictly lower wins
@@ -1660,7 +1756,7 @@ hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
 }
 
 hipError_t launch_pass(const PassArgs &a, int half, hipStream_t s) {
-    const size_t lds = pass_lds_bytes(a.n_src, a.waves);
+    const size_t lds = pass_lds_bytes(a.n_src, a.waves, a.m.sym_prop == 2 ? 3 : 1);
     const dim3 grid(grid_for(a.n_tiles)), block(64 * a.waves);
     const bool abl = a.m.sym_prop || a.m.heuristic;
     if (a.waves == 2) {

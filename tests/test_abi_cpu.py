@@ -118,8 +118,8 @@ def test_conf_min_validated(amh):
 def test_ablation_switches_validated(amh):
     p = amh.params_default()
     assert p.sym_prop == 0 and p.heuristic_views == 0
-    for field in ("sym_prop", "heuristic_views"):
-        for bad in (-1, 2):
+    for field, bads in (("sym_prop", (-1, 3)), ("heuristic_views", (-1, 2)), ("sweep_sources", (-1, 33))):
+        for bad in bads:
             q = amh.params_default(**{field: bad})
             assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(q), None) == amh.AMH_E_INVALID_ARG
 
