@@ -571,6 +571,8 @@ amh_status build_batch(amh_ctx *c, int n_jobs, const amh_job *jobs, bool proposa
         pa.arrived = sync32 + (size_t)n_pp * 8;
         pa.fault = sync32 + (size_t)n_pp * 8 + 1;
         pa.spin_limit = (unsigned long long)khz * 1000ull * 4ull;  // 4 s of device clock per wait
+        if (const char *sl = getenv("AMH_PERSIST_SPIN_TICKS"))     // test hook: a wait this short fails
+            pa.spin_limit = strtoull(sl, nullptr, 10);
         pa.probe = 0;
         pa.probe_ticks = (unsigned long long)khz * 20ull;  // 20 ms
         c->d_pfault = pa.fault;

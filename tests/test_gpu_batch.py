@@ -336,3 +336,31 @@ def test_persistent_launch_equals_per_phase_launches(amh, batch_setup, config):
     for a, b in zip(ref_p, out_p):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def test_persistent_barrier_timeout_is_reported(amh, batch_setup, monkeypatch):
+    """The persistent launch's grid barriers wait a bounded time.  With the bound forced to 0 device-clock
+    ticks from the host (test hook AMH_PERSIST_SPIN_TICKS, read when the batch is built) a waiting workgroup
+    runs out at once: it sets the fault flag, every other workgroup leaves at its next barrier, the kernel
+    ends, and the calls that read the batch's results report AMH_E_HIP.  Rebuilt without the hook, the same
+    context runs the batch again and matches the per-phase launches."""
+    say("case persistent batch, barrier timeout forced from the host")
+    images, cams, jobs = batch_setup
+    with amh.Context(refine=1, seed=13) as ctx:
+        ctx.init_views(images, cams)
+        ctx.set_launch_config(0)
+        ctx.run_batch(jobs)
+        ref = [ctx.get_job_result(i) for i in range(len(jobs))]
+        monkeypatch.setenv("AMH_PERSIST_SPIN_TICKS", "0")
+        ctx.set_launch_config(8)
+        ctx.run_batch(jobs)
+        with pytest.raises(amh.AmhError) as e:
+            ctx.get_job_result(0)
+        assert e.value.status == amh.AMH_E_HIP and "timed out" in str(e.value)
+        monkeypatch.delenv("AMH_PERSIST_SPIN_TICKS")
+        ctx.set_launch_config(12)  # another configuration: the batch is rebuilt without the hook
+        ctx.run_batch(jobs)
+        out = [ctx.get_job_result(i) for i in range(len(jobs))]
+    for a, b in zip(ref, out):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
