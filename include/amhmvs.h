@@ -258,7 +258,10 @@ amh_status amh_get_job_times(amh_ctx *ctx, int n, float *job_ms);
  * release, arrival count, acquire), so its grid is sized to the workgroups
  * that are resident at once; every wait is bounded, and a barrier that runs out
  * (workgroups not all resident, e.g. other work on the GPU) is reported as
- * AMH_E_HIP by amh_get_job_result, amh_get_job_times and amh_get_stats.  If the environment variable AMH_TUNE_CACHE
+ * AMH_E_HIP by amh_get_job_result, amh_get_job_times and amh_get_stats (the
+ * bound is 4 s of device clock; the environment variable AMH_PERSIST_SPIN_TICKS,
+ * read when a batch is built, replaces it by that many device-clock ticks -- a
+ * test hook).  If the environment variable AMH_TUNE_CACHE
  * names a file, the choice is looked up there by shape bucket (job count,
  * largest view count, pixel count) and appended after tuning. */
 amh_status amh_tune(amh_ctx *ctx, int n_jobs, const amh_job *jobs, int *best_config, float *ms_per_config);
