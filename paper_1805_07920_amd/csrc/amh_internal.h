@@ -75,8 +75,8 @@ struct PassArgs {
     float conf_min = 0.f;
 };
 
-// Pixels of one colour per initialisation workgroup (one per lane), and the workgroups of one colour.
-constexpr int kInitBlock = 256;
+// Pixels of one colour per initialisation workgroup (one per pair of lanes), and the workgroups of one colour.
+constexpr int kInitBlock = 128;
 __host__ __device__ inline long long init_blocks(int W, int H) {
     return ((long long)H * ((W + 1) / 2) + kInitBlock - 1) / kInitBlock;
 }

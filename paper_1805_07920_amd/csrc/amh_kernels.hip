@@ -21,14 +21,18 @@
 
 // Minimum waves per SIMD the kernels are compiled for (a register budget of
 // 512 / waves VGPRs).  The single-image and batched half-passes are held to 4
-// waves per SIMD (128 VGPRs), which they fit without spilling; the batched
-// initialisation and the ablation build get the budget of 2 waves and settle
-// near 125 VGPRs by themselves.
+// waves per SIMD (128 VGPRs), which they fit without spilling; the ablation
+// build gets the budget of 2 waves and settles near 125 VGPRs by itself; the
+// initialisation kernels, which hold half a window block per lane, fit 3
+// waves (at 4 they spill inside the source loop).
 #ifndef AMH_PASS_WAVES_PER_EU
 #define AMH_PASS_WAVES_PER_EU 4
 #endif
 #ifndef AMH_BATCH_WAVES_PER_EU
 #define AMH_BATCH_WAVES_PER_EU 2
+#endif
+#ifndef AMH_INIT_WAVES_PER_EU
+#define AMH_INIT_WAVES_PER_EU 3
 #endif
 
 namespace amh {
@@ -420,44 +424,56 @@ __device__ __forceinline__ float short_to_cost(float c, unsigned *nshort) {
     return c;
 }
 
-template <int HALF, bool SPLIT, typename Win>
-__device__ __forceinline__ float ncc_cost_win(const ViewDev &vw, const Win &rw, const WinStats &ws, int x, int y,
-                                              double q0, float qu, float qv) {
+// The warp of a window onto one source, relative to the texel (ix, iy) its centre is re-centred on: the
+// homogeneous position of window offset (u, v) is N0 + u Pu + v Pv, texel indices are clamped to
+// [xlo, xhi] x [ylo, yhi], and a texel's byte offset is base + yrel * row_bytes + xrel * entry bytes.
+struct SrcWarp {
+    float N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz;
+    int xlo, xhi, ylo, yhi, row_bytes, base;
+    bool interior;  // every texel index is inside the layout without clamping
+};
+
+// False where the evaluation is decided before any sample is taken (cost kShort).
+template <int HALF>
+__device__ __forceinline__ bool src_warp(const ViewDev &vw, int x, int y, double q0, float qu, float qv,
+                                         SrcWarp &w) {
     const double P0x = fma(vw.A[1], (double)y, fma(vw.A[0], (double)x, vw.A[2])) + vw.b[0] * q0;
     const double P0y = fma(vw.A[4], (double)y, fma(vw.A[3], (double)x, vw.A[5])) + vw.b[1] * q0;
     const double P0z = fma(vw.A[7], (double)y, fma(vw.A[6], (double)x, vw.A[8])) + vw.b[2] * q0;
-    if (!(P0z > 0.0)) return kShort;
+    if (!(P0z > 0.0)) return false;
     const int W = vw.W, H = vw.H;
     // centre inside the source: 0 <= P0x / P0z <= W - 1 with P0z > 0, tested without a division
     if (!(P0x >= 0.0 && P0x <= (double)(W - 1) * P0z && P0y >= 0.0 && P0y <= (double)(H - 1) * P0z))
-        return kShort;
+        return false;
     // the texel the window is re-centred on need not be the exact floor of the centre: everything below is
     // relative to it (N0 = P0 - (ix, iy) P0z in double, the bound on the sample offsets includes |N0|), so a
     // float estimate serves; it lies in [-1, W - 1] x [-1, H - 1] (the estimate is a few 1e-3 px off at most)
     const float rzf = __builtin_amdgcn_rcpf((float)P0z);
     const int ix = (int)floorf((float)P0x * rzf), iy = (int)floorf((float)P0y * rzf);
-    const float N0x = (float)(P0x - (double)ix * P0z);
-    const float N0y = (float)(P0y - (double)iy * P0z);
-    const float Z0 = (float)P0z;
-    const float puz = (float)vw.A[6] + (float)vw.b[2] * qu;
-    const float pvz = (float)vw.A[7] + (float)vw.b[2] * qv;
-    const float pux = (float)vw.A[0] + (float)vw.b[0] * qu - (float)ix * puz;
-    const float puy = (float)vw.A[3] + (float)vw.b[1] * qu - (float)iy * puz;
-    const float pvx = (float)vw.A[1] + (float)vw.b[0] * qv - (float)ix * pvz;
-    const float pvy = (float)vw.A[4] + (float)vw.b[1] * qv - (float)iy * pvz;
+    w.N0x = (float)(P0x - (double)ix * P0z);
+    w.N0y = (float)(P0y - (double)iy * P0z);
+    w.Z0 = (float)P0z;
+    w.puz = (float)vw.A[6] + (float)vw.b[2] * qu;
+    w.pvz = (float)vw.A[7] + (float)vw.b[2] * qv;
+    w.pux = (float)vw.A[0] + (float)vw.b[0] * qu - (float)ix * w.puz;
+    w.puy = (float)vw.A[3] + (float)vw.b[1] * qu - (float)iy * w.puz;
+    w.pvx = (float)vw.A[1] + (float)vw.b[0] * qv - (float)ix * w.pvz;
+    w.pvy = (float)vw.A[4] + (float)vw.b[1] * qv - (float)iy * w.pvz;
     // every sample must see the plane in front of the source camera: the depth is affine in the
     // window offsets, so the four corners decide
-    const float zc0 = Z0 - 5.f * puz - 5.f * pvz, zc1 = Z0 + 5.f * puz - 5.f * pvz;
-    const float zc2 = Z0 - 5.f * puz + 5.f * pvz, zc3 = Z0 + 5.f * puz + 5.f * pvz;
-    if (!(fminf(fminf(zc0, zc1), fminf(zc2, zc3)) > 1e-20f)) return kShort;
+    const float zc0 = w.Z0 - 5.f * w.puz - 5.f * w.pvz, zc1 = w.Z0 + 5.f * w.puz - 5.f * w.pvz;
+    const float zc2 = w.Z0 - 5.f * w.puz + 5.f * w.pvz, zc3 = w.Z0 + 5.f * w.puz + 5.f * w.pvz;
+    if (!(fminf(fminf(zc0, zc1), fminf(zc2, zc3)) > 1e-20f)) return false;
 
-    const void *__restrict__ quads = vw.quads;
     // texel indices relative to (ix, iy), clamped to [-1, W-1] x [-1, H-1] in absolute terms;
     // byte offset = base + yrel * row_bytes + xrel * entry_bytes (non-negative after clamping)
     constexpr int kEntry = HALF ? 4 : 8;
-    const int row_bytes = (W + 2 + 2 * kQuadPad) * kEntry;
-    const int xlo = -1 - ix, xhi = W - 1 - ix, ylo = -1 - iy, yhi = H - 1 - iy;
-    const int base = ((iy + 1 + kQuadPad) * (W + 2 + 2 * kQuadPad) + (ix + 1 + kQuadPad)) * kEntry;
+    w.row_bytes = (W + 2 + 2 * kQuadPad) * kEntry;
+    w.xlo = -1 - ix;
+    w.xhi = W - 1 - ix;
+    w.ylo = -1 - iy;
+    w.yhi = H - 1 - iy;
+    w.base = ((iy + 1 + kQuadPad) * (W + 2 + 2 * kQuadPad) + (ix + 1 + kQuadPad)) * kEntry;
     // Clamp-free fast path: the samples lie in the convex image of the window square (the depth is
     // positive at its corners, so the warp has no pole inside), hence |dx| <= (|N0x| + 5 |pux| + 5 |pvx|)
     // / min corner depth, likewise dy.  When that bound (widened by 1 % + 0.01 px, far above the float
@@ -466,26 +482,39 @@ __device__ __forceinline__ float ncc_cost_win(const ViewDev &vw, const Win &rw, 
     // range they change nothing, and the border holds the clamped footprint: the same values, the same result.
     const float zmin = fminf(fminf(zc0, zc1), fminf(zc2, zc3));
     const float rzm = __builtin_amdgcn_rcpf(zmin);
-    const float bx = fmaf(fmaf(5.f, fabsf(pux) + fabsf(pvx), fabsf(N0x)) * rzm, 1.01f, 0.01f);
-    const float by = fmaf(fmaf(5.f, fabsf(puy) + fabsf(pvy), fabsf(N0y)) * rzm, 1.01f, 0.01f);
+    const float bx = fmaf(fmaf(5.f, fabsf(w.pux) + fabsf(w.pvx), fabsf(w.N0x)) * rzm, 1.01f, 0.01f);
+    const float by = fmaf(fmaf(5.f, fabsf(w.puy) + fabsf(w.pvy), fabsf(w.N0y)) * rzm, 1.01f, 0.01f);
     // (the border of the layout extends the clamp-free range by kQuadPad texels on every side)
-    const bool interior = zmin > 1e-3f * Z0 && bx <= (float)(ix + 1 + kQuadPad) && bx < (float)(W - ix + kQuadPad) &&
-                          by <= (float)(iy + 1 + kQuadPad) && by < (float)(H - iy + kQuadPad);
-    // SPLIT = false: every lane takes the clamped path, which gives interior lanes the same result.  A wave
-    // whose lanes disagree runs both paths in turn, so where the hypotheses are random (steep planes, windows
-    // at the image edges: the two mix in nearly every wave) the clamped path alone is the cheaper one.
-    float m2, cab;
-    if (SPLIT && interior)
-        window_moments<HALF, false>(quads, rw, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
-                                    row_bytes, base, m2, cab);
-    else
-        window_moments<HALF, true>(quads, rw, N0x, N0y, Z0, pux, puy, puz, pvx, pvy, pvz, xlo, xhi, ylo, yhi,
-                                   row_bytes, base, m2, cab);
+    w.interior = zmin > 1e-3f * w.Z0 && bx <= (float)(ix + 1 + kQuadPad) && bx < (float)(W - ix + kQuadPad) &&
+                 by <= (float)(iy + 1 + kQuadPad) && by < (float)(H - iy + kQuadPad);
+    return true;
+}
+
+// The cost from the source moments: 1 - NCC, clamped to [0, 2]; 2 for a textureless window on either side.
+__device__ __forceinline__ float cost_from_moments(const WinStats &ws, float m2, float cab) {
     const float var_b = m2 * ws.invW;
     const float cov = cab * ws.invW;
     if (ws.var_a < 1e-5f || var_b < 1e-5f) return 2.f;
     const float mm = 1.f - cov * rsqrtf(ws.var_a * var_b);
     return fminf(fmaxf(mm, 0.f), 2.f);
+}
+
+template <int HALF, bool SPLIT, typename Win>
+__device__ __forceinline__ float ncc_cost_win(const ViewDev &vw, const Win &rw, const WinStats &ws, int x, int y,
+                                              double q0, float qu, float qv) {
+    SrcWarp w;
+    if (!src_warp<HALF>(vw, x, y, q0, qu, qv, w)) return kShort;
+    // SPLIT = false: every lane takes the clamped path, which gives interior lanes the same result.  A wave
+    // whose lanes disagree runs both paths in turn, so where the hypotheses are random (steep planes, windows
+    // at the image edges: the two mix in nearly every wave) the clamped path alone is the cheaper one.
+    float m2, cab;
+    if (SPLIT && w.interior)
+        window_moments<HALF, false>(vw.quads, rw, w.N0x, w.N0y, w.Z0, w.pux, w.puy, w.puz, w.pvx, w.pvy, w.pvz,
+                                    w.xlo, w.xhi, w.ylo, w.yhi, w.row_bytes, w.base, m2, cab);
+    else
+        window_moments<HALF, true>(vw.quads, rw, w.N0x, w.N0y, w.Z0, w.pux, w.puy, w.puz, w.pvx, w.pvy, w.pvz,
+                                   w.xlo, w.xhi, w.ylo, w.yhi, w.row_bytes, w.base, m2, cab);
+    return cost_from_moments(ws, m2, cab);
 }
 
 template <int HALF, bool SPLIT = true>
@@ -500,6 +529,116 @@ __device__ __forceinline__ float ncc_cost(const ViewDev &vw, const float2 *__res
                                           int y, double q0, float qu, float qv) {
     const float c = ncc_cost_raw<HALF>(vw, rw, ws, x, y, q0, qu, qv);
     return c < 0.f ? 2.f : c;
+}
+
+// ---------------------------------------------------------------------------
+// One evaluation on a pair of lanes (lanes 2i, 2i + 1 of a wave, the same
+// pixel and hypothesis): lane h takes the window columns h, h + 2, h + 4 of
+// every row, so that the two loads a pair issues together fall on
+// neighbouring texels of one source row (where hypotheses are random, a wave
+// whose 64 lanes each gather their own window touches 64 cache lines per
+// load instruction).  The warp setup and the row merge are computed by both
+// lanes alike (the same values, bit for bit, so the pair never diverges); the
+// row sums are exchanged within the pair, and each lane's part of the second
+// moments is summed at the end.
+// ---------------------------------------------------------------------------
+// the value held by the other lane of the pair
+__device__ __forceinline__ float pair_other(float v) {
+    // quad permutation (1, 0, 3, 2)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// The half of a pixel's window block that one lane of the pair holds: the entries of its 18 samples (sample
+// s = 6 row + column, the lane's are those with s mod 2 = h, at s / 2) and the 6 row constants, with the two
+// merge terms (W_<r W_r / W_<=r, A_r) zeroed in lane 1 so that each row's cross terms enter once.
+struct PairWin {
+    float2 smp[18];
+    float4 rc[6];
+};
+struct PairWinSink {
+    PairWin *win;
+    bool odd;
+    __device__ __forceinline__ void sample(int s, float2 v) const {
+        if ((s & 1) == 0 || odd) win->smp[s >> 1] = v;
+    }
+    __device__ __forceinline__ void row(int r, float4 v) const {
+        win->rc[r] = odd ? make_float4(v.x, v.y, 0.f, 0.f) : v;
+    }
+};
+
+// the gathers of the lane's 3 samples of window row vf (offsets uf[k] = -5 + 2 h + 4 k), always clamped
+template <int HALF>
+__device__ __forceinline__ void issue_cols(const void *quads, float vf, const float (&uf)[3], const SrcWarp &w,
+                                           typename QuadT<HALF>::type (&qd)[3], float (&fxs)[3], float (&fys)[3]) {
+    constexpr int kEntry = HALF ? 4 : 8;
+    const float rx = fmaf(vf, w.pvx, w.N0x), ry = fmaf(vf, w.pvy, w.N0y), rzz = fmaf(vf, w.pvz, w.Z0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float nx = fmaf(uf[k], w.pux, rx), ny = fmaf(uf[k], w.puy, ry), nz = fmaf(uf[k], w.puz, rzz);
+        const float r = __builtin_amdgcn_rcpf(nz);
+        const float dx = nx * r, dy = ny * r;
+        const int xr = med3i(cvt_floor(dx), w.xlo, w.xhi);
+        const int yr = med3i(cvt_floor(dy), w.ylo, w.yhi);
+        fxs[k] = __builtin_amdgcn_fractf(dx);
+        fys[k] = __builtin_amdgcn_fractf(dy);
+        const uint32_t off = (uint32_t)__mul24(yr, w.row_bytes) + (uint32_t)w.base + (uint32_t)xr * kEntry;
+        qd[k] = load_quad<HALF>(quads, off);
+    }
+}
+
+// Source moments of the window on the pair, row by row as in window_moments: the row mean needs the row's
+// weighted sum over both lanes; the centred sums over the lane's 3 samples and the merge terms (zero in
+// lane 1) accumulate per lane and are added over the pair at the end.
+template <int HALF>
+__device__ __forceinline__ void pair_moments(const void *__restrict__ quads, const PairWin &win,
+                                             const float (&uf)[3], const SrcWarp &w, float &m2, float &cab) {
+#pragma clang fp contract(off)
+    float mu = 0.f, acum = 0.f;
+    m2 = 0.f;
+    cab = 0.f;
+    typename QuadT<HALF>::type qd[3];
+    float fxs[3], fys[3];
+    issue_cols<HALF>(quads, -5.f, uf, w, qd, fxs, fys);
+#pragma unroll
+    for (int sv = 0; sv < 6; ++sv) {
+        float v3[3];
+        float sp = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v3[k] = eval_quad<HALF>(qd[k], fxs[k], fys[k]);
+            sp = fmaf(win.smp[sv * 3 + k].x, v3[k], sp);
+        }
+        if (sv < 5) issue_cols<HALF>(quads, -3.f + 2.f * sv, uf, w, qd, fxs, fys);
+        // the same sum in both lanes (addition commutes bit for bit)
+        const float srow = sp + pair_other(sp);
+        const float4 rc = win.rc[sv];
+        float m2r = 0.f, cr = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 wa = win.smp[sv * 3 + k];
+            const float d = fmaf(-srow, rc.x, v3[k]);
+            m2r = fmaf(wa.x * d, d, m2r);
+            cr = fmaf(wa.y, d, cr);
+        }
+        const float delta = fmaf(srow, rc.x, -mu);
+        const float mun = fmaf(delta, rc.y, mu);
+        m2 += fmaf(rc.z * delta, delta, m2r);
+        cab += fmaf(fmaf(srow, rc.x, -mun), rc.w, fmaf(mu - mun, acum, cr));
+        acum += rc.w;
+        mu = mun;
+    }
+    m2 += pair_other(m2);
+    cab += pair_other(cab);
+}
+
+template <int HALF>
+__device__ __forceinline__ float ncc_cost_pair(const ViewDev &vw, const PairWin &win, const WinStats &ws, int x,
+                                               int y, double q0, float qu, float qv, const float (&uf)[3]) {
+    SrcWarp w;
+    if (!src_warp<HALF>(vw, x, y, q0, qu, qv, w)) return kShort;
+    float m2, cab;
+    pair_moments<HALF>(vw.quads, win, uf, w, m2, cab);
+    return cost_from_moments(ws, m2, cab);
 }
 
 // inverse-depth terms of a plane at reference pixel (x, y): q = -(n . K^-1 (x, y, 1)) / d
@@ -723,30 +862,30 @@ __device__ __forceinline__ bool proposal_plane(const PassArgs &a, float2 r, int 
 }
 
 // ---------------------------------------------------------------------------
-// Initialisation of one colour with one pixel per lane: the pixel's window
-// block is built once, in its lane's registers, and the wave walks the sources
-// together (the view's warp constants in scalar registers, as in the pass), so
-// that the per-pixel work (window block, random plane) is done once per pixel
-// and no lane loads warp constants of its own.  256 pixels of the colour per
-// workgroup in row-major order, workgroups in XCD bands; the costs go to LDS,
-// one row per source, and each lane takes the mean of its k lowest.  The
-// batched initialisation runs the same body, so a job's initial state is the
-// same bits either way.  The block takes 96 registers of the lane; the kernel
-// is compiled for 2 waves per SIMD (at 3 it spills inside the source loop).
+// Initialisation of one colour with one pixel per pair of lanes (see
+// ncc_cost_pair): each lane of the pair builds the pixel's window block and
+// keeps its half in registers, and the wave walks the sources together (the
+// view's warp constants in scalar registers, as in the pass).  kInitBlock
+// pixels of the colour per workgroup of 2 kInitBlock lanes, in row-major
+// order, workgroups in XCD bands; the costs go to LDS, one row per source,
+// and the pair's even lane takes the mean of the k lowest.  The batched
+// initialisation runs the same body, so a job's initial state is the same
+// bits either way.
 // ---------------------------------------------------------------------------
-// Block blk (of init_blocks) of the colour: cst is [n_src][256] floats of LDS, nshort an LDS counter.
+// Block blk (of init_blocks) of the colour: cst is [n_src][kInitBlock] floats of LDS, nshort an LDS counter.
 template <int HALF>
-__device__ __forceinline__ void init_reg_body(const PassArgs &a, long long blk, float *cst, unsigned *nshort_p) {
+__device__ __forceinline__ void init_pair_body(const PassArgs &a, long long blk, float *cst, unsigned *nshort_p) {
     unsigned &nshort = *nshort_p;
     const int N = a.n_src;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, pi = t >> 1;
+    const bool odd = (t & 1) != 0;
     const int per_row = (a.ref.W + 1) / 2;  // slots per row; x beyond the image is skipped
-    const long long pc = blk * kInitBlock + t;
+    const long long pc = blk * kInitBlock + pi;
     const int y = (int)(pc / per_row);
     const int x = 2 * (int)(pc - (long long)y * per_row) + ((y + a.colour) & 1);
     const bool pix_ok = y < a.ref.H && x < a.ref.W;
     if (t == 0) nshort = 0u;
-    RegWin win;
+    PairWin win;
     WinStats ws = {1.f, 0.f};
     float4 pl = make_float4(0.f, 0.f, -1.f, 1.f);
     bool fell_back = false;
@@ -754,7 +893,7 @@ __device__ __forceinline__ void init_reg_body(const PassArgs &a, long long blk, 
     q.ok = false;
     if (pix_ok) {
         GlobalReader rd{&a.ref, x, y};
-        RegWinSink sink{&win};
+        PairWinSink sink{&win, odd};
         ws = build_window_to(rd, a.m, sink);
         const float2 r = ref_ray(a.ref, x, y);
         if (!(a.prop && proposal_plane(a, r, x, y, pl))) {
@@ -767,18 +906,21 @@ __device__ __forceinline__ void init_reg_body(const PassArgs &a, long long blk, 
         }
         q = plane_q(a.ref, a.m, pl, x, y);
         // the plane is final: store it now, so that it is not held through the source loop
-        store_plane(a.st.planes, (size_t)y * a.ref.W + x, pl);
+        if (!odd) store_plane(a.st.planes, (size_t)y * a.ref.W + x, pl);
     }
+    const float u0 = odd ? -3.f : -5.f;
+    const float uf[3] = {u0, u0 + 4.f, u0 + 8.f};
     __syncthreads();
     for (int j = 0; j < N; ++j) {
-        if (pix_ok)
-            cst[j * 256 + t] = short_to_cost(
-                q.ok ? ncc_cost_win<HALF, false>(a.views[j], RegWinRef{win}, ws, x, y, q.q0, q.qu, q.qv) : kShort,
-                &nshort);
+        if (pix_ok) {
+            const float c = q.ok ? ncc_cost_pair<HALF>(a.views[j], win, ws, x, y, q.q0, q.qu, q.qv, uf) : kShort;
+            if (!odd) cst[j * kInitBlock + pi] = short_to_cost(c, &nshort);
+        }
     }
-    count_evals(a.counters, 0, pix_ok ? (unsigned long long)N : 0ull);
-    if (a.prop) count_evals(a.counters, 3, fell_back ? 1ull : 0ull);
-    if (pix_ok) {
+    const bool counts = pix_ok && !odd;
+    count_evals(a.counters, 0, counts ? (unsigned long long)N : 0ull);
+    if (a.prop) count_evals(a.counters, 3, counts && fell_back ? 1ull : 0ull);
+    if (counts) {
         // mean of the k lowest costs, in ascending order (each lane reads only the costs it wrote)
         const int kk = a.m.k < N ? a.m.k : N;
         uint32_t taken = 0;
@@ -788,7 +930,7 @@ __device__ __forceinline__ void init_reg_body(const PassArgs &a, long long blk, 
             float bc = 0.f;
             for (int v = 0; v < N; ++v) {
                 if ((taken >> v) & 1u) continue;
-                const float c = cst[v * 256 + t];
+                const float c = cst[v * kInitBlock + pi];
                 if (best < 0 || c < bc) {
                     best = v;
                     bc = c;
@@ -807,15 +949,16 @@ __device__ __forceinline__ void init_reg_body(const PassArgs &a, long long blk, 
 }
 
 template <int HALF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void init_reg_kernel(PassArgs a) {
-    extern __shared__ __align__(16) float cst[];  // [n_src][256]
+__global__ __launch_bounds__(2 * kInitBlock) __attribute__((amdgpu_waves_per_eu(AMH_INIT_WAVES_PER_EU))) void
+init_pair_kernel(PassArgs a) {
+    extern __shared__ __align__(16) float cst[];  // [n_src][kInitBlock]
     __shared__ unsigned nshort;
     // XCD bands: block b runs on XCD b mod 8 and takes the (b / 8)-th block of that XCD's band
     const long long n_blocks = init_blocks(a.ref.W, a.ref.H);
     const long long per_xcd = (n_blocks + 7) >> 3;
     const long long blk = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (blk >= n_blocks) return;  // the whole workgroup leaves before any barrier
-    init_reg_body<HALF>(a, blk, cst, &nshort);
+    init_pair_body<HALF>(a, blk, cst, &nshort);
 }
 
 // ---------------------------------------------------------------------------
@@ -1381,18 +1524,19 @@ void batch_kernel(BatchPhaseArgs b) {
     batch_stamp(b, lo, j, J.n_tiles);
 }
 
-// Batched initialisation: one initialisation block (256 pixels of the colour) per workgroup, the body of
-// the single-image kernel, so that a job's initial state is the same bits either way.
+// Batched initialisation: one initialisation block (kInitBlock pixels of the colour) per workgroup, the body
+// of the single-image kernel, so that a job's initial state is the same bits either way.
 template <int HALF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void batch_init_kernel(BatchPhaseArgs b) {
-    extern __shared__ __align__(16) float cst[];  // [max n_src][256]
+__global__ __launch_bounds__(2 * kInitBlock) __attribute__((amdgpu_waves_per_eu(AMH_INIT_WAVES_PER_EU))) void
+batch_init_kernel(BatchPhaseArgs b) {
+    extern __shared__ __align__(16) float cst[];  // [max n_src][kInitBlock]
     __shared__ unsigned nshort;
     int lo, L;
     if (!batch_locate(b, lo, L)) return;
     const int j = b.job_of[lo];
     const BatchJobDev &J = b.jobs[j];
     const PassArgs a = batch_pass_args(b, J, 4);
-    init_reg_body<HALF>(a, __builtin_amdgcn_readfirstlane(L), cst, &nshort);
+    init_pair_body<HALF>(a, __builtin_amdgcn_readfirstlane(L), cst, &nshort);
     batch_stamp(b, lo, j, J.n_iblocks);
 }
 
@@ -1750,8 +1894,8 @@ static inline int grid_for(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
 hipError_t launch_init(const PassArgs &a, int half, hipStream_t s) {
     const dim3 grid((unsigned)(8 * ((init_blocks(a.ref.W, a.ref.H) + 7) / 8)));
     const size_t lds = sizeof(float) * kInitBlock * a.n_src;
-    if (half) AMH_LAUNCH(init_reg_kernel<1>, grid, dim3(256), lds, s, a);
-    else AMH_LAUNCH(init_reg_kernel<0>, grid, dim3(256), lds, s, a);
+    if (half) AMH_LAUNCH(init_pair_kernel<1>, grid, dim3(2 * kInitBlock), lds, s, a);
+    else AMH_LAUNCH(init_pair_kernel<0>, grid, dim3(2 * kInitBlock), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1786,8 +1930,8 @@ hipError_t launch_batch(const BatchPhaseArgs &b, int half, int max_src, hipStrea
     const dim3 grid(b.grid);
     if (b.kind == 0) {
         const size_t lds = sizeof(float) * kInitBlock * max_src;
-        if (half) AMH_LAUNCH(batch_init_kernel<1>, grid, dim3(kInitBlock), lds, s, b);
-        else AMH_LAUNCH(batch_init_kernel<0>, grid, dim3(kInitBlock), lds, s, b);
+        if (half) AMH_LAUNCH(batch_init_kernel<1>, grid, dim3(2 * kInitBlock), lds, s, b);
+        else AMH_LAUNCH(batch_init_kernel<0>, grid, dim3(2 * kInitBlock), lds, s, b);
         return hipGetLastError();
     }
     const size_t lds = pass_lds_bytes(max_src, b.waves);
