@@ -1164,8 +1164,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             }
         }
     } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) nv += S.valid[wave * 64 + g * kRows + i];
+        // valid propagated rows of the pixel: one ballot
+        nv = __popcll((__ballot(valid && row < 8) >> (kRows * grp)) & 0xFFull);
         if (pix_ok && !heur) {
             for (int j = row; j < N; j += kRows) {
                 int lt = 0, gt = 0;
@@ -1183,46 +1183,65 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
     }
     __syncthreads();
 
-    // (5) view inference, part 2 (Eq. 4-6): S_t and v_t = argmax psi (every lane of the pixel, identical
-    //     result); then lane r sets the weights of views r, r+9, ...: a view of S_t keeps its modified
-    //     importance (x2 for v_{t-1}) when fewer than k views of S_t rank above it (larger modified
-    //     importance, or equal and a lower index: the k largest, ties to the lower index), a view of
-    //     S_{t-1} that left the selection weighs 0.2, every other view 0
+    // (5) view inference, part 2 (Eq. 4-6).  Lane r of the pixel holds views r, r+9, r+18, r+27.  S_t comes
+    //     from one ballot per view slot.  Each lane ranks its views of S_t against the pixel's others (psi in
+    //     LDS, the same address for the pixel's 9 lanes): a view keeps its modified importance (x2 for
+    //     v_{t-1}) when fewer than k views of S_t rank above it by modified importance (larger, or equal and a
+    //     lower index), a view of S_{t-1} that left the selection weighs 0.2, every other view 0; the view no
+    //     other outranks by importance itself is v_t = argmax psi (ties to the lower index), found by a ballot
     uint32_t Sm = 0;
     int vt = -1;
     int vprev = -1;
     float *wgt = S.wgt + (wave * kGroups + g) * kMaxSrc;
-    if (pix_ok && !heur) {
-        vprev = glob(a.st.v)[p];
-        const uint32_t Sprev = glob(a.st.S)[p];
-        float best = 0.f;
-        for (int j = 0; j < N; ++j) {
-            const float ps = psi[j];
-            if (ps >= 0.f) {
-                Sm |= 1u << j;
-                if (vt < 0 || ps > best) { vt = j; best = ps; }
+    if (!heur) {  // uniform over the launch: every lane takes part in the ballots
+        uint32_t Sprev = 0;
+        if (pix_ok) {
+            vprev = glob(a.st.v)[p];
+            Sprev = glob(a.st.S)[p];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = row + kRows * i;
+            const bool in = pix_ok && j < N && psi[j] >= 0.f;
+            // bits of views j >= 32 fall off the 32-bit shift; such views do not exist (N <= 32)
+            Sm |= (uint32_t)((__ballot(in) >> (kRows * grp)) & 0x1FFull) << (kRows * i);
+        }
+        uint32_t top = 0;  // bit i: the lane's view slot i is v_t
+        if (pix_ok) {
+            for (int i = 0, j = row; j < N; ++i, j += kRows) {
+                const float pj = psi[j];
+                if (pj >= 0.f) {  // j in S_t
+                    const float mj = (j == vprev ? 2.f : 1.f) * pj;
+                    int rank = 0, rpsi = 0;
+                    for (uint32_t rest = Sm; rest; rest &= rest - 1u) {  // the views of S_t
+                        const int q = __builtin_ctz(rest);
+                        const float pq = psi[q];
+                        const float mq = (q == vprev ? 2.f : 1.f) * pq;
+                        rank += (mq > mj || (mq == mj && q < j)) ? 1 : 0;
+                        rpsi += (pq > pj || (pq == pj && q < j)) ? 1 : 0;
+                    }
+                    if (rpsi == 0) top |= 1u << i;
+                    wgt[j] = rank < m.k ? mj : 0.f;
+                } else {
+                    wgt[j] = ((Sprev >> j) & 1u) ? 0.2f : 0.f;
+                }
             }
         }
-        for (int j = row; j < N; j += kRows) {
-            float wj = 0.f;
-            if ((Sm >> j) & 1u) {
-                const float mj = (j == vprev ? 2.f : 1.f) * psi[j];
-                int rank = 0;
-                for (int i = 0; i < N; ++i) {
-                    if (!((Sm >> i) & 1u)) continue;
-                    const float mi = (i == vprev ? 2.f : 1.f) * psi[i];
-                    rank += (mi > mj || (mi == mj && i < j)) ? 1 : 0;
-                }
-                if (rank < m.k) wj = mj;
-            } else if ((Sprev >> j) & 1u) {
-                wj = 0.2f;
-            }
-            wgt[j] = wj;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t bits = (uint32_t)((__ballot((top >> i) & 1u) >> (kRows * grp)) & 0x1FFull);
+            if (bits) vt = kRows * i + __builtin_ctz(bits);
         }
     } else if (pix_ok) {  // heuristic selection (ablation): every view weighs 1
         for (int j = row; j < N; j += kRows) wgt[j] = 1.f;
     }
     __syncthreads();
+    // S_t and v_t wait in the pixel's psi block (read no more) until the pixel is written, so that they are
+    // not held in registers through the refinement
+    if (pix_ok && row == 0) {
+        psi[0] = __uint_as_float(Sm);
+        psi[1] = __int_as_float(vt);
+    }
     // the pixel's weight sum in view order; all weights 0: the plain mean over all views (uniform weights)
     float wsum = 0.f;
     if (pix_ok)
@@ -1398,8 +1417,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
         const float4 best = bcand < 0 ? S.pl[bslot] : S.cand[(wave * kGroups + g) * 6 + bcand];
         store_plane(a.st.planes, p, best);
         glob(a.st.cost)[p] = bcost;
-        glob(a.st.S)[p] = Sm;
-        glob(a.st.v)[p] = vt;
+        glob(a.st.S)[p] = __float_as_uint(psi[0]);
+        glob(a.st.v)[p] = __float_as_int(psi[1]);
     }
     count_evals(a.counters, 1, (unsigned long long)n_prop);
     if (m.refine) count_evals(a.counters, 2, (unsigned long long)n_ref);

@@ -551,7 +551,10 @@ def test_degenerate_sizes(amh, oracle_mod, W, H, n, sym, heur):
     st = O.run(V, O.Params(refine=1, seed=1, prop_mode=sym, view_mode=2 if heur else 0), 2)
     od, _ = O.depth_normal(V, st)
     assert np.all(np.isfinite(d)) and np.all(np.isfinite(c))
-    assert (np.abs(d - od) / od <= 1e-3).mean() >= 0.9
+    agree = (np.abs(d - od) / od <= 1e-3).mean()
+    say("agreement", agree)
+    # the method's full-run bar: 99.5 % of the pixels within 0.1 % (on images this small: every pixel)
+    assert agree >= 0.995
 
 
 def test_many_sources(amh, oracle_mod):
