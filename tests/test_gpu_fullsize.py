@@ -97,7 +97,7 @@ def test_sampled_half_pass_matches_oracle(amh, oracle_mod, big_scene):
     say(f"  robust {robust.mean():.3f}, agree on robust {ok[robust].mean():.4f}, plane agreement {ok_plane.mean():.4f}")
     assert robust.mean() >= 0.5
     assert ok[robust].all()
-    assert ok_plane.mean() >= 0.98
+    assert ok_plane.mean() >= 0.99  # the one-half-pass bar: >= 99 % of all pixels keep the oracle's plane
 
 
 def test_sampled_fixed_costs_match_oracle(amh, oracle_mod, big_scene):
@@ -120,13 +120,17 @@ def test_sampled_fixed_costs_match_oracle(amh, oracle_mod, big_scene):
         ctx.begin(0, list(range(1, n + 1)))
         got = ctx.score_fixed(planes, np.array(pix, np.int32))
     V = O.Views.from_scene(sc)
-    P = O.Params()
-    want = np.array([[O.matching_cost(V, P, x, y, pl.astype(np.float64), j) for j in range(n)]
-                     for (x, y), pl in zip(pix, planes)])
+    # the cost-2 decisions (weighted variance at the 1e-5 threshold) against the oracle's own with its
+    # positions, samples and moments in float32 (conditioning probe, level 2): a decision that rounding can
+    # flip there may flip on the GPU too
+    want, probe = (np.array([[O.matching_cost(V, Q, x, y, pl.astype(np.float64), j) for j in range(n)]
+                             for (x, y), pl in zip(pix, planes)]) for Q in (O.Params(), O.Params(sample_f32=2)))
     both = (want < 2) & (got < 2)
     err = np.abs(got - want)[both]
-    say(f"  max err {err.max():.2e} over {both.sum()} scored pairs")
-    assert ((want < 2) != (got < 2)).mean() < 1e-2
+    flips, probe_flips = ((want < 2) != (got < 2)).mean(), ((want < 2) != (probe < 2)).mean()
+    say(f"  max err {err.max():.2e} over {both.sum()} scored pairs; cost-2 decisions differing: gpu {flips:.4f}, "
+        f"probe {probe_flips:.4f}")
+    assert flips <= probe_flips + 5e-3
     assert err.max() <= 1e-4
 
 
