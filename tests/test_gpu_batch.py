@@ -297,7 +297,12 @@ def test_batched_proposal_initial_state_matches_oracle(amh, oracle_mod, batch_se
         assert ok.mean() >= 0.6 and used[ok].mean() >= 0.99
         np.testing.assert_allclose(d[ok], od[ok], rtol=2e-5)
         np.testing.assert_allclose(nrm[ok], on[ok], atol=2e-5)
-        assert (np.abs(c - ost.cost)[ok] <= 1e-4).mean() >= 0.999
+        # initial costs within the per-cost bar, except where the oracle's float32 probe (level 2) misses it too
+        pst, _ = proposal.proposal_state(V, O.Params(seed=7, sample_f32=2), depth, normal, conf, conf_min=0.5)
+        unsure = np.abs(pst.cost - ost.cost) > 1e-4
+        dc = np.abs(c - ost.cost)
+        say(f"  initial cost within 1e-4 on {(dc[ok] <= 1e-4).mean():.5f}; the probe misses it on {int(unsure.sum())}")
+        assert np.all((dc <= 1e-4) | unsure | ~ok) and unsure.mean() <= 1e-3
 
 
 @pytest.mark.parametrize("config", [8, 13])

@@ -163,6 +163,18 @@ def test_score_fixed_windows_crossing_source_edges(amh, oracle_mod, scene_c1):
     assert ((want < 2) != (got < 2)).mean() < 1e-3
 
 
+def _init_cost_bar(O, sc, ost, d, seed):
+    """Initial costs (mean of the k lowest per-view costs, a continuous function of them) within the per-cost
+    bar 1e-4 on every pixel, except where a per-view cost-2 decision sits on its threshold: there the oracle's
+    own initialisation with float32 positions, samples and moments (conditioning probe, level 2) misses the
+    bar too."""
+    probe = O.init(O.Views.from_scene(sc), O.Params(seed=seed, sample_f32=2))
+    unsure = np.abs(probe.cost - ost.cost) > 1e-4
+    say(f"  pixels where the float32 probe misses the bar: {int(unsure.sum())}")
+    assert np.all((d <= 1e-4) | unsure)
+    assert unsure.mean() <= 1e-3
+
+
 def test_init_matches_oracle(amh, oracle_mod, scene_c1):
     say("case init c1")
     O = oracle_mod
@@ -176,14 +188,15 @@ def test_init_matches_oracle(amh, oracle_mod, scene_c1):
     assert np.all(S == 0) and np.all(v == -1)
     np.testing.assert_allclose(pl, ost.plane, atol=2e-5, rtol=2e-5)
     d = np.abs(cost - ost.cost)
-    assert (d <= 1e-4).mean() >= 0.999
+    say(f"  initial cost within 1e-4 on {(d <= 1e-4).mean():.5f}, max diff {d.max():.2e}")
+    _init_cost_bar(O, sc, ost, d, 11)
     assert st["evals_init"] == sc.width * sc.height * 4
 
 
 @pytest.mark.parametrize("n", [1, 5, 8, 9, 17, 32])
 def test_init_matches_oracle_source_counts(amh, oracle_mod, n):
-    """Initialisation with 1, 5, 8, 9, 17 and 32 sources: every mapping of sources to the lanes of a pixel
-    (one per lane, two per lane for some or all lanes, 16 lanes per pixel), on a ragged 61x37 image."""
+    """Initialisation with 1, 5, 8, 9, 17 and 32 sources (up to the largest view set, one LDS row of costs per
+    source) on a ragged 61x37 image: the colour's last workgroup is partial and rows end mid-block."""
     say("case init n", n)
     import scenegen
 
@@ -198,7 +211,8 @@ def test_init_matches_oracle_source_counts(amh, oracle_mod, n):
     assert np.all(S == 0) and np.all(v == -1)
     np.testing.assert_allclose(pl, ost.plane, atol=2e-5, rtol=2e-5)
     d = np.abs(cost - ost.cost)
-    assert (d <= 1e-4).mean() >= 0.999
+    say(f"  initial cost within 1e-4 on {(d <= 1e-4).mean():.5f}, max diff {d.max():.2e}")
+    _init_cost_bar(O, sc, ost, d, 13)
     assert st["evals_init"] == sc.width * sc.height * n
     ys, xs = np.mgrid[0:sc.height, 0:sc.width]
     want = int(short_mask(sc, np.c_[xs.ravel(), ys.ravel()], pl.reshape(-1, 4), 2.0, 6.0).sum())
@@ -263,7 +277,7 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
     assert np.array_equal(pl1.reshape(-1, 4)[other], pl0.reshape(-1, 4)[other])
     # every robust pixel must agree, and almost every pixel keeps the same plane
     assert frac_robust >= 0.5
-    assert ok[robust].mean() >= 0.999
+    assert ok[robust].all()
     assert ok_plane.mean() >= min_plane
     return ok, robust, float(ok_plane.mean())
 
