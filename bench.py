@@ -35,10 +35,11 @@ METRIC = "hypothesis·view NCC evals/s; sec per depth map at equal accuracy vs p
 # rsqrt, clamp) + ~15 for the warp from the plane -> ~950.  The roofline fraction is taken on this count.
 OPS_PER_EVAL = 950
 # What this implementation issues per evaluation, counted on its instruction stream: the reciprocal at
-# quarter rate (4 slots), 6 texel-index operations, a bilinear sample in 4 operations from the texel-column
-# layout (two column interpolations and their blend), the two-pass row moments and ~62 set-up and
-# epilogue slots -> 1196.  Reported beside the fraction as the issue-slot figure.
-ISSUE_SLOTS_PER_EVAL = 1196
+# half rate (2 slots: on MI355X v_rcp_f32 issues at half the rate of v_fma_f32, measured), 6 texel-index
+# operations, a bilinear sample in 4 operations from the texel-column layout (two column interpolations
+# and their blend), the two-pass row moments and ~62 set-up and epilogue slots -> 1124.  Reported beside
+# the fraction as the issue-slot figure.
+ISSUE_SLOTS_PER_EVAL = 1124
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one VALU lane-operation per lane per clock
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # Bytes the half-pass kernel moves between L2 and memory per launch, from two rocprofv3 --pmc runs
