@@ -34,14 +34,16 @@ METRIC = "hypothesis·view NCC evals/s; sec per depth map at equal accuracy vs p
 # shift-subtract, w*b and 3 moment accumulations (5) = 26; x 36, + ~20 for the epilogue (variances,
 # rsqrt, clamp) + ~15 for the warp from the plane -> ~950.  The roofline fraction is taken on this count.
 OPS_PER_EVAL = 950
-# What this implementation issues per evaluation, counted on its instruction stream: the reciprocal at
-# half rate (2 slots: on MI355X v_rcp_f32 issues at half the rate of v_fma_f32, measured), 6 texel-index
-# operations, a bilinear sample in 4 operations from the texel-column layout (two column interpolations
-# and their blend), the two-pass row moments and ~62 set-up and epilogue slots -> 1124.  Reported beside
-# the fraction as the issue-slot figure.
-ISSUE_SLOTS_PER_EVAL = 1124
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz, one VALU lane-operation per lane per clock
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# What this implementation issues per evaluation, counted on its instruction stream in full-rate slots (one
+# wave instruction every 2 clocks per SIMD, the rate of v_add_f32 / v_fma_f32 with vector-register operands;
+# bench.py --calibrate-valu measures each kind): 621 full-rate fp32 instructions, 284 at half rate
+# (conversions, fractions, clamps, integer address arithmetic, fp64 set-up, fp32 instructions reading a
+# scalar register: 2 slots each) and 38 reciprocals at quarter rate (4 slots) -> 1341.  Reported beside the
+# fraction as the issue-slot figure.
+ISSUE_SLOTS_PER_EVAL = 1341
+# MI355X: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T fp32 lane-operations/s (157.3 TFLOP/s with an FMA
+# counted as two): unpacked v_add_f32 issues at 91 % of it and v_fma_f32 at 72 % (bench.py --calibrate-valu)
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
 # Bytes the half-pass kernel moves between L2 and memory per launch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean of the 6 half-passes of one depth map) scaled by
 # what the same counters read for a plain 256 MiB copy (bench.py --calibrate-copy: FETCH_SIZE 131080 KiB
@@ -554,6 +556,30 @@ def bench_fusion(args):
     print(json.dumps(out))
 
 
+def calibrate_valu(blocks=8192, iters=1024, reps=3):
+    """Issue rate of each instruction kind of amh_probe_valu (16 independent chains per lane, 8192
+    workgroups of 256 threads): best of `reps` launches, in wave instructions and lane-operations per second,
+    and its cost in full-rate slots (v_fma_f32 with vector operands = 1)."""
+    import torch
+
+    import paper_1805_07920_amd as amh
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    winstr = 16.0 * iters * blocks * 4
+    rows = []
+    for kind, name in enumerate(amh.PROBE_KINDS):
+        ms = min(amh.probe_valu(kind, blocks, iters) for _ in range(reps))
+        rows.append({"kind": kind, "instruction": name, "ms": ms, "wave_instr_per_s": winstr / (ms / 1000.0),
+                     "lane_ops_per_s": 64 * winstr / (ms / 1000.0)})
+    base = rows[0]["wave_instr_per_s"]
+    for r in rows:
+        r["slots"] = round(base / r["wave_instr_per_s"], 2)
+    clock_peak = 256 * 4 * 2.4e9 / 2  # wave instructions per second at 2 clocks each (32 lanes per SIMD)
+    print(json.dumps({"probe": "vector-ALU issue rate, MI355X", "blocks": blocks, "iters": iters,
+                      "full_rate_wave_instr_per_s_at_2_clocks": clock_peak, "kinds": rows}))
+
+
 def bench_scaling(args):
     """Time per depth map against image size (the shape of the paper's Table 3: time proportional to the
     pixel count): the 1920x1280 / 10-source recipe at scales 1, 0.5 and 0.25 (3 iterations + refinement)."""
@@ -640,6 +666,9 @@ def main():
                     help="skip the autotuner and run this launch configuration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB element-wise copy (reference for the HBM byte counters)")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only measure the issue rate of the vector-ALU instruction kinds the evaluation uses "
+                         "(the roofline's peak and the instruction mix's slot costs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}). "
@@ -655,6 +684,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 3}))
         return
+    if args.calibrate_valu:
+        return calibrate_valu()
     if args.batch:
         return bench_batch(args)
     if args.learned:

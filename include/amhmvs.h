@@ -438,6 +438,20 @@ amh_status amh_fuse(amh_ctx *ctx, int n_views, const int *views, const float *co
                     const float *const *normal, const amh_fusion_params *fp, float *points, float *point_normals,
                     int32_t *origin, int64_t capacity, int64_t *n_points);
 
+/* Instruction-throughput probe of the current device: a measurement utility for
+ * the roofline (the issue rate of one vector-ALU instruction kind), no part of
+ * the method.  Launches `blocks` workgroups of 256 threads on the null stream;
+ * every lane runs 16 independent chains of `iters` instructions of one kind,
+ * so the launch issues 16 * iters * blocks * 4 wave instructions of it.  kind:
+ * 0 v_fma_f32 (vector-register operands), 1 v_fma_f32 reading a scalar
+ * register, 2 v_rcp_f32, 3 v_fract_f32, 4 v_cvt_flr_i32_f32, 5 v_med3_i32,
+ * 6 v_mad_u32_u24, 7 v_add_f32 with a literal.  *ms (host) receives the
+ * launch's device time (a first one-block launch loads the code untimed).
+ * INVALID_ARG for another kind, blocks or iters outside 1..65536 or ms NULL;
+ * OOM if its output (blocks KiB, freed on return) cannot be allocated; HIP_ERROR
+ * without a device.  Synchronous. */
+amh_status amh_probe_valu(int kind, int blocks, int iters, float *ms);
+
 const char *amh_status_str(amh_status s);
 const char *amh_last_error(const amh_ctx *ctx);
 

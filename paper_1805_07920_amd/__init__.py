@@ -29,7 +29,7 @@ EXPORTS = [
     "amh_nn_forward", "amh_nn_backward", "amh_nn_adam_step", "amh_nn_save", "amh_nn_load", "amh_sweep_features",
     "amh_init_from_proposal", "amh_run_proposal", "amh_set_launch_config", "amh_run_batch_proposal",
     "amh_fusion_params_default", "amh_median_filter4", "amh_fuse", "amh_run_checkerboard_static",
-    "amh_set_initial_hypotheses", "amh_nn_targets",
+    "amh_set_initial_hypotheses", "amh_nn_targets", "amh_probe_valu",
 ]
 NET_CELL = 4  # reference pixels per proposal cell side
 NET_IN, NET_OUT = 16, 5
@@ -132,10 +132,24 @@ def lib():
         L.amh_run_batch_proposal.argtypes = [vp, ip, C.POINTER(amh_job)]
         L.amh_fusion_params_default.argtypes = [C.POINTER(amh_fusion_params)]
         L.amh_median_filter4.argtypes = [vp, vp, vp, ip, ip]
+        L.amh_probe_valu.argtypes = [ip, ip, ip, C.POINTER(C.c_float)]
         L.amh_fuse.argtypes = [vp, ip, C.POINTER(C.c_int), C.POINTER(vp), C.POINTER(vp),
                                C.POINTER(amh_fusion_params), vp, vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
+
+
+PROBE_KINDS = ("v_fma_f32 (vector operands)", "v_fma_f32 (scalar operand)", "v_rcp_f32", "v_fract_f32",
+               "v_cvt_flr_i32_f32", "v_med3_i32", "v_mad_u32_u24", "v_add_f32 (literal)")
+
+
+def probe_valu(kind: int, blocks: int, iters: int) -> float:
+    """Device milliseconds of amh_probe_valu's launch (16 * iters * blocks * 4 wave instructions of one kind)."""
+    ms = C.c_float()
+    rc = lib().amh_probe_valu(kind, blocks, iters, C.byref(ms))
+    if rc != AMH_OK:
+        raise AmhError(rc, f"amh_probe_valu: {lib().amh_status_str(rc).decode()}")
+    return float(ms.value)
 
 
 def params_default(**kw) -> amh_params:

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "_build", "libamhmvs.so")
-SOURCES = ["amh_kernels.hip", "amh_api.hip", "amh_nn.hip", "amh_nn_api.hip", "amh_fusion.hip"]
+SOURCES = ["amh_kernels.hip", "amh_api.hip", "amh_nn.hip", "amh_nn_api.hip", "amh_fusion.hip", "amh_probe.hip"]
 
 
 def hipcc() -> str:

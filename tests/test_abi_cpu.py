@@ -140,3 +140,12 @@ def test_bilateral_switch_validated(amh):
     for bad in (-1, 2):
         q = amh.params_default(bilateral_squared=bad)
         assert amh.lib().amh_create(C.byref(C.c_void_p()), C.byref(q), None) == amh.AMH_E_INVALID_ARG
+
+
+def test_probe_arguments_validated(amh):
+    L = amh.lib()
+    ms = C.c_float()
+    for kind, blocks, iters in ((-1, 1, 1), (8, 1, 1), (0, 0, 1), (0, 65537, 1), (0, 1, 0), (0, 1, 65537)):
+        assert L.amh_probe_valu(kind, blocks, iters, C.byref(ms)) == amh.AMH_E_INVALID_ARG
+    assert L.amh_probe_valu(0, 1, 1, None) == amh.AMH_E_INVALID_ARG
+    assert len(amh.PROBE_KINDS) == 8
