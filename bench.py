@@ -801,6 +801,9 @@ def main():
         "accuracy_within_1pct_of_ground_truth": acc,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                      "frac": achieved / VALU_PEAK_OPS,
+                     "peak_basis": "fp32 lane-operations: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (157.3 TFLOP/s, "
+                                   "FMA = 2 flops); unpacked v_add_f32 reaches 91 %, v_fma_f32 72 % "
+                                   "(bench.py --calibrate-valu)",
                      # the counters were taken on the 1920x1280 workload only
                      "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4) if args.config == "c2" else None,
                      "traffic_unit": "bytes per launch (L2 <-> memory, calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
