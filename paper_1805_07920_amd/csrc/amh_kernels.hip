@@ -1071,20 +1071,31 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                 pl = load_plane(a.st.planes, (size_t)ny * W + nx);
             }
         } else if (row < 8) {
-            int bx = -1, by = -1;
-            float bc = 0.f;
+            // the region's stored costs are loaded together (all in flight at once), then taken in table order
             const int ne = region_size(row);
-            for (int e = 0; e < ne; ++e) {
+            float cr[11];
+            bool in[11];
+#pragma unroll
+            for (int e = 0; e < 11; ++e) {
                 int dx, dy;
                 region_offset(row, e, dx, dy);
                 const int nx = x + dx, ny = y + dy;
-                if (nx < 0 || nx >= W || ny < 0 || ny >= H) continue;
-                const float c = glob(a.st.cost)[(size_t)ny * W + nx];
-                if (bx < 0 || c < bc) { bx = nx; by = ny; bc = c; }
+                in[e] = e < ne && nx >= 0 && nx < W && ny >= 0 && ny < H;
+                cr[e] = in[e] ? glob(a.st.cost)[(size_t)ny * W + nx] : 0.f;
             }
-            if (bx >= 0) {
+            int be = -1;
+            float bc = 0.f;
+#pragma unroll
+            for (int e = 0; e < 11; ++e)
+                if (in[e] && (be < 0 || cr[e] < bc)) {
+                    be = e;
+                    bc = cr[e];
+                }
+            if (be >= 0) {
+                int dx, dy;
+                region_offset(row, be, dx, dy);
                 valid = true;
-                pl = load_plane(a.st.planes, (size_t)by * W + bx);
+                pl = load_plane(a.st.planes, (size_t)(y + dy) * W + (x + dx));
             }
         } else {
             valid = m.include_self != 0;
