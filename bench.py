@@ -258,7 +258,7 @@ def learned_comparison(seeds, steps: int, warmup: int, seed: int = 0, weights=No
     H = W = 0
     tuned = (None, None)
     for sd in seeds:
-        sc = scenegen.config_scene("c2", sd, device="cuda")
+        sc = scenegen.config_scene("1920x1280_n10", sd, device="cuda")
         H, W = sc.height, sc.width
         ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
         srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]  # nearest sources first
@@ -358,7 +358,7 @@ def bench_variants(args, variants, metric: str):
     H = W = 0
     tuned = None
     for si, seed in enumerate(seeds):
-        sc = scenegen.config_scene("c2", seed, device="cuda")
+        sc = scenegen.config_scene("1920x1280_n10", seed, device="cuda")
         H, W = sc.height, sc.width
         ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
         srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]  # nearest sources first
@@ -453,7 +453,7 @@ def bench_fusion(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     seed = args.eval_seed0
-    sc = scenegen.config_scene("c2", seed, device="cuda", all_views=True)
+    sc = scenegen.config_scene("1920x1280_n10", seed, device="cuda", all_views=True)
     V = len(sc.images)
     H, W = sc.height, sc.width
     ctx = amh.Context(refine=1, seed=args.seed)
@@ -590,13 +590,13 @@ def bench_scaling(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    base = scenegen.CONFIGS["c2"]
+    base = scenegen.CONFIGS["1920x1280_n10"]
     ctx = amh.Context(refine=1, seed=args.seed)
     rows = []
     tuned = None
     for eta in (1.0, 0.5, 0.25):
         W, H = int(base["width"] * eta), int(base["height"] * eta)
-        sc = scenegen.config_scene("c2", args.seed, device="cuda", width=W, height=H)
+        sc = scenegen.config_scene("1920x1280_n10", args.seed, device="cuda", width=W, height=H)
         srcs = list(range(1, len(sc.images)))
         imgs = [torch.from_numpy(np.ascontiguousarray(im)).to(dev) for im in sc.images]
         ctx.init_views(imgs, sc.cams)
@@ -659,8 +659,8 @@ def main():
                     help="iterations per depth map (--ablation, --readings)")
     ap.add_argument("--fusion", action="store_true",
                     help="the stage after the depth maps: median filter + consistency-check fusion of 11 views")
-    ap.add_argument("--config", default="c2", choices=("c2", "c3"),
-                    help="single-image workload: c2 = 1920x1280, 10 sources (the headline); c3 = 3200x2130, 20 sources "
+    ap.add_argument("--config", default="1920x1280_n10", choices=("1920x1280_n10", "3200x2130_n20"),
+                    help="single-image workload: 1920x1280, 10 sources (the headline), or 3200x2130, 20 sources "
                          "stored fp16, 30 %% low texture, 4 iterations")
     ap.add_argument("--launch-config", type=int, default=None, choices=range(16),
                     help="skip the autotuner and run this launch configuration")
@@ -766,7 +766,7 @@ def main():
     # the metric's second half: seconds per depth map of the learned proposal + 1 iteration against the
     # plain method (random init + 3 iterations) at equal accuracy, on a held-out scene of the same recipe
     learned = None
-    if args.config == "c2" and not args.no_learned:
+    if args.config == "1920x1280_n10" and not args.no_learned:
         learned = learned_comparison([1], steps=max(3, args.steps), warmup=1, seed=args.seed)
         learned = {k: learned[k] for k in ("sec_per_depth_map", "plain_sec_per_depth_map", "speedup_vs_plain",
                                             "equal_accuracy", "equal_accuracy_rule", "workload", "accuracy")}
@@ -785,7 +785,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"{W}x{H} reference + {n} sources, 20-plane seeded scene with occlusions and "
                                 "+-5% gain, 11x11 window stride 2, 3 iterations + refinement, random init")
-                   if args.config == "c2" else
+                   if args.config == "1920x1280_n10" else
                    (f"{W}x{H} reference + {n} sources stored fp16 (fp32 arithmetic), 20-plane seeded scene, 30% "
                     f"low-texture area, 11x11 window stride 2, {cfg['iters']} iterations + refinement, random init"),
                    "width": W, "height": H, "n_src": n, "iters": cfg["iters"], "refine": cfg["refine"],
@@ -805,7 +805,7 @@ def main():
                                    "FMA = 2 flops); unpacked v_add_f32 reaches 91 %, v_fma_f32 72 % "
                                    "(bench.py --calibrate-valu)",
                      # the counters were taken on the 1920x1280 workload only
-                     "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4) if args.config == "c2" else None,
+                     "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4) if args.config == "1920x1280_n10" else None,
                      "traffic_unit": "bytes per launch (L2 <-> memory, calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "kernel": f"pass_kernel<{1 if store == amh.AMH_F16 else 0}, {2 if best_cfg & 4 else 4}> "
                                f"(fused checkerboard half-pass, {2 if best_cfg & 4 else 4}-row tiles)",

@@ -59,7 +59,7 @@ def make_dataset(ctx, seeds, iters: int = 3, n_src=(8, 8)):
     t0 = time.time()
     for k, seed in enumerate(seeds):
         n = int(np.random.default_rng(seed).integers(n_src[0], n_src[1] + 1))
-        sc = scenegen.config_scene("c5", seed, device="cuda", n_src=n)
+        sc = scenegen.config_scene("640x480_n8", seed, device="cuda", n_src=n)
         srcs = nearest_first(sc)
         scene_views(ctx, sc)
         ctx.run_checkerboard(0, srcs, iters)

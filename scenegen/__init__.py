@@ -405,16 +405,16 @@ def make_scene(width: int, height: int, n_src: int, arc_deg: float, n_planes: in
 
 CONFIGS = {
     # tiny: 128x96, 4 sources, 15 deg arc, 3 planes, fp32, 3 iterations, no refinement
-    "c1": dict(width=128, height=96, n_src=4, arc_deg=15.0, n_planes=3, gain=0.0, low_texture_frac=0.0,
+    "128x96_n4": dict(width=128, height=96, n_src=4, arc_deg=15.0, n_planes=3, gain=0.0, low_texture_frac=0.0,
                src_dtype="f32", supersample=4, iters=3, refine=0),
     # 1920x1280, 10 sources, 40 deg arc, 20 planes with occlusions, +-5 % per-view gain, 3 iterations + refinement
-    "c2": dict(width=1920, height=1280, n_src=10, arc_deg=40.0, n_planes=20, gain=0.05, low_texture_frac=0.0,
+    "1920x1280_n10": dict(width=1920, height=1280, n_src=10, arc_deg=40.0, n_planes=20, gain=0.05, low_texture_frac=0.0,
                src_dtype="f32", supersample=2, iters=3, refine=1),
     # 3200x2130, 20 sources stored fp16, 30 % low texture, 4 iterations + refinement
-    "c3": dict(width=3200, height=2130, n_src=20, arc_deg=40.0, n_planes=20, gain=0.0, low_texture_frac=0.30,
+    "3200x2130_n20": dict(width=3200, height=2130, n_src=20, arc_deg=40.0, n_planes=20, gain=0.0, low_texture_frac=0.30,
                src_dtype="f16", supersample=2, iters=4, refine=1),
     # training scenes of the learned proposal (seeds 1000-2999): 640x480, 8 sources, the 1920x1280 recipe
-    "c5": dict(width=640, height=480, n_src=8, arc_deg=40.0, n_planes=20, gain=0.05, low_texture_frac=0.0,
+    "640x480_n8": dict(width=640, height=480, n_src=8, arc_deg=40.0, n_planes=20, gain=0.05, low_texture_frac=0.0,
                src_dtype="f32", supersample=2, iters=3, refine=1),
 }
 

@@ -25,4 +25,4 @@ def oracle_mod():
 def scene_c1():
     import scenegen
 
-    return scenegen.config_scene("c1", 0)
+    return scenegen.config_scene("128x96_n4", 0)

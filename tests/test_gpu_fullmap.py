@@ -57,8 +57,8 @@ def amh():
 
 
 CASES = {
-    "1920x1280_n10_3it_refine": dict(cfg="c2", seed=0, overrides={}),
-    "800x532_n20_fp16_lowtex_4it_refine": dict(cfg="c3", seed=0, overrides=dict(width=800, height=532)),
+    "1920x1280_n10_3it_refine": dict(cfg="1920x1280_n10", seed=0, overrides={}),
+    "800x532_n20_fp16_lowtex_4it_refine": dict(cfg="3200x2130_n20", seed=0, overrides=dict(width=800, height=532)),
 }
 
 

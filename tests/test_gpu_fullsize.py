@@ -33,7 +33,7 @@ def amh():
     return amh
 
 
-@pytest.fixture(scope="module", params=["c2", "c3"])
+@pytest.fixture(scope="module", params=["1920x1280_n10", "3200x2130_n20"])
 def big_scene(request):
     import scenegen
 
@@ -166,4 +166,4 @@ def test_full_run_properties(amh, big_scene):
     # calibrated once (seed 0): 0.995 at 1920x1280 after 3 iterations; 0.41 at 3200x2130 after 4
     # iterations, where 30 % of the reference is constant-intensity planes and the propagation reach
     # (23 px per half-pass) covers less of the image
-    assert acc >= (0.97 if name == "c2" else 0.38)
+    assert acc >= (0.97 if name == "1920x1280_n10" else 0.38)

@@ -36,8 +36,8 @@ def setup():
     import paper_1805_07920_amd as amh
     import scenegen
 
-    say("rendering c2 seed 1")
-    sc = scenegen.config_scene("c2", 1, device="cuda")
+    say("rendering 1920x1280_n10 seed 1")
+    sc = scenegen.config_scene("1920x1280_n10", 1, device="cuda")
     ang = scenegen.source_angles(len(sc.srcs), sc.meta["arc_deg"])
     srcs = [int(i) + 1 for i in np.argsort(np.abs(ang), kind="stable")]
     ctx = amh.Context(seed=5)

@@ -185,7 +185,7 @@ def test_fusion_fullsize_sampled(amh):
     import scenegen
 
     say("case fusion 1920x1280, 11 views, sampled pixels of the first view")
-    sc = scenegen.config_scene("c2", 1, device="cuda")
+    sc = scenegen.config_scene("1920x1280_n10", 1, device="cuda")
     ctx, depths, normals = method_maps(amh, sc)
     with ctx:
         filt = [ctx.median_filter4(d) for d in depths]

@@ -42,7 +42,7 @@ def test_set_initial_hypotheses_matches_oracle(amh, oracle_mod, scene_c1):
     import torch
     from oracle import proposal
 
-    say("case per-pixel initial hypotheses c1")
+    say("case per-pixel initial hypotheses 128x96_n4")
     sc = scene_c1
     depth, normal, conf = _estimates(sc, 3)
     ctx = amh.Context(seed=13, conf_min=0.5)

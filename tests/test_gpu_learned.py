@@ -53,9 +53,9 @@ def test_learned_proposal_gain():
     import scenegen
 
     assert os.path.exists(WEIGHTS), f"missing trained weights {WEIGHTS}"
-    sc = scenegen.config_scene("c2", 1, device="cuda")
+    sc = scenegen.config_scene("1920x1280_n10", 1, device="cuda")
     srcs = nearest_first(sc)
-    say(f"case learned gain c2 seed 1, sources {srcs}")
+    say(f"case learned gain 1920x1280_n10 seed 1, sources {srcs}")
     res = {}
     with amh.Context(seed=5) as ctx:
         ctx.init_views([torch.from_numpy(np.ascontiguousarray(im)).cuda() for im in sc.images], sc.cams)

@@ -333,7 +333,7 @@ def check_features(f, q, V, P, min_robust=0.9, n_sweep=4):
 
 
 def test_sweep_features_match_oracle(amh, oracle_mod, scene_c1):
-    say("case sweep features c1")
+    say("case sweep features 128x96_n4")
     sc = scene_c1
     with make_ctx(amh, sc) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
@@ -449,7 +449,7 @@ def proposal_maps(sc, seed, h, w):
 
 
 def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
-    say("case init from proposal c1")
+    say("case init from proposal 128x96_n4")
     import torch
     from oracle import proposal
 
@@ -489,7 +489,7 @@ def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
 
 
 def test_run_proposal_equals_its_steps(amh, scene_c1):
-    say("case run_proposal c1")
+    say("case run_proposal 128x96_n4")
     import torch
 
     sc = scene_c1

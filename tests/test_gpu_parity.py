@@ -71,7 +71,7 @@ def make_ctx(amh, sc, **kw):
 
 
 SCENES = {
-    "c1": dict(name="c1", seed=0),
+    "128x96_n4": dict(name="128x96_n4", seed=0),
     "ragged_131x77_n5": dict(w=131, h=77, n=5, arc=20.0, planes=4, seed=7),
     "fp16_96x64_n6": dict(w=96, h=64, n=6, arc=30.0, planes=3, seed=3, src_dtype="f16", low=0.3),
 }
@@ -176,7 +176,7 @@ def _init_cost_bar(O, sc, ost, d, seed):
 
 
 def test_init_matches_oracle(amh, oracle_mod, scene_c1):
-    say("case init c1")
+    say("case init 128x96_n4")
     O = oracle_mod
     sc = scene_c1
     with make_ctx(amh, sc, seed=11) as ctx:
@@ -284,7 +284,7 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
 
 @pytest.mark.parametrize("t,colour,refine", [(0, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (3, 0, 1)])
 def test_single_pass_matches_oracle(amh, oracle_mod, scene_c1, t, colour, refine):
-    say("case pass c1", t, colour, refine)
+    say("case pass 128x96_n4", t, colour, refine)
     _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=3, refine=refine)
 
 
@@ -304,7 +304,7 @@ def test_single_pass_without_self_row(amh, oracle_mod, scene_c1):
 def test_short_evaluation_counters(amh, oracle_mod, scene_c1):
     """evals_init_short / evals_short count the evaluations whose cost was decided before sampling:
     compared with the same predicate evaluated on the planes the oracle's pass actually scores."""
-    say("case short-evaluation counters c1")
+    say("case short-evaluation counters 128x96_n4")
     sc, O = scene_c1, oracle_mod
     Wd, Hd, n = sc.width, sc.height, len(sc.srcs)
     with make_ctx(amh, sc, refine=0, seed=5) as ctx:
@@ -358,7 +358,7 @@ def test_short_evaluation_counters(amh, oracle_mod, scene_c1):
                                                       (0, 1, 1, 0, 1), (1, 1, 3, 1, 1), (2, 0, 0, 0, 1),
                                                       (2, 0, 1, 1, 1), (2, 0, 3, 0, 1), (2, 1, 1, 0, 1)])
 def test_ablation_pass_matches_oracle(amh, oracle_mod, scene_c1, sym, heur, t, colour, refine):
-    say("case ablation pass c1", sym, heur, t, colour, refine)
+    say("case ablation pass 128x96_n4", sym, heur, t, colour, refine)
     _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=6, refine=refine, sym_prop=sym, heuristic=heur)
 
 
@@ -371,7 +371,7 @@ def test_ablation_pass_other_shapes(amh, oracle_mod, key, sym, heur):
 
 @pytest.mark.parametrize("sym,heur", [(1, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
 def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_c1, sym, heur):
-    say("case ablation full run c1", sym, heur)
+    say("case ablation full run 128x96_n4", sym, heur)
     O = oracle_mod
     with make_ctx(amh, scene_c1, refine=1, seed=4, sym_prop=sym, heuristic_views=heur) as ctx:
         ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
@@ -480,7 +480,7 @@ def test_squared_bilateral_full_run_accuracy(amh, oracle_mod, include_self):
     O = oracle_mod
     probe_agree = []
     for seed in (0, 1, 2):
-        sc = scenegen.config_scene("c1", seed)
+        sc = scenegen.config_scene("128x96_n4", seed)
         with make_ctx(amh, sc, refine=1, seed=4, bilateral_squared=1, include_self=include_self) as ctx:
             ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
             depth, _, _ = ctx.get_depth_normal_cost()
@@ -510,7 +510,7 @@ def test_ablation_rejected_by_the_batched_path(amh, scene_c1):
 
 def test_full_run_depth_parity(amh, oracle_mod, scene_c1):
     """3 iterations + refinement: GPU and oracle depth maps agree on >= 99.5 % of pixels (0.1 % relative)."""
-    say("case full run c1")
+    say("case full run 128x96_n4")
     O = oracle_mod
     sc = scene_c1
     with make_ctx(amh, sc, refine=1, seed=4) as ctx:

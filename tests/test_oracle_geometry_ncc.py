@@ -241,7 +241,7 @@ def test_short_predicate_matches_oracle_early_exits():
     import oracle as O
     import scenegen
     from short_predicate import short_mask
-    sc = scenegen.config_scene("c1", seed=0)
+    sc = scenegen.config_scene("128x96_n4", seed=0)
     V = O.Views(sc.images, sc.cams)
     P = O.Params(seed=5, refine=0)
     st = O.init(V, P)

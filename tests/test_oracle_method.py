@@ -38,7 +38,7 @@ def test_half_pass_order_independent(oracle_mod, scene_c1):
 def test_recovers_rendered_depth(oracle_mod, seed, frac_1pct):
     import scenegen
 
-    sc = scenegen.config_scene("c1", seed)
+    sc = scenegen.config_scene("128x96_n4", seed)
     O = oracle_mod
     V = O.Views.from_scene(sc)
     st = O.run(V, O.Params(refine=1), 3)
