@@ -22,7 +22,7 @@ def oracle_mod():
 
 
 @pytest.fixture(scope="session")
-def scene_c1():
+def scene_128x96():
     import scenegen
 
     return scenegen.config_scene("128x96_n4", 0)

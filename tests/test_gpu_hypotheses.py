@@ -38,12 +38,12 @@ def _estimates(sc, seed):
     return depth, normal, conf
 
 
-def test_set_initial_hypotheses_matches_oracle(amh, oracle_mod, scene_c1):
+def test_set_initial_hypotheses_matches_oracle(amh, oracle_mod, scene_128x96):
     import torch
     from oracle import proposal
 
     say("case per-pixel initial hypotheses 128x96_n4")
-    sc = scene_c1
+    sc = scene_128x96
     depth, normal, conf = _estimates(sc, 3)
     ctx = amh.Context(seed=13, conf_min=0.5)
     ctx.init_views([np.ascontiguousarray(im) for im in sc.images], sc.cams)
@@ -83,10 +83,10 @@ def test_set_initial_hypotheses_matches_oracle(amh, oracle_mod, scene_c1):
     assert all_fb < fallbacks
 
 
-def test_one_iteration_from_near_truth(amh, scene_c1):
+def test_one_iteration_from_near_truth(amh, scene_128x96):
     """From estimates within 0.5 % of the rendered depth, one iteration keeps the depth map that accurate."""
     say("case one iteration from near-truth hypotheses")
-    sc = scene_c1
+    sc = scene_128x96
     depth, normal, _ = _estimates(sc, 4)
     with amh.Context(seed=2, refine=1) as ctx:
         ctx.init_views([np.ascontiguousarray(im) for im in sc.images], sc.cams)

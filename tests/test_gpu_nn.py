@@ -332,9 +332,9 @@ def check_features(f, q, V, P, min_robust=0.9, n_sweep=4):
     assert robust >= min_robust * fo.shape[0] * fo.shape[1]
 
 
-def test_sweep_features_match_oracle(amh, oracle_mod, scene_c1):
+def test_sweep_features_match_oracle(amh, oracle_mod, scene_128x96):
     say("case sweep features 128x96_n4")
-    sc = scene_c1
+    sc = scene_128x96
     with make_ctx(amh, sc) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
         fd, qd = ctx.sweep_features()
@@ -448,12 +448,12 @@ def proposal_maps(sc, seed, h, w):
     return pred
 
 
-def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
+def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_128x96):
     say("case init from proposal 128x96_n4")
     import torch
     from oracle import proposal
 
-    sc = scene_c1
+    sc = scene_128x96
     pred = proposal_maps(sc, 4, 24, 32)
     with make_ctx(amh, sc, seed=13, conf_min=0.5) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
@@ -488,11 +488,11 @@ def test_init_from_proposal_matches_oracle(amh, oracle_mod, scene_c1):
     assert abs(int(fallbacks) - int((~used).sum())) <= int(near.sum())
 
 
-def test_run_proposal_equals_its_steps(amh, scene_c1):
+def test_run_proposal_equals_its_steps(amh, scene_128x96):
     say("case run_proposal 128x96_n4")
     import torch
 
-    sc = scene_c1
+    sc = scene_128x96
     srcs = [1, 2, 3, 4]
     with make_ctx(amh, sc, seed=2) as ctx:
         with pytest.raises(amh.AmhError) as e:

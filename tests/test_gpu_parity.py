@@ -129,12 +129,12 @@ def _centre_in_source(sc, xy, planes):
     return np.stack(out, axis=1)
 
 
-def test_score_fixed_windows_crossing_source_edges(amh, oracle_mod, scene_c1):
+def test_score_fixed_windows_crossing_source_edges(amh, oracle_mod, scene_128x96):
     """Windows whose centre lies within 6 px inside a source's edge read texels beyond it: through the
     gather layout's clamped border (up to 16 texels) or the clamped path.  Their costs must equal the
     oracle's, which clamps every texel index."""
     say("case score_fixed near source edges")
-    sc, O = scene_c1, oracle_mod
+    sc, O = scene_128x96, oracle_mod
     rng = np.random.default_rng(4)
     W, H, n = sc.width, sc.height, len(sc.srcs)
     pix = [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(4000)]
@@ -175,10 +175,10 @@ def _init_cost_bar(O, sc, ost, d, seed):
     assert unsure.mean() <= 1e-3
 
 
-def test_init_matches_oracle(amh, oracle_mod, scene_c1):
+def test_init_matches_oracle(amh, oracle_mod, scene_128x96):
     say("case init 128x96_n4")
     O = oracle_mod
-    sc = scene_c1
+    sc = scene_128x96
     with make_ctx(amh, sc, seed=11) as ctx:
         ctx.begin(0, [1, 2, 3, 4])
         ctx.init_hypotheses()
@@ -283,9 +283,9 @@ def _pass_parity(amh, O, sc, t, colour, seed, refine, n_src=None, include_self=1
 
 
 @pytest.mark.parametrize("t,colour,refine", [(0, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (3, 0, 1)])
-def test_single_pass_matches_oracle(amh, oracle_mod, scene_c1, t, colour, refine):
+def test_single_pass_matches_oracle(amh, oracle_mod, scene_128x96, t, colour, refine):
     say("case pass 128x96_n4", t, colour, refine)
-    _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=3, refine=refine)
+    _pass_parity(amh, oracle_mod, scene_128x96, t, colour, seed=3, refine=refine)
 
 
 @pytest.mark.parametrize("key", ["ragged_131x77_n5", "fp16_96x64_n6"])
@@ -295,17 +295,17 @@ def test_single_pass_other_shapes(amh, oracle_mod, key):
     _pass_parity(amh, oracle_mod, sc, 1, 0, seed=8, refine=1)
 
 
-def test_single_pass_without_self_row(amh, oracle_mod, scene_c1):
+def test_single_pass_without_self_row(amh, oracle_mod, scene_128x96):
     say("case pass include_self=0")
-    _pass_parity(amh, oracle_mod, scene_c1, 0, 0, seed=2, refine=0, include_self=0)
+    _pass_parity(amh, oracle_mod, scene_128x96, 0, 0, seed=2, refine=0, include_self=0)
 
 
 
-def test_short_evaluation_counters(amh, oracle_mod, scene_c1):
+def test_short_evaluation_counters(amh, oracle_mod, scene_128x96):
     """evals_init_short / evals_short count the evaluations whose cost was decided before sampling:
     compared with the same predicate evaluated on the planes the oracle's pass actually scores."""
     say("case short-evaluation counters 128x96_n4")
-    sc, O = scene_c1, oracle_mod
+    sc, O = scene_128x96, oracle_mod
     Wd, Hd, n = sc.width, sc.height, len(sc.srcs)
     with make_ctx(amh, sc, refine=0, seed=5) as ctx:
         ctx.begin(0, list(range(1, n + 1)))
@@ -357,9 +357,9 @@ def test_short_evaluation_counters(amh, oracle_mod, scene_c1):
 @pytest.mark.parametrize("sym,heur,t,colour,refine", [(1, 0, 0, 0, 1), (1, 0, 1, 1, 1), (0, 1, 0, 1, 0),
                                                       (0, 1, 1, 0, 1), (1, 1, 3, 1, 1), (2, 0, 0, 0, 1),
                                                       (2, 0, 1, 1, 1), (2, 0, 3, 0, 1), (2, 1, 1, 0, 1)])
-def test_ablation_pass_matches_oracle(amh, oracle_mod, scene_c1, sym, heur, t, colour, refine):
+def test_ablation_pass_matches_oracle(amh, oracle_mod, scene_128x96, sym, heur, t, colour, refine):
     say("case ablation pass 128x96_n4", sym, heur, t, colour, refine)
-    _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=6, refine=refine, sym_prop=sym, heuristic=heur)
+    _pass_parity(amh, oracle_mod, scene_128x96, t, colour, seed=6, refine=refine, sym_prop=sym, heuristic=heur)
 
 
 @pytest.mark.parametrize("key,sym,heur", [("ragged_131x77_n5", 1, 1), ("fp16_96x64_n6", 0, 1),
@@ -370,14 +370,14 @@ def test_ablation_pass_other_shapes(amh, oracle_mod, key, sym, heur):
 
 
 @pytest.mark.parametrize("sym,heur", [(1, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
-def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_c1, sym, heur):
+def test_ablation_full_run_depth_parity(amh, oracle_mod, scene_128x96, sym, heur):
     say("case ablation full run 128x96_n4", sym, heur)
     O = oracle_mod
-    with make_ctx(amh, scene_c1, refine=1, seed=4, sym_prop=sym, heuristic_views=heur) as ctx:
+    with make_ctx(amh, scene_128x96, refine=1, seed=4, sym_prop=sym, heuristic_views=heur) as ctx:
         ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
         depth, _, _ = ctx.get_depth_normal_cost()
         _, _, S, v = ctx.get_state()
-    V = O.Views.from_scene(scene_c1)
+    V = O.Views.from_scene(scene_128x96)
     st = O.run(V, O.Params(refine=1, seed=4, prop_mode=sym, view_mode=2 if heur else 0), 3)
     od, _ = O.depth_normal(V, st)
     frac = (np.abs(depth - od) / od <= 1e-3).mean()
@@ -440,14 +440,14 @@ def test_score_fixed_squared_weights(amh, oracle_mod, key):
 
 
 @pytest.mark.parametrize("t,colour,include_self", [(0, 0, 1), (1, 1, 0)])
-def test_squared_bilateral_pass_matches_oracle(amh, oracle_mod, scene_c1, t, colour, include_self):
+def test_squared_bilateral_pass_matches_oracle(amh, oracle_mod, scene_128x96, t, colour, include_self):
     """One half-pass with squared weights: a decision must clear the cost bar itself (1e-4) to count as robust;
     on robust pixels exact agreement and the 1e-4 cost bar hold.  Over all pixels the GPU keeps the oracle's
     plane at least as often as the oracle with costs moved within the bar does (cost_noise), less 0.5 %."""
     say("case pass squared bilateral", t, colour, include_self)
-    _, _, gpu_keeps = _pass_parity(amh, oracle_mod, scene_c1, t, colour, seed=9, refine=1,
+    _, _, gpu_keeps = _pass_parity(amh, oracle_mod, scene_128x96, t, colour, seed=9, refine=1,
                                    include_self=include_self, bil_sq=1, delta=1e-4, ctol=1e-4, min_plane=0.0)
-    O, sc = oracle_mod, scene_c1
+    O, sc = oracle_mod, scene_128x96
     V = O.Views.from_scene(sc)
     P = O.Params(refine=1, seed=9, include_self=include_self, bilateral_sq=1)
     Pn = O.Params(refine=1, seed=9, include_self=include_self, bilateral_sq=1, cost_noise=NOISE_AT_BAR)
@@ -501,18 +501,18 @@ def test_squared_bilateral_full_run_accuracy(amh, oracle_mod, include_self):
     assert min(probe_agree) < 0.995  # the premise
 
 
-def test_ablation_rejected_by_the_batched_path(amh, scene_c1):
+def test_ablation_rejected_by_the_batched_path(amh, scene_128x96):
     say("case ablation batch rejected")
-    with make_ctx(amh, scene_c1, sym_prop=1) as ctx:
+    with make_ctx(amh, scene_128x96, sym_prop=1) as ctx:
         with pytest.raises(amh.AmhError) as e:
             ctx.run_batch([dict(ref=0, srcs=[1, 2, 3, 4], iters=1)])
         assert e.value.status == amh.AMH_E_UNSUPPORTED
 
-def test_full_run_depth_parity(amh, oracle_mod, scene_c1):
+def test_full_run_depth_parity(amh, oracle_mod, scene_128x96):
     """3 iterations + refinement: GPU and oracle depth maps agree on >= 99.5 % of pixels (0.1 % relative)."""
     say("case full run 128x96_n4")
     O = oracle_mod
-    sc = scene_c1
+    sc = scene_128x96
     with make_ctx(amh, sc, refine=1, seed=4) as ctx:
         ctx.run_checkerboard(0, [1, 2, 3, 4], 3)
         depth, normal, cost = ctx.get_depth_normal_cost()
@@ -529,9 +529,9 @@ def test_full_run_depth_parity(amh, oracle_mod, scene_c1):
     assert stats["evals_propagation"] > 0 and stats["evals_refine"] > 0
 
 
-def test_run_is_deterministic_and_composes(amh, scene_c1):
+def test_run_is_deterministic_and_composes(amh, scene_128x96):
     say("case determinism")
-    sc = scene_c1
+    sc = scene_128x96
     outs = []
     for mode in range(3):
         with make_ctx(amh, sc, refine=1, seed=9) as ctx:
@@ -580,9 +580,9 @@ def test_many_sources(amh, oracle_mod):
     _pass_parity(amh, oracle_mod, sc, 1, 0, seed=5, refine=1)
 
 
-def test_errors_on_device(amh, scene_c1):
+def test_errors_on_device(amh, scene_128x96):
     say("case errors")
-    sc = scene_c1
+    sc = scene_128x96
     ctx = amh.Context()
     with pytest.raises(amh.AmhError) as e:
         ctx.begin(0, [1])

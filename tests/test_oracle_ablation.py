@@ -93,9 +93,9 @@ def _diag_pass(oracle_mod, scene, **kw):
     return V, P, before, st, order, dg
 
 
-def test_symmetric_rows_are_the_fixed_neighbours(oracle_mod, scene_c1):
+def test_symmetric_rows_are_the_fixed_neighbours(oracle_mod, scene_128x96):
     O = oracle_mod
-    V, P, before, st, order, dg = _diag_pass(O, scene_c1, refine=0, prop_mode=1, seed=3)
+    V, P, before, st, order, dg = _diag_pass(O, scene_128x96, refine=0, prop_mode=1, seed=3)
     dx, dy, _ = O.scp_offsets()
     N = V.n_src
     rng = np.random.default_rng(0)
@@ -117,9 +117,9 @@ def test_symmetric_rows_are_the_fixed_neighbours(oracle_mod, scene_c1):
 
 
 @pytest.mark.parametrize("k", [1, 2, 4])
-def test_heuristic_cost_is_mean_of_k_lowest(oracle_mod, scene_c1, k):
+def test_heuristic_cost_is_mean_of_k_lowest(oracle_mod, scene_128x96, k):
     O = oracle_mod
-    V, P, before, st, order, dg = _diag_pass(O, scene_c1, refine=1, view_mode=2, k=k, seed=4)
+    V, P, before, st, order, dg = _diag_pass(O, scene_128x96, refine=1, view_mode=2, k=k, seed=4)
     N = V.n_src
     for q, idx in enumerate(order[:300]):
         d = dg[q]
@@ -141,11 +141,11 @@ def test_heuristic_cost_is_mean_of_k_lowest(oracle_mod, scene_c1, k):
     assert np.all(st.S == 0) and np.all(st.v == -1)
 
 
-def test_heuristic_with_k_at_least_n_is_the_plain_mean(oracle_mod, scene_c1):
+def test_heuristic_with_k_at_least_n_is_the_plain_mean(oracle_mod, scene_128x96):
     O = oracle_mod
-    N = len(scene_c1.srcs)
-    a = _diag_pass(O, scene_c1, refine=1, view_mode=2, k=N + 3, seed=5)
-    b = _diag_pass(O, scene_c1, refine=1, view_mode=1, k=N + 3, seed=5)
+    N = len(scene_128x96.srcs)
+    a = _diag_pass(O, scene_128x96, refine=1, view_mode=2, k=N + 3, seed=5)
+    b = _diag_pass(O, scene_128x96, refine=1, view_mode=1, k=N + 3, seed=5)
     for q in range(len(a[4])):
         for r in range(9):
             assert a[5][q].mfinal[r] == pytest.approx(b[5][q].mfinal[r], rel=1e-13)
@@ -175,9 +175,9 @@ def test_standard_symmetric_reach_is_its_neighbour_set(oracle_mod, view_mode):
     assert got == set(zip(dx.tolist(), dy.tolist()))
 
 
-def test_standard_symmetric_rows_and_selection(oracle_mod, scene_c1):
+def test_standard_symmetric_rows_and_selection(oracle_mod, scene_128x96):
     O = oracle_mod
-    V, P, before, st, order, dg = _diag_pass(O, scene_c1, refine=1, prop_mode=2, seed=3)
+    V, P, before, st, order, dg = _diag_pass(O, scene_128x96, refine=1, prop_mode=2, seed=3)
     dx, dy, _ = O.sscp_offsets()
     N = V.n_src
     rng = np.random.default_rng(1)

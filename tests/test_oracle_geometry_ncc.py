@@ -62,9 +62,9 @@ def test_warp_matches_closed_form_homography(oracle_mod):
             np.testing.assert_allclose(o[:2] / o[2], h[:2] / h[2], rtol=1e-9, atol=1e-9)
 
 
-def test_warp_agrees_with_rendered_views(oracle_mod, scene_c1):
+def test_warp_agrees_with_rendered_views(oracle_mod, scene_128x96):
     """Ground-truth planes warp reference pixels onto matching source intensities."""
-    O, sc = oracle_mod, scene_c1
+    O, sc = oracle_mod, scene_128x96
     V = O.Views.from_scene(sc)
     Kinv = np.linalg.inv(sc.cams[0].K)
     rng = np.random.default_rng(0)
@@ -257,7 +257,7 @@ def test_short_predicate_matches_oracle_early_exits():
             assert (c == 2.0) == bool(m[i, j]), (xy[i], j, c)
 
 
-def test_sample_f32_probe_only_rounds_positions_and_samples(oracle_mod, scene_c1):
+def test_sample_f32_probe_only_rounds_positions_and_samples(oracle_mod, scene_128x96):
     """The conditioning probe (sample_f32 = 1) changes nothing but the precision of the samples' source
     positions (relative to the centre's texel) and interpolated values: where every sample lands on a texel
     (integer disparity) both are float32 numbers already and the cost is unchanged; elsewhere it moves by no
@@ -276,7 +276,7 @@ def test_sample_f32_probe_only_rounds_positions_and_samples(oracle_mod, scene_c1
         # (the warped positions are texel centres up to double rounding)
         assert oracle_mod.matching_cost(V, P1, x, y, exact, 0) == pytest.approx(
             oracle_mod.matching_cost(V, P0, x, y, exact, 0), abs=1e-12)
-    V = oracle_mod.Views.from_scene(scene_c1)
+    V = oracle_mod.Views.from_scene(scene_128x96)
     diffs = []
     for _ in range(300):
         x, y = int(rng.integers(0, V.W)), int(rng.integers(0, V.H))
@@ -289,7 +289,7 @@ def test_sample_f32_probe_only_rounds_positions_and_samples(oracle_mod, scene_c1
     assert diffs.max() <= 1e-4 and diffs.max() > 0.0
 
 
-def test_sample_f32_probe_level_two_rounds_the_moments(oracle_mod, scene_c1):
+def test_sample_f32_probe_level_two_rounds_the_moments(oracle_mod, scene_128x96):
     """Level 2 of the probe also forms the weights' sums and the NCC's moments in float32.  On samples that
     land on texels (nothing for level 1 to round) it moves the cost by float32 rounding of the moments only
     (< 1e-5, and it does move); a constant source window stays at cost 2 (zero variance is exact in float32
@@ -314,7 +314,7 @@ def test_sample_f32_probe_level_two_rounds_the_moments(oracle_mod, scene_c1):
     flat = O.Views([ref, np.full_like(ref, 77.0)], [cam(K, np.eye(3), np.zeros(3), W, H),
                                                    cam(K, np.eye(3), [-B, 0, 0], W, H)])
     assert O.matching_cost(flat, P2, 30, 20, exact, 0) == 2.0
-    V = O.Views.from_scene(scene_c1)
+    V = O.Views.from_scene(scene_128x96)
     d1, d0 = [], []
     for _ in range(200):
         x, y = int(rng.integers(0, V.W)), int(rng.integers(0, V.H))
@@ -327,13 +327,13 @@ def test_sample_f32_probe_level_two_rounds_the_moments(oracle_mod, scene_c1):
     assert max(d1) <= 1e-4 and max(d0) <= 1e-4 and max(d1) > 0.0
 
 
-def test_sample_f32_probe_level_three_is_the_first_order_worst_case(oracle_mod, scene_c1):
+def test_sample_f32_probe_level_three_is_the_first_order_worst_case(oracle_mod, scene_128x96):
     """Level 3 moves every sample value by the first-order bound of rounding its position and value to float32,
     in the direction that moves the cost towards 1: the cost moves towards 1 (never away, never past it), by
     no more than 1e-4 with the printed weights, and by at least what the actual rounding (level 1) moves it in
     nearly every case -- a worst case bounds the actual rounding to first order."""
     O = oracle_mod
-    V = O.Views.from_scene(scene_c1)
+    V = O.Views.from_scene(scene_128x96)
     P0, P1, P3 = O.Params(), O.Params(sample_f32=1), O.Params(sample_f32=3)
     rng = np.random.default_rng(13)
     d1, d3 = [], []
@@ -356,11 +356,11 @@ def test_sample_f32_probe_level_three_is_the_first_order_worst_case(oracle_mod, 
     assert np.mean(d3 >= d1) >= 0.9
 
 
-def test_cost_noise_probe_is_bounded_deterministic_and_centred(oracle_mod, scene_c1):
+def test_cost_noise_probe_is_bounded_deterministic_and_centred(oracle_mod, scene_128x96):
     """The second conditioning probe (cost_noise = e) moves every scored cost by a fixed offset in
     [-e/2, e/2) that depends only on (pixel, view, plane); cost 2 and the clamp are untouched."""
     O = oracle_mod
-    V = O.Views.from_scene(scene_c1)
+    V = O.Views.from_scene(scene_128x96)
     P0, P1 = O.Params(), O.Params(cost_noise=2e-4)
     rng = np.random.default_rng(3)
     d = []

@@ -15,9 +15,9 @@ import numpy as np
 import pytest
 
 
-def test_half_pass_order_independent(oracle_mod, scene_c1):
+def test_half_pass_order_independent(oracle_mod, scene_128x96):
     O = oracle_mod
-    V = O.Views.from_scene(scene_c1)
+    V = O.Views.from_scene(scene_128x96)
     P = O.Params(refine=1, seed=9)
     base = O.init(V, P)
     for t, colour in [(0, 0), (3, 1)]:

@@ -272,10 +272,10 @@ def test_sweep_features_find_the_true_depth(oracle_mod, W, fine):
     assert Fm[3, 5, 1] == pytest.approx(np.sqrt(((blk - blk.mean()) ** 2).mean()) / 32, rel=1e-12)
 
 
-def test_proposal_low_confidence_is_random_init(oracle_mod, scene_c1):
+def test_proposal_low_confidence_is_random_init(oracle_mod, scene_128x96):
     from oracle import proposal
 
-    sc = scene_c1
+    sc = scene_128x96
     img = [im[:32, :48] for im in sc.images]
     V = oracle_mod.Views(img, sc.cams)
     P = oracle_mod.Params(seed=3)

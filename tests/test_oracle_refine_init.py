@@ -48,8 +48,8 @@ def cheb_residual(a, b):
 
 
 @pytest.fixture(scope="module")
-def views(oracle_mod, scene_c1):
-    return oracle_mod.Views.from_scene(scene_c1)
+def views(oracle_mod, scene_128x96):
+    return oracle_mod.Views.from_scene(scene_128x96)
 
 
 def test_random_planes_are_uniform_and_face_the_camera(oracle_mod, views):
@@ -82,8 +82,8 @@ def test_random_planes_are_uniform_and_face_the_camera(oracle_mod, views):
 
 
 @pytest.mark.parametrize("k,n_src", [(4, 4), (2, 4), (1, 4), (4, 2), (3, 3)])
-def test_initial_cost_is_mean_of_k_lowest(oracle_mod, scene_c1, k, n_src):
-    O, sc = oracle_mod, scene_c1
+def test_initial_cost_is_mean_of_k_lowest(oracle_mod, scene_128x96, k, n_src):
+    O, sc = oracle_mod, scene_128x96
     V = O.Views(sc.images[: n_src + 1], sc.cams[: n_src + 1])
     P = O.Params(seed=5, k=k)
     st = O.init(V, P)
@@ -124,9 +124,9 @@ def _current_plane(d, pre, x, y, odx, ody):
 
 
 @pytest.mark.parametrize("t", [0, 1, 2, 3, 4])
-def test_refinement_candidates(oracle_mod, scene_c1, t):
+def test_refinement_candidates(oracle_mod, scene_128x96, t):
     O = oracle_mod
-    V, P, pre, st, order, dg = _refined_pass(O, scene_c1, t, seed=7 + t)
+    V, P, pre, st, order, dg = _refined_pass(O, scene_128x96, t, seed=7 + t)
     odx, ody, _ = O.acp_offsets()
     Kinv = np.linalg.inv(np.array(V.c.Kref[:]).reshape(3, 3))
     rho = 2.0 ** -(t + 2)
@@ -204,13 +204,13 @@ def test_refinement_candidates(oracle_mod, scene_c1, t):
         assert abs(np.corrcoef(pairs[ok], drnd[ok])[0, 1]) < 0.1
 
 
-def test_refinement_keeps_the_plane_on_exact_ties(oracle_mod, scene_c1):
+def test_refinement_keeps_the_plane_on_exact_ties(oracle_mod, scene_128x96):
     """A source that sees nothing (turned away from the scene): every cost is 2, the joint selection
     is empty and falls back to uniform weights, every row and candidate costs exactly 2, so the own
     plane stays (ties keep it) and no candidate is accepted (strictly lower only)."""
     import dataclasses
 
-    O, sc = oracle_mod, scene_c1
+    O, sc = oracle_mod, scene_128x96
     # the reference camera is the world frame; a source at its centre looking down -z sees every point
     # in front of the reference behind itself
     assert np.allclose(sc.cams[0].R, np.eye(3)) and np.allclose(sc.cams[0].t, 0.0)
@@ -231,13 +231,13 @@ def test_refinement_keeps_the_plane_on_exact_ties(oracle_mod, scene_c1):
         assert np.all(st.cost == 2.0)
 
 
-def test_per_pixel_hypotheses_pass_through_their_point(oracle_mod, scene_c1):
+def test_per_pixel_hypotheses_pass_through_their_point(oracle_mod, scene_128x96):
     """Initial hypotheses from per-pixel estimates (cells of one pixel): a confident, in-range pixel's plane
     passes through the point at its depth on its own ray with its normal (unit, facing the camera); the
     others keep the random plane; the cost is the initial cost of that plane."""
     from oracle import proposal
 
-    O, sc = oracle_mod, scene_c1
+    O, sc = oracle_mod, scene_128x96
     V = O.Views.from_scene(sc)
     P = O.Params(seed=4)
     H, W = sc.height, sc.width

@@ -106,10 +106,10 @@ def test_invalid_rows_excluded(oracle_mod):
     assert S == 0  # the three cost-2 rows now count: 3 > tau_up is not fewer than n2
 
 
-def test_unified_cost_is_weighted_mean(oracle_mod, scene_c1):
+def test_unified_cost_is_weighted_mean(oracle_mod, scene_128x96):
     """Eq. 7 on a real pixel: the kept cost equals sum_j w_j m_ij / sum_j w_j of the chosen row."""
     O = oracle_mod
-    V = O.Views.from_scene(scene_c1)
+    V = O.Views.from_scene(scene_128x96)
     P = O.Params(refine=0)
     st = O.init(V, P)
     order = np.array([y * V.W + x for y in range(20, 40) for x in range(20, 60) if (x + y) % 2 == 0], np.int32)
