@@ -48,10 +48,12 @@ VALU_PEAK_OPS = 256 * 128 * 2.4e9
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean of the 6 half-passes of one depth map) scaled by
 # what the same counters read for a plain 256 MiB copy (bench.py --calibrate-copy: FETCH_SIZE 131080 KiB
 # for 262144 KiB read -> x2.0, WRITE_SIZE 262144 KiB for 262144 KiB written -> x1.0); summary in
-# profiles/pass_kernel_1920x1280_n10_traffic.md.  Per tile shape (rows per workgroup) of the variant the
-# autotuner picks, and valid only for the kernel source they were taken on.
-PASS_TRAFFIC = {"by_tile_rows": {2: {"fetch_kib": 457461.3, "write_kib": 85930.2},
-                                 4: {"fetch_kib": 362159.1, "write_kib": 83631.9}},
+# profiles/pass_kernel_1920x1280_n10_traffic.md and pass_kernel_3200x2130_n20_fp16_traffic.md.  Per workload
+# and tile shape (rows per workgroup) of the variant the autotuner picks, and valid only for the kernel source
+# they were taken on.
+PASS_TRAFFIC = {"by_workload": {"1920x1280_n10": {2: {"fetch_kib": 457461.3, "write_kib": 85930.2},
+                                                  4: {"fetch_kib": 362159.1, "write_kib": 83631.9}},
+                                "3200x2130_n20": {4: {"fetch_kib": 2483597.6, "write_kib": 245938.3}}},
                 "fetch_scale": 2.0, "write_scale": 1.0,
                 "kernel_sha256": "bb7640629711bb6e1a069340a8003260f0c3a8f2727a83e938d17953ed3682be"}
 
@@ -74,16 +76,16 @@ def fuse_traffic_bytes():
                      + FUSE_TRAFFIC["write_kib"] * FUSE_TRAFFIC["write_scale"])
 
 
-def pass_traffic_bytes(tile_rows: int):
-    """HBM-side bytes per half-pass launch of the variant with `tile_rows` rows per workgroup, or None
-    when not measured for it or once the kernel source has changed since the counters."""
+def pass_traffic_bytes(workload: str, tile_rows: int):
+    """HBM-side bytes per half-pass launch on `workload` of the variant with `tile_rows` rows per workgroup,
+    or None when not measured for it or once the kernel source has changed since the counters."""
     import hashlib
 
     src = os.path.join(ROOT, "paper_1805_07920_amd", "csrc", "amh_kernels.hip")
     with open(src, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != PASS_TRAFFIC["kernel_sha256"]:
             return None
-    c = PASS_TRAFFIC["by_tile_rows"].get(tile_rows)
+    c = PASS_TRAFFIC["by_workload"].get(workload, {}).get(tile_rows)
     if c is None:
         return None
     return 1024.0 * (c["fetch_kib"] * PASS_TRAFFIC["fetch_scale"] + c["write_kib"] * PASS_TRAFFIC["write_scale"])
@@ -804,8 +806,8 @@ def main():
                      "peak_basis": "fp32 lane-operations: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (157.3 TFLOP/s, "
                                    "FMA = 2 flops); unpacked v_add_f32 reaches 91 %, v_fma_f32 72 % "
                                    "(bench.py --calibrate-valu)",
-                     # the counters were taken on the 1920x1280 workload only
-                     "traffic": pass_traffic_bytes(2 if best_cfg & 4 else 4) if args.config == "1920x1280_n10" else None,
+                     # counters taken per workload and tile shape; null for a shape not measured
+                     "traffic": pass_traffic_bytes(args.config, 2 if best_cfg & 4 else 4),
                      "traffic_unit": "bytes per launch (L2 <-> memory, calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "kernel": f"pass_kernel<{1 if store == amh.AMH_F16 else 0}, {2 if best_cfg & 4 else 4}> "
                                f"(fused checkerboard half-pass, {2 if best_cfg & 4 else 4}-row tiles)",
