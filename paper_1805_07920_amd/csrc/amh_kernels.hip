@@ -1359,32 +1359,23 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                           : plane_from(rr, kind == 1 ? dcur : dnew, qx, qy, qz);
         }
         __syncthreads();
-        // The (candidate, active view) pairs of the wave's 7 pixels, numbered pixel by pixel, spread over
-        // all 64 lanes (pixels with more active views no longer hold the wave for extra rounds); results go
-        // to the pixel's area of the cost-matrix LDS (7 * 6N <= 64N).
-        float *resw = S.ms + wave * N * 64;
-        int start[kGroups + 1];
-        start[0] = 0;
-#pragma unroll
-        for (int h = 0; h < kGroups; ++h)
-            start[h + 1] = start[h] + ncand * __builtin_amdgcn_readfirstlane(S.gnw[wave * 8 + h]);
-        const int yrow = __builtin_amdgcn_readfirstlane(y);
-        for (int qi = lane; qi < start[kGroups]; qi += 64) {
-            int h = 0;
-#pragma unroll
-            for (int k = 1; k < kGroups; ++k) h += qi >= start[k];
-            const int base = wave * kGroups + h;
-            const int nwh = S.gnw[wave * 8 + h];
-            const int loc = qi - start[h];
+        // The (candidate, active view) pairs of a wave's 7 pixels, numbered pixel by pixel, spread over all 64
+        // lanes (pixels with more active views no longer hold the wave for extra rounds); results go to the
+        // pixel's area of its wave's cost-matrix LDS (7 * 6N <= 64N).  Each wave runs its own full rounds of
+        // 64; the pairs of the waves' last, partial rounds are pooled over the workgroup and taken 64 at a
+        // time, wave w taking the w-th chunk, so that the partial rounds do not each cost a whole round.
+        const auto ref_pair = [&](int w2, int h, int loc, int yrow) {
+            const int base = w2 * kGroups + h;
+            const int nwh = S.gnw[w2 * 8 + h];
             const int c = loc / nwh;
             const int j = S.act[base * kMaxSrc + (loc - c * nwh)];
             const float4 cp = S.cand[base * 6 + c];
-            const float2 wsh = S.gws[wave * 8 + h];
+            const float2 wsh = S.gws[w2 * 8 + h];
             const WinStats wsv = {wsh.x, wsh.y};
             const int xh = 2 * (tx * kTilePix + h) + ((yrow + a.colour) & 1);
             // only the weight and the destination stay live across the evaluation
             const float wj = S.wgt[base * kMaxSrc + j];
-            float *dst = resw + (h * (6 * N) + loc);
+            float *dst = S.ms + w2 * N * 64 + (h * (6 * N) + loc);
             const PlaneQ cq = plane_q(a.ref, m, cp, xh, yrow);
             // kShort stays in the stored product (wgt > 0 on active views): counted after the loop
             const float cost = cq.ok ? ncc_cost_raw<HALF>(a.views[j], S.rw + base * kWinStride, wsv, xh, yrow, cq.q0,
@@ -1392,13 +1383,59 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                                      : kShort;
             *dst = wj * cost;
             ++n_ref;
+        };
+        // pair counts of every wave's pixels (wave-uniform), and the pool of the waves' partial rounds
+        int tot[WAVES], pool[WAVES + 1];
+        pool[0] = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < WAVES; ++w2) {
+            int acc = 0;
+#pragma unroll
+            for (int h = 0; h < kGroups; ++h) acc += ncand * __builtin_amdgcn_readfirstlane(S.gnw[w2 * 8 + h]);
+            tot[w2] = acc;
+            pool[w2 + 1] = pool[w2] + (acc & 63);
+        }
+        int own_full = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < WAVES; ++w2)
+            if (w2 == wave) own_full = tot[w2] >> 6;
+        // rounds of this wave: its own full rounds, then pool chunks wave, wave + WAVES, ...
+        const int nchunks = (pool[WAVES] + 63) >> 6;
+        const int rounds = own_full + (nchunks > wave ? (nchunks - wave + WAVES - 1) / WAVES : 0);
+        for (int rd = 0; rd < rounds; ++rd) {
+            int w2 = wave, qi = rd * 64 + lane;
+            if (rd >= own_full) {
+                // pair pi of the pool belongs to wave w2, at its index (full rounds of w2) + (pi - pool[w2])
+                const int pi = (wave + (rd - own_full) * WAVES) * 64 + lane;
+                if (pi >= pool[WAVES]) continue;
+                int first = 0, fullw = 0;
+#pragma unroll
+                for (int k = 0; k < WAVES; ++k)
+                    if (pi >= pool[k]) {
+                        w2 = k;
+                        first = pool[k];
+                        fullw = tot[k] & ~63;
+                    }
+                qi = fullw + (pi - first);
+            }
+            // the pixel h of wave w2 whose pairs hold index qi, and the pair's index within the pixel
+            int h = 0, hs = 0, acc = 0;
+#pragma unroll
+            for (int k = 0; k < kGroups; ++k) {
+                acc += ncand * S.gnw[w2 * 8 + k];
+                if (qi >= acc) {
+                    h = k + 1;
+                    hs = acc;
+                }
+            }
+            ref_pair(w2, h, qi - hs, y0 + w2);
         }
         __syncthreads();
         if (pix_ok) {
             bcost = S.mf[bslot];
             const int nw = S.gnw[wave * 8 + g];
             const int pairs = ncand * nw;
-            const float *res = resw + g * (6 * N);
+            const float *res = S.ms + wave * N * 64 + g * (6 * N);
             if (row == 0) {
                 unsigned ns = 0;
                 for (int i = 0; i < pairs; ++i) ns += res[i] < 0.f;
