@@ -1361,9 +1361,9 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
         __syncthreads();
         // The (candidate, active view) pairs of a wave's 7 pixels, numbered pixel by pixel, spread over all 64
         // lanes (pixels with more active views no longer hold the wave for extra rounds); results go to the
-        // pixel's area of its wave's cost-matrix LDS (7 * 6N <= 64N).  Each wave runs its own full rounds of
-        // 64; the pairs of the waves' last, partial rounds are pooled over the workgroup and taken 64 at a
-        // time, wave w taking the w-th chunk, so that the partial rounds do not each cost a whole round.
+        // pixel's area of its wave's cost-matrix LDS (7 * 6N <= 64N).  Float32 sources: each wave runs its own
+        // full rounds of 64; the pairs of the waves' last, partial rounds are pooled over the workgroup and
+        // taken 64 at a time, wave w taking the w-th chunk, so that the partial rounds do not each cost a round.
         const auto ref_pair = [&](int w2, int h, int loc, int yrow) {
             const int base = w2 * kGroups + h;
             const int nwh = S.gnw[w2 * 8 + h];
@@ -1384,6 +1384,22 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             *dst = wj * cost;
             ++n_ref;
         };
+        if constexpr (HALF) {
+            // float16 sources: each wave takes its own pairs, its last round partial (pooling measured slower here:
+            // with many sources and candidates the waves' last rounds are nearly full already)
+            int start[kGroups + 1];
+            start[0] = 0;
+#pragma unroll
+            for (int h = 0; h < kGroups; ++h)
+                start[h + 1] = start[h] + ncand * __builtin_amdgcn_readfirstlane(S.gnw[wave * 8 + h]);
+            const int yrow = __builtin_amdgcn_readfirstlane(y);
+            for (int qi = lane; qi < start[kGroups]; qi += 64) {
+                int h = 0;
+#pragma unroll
+                for (int k = 1; k < kGroups; ++k) h += qi >= start[k];
+                ref_pair(wave, h, qi - start[h], yrow);
+            }
+        } else {
         // pair counts of every wave's pixels (wave-uniform), and the pool of the waves' partial rounds
         int tot[WAVES], pool[WAVES + 1];
         pool[0] = 0;
@@ -1395,17 +1411,26 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             tot[w2] = acc;
             pool[w2 + 1] = pool[w2] + (acc & 63);
         }
-        int own_full = 0;
+        // this wave's prefix of pair counts over its pixels (wave-uniform), for the decode of its own rounds
+        int start[kGroups + 1];
+        start[0] = 0;
 #pragma unroll
-        for (int w2 = 0; w2 < WAVES; ++w2)
-            if (w2 == wave) own_full = tot[w2] >> 6;
+        for (int h = 0; h < kGroups; ++h)
+            start[h + 1] = start[h] + ncand * __builtin_amdgcn_readfirstlane(S.gnw[wave * 8 + h]);
+        const int own_full = start[kGroups] >> 6;
         // rounds of this wave: its own full rounds, then pool chunks wave, wave + WAVES, ...
         const int nchunks = (pool[WAVES] + 63) >> 6;
         const int rounds = own_full + (nchunks > wave ? (nchunks - wave + WAVES - 1) / WAVES : 0);
         for (int rd = 0; rd < rounds; ++rd) {
-            int w2 = wave, qi = rd * 64 + lane;
-            if (rd >= own_full) {
-                // pair pi of the pool belongs to wave w2, at its index (full rounds of w2) + (pi - pool[w2])
+            int w2 = wave, h = 0, loc;
+            if (rd < own_full) {
+                const int qi = rd * 64 + lane;
+#pragma unroll
+                for (int k = 1; k < kGroups; ++k) h += qi >= start[k];
+                loc = qi - start[h];
+            } else {
+                // pair pi of the pool belongs to wave w2, at its index (full rounds of w2) + (pi - pool[w2]);
+                // the pixel h of wave w2 whose pairs hold that index, from w2's pair counts
                 const int pi = (wave + (rd - own_full) * WAVES) * 64 + lane;
                 if (pi >= pool[WAVES]) continue;
                 int first = 0, fullw = 0;
@@ -1416,19 +1441,20 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
                         first = pool[k];
                         fullw = tot[k] & ~63;
                     }
-                qi = fullw + (pi - first);
-            }
-            // the pixel h of wave w2 whose pairs hold index qi, and the pair's index within the pixel
-            int h = 0, hs = 0, acc = 0;
+                const int qi = fullw + (pi - first);
+                int hs = 0, acc = 0;
 #pragma unroll
-            for (int k = 0; k < kGroups; ++k) {
-                acc += ncand * S.gnw[w2 * 8 + k];
-                if (qi >= acc) {
-                    h = k + 1;
-                    hs = acc;
+                for (int k = 0; k < kGroups; ++k) {
+                    acc += ncand * S.gnw[w2 * 8 + k];
+                    if (qi >= acc) {
+                        h = k + 1;
+                        hs = acc;
+                    }
                 }
+                loc = qi - hs;
             }
-            ref_pair(w2, h, qi - hs, y0 + w2);
+            ref_pair(w2, h, loc, y0 + w2);
+        }
         }
         __syncthreads();
         if (pix_ok) {
