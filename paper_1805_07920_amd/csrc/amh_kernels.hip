@@ -1361,8 +1361,8 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
         __syncthreads();
         // The (candidate, active view) pairs of a wave's 7 pixels, numbered pixel by pixel, spread over all 64
         // lanes (pixels with more active views no longer hold the wave for extra rounds); results go to the
-        // pixel's area of its wave's cost-matrix LDS (7 * 6N <= 64N).  Float32 sources: each wave runs its own
-        // full rounds of 64; the pairs of the waves' last, partial rounds are pooled over the workgroup and
+        // pixel's area of its wave's cost-matrix LDS (7 * 6N <= 64N).  Float32 sources (the method's build): each
+        // wave runs its own full rounds of 64; the pairs of the waves' last, partial rounds are pooled over the workgroup and
         // taken 64 at a time, wave w taking the w-th chunk, so that the partial rounds do not each cost a round.
         const auto ref_pair = [&](int w2, int h, int loc, int yrow) {
             const int base = w2 * kGroups + h;
@@ -1384,9 +1384,10 @@ __device__ __forceinline__ void pass_body(const PassArgs &a, int L, unsigned cha
             *dst = wj * cost;
             ++n_ref;
         };
-        if constexpr (HALF) {
-            // float16 sources: each wave takes its own pairs, its last round partial (pooling measured slower here:
-            // with many sources and candidates the waves' last rounds are nearly full already)
+        if constexpr (HALF || ABL) {
+            // float16 sources and the ablation build: each wave takes its own pairs, its last round partial
+            // (pooling measured slower in both: with many sources and candidates the waves' last rounds are
+            // nearly full already, and the ablation build's code generation suffers)
             int start[kGroups + 1];
             start[0] = 0;
 #pragma unroll
